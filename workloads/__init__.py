@@ -1,0 +1,111 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle scripts.
+
+This module only describes inputs: contours as Fourier coefficients of z(t), wavenumbers,
+plane-wave incidence angles and seeds.  It holds none of the solver's arithmetic, so both
+the HIP path and the CPU oracle can take their inputs from here without sharing any code.
+
+Contour convention: z(t) = sum_{m=-M..M} zhat[m+M] exp(i m t), t in [0, 2*pi),
+counter-clockwise, complex plane identified with R^2.
+
+The paper (Sec. VI) works on an ellipse with semi-axes 2 m and 1 m at increasing k with the
+mesh a fixed fraction of the wavelength.  The named workloads below are synthetic stand-ins
+shaped like that: ellipses and a smooth, convex, seeded perturbation of the unit circle,
+all discretised at about 10 nodes per wavelength (the first one is coarser, 15.7 nodes per
+wavelength, and small enough for a dense CPU solve).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Workload",
+    "ellipse_coeffs",
+    "perturbed_circle_coeffs",
+    "circle_coeffs",
+    "plane_wave_angles",
+    "WORKLOADS",
+    "get",
+]
+
+
+def ellipse_coeffs(a: float, b: float) -> np.ndarray:
+    """x = a cos t, y = b sin t  ->  z = (a+b)/2 e^{it} + (a-b)/2 e^{-it}; modes -1..1."""
+    return np.array([(a - b) / 2.0, 0.0, (a + b) / 2.0], dtype=np.complex128)
+
+
+def circle_coeffs(radius: float) -> np.ndarray:
+    return ellipse_coeffs(radius, radius)
+
+
+def perturbed_circle_coeffs(seed: int = 0, mmin: int = 2, mmax: int = 8,
+                            amp: float = 0.02) -> np.ndarray:
+    """r(theta) = 1 + sum_{m=mmin..mmax} c_m cos(m theta + phi_m),
+    c_m ~ U(0, amp/m^2) drawn as one vector, then phi_m ~ U(0, 2 pi) as one vector,
+    from numpy.random.default_rng(seed).  z(theta) = r(theta) e^{i theta} expanded in
+    Fourier modes -(mmax-1) .. mmax+1."""
+    rng = np.random.default_rng(seed)
+    ms = np.arange(mmin, mmax + 1)
+    c = rng.uniform(0.0, amp / ms.astype(np.float64) ** 2)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=ms.size)
+    M = mmax + 1
+    zhat = np.zeros(2 * M + 1, dtype=np.complex128)
+    zhat[M + 1] += 1.0
+    for mi, cm, ph in zip(ms, c, phi):
+        zhat[M + mi + 1] += 0.5 * cm * np.exp(1j * ph)
+        zhat[M + 1 - mi] += 0.5 * cm * np.exp(-1j * ph)
+    return zhat
+
+
+def plane_wave_angles(m: int) -> np.ndarray:
+    """Propagation directions alpha_j = 2 pi j / m, j = 0..m-1."""
+    return 2.0 * math.pi * np.arange(m, dtype=np.float64) / m
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    zhat: np.ndarray = field(repr=False)
+    n_nodes: int
+    k: float
+    nrhs: int
+    compress_tol: float
+    description: str
+    sketch_seed: int = 1
+
+    @property
+    def angles(self) -> np.ndarray:
+        return plane_wave_angles(self.nrhs)
+
+    @property
+    def n_modes(self) -> int:
+        return (len(self.zhat) - 1) // 2
+
+
+# Wavenumbers of the 10-nodes-per-wavelength workloads: k = 2 pi N / (10 L), with the
+# perimeter L of the contour (ellipse 1 x 0.5: L = 4.844224110273; perturbed circle,
+# seed 0: L = 6.283280042604).  They are fixed here as plain input numbers.
+_K_ELLIPSE_4096 = 531.2703630624
+_K_PERTURBED_16384 = 1638.375300000
+
+WORKLOADS = {
+    "ellipse256": Workload(
+        name="ellipse256", zhat=ellipse_coeffs(1.0, 0.6), n_nodes=256, k=20.0, nrhs=8,
+        compress_tol=1e-10,
+        description="ellipse a=1, b=0.6, k=20, N=256, 8 plane waves"),
+    "ellipse4096": Workload(
+        name="ellipse4096", zhat=ellipse_coeffs(1.0, 0.5), n_nodes=4096, k=_K_ELLIPSE_4096,
+        nrhs=256, compress_tol=1e-10,
+        description="ellipse a=1, b=0.5, 10 nodes/wavelength, N=4096, 256 plane waves"),
+    "perturbed16384": Workload(
+        name="perturbed16384", zhat=perturbed_circle_coeffs(0), n_nodes=16384,
+        k=_K_PERTURBED_16384, nrhs=1024, compress_tol=1e-4,
+        description="seed-0 convex Fourier-perturbed circle, 10 nodes/wavelength, "
+                    "N=16384, 1024 plane waves"),
+}
+
+
+def get(name: str) -> Workload:
+    return WORKLOADS[name]
