@@ -1,0 +1,170 @@
+/*
+ * cfie.h - C ABI of the MI355X fast direct solver for the preconditioned 2D TE combined
+ * field integral equation on a closed PEC contour.
+ *
+ * The operation follows the paper "On the Fast Direct Solution of a Preconditioned
+ * Electromagnetic Integral Equation":
+ *   - Sec. II, eqs. (1)-(4): CFIE for the tangential current j_t on the contour gamma,
+ *     discretised with hat functions piecewise linear in arc length (Galerkin, bilinear
+ *     pairing <f,g> = int f g ds).  Matrices N^k (hypersingular, Maue form), D^k
+ *     (double layer), Gram matrix G.
+ *   - Sec. III, eq. (5): the preconditioned system C j = b with
+ *       C = S^kt G^-1 N^k + (G/2 + D^kt) G^-1 (G/2 - D^k),
+ *       b = -(i k/eta) S^kt G^-1 e - (G/2 + D^kt) G^-1 h,
+ *       kt = k + 0.4 i k^(1/3) a^(-2/3).
+ *   - Sec. V, eqs. (6)-(9): C_c is C on the circle of equal perimeter (circulant,
+ *     diagonalised by the FFT); the remainder C - C_c = U V^T is compressed to a skeleton;
+ *     C^-1 = C_c^-1 - C_c^-1 U (I + V^T C_c^-1 U)^-1 V^T C_c^-1 (Woodbury) serves any number
+ *     of right-hand sides.
+ *
+ * Conventions used by every entry point:
+ *   - Complex numbers are interleaved (re, im) pairs: complex128 = 2 doubles.
+ *   - Vectors and matrices are column-major; a "device pointer" is memory allocated on
+ *     the device given to cfie_create (hipMalloc, torch CUDA tensors, ...).
+ *   - Every call is enqueued on the stream given to cfie_create and returns after that
+ *     stream has drained.  A context must not be used from two threads at once.
+ *   - The library owns every internal buffer; the caller owns what it passes in.
+ *   - Return value: CFIE_OK (0), an error (1..99; nothing was changed unless stated), or a
+ *     warning (>= 100; the call completed and its result is valid).  cfie_last_error
+ *     gives a text for the last non-OK status of a context.
+ */
+#ifndef CFIE_H
+#define CFIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cfie_ctx cfie_ctx;
+
+typedef enum {
+    CFIE_OK = 0,
+    CFIE_EINVAL = 1,      /* an argument is out of range or malformed                    */
+    CFIE_ENOMEM = 2,      /* device allocation failed (or the injected failure fired)    */
+    CFIE_EHIP = 3,        /* a HIP runtime call or kernel launch failed                  */
+    CFIE_ESTATE = 4,      /* call out of order (e.g. solve before factor)               */
+    CFIE_ESINGULAR = 5,   /* zero circulant eigenvalue or zero pivot in the capacitance */
+    CFIE_ENOCONV = 6,     /* refinement did not reach refine_tol; X holds the best iterate */
+    CFIE_WNONCONVEX = 100 /* warning: contour has negative curvature somewhere          */
+} cfie_status;
+
+enum { CFIE_FP64 = 0, CFIE_MIXED = 1 };
+
+/* Matrices that cfie_export_matrix can copy out (complex128, N x N unless stated). */
+enum {
+    CFIE_MAT_G = 0,       /* Gram matrix (real values stored as complex)               */
+    CFIE_MAT_DK = 1,      /* D^k   on gamma                                            */
+    CFIE_MAT_NK = 2,      /* N^k   on gamma (Maue form)                                */
+    CFIE_MAT_DKT = 3,     /* D^kt  on gamma                                            */
+    CFIE_MAT_SKT = 4,     /* S^kt  on gamma                                            */
+    CFIE_MAT_CC_EIG = 5,  /* N eigenvalues c_m of C_c, natural DFT order (N x 1)        */
+    CFIE_MAT_CIRCLE_ROW = 6 /* first rows of D^k, N^k, D^kt, S^kt on the circle (N x 4) */
+};
+
+typedef struct {
+    int32_t n_nodes;      /* N >= 8 nodes = elements, uniform in arc length from t = 0 */
+    int32_t n_modes;      /* M >= 1: z(t) = sum_{m=-M..M} zhat[m+M] e^{imt}, CCW       */
+    const double *zhat;   /* host, 2*(2M+1) doubles (re, im); read during the call only */
+} cfie_contour;
+
+typedef struct {
+    int32_t precision;    /* CFIE_FP64 or CFIE_MIXED (complex64 skeleton, GEMMs and FFTs,
+                             complex128 capacitance LU, FP64 iterative refinement)      */
+    double compress_tol;  /* epsilon: keep the sketch until the remainder's estimated
+                             norm is below epsilon * ||C_c||_2 (||C_c||_2 = max |c_m|)  */
+    int32_t block;        /* columns added to the sketch per adaptive step (b)         */
+    int32_t max_rank;     /* cap on the skeleton rank; 0 = N                            */
+    uint64_t seed;        /* seed of the Gaussian sketch (Philox4x32-10 counter stream) */
+    double refine_tol;    /* mixed precision: stop when every column has
+                             ||b_j - C x_j|| <= refine_tol ||b_j||                      */
+    int32_t max_refine;   /* mixed precision: maximum number of refinement sweeps       */
+    int32_t quad_far;     /* Gauss-Legendre points per element, well-separated pairs    */
+    int32_t quad_near;    /* Gauss-Legendre points per element, near pairs              */
+    int32_t near_band;    /* element pairs at cyclic distance <= near_band are near     */
+    int64_t fail_alloc_after; /* test hook: fail the (n+1)-th device allocation; -1 off */
+} cfie_options;
+
+typedef struct {
+    int32_t n_nodes;
+    int32_t rank;             /* skeleton rank r after cfie_factor                     */
+    double perimeter;         /* L                                                     */
+    double radius;            /* a = L / (2 pi), radius of the equivalent circle       */
+    double k;
+    double ktilde_re, ktilde_im;
+    double h;                 /* L / N                                                 */
+    double cc_norm;           /* ||C_c||_2 = max_m |c_m|                               */
+    double remainder_est;     /* last sketch block's largest column norm               */
+    double t_assemble_ms;     /* device time of the last cfie_assemble                 */
+    double t_factor_ms;       /* device time of the last cfie_factor                   */
+    double t_solve_ms;        /* device time of the last cfie_solve                    */
+    int32_t refine_sweeps;    /* sweeps used by the last mixed-precision cfie_solve    */
+    double refine_residual;   /* max_j ||b_j - C x_j|| / ||b_j|| after the last sweep  */
+    int32_t precision;
+    int32_t convex;           /* 1 if curvature >= 0 everywhere sampled                */
+} cfie_info;
+
+/* Fill *opt with defaults: FP64, compress_tol 1e-10, block 128, max_rank 0, seed 1,
+ * refine_tol 1e-8, max_refine 20, quad_far 5, quad_near 10, near_band 6, no injection. */
+void cfie_default_options(cfie_options *opt);
+
+/* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for
+ * the null stream).  *out is set only on success.  EINVAL on bad options, EHIP if the
+ * device cannot be selected. */
+cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream,
+                        cfie_ctx **out);
+
+/* Steps A1-A3 (Sec. II eq. (4), Sec. V): geometry of gamma and of its equivalent circle,
+ * dense assembly of D^k, N^k, D^kt, S^kt on gamma (complex128, library-owned, 64 N^2
+ * bytes), and the N eigenvalues c_m of C_c.  EINVAL: N < 8, k <= 0 or not finite, M < 1,
+ * non-finite coefficients, clockwise or self-intersecting contour.  WNONCONVEX: the
+ * contour is not convex (the algebra is unaffected).  Invalidates a previous factor. */
+cfie_status cfie_assemble(cfie_ctx *ctx, const cfie_contour *contour, double k);
+
+/* Steps A4-A5 (Sec. V eqs. (7)-(9)): randomized skeleton C - C_c ~ U V^T grown in blocks
+ * until the remainder estimate drops below compress_tol * ||C_c||_2 (or max_rank / N),
+ * then the capacitance matrix K = I + V^T C_c^-1 U and its LU factorisation with partial
+ * pivoting (complex128).  ESTATE before assemble; ESINGULAR on a zero pivot. */
+cfie_status cfie_factor(cfie_ctx *ctx);
+
+/* Step A6 (+ A7 in mixed precision): X = C^-1 B for nrhs right-hand sides by eq. (9).
+ * B_dev, X_dev: device, complex128, N x nrhs column-major with leading dimensions
+ * ldb, ldx >= N.  B_dev == X_dev is allowed (in place); other overlaps are not.
+ * nrhs == 0 is a no-op.  ESTATE before factor; ENOCONV (mixed only) if max_refine sweeps
+ * do not reach refine_tol, X then holds the last iterate. */
+cfie_status cfie_solve(cfie_ctx *ctx, const void *B_dev, int64_t ldb, void *X_dev,
+                       int64_t ldx, int64_t nrhs);
+
+/* Step A8 (Sec. II eq. (4), Sec. III eq. (5)): right-hand sides b of eq. (5) for unit TE
+ * plane waves H_z^inc = exp(i k d.r), d = (cos alpha_j, sin alpha_j); eta cancels.
+ * angles_host: host, nrhs doubles.  B_dev: device, complex128, N x nrhs, ldb >= N.
+ * ESTATE before assemble. */
+cfie_status cfie_plane_wave_rhs(cfie_ctx *ctx, const double *angles_host, int64_t nrhs,
+                                void *B_dev, int64_t ldb);
+
+/* Y = C X in complex128 from the assembled matrices (eq. (6), applied factor by factor).
+ * Device pointers, N x nrhs, column-major.  ESTATE before assemble.  Used for residuals
+ * and by the tests. */
+cfie_status cfie_apply_C(cfie_ctx *ctx, const void *X_dev, int64_t ldx, void *Y_dev,
+                         int64_t ldy, int64_t nrhs);
+
+/* Copy one internal matrix (CFIE_MAT_*) to dst_dev (device, complex128, column-major,
+ * leading dimension ld >= N).  ESTATE if it does not exist yet. */
+cfie_status cfie_export_matrix(cfie_ctx *ctx, int which, void *dst_dev, int64_t ld);
+
+cfie_status cfie_query(const cfie_ctx *ctx, cfie_info *out);
+
+/* Text for the last non-OK status on ctx (or for errors of cfie_create if ctx is NULL);
+ * valid until the next call on ctx. */
+const char *cfie_last_error(const cfie_ctx *ctx);
+
+const char *cfie_status_string(cfie_status s);
+
+/* Release every device buffer of ctx.  NULL is ignored. */
+void cfie_destroy(cfie_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFIE_H */

@@ -1,0 +1,160 @@
+"""MI355X fast direct solver for the preconditioned 2D TE CFIE (Python front end).
+
+    s = Solver(compress_tol=1e-10)
+    s.assemble(zhat, n_nodes, k)       # steps A1-A3: geometry, BEM matrices, C_c spectrum
+    s.factor()                          # steps A4-A5: randomized skeleton, capacitance LU
+    B = s.plane_wave_rhs(angles)        # step A8: right-hand sides of the preconditioned CFIE
+    X = s.solve(B)                      # step A6 (+ A7 refinement in mixed precision)
+
+Batches are (m, N) complex128 CUDA tensors (row j = right-hand side j).  The compute runs
+in libcfie.so; torch is used for device memory and the current stream only.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW, MAT_DK,
+                   MAT_DKT, MAT_G, MAT_NK, MAT_SKT)
+
+__all__ = ["Solver", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK", "MAT_NK",
+           "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "load_library"]
+
+
+def load_library():
+    return _lib.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class Solver:
+    """One problem (contour, N, k) on one HIP device."""
+
+    def __init__(self, precision: int = CFIE_FP64, compress_tol: float = 1e-10,
+                 block: int = 128, max_rank: int = 0, seed: int = 1,
+                 refine_tol: float = 1e-8, max_refine: int = 20, quad_far: int = 5,
+                 quad_near: int = 10, near_band: int = 6, fail_alloc_after: int = -1,
+                 device: int = 0, stream=None):
+        lib = _lib.load()
+        torch = _torch()
+        o = _lib.default_options()
+        o.precision = precision
+        o.compress_tol = compress_tol
+        o.block = block
+        o.max_rank = max_rank
+        o.seed = seed
+        o.refine_tol = refine_tol
+        o.max_refine = max_refine
+        o.quad_far = quad_far
+        o.quad_near = quad_near
+        o.near_band = near_band
+        o.fail_alloc_after = fail_alloc_after
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._stream = stream
+        handle = ctypes.c_void_p()
+        st = lib.cfie_create(ctypes.byref(o), device, ctypes.c_void_p(stream.cuda_stream),
+                             ctypes.byref(handle))
+        if st != 0:
+            raise CfieError(st, "cfie_create", lib.cfie_last_error(None).decode())
+        self._h = handle
+        self._lib = lib
+        self.N = 0
+        self.warning = None
+
+    # -- helpers ------------------------------------------------------------------------------
+    def _check(self, st: int, where: str):
+        if st == 0:
+            return
+        msg = self._lib.cfie_last_error(self._h).decode()
+        if st >= 100:
+            self.warning = (st, msg)
+            return
+        raise CfieError(st, where, msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cfie_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _batch(self, m):
+        torch = _torch()
+        return torch.empty((m, self.N), dtype=torch.complex128, device=self.device)
+
+    @staticmethod
+    def _check_batch(t, N, name):
+        torch = _torch()
+        if t.dtype != torch.complex128 or not t.is_cuda or t.dim() != 2 or t.shape[1] != N:
+            raise ValueError(f"{name} must be a (m, {N}) complex128 CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    # -- API ------------------------------------------------------------------------------------
+    def assemble(self, zhat, n_nodes: int, k: float):
+        z = np.ascontiguousarray(np.asarray(zhat, dtype=np.complex128))
+        flat = np.ascontiguousarray(z.view(np.float64))
+        c = _lib.Contour(n_nodes, (z.size - 1) // 2,
+                         flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self.warning = None
+        self._check(self._lib.cfie_assemble(self._h, ctypes.byref(c), float(k)),
+                    "cfie_assemble")
+        self.N = n_nodes
+        return self
+
+    def factor(self):
+        self._check(self._lib.cfie_factor(self._h), "cfie_factor")
+        return self
+
+    def solve(self, B, out=None):
+        self._check_batch(B, self.N, "B")
+        m = B.shape[0]
+        X = out if out is not None else self._batch(m)
+        self._check_batch(X, self.N, "X")
+        self._check(self._lib.cfie_solve(self._h, _ptr(B), self.N, _ptr(X), self.N, m),
+                    "cfie_solve")
+        return X
+
+    def plane_wave_rhs(self, angles, out=None):
+        a = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
+        B = out if out is not None else self._batch(a.size)
+        self._check(self._lib.cfie_plane_wave_rhs(
+            self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size, _ptr(B),
+            self.N), "cfie_plane_wave_rhs")
+        return B
+
+    def apply_C(self, X):
+        self._check_batch(X, self.N, "X")
+        Y = self._batch(X.shape[0])
+        self._check(self._lib.cfie_apply_C(self._h, _ptr(X), self.N, _ptr(Y), self.N,
+                                           X.shape[0]), "cfie_apply_C")
+        return Y
+
+    def export_matrix(self, which: int):
+        """Matrix as a torch tensor in natural (row, column) indexing."""
+        torch = _torch()
+        cols = {MAT_CC_EIG: 1, MAT_CIRCLE_ROW: 4}.get(which, self.N)
+        buf = torch.empty((cols, self.N), dtype=torch.complex128, device=self.device)
+        self._check(self._lib.cfie_export_matrix(self._h, which, _ptr(buf), self.N),
+                    "cfie_export_matrix")
+        return buf.t() if cols == self.N else buf
+
+    def info(self) -> dict:
+        i = _lib.Info()
+        self._check(self._lib.cfie_query(self._h, ctypes.byref(i)), "cfie_query")
+        return {f: getattr(i, f) for f, _ in i._fields_}

@@ -1,0 +1,1005 @@
+// C ABI of libcfie: context, state machine, device buffers and the orchestration of the
+// assembly (Sec. II, III), the circulant extraction and randomized skeleton (Sec. V eqs.
+// (6)-(8)) and the Woodbury solve (Sec. V eq. (9)).  Every step runs in this library's
+// kernels on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace cfie {
+// launchers defined in the kernel translation units
+void ginv_taps(int N, double h, std::vector<double> &coef, int &t0);
+template <typename T>
+void launch_ginv_ex(int N, int ntap, int t0, const double *coef, cpx<T> a, const cpx<T> *X,
+                    int64_t ldx, cpx<T> b, const cpx<T> *Y, int64_t ldy, cpx<T> *out,
+                    int64_t ldo, int64_t ncol, hipStream_t s);
+template <typename T>
+void launch_gmul(int N, double h, cpx<T> a, const cpx<T> *X, int64_t ldx, cpx<T> b,
+                 const cpx<T> *Y, int64_t ldy, cpx<T> *out, int64_t ldo, int64_t ncol,
+                 hipStream_t s);
+template <typename T>
+void axpby(int64_t m, int64_t n, cpx<T> a, const cpx<T> *X, int64_t ldx, cpx<T> b, cpx<T> *Y,
+           int64_t ldy, hipStream_t s);
+template <typename TO, typename TI>
+void convert(int64_t m, int64_t n, const cpx<TI> *X, int64_t ldx, cpx<TO> *Y, int64_t ldy,
+             hipStream_t s);
+template <typename T>
+void randn(int64_t m, int64_t n, uint64_t seed, uint64_t stream, cpx<T> *X, int64_t ldx,
+           hipStream_t s);
+template <typename T>
+void colnorm2(int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, double *out, hipStream_t s);
+void launch_circ_eigs(int N, int N1, int N2, double h, const zd *mu, zd *c, zd *dC, zd *dCH,
+                      zd *dCinv, zf *fC, zf *fCH, zf *fCinv, double *absc, hipStream_t s);
+void launch_maxmin(int64_t n, const double *x, double *out, hipStream_t s);
+void launch_dft_direct_tw(int N, const zd *x, int64_t ldx, zd *y, int64_t ldy, int ncol,
+                          const zd *twN, hipStream_t s);
+void launch_chol_inv(int b, zd *W, int ldw, double shift, zd *Rinv, int ldr, int *info,
+                     hipStream_t s);
+void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info,
+                     hipStream_t s);
+template <typename T>
+void launch_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0,
+                  int64_t c1, hipStream_t s);
+void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
+                    hipStream_t s);
+void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s);
+void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out,
+                      hipStream_t s);
+}  // namespace cfie
+
+using namespace cfie;
+
+namespace {
+
+constexpr int kLUBlock = 64;
+
+struct HipError {
+    cfie_status st;
+    std::string msg;
+};
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            throw HipError{CFIE_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};     \
+    } while (0)
+
+template <typename T> zd *asz(T *p) { return reinterpret_cast<zd *>(p); }
+
+}  // namespace
+
+struct cfie_ctx {
+    cfie_options opt;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int state = 0;                       // 0 created, 1 assembled, 2 factored
+    int64_t n_alloc = 0;
+    std::map<void *, size_t> live;
+
+    // problem
+    int N = 0;
+    double k = 0.0;
+    zd kt = mk(0.0, 0.0);
+    HostGeometry hg, hc;
+    double cc_norm = 0.0, cc_min = 0.0;
+    int rank = 0;
+    double remainder_est = 0.0;
+    float t_asm = 0, t_fac = 0, t_sol = 0;
+    int refine_sweeps = 0;
+    double refine_res = 0.0;
+
+    // quadrature tables
+    std::vector<double> xf, wf, xn, wn, moments;
+    double *d_xf = nullptr, *d_wf = nullptr, *d_xn = nullptr, *d_wn = nullptr, *d_mom = nullptr;
+    std::vector<double> gcoef;
+    int g_t0 = 0;
+    double *d_gcoef = nullptr;
+
+    // geometry on device
+    GeomDev gd, gc;
+    PointTable pf, pn, cf, cn;
+
+    // matrices
+    zd *mat[4] = {nullptr, nullptr, nullptr, nullptr};   // Dk, Nk, Dkt, Skt
+    zf *mat32[4] = {nullptr, nullptr, nullptr, nullptr};
+    zd *crow = nullptr, *mu = nullptr, *cvals = nullptr;
+    zd *dC = nullptr, *dCH = nullptr, *dCinv = nullptr;
+    zf *fC = nullptr, *fCH = nullptr, *fCinv = nullptr;
+    double *absc = nullptr, *scal = nullptr;
+    FFTPlan fft;
+
+    // factor
+    int cap = 0;
+    void *Q = nullptr, *P = nullptr, *Ut = nullptr;    // N x cap (zd or zf)
+    zd *K = nullptr;                                    // cap x cap
+    int *piv = nullptr, *info = nullptr;
+    zd *Linv = nullptr, *Uinv = nullptr;                // diagonal block inverses
+    void *w_om = nullptr, *w_y = nullptr, *w_t = nullptr, *w_w1 = nullptr, *w_w2 = nullptr,
+         *w_z = nullptr, *w_s = nullptr, *w_rinvT = nullptr;
+    zd *w_gram = nullptr, *w_rinv = nullptr;
+    double *w_norm = nullptr;
+
+    ~cfie_ctx() {
+        for (auto &kv : live) (void)hipFree(kv.first);
+        live.clear();
+        if (stream_owned && stream) (void)hipStreamDestroy(stream);
+    }
+    bool stream_owned = false;
+
+    void *dalloc(size_t bytes) {
+        if (opt.fail_alloc_after >= 0 && n_alloc >= opt.fail_alloc_after)
+            throw HipError{CFIE_ENOMEM, "injected allocation failure"};
+        ++n_alloc;
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw HipError{CFIE_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+        }
+        live[p] = bytes;
+        return p;
+    }
+    void dfree(void *p) {
+        if (!p) return;
+        auto it = live.find(p);
+        if (it != live.end()) {
+            (void)hipFree(p);
+            live.erase(it);
+        }
+    }
+    template <typename T> T *alloc_n(size_t n) { return (T *)dalloc(n * sizeof(T)); }
+    template <typename T> void upload(T *d, const T *h, size_t n) {
+        HIPCHK(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, stream));
+    }
+    void sync() { HIPCHK(hipStreamSynchronize(stream)); }
+    void check_launch() { HIPCHK(hipGetLastError()); }
+};
+
+namespace {
+
+cfie_status fail(cfie_ctx *c, cfie_status s, const std::string &m) {
+    if (c) c->err = m;
+    return s;
+}
+
+thread_local std::string g_create_err;
+
+template <typename F> cfie_status guarded(cfie_ctx *c, F &&f) {
+    try {
+        return f();
+    } catch (const HipError &e) {
+        if (c) {
+            c->err = e.msg;
+            (void)hipGetLastError();
+        }
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        return fail(c, CFIE_ENOMEM, "host allocation failed");
+    }
+}
+
+void free_factor(cfie_ctx *c) {
+    void *bufs[] = {c->Q, c->P, c->Ut, c->K, c->piv, c->info, c->Linv, c->Uinv, c->w_om,
+                    c->w_y, c->w_t, c->w_w1, c->w_w2, c->w_z, c->w_s, c->w_rinvT, c->w_gram,
+                    c->w_rinv, c->w_norm};
+    for (void *p : bufs) c->dfree(p);
+    c->Q = c->P = c->Ut = nullptr;
+    c->K = nullptr;
+    c->piv = c->info = nullptr;
+    c->Linv = c->Uinv = nullptr;
+    c->w_om = c->w_y = c->w_t = c->w_w1 = c->w_w2 = c->w_z = c->w_s = c->w_rinvT = nullptr;
+    c->w_gram = c->w_rinv = nullptr;
+    c->w_norm = nullptr;
+    c->rank = 0;
+}
+
+void alloc_points(cfie_ctx *c, PointTable &pt, int q) {
+    pt.q = q;
+    size_t n = (size_t)c->N * q;
+    pt.x = c->alloc_n<double>(n);
+    pt.y = c->alloc_n<double>(n);
+    pt.tx = c->alloc_n<double>(n);
+    pt.ty = c->alloc_n<double>(n);
+    pt.curv = c->alloc_n<double>(n);
+}
+void free_points(cfie_ctx *c, PointTable &pt) {
+    c->dfree(pt.x); c->dfree(pt.y); c->dfree(pt.tx); c->dfree(pt.ty); c->dfree(pt.curv);
+    pt = PointTable{};
+}
+
+void upload_geom(cfie_ctx *c, const HostGeometry &h, GeomDev &g) {
+    if (g.zhat) c->dfree(g.zhat);
+    if (g.cm) c->dfree(g.cm);
+    g.M = h.M;
+    g.Ms = (int)h.cm.size();
+    g.zhat = c->alloc_n<zd>(h.zhat.size());
+    c->upload(g.zhat, h.zhat.data(), h.zhat.size());
+    g.cm = c->alloc_n<zd>(std::max<size_t>(1, h.cm.size()));
+    if (!h.cm.empty()) c->upload(g.cm, h.cm.data(), h.cm.size());
+    g.c0 = h.c0;
+    g.L = h.L;
+    g.h = h.L / c->N;
+    g.N = c->N;
+}
+
+void setup_fft(cfie_ctx *c) {
+    FFTPlan &p = c->fft;
+    c->dfree(p.tw1); c->dfree(p.twN); c->dfree(p.tw1f); c->dfree(p.twNf);
+    int N = c->N;
+    p.N = N;
+    p.N1 = std::min(N, 4096);
+    p.N2 = N / p.N1;
+    std::vector<double> t1(2 * (size_t)p.N1), tN(2 * (size_t)N);
+    std::vector<float> t1f(2 * (size_t)p.N1), tNf(2 * (size_t)N);
+    for (int j = 0; j < p.N1; ++j) {
+        // exact reduction of the angle: e^{-2 pi i j / n} via sin/cos of pi * (2j/n)
+        double a = -2.0 * kPi * (double)j / p.N1;
+        t1[2 * j] = std::cos(a);
+        t1[2 * j + 1] = std::sin(a);
+        t1f[2 * j] = (float)t1[2 * j];
+        t1f[2 * j + 1] = (float)t1[2 * j + 1];
+    }
+    for (int j = 0; j < N; ++j) {
+        double a = -2.0 * kPi * (double)j / N;
+        tN[2 * j] = std::cos(a);
+        tN[2 * j + 1] = std::sin(a);
+        tNf[2 * j] = (float)tN[2 * j];
+        tNf[2 * j + 1] = (float)tN[2 * j + 1];
+    }
+    p.tw1 = c->alloc_n<double>(t1.size());
+    p.twN = c->alloc_n<double>(tN.size());
+    p.tw1f = c->alloc_n<float>(t1f.size());
+    p.twNf = c->alloc_n<float>(tNf.size());
+    c->upload(p.tw1, t1.data(), t1.size());
+    c->upload(p.twN, tN.data(), tN.size());
+    c->upload(p.tw1f, t1f.data(), t1f.size());
+    c->upload(p.twNf, tNf.data(), tNf.size());
+}
+
+template <typename T> cpx<T> cz(double a, double b = 0.0) { return mk((T)a, (T)b); }
+
+// ---------------------------------------------------------------- operator applications ---
+template <typename T> struct Ops;
+template <> struct Ops<double> {
+    static zd *mat(cfie_ctx *c, int i) { return c->mat[i]; }
+    static const zd *dC(cfie_ctx *c) { return c->dC; }
+    static const zd *dCH(cfie_ctx *c) { return c->dCH; }
+    static const zd *dCinv(cfie_ctx *c) { return c->dCinv; }
+};
+template <> struct Ops<float> {
+    static zf *mat(cfie_ctx *c, int i) { return c->mat32[i]; }
+    static const zf *dC(cfie_ctx *c) { return c->fC; }
+    static const zf *dCH(cfie_ctx *c) { return c->fCH; }
+    static const zf *dCinv(cfie_ctx *c) { return c->fCinv; }
+};
+
+// Y = C X, C = (G/2 + Dkt) G^{-1} (G/2 - Dk) + Skt G^{-1} Nk   (eq. (6))
+// temps: T, W1, W2 (N x m each)
+template <typename T>
+void apply_C(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
+             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2) {
+    const int N = c->N;
+    const double h = c->hg.L / N;
+    hipStream_t s = c->stream;
+    const int nt = (int)c->gcoef.size();
+    gemm<T>(false, N, m, N, cz<T>(1), Ops<T>::mat(c, 0), N, X, ldx, cz<T>(0), Tt, N, s);
+    launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0.5), X, ldx, cz<T>(-1), Tt, N, W1, N, m, s);
+    gemm<T>(false, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, X, ldx, cz<T>(0), Tt, N, s);
+    launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(1),
+                      Tt, N, W2, N, m, s);
+    launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), W1, N, Y, ldy, m, s);
+    gemm<T>(false, N, m, N, cz<T>(1), Ops<T>::mat(c, 2), N, W1, N, cz<T>(1), Y, ldy, s);
+    gemm<T>(false, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, W2, N, cz<T>(1), Y, ldy, s);
+    c->check_launch();
+}
+
+// Y = (C - C_c) X ; temps T, W1, W2, Z
+template <typename T>
+void apply_R(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
+             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z) {
+    const int N = c->N;
+    apply_C<T>(c, X, ldx, Y, ldy, m, Tt, W1, W2);
+    axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, c->stream);
+    launch_circ_apply<T>(c->fft, Ops<T>::dC(c), Z, N, m, c->stream);
+    axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, c->stream);
+    c->check_launch();
+}
+
+// Y = (C - C_c)^H X = (G/2 - Dk^H) V1 + Nk^H V2 - C_c^H X,
+// V1 = X/2 + G^{-1} Dkt^H X, V2 = G^{-1} Skt^H X
+template <typename T>
+void apply_RH(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
+              cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z) {
+    const int N = c->N;
+    const double h = c->hg.L / N;
+    hipStream_t s = c->stream;
+    const int nt = (int)c->gcoef.size();
+    gemm<T>(true, N, m, N, cz<T>(1), Ops<T>::mat(c, 2), N, X, ldx, cz<T>(0), Tt, N, s);
+    launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0.5), X, ldx, cz<T>(1), Tt, N, W1, N, m, s);
+    gemm<T>(true, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, X, ldx, cz<T>(0), Tt, N, s);
+    launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(1),
+                      Tt, N, W2, N, m, s);
+    launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), W1, N, Y, ldy, m, s);
+    gemm<T>(true, N, m, N, cz<T>(-1), Ops<T>::mat(c, 0), N, W1, N, cz<T>(1), Y, ldy, s);
+    gemm<T>(true, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, W2, N, cz<T>(1), Y, ldy, s);
+    axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, s);
+    launch_circ_apply<T>(c->fft, Ops<T>::dCH(c), Z, N, m, s);
+    axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, s);
+    c->check_launch();
+}
+
+double unit_roundoff(double) { return 1.1102230246251565e-16; }
+double unit_roundoff(float) { return 5.9604644775390625e-08; }
+
+// orthonormalise the N x b block Y in place (shifted Cholesky QR, then two plain passes)
+template <typename T>
+void orthonormalise(cfie_ctx *c, cpx<T> *Y, int b) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    cpx<T> *gramT = (cpx<T> *)c->w_s;                    // b x b scratch in T (first b*b)
+    cpx<T> *rinvT = (cpx<T> *)c->w_rinvT;
+    cpx<T> *Y2 = (cpx<T> *)c->w_t;
+    for (int pass = 0; pass < 3; ++pass) {
+        gemm<T>(true, b, b, N, cz<T>(1), Y, N, Y, N, cz<T>(0), gramT, b, s);
+        convert<double, T>(b, b, gramT, b, c->w_gram, b, s);
+        double shift = 0.0;
+        if (pass == 0) {
+            // shift = 11 (N b + b (b + 1)) u ||Y||_F^2 (Fukaya et al., shifted CholeskyQR)
+            colnorm2<T>(N, b, Y, N, c->w_norm, s);
+            std::vector<double> nrm(b);
+            HIPCHK(hipMemcpyAsync(nrm.data(), c->w_norm, b * sizeof(double), hipMemcpyDeviceToHost, s));
+            c->sync();
+            double fro = 0.0;
+            for (double v : nrm) fro += v;
+            shift = 11.0 * ((double)N * b + (double)b * (b + 1)) * unit_roundoff((T)0) * fro;
+        }
+        HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
+        launch_chol_inv(b, c->w_gram, b, shift, c->w_rinv, b, c->info, s);
+        convert<T, double>(b, b, c->w_rinv, b, rinvT, b, s);
+        gemm<T>(false, N, b, b, cz<T>(1), Y, N, rinvT, b, cz<T>(0), Y2, N, s);
+        axpby<T>(N, b, cz<T>(1), Y2, N, cz<T>(0), Y, N, s);
+        c->check_launch();
+    }
+}
+
+template <typename T>
+void alloc_factor(cfie_ctx *c) {
+    free_factor(c);
+    const int N = c->N;
+    int cap = c->opt.max_rank > 0 ? std::min(c->opt.max_rank, N) : N;
+    c->cap = cap;
+    int b = std::min(c->opt.block, N);
+    size_t nb = (size_t)N * b;
+    c->Q = c->alloc_n<cpx<T>>((size_t)N * cap);
+    c->w_om = c->alloc_n<cpx<T>>(nb);
+    c->w_y = c->alloc_n<cpx<T>>(nb);
+    c->w_t = c->alloc_n<cpx<T>>(nb);
+    c->w_w1 = c->alloc_n<cpx<T>>(nb);
+    c->w_w2 = c->alloc_n<cpx<T>>(nb);
+    c->w_z = c->alloc_n<cpx<T>>(nb);
+    c->w_s = c->alloc_n<cpx<T>>((size_t)std::max(cap, b) * b);
+    c->w_rinvT = c->alloc_n<cpx<T>>((size_t)b * b);
+    c->w_gram = c->alloc_n<zd>((size_t)b * b);
+    c->w_rinv = c->alloc_n<zd>((size_t)b * b);
+    c->w_norm = c->alloc_n<double>((size_t)std::max(b, 64));
+    c->info = c->alloc_n<int>(4);
+}
+
+// solve K Z = Z in place with the LU factors (piv, L, U; diagonal block inverses)
+void lu_solve(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
+    const int n = c->rank;
+    hipStream_t s = c->stream;
+    launch_swaps<double>(0, n, c->piv, Z, ldz, 0, m, s);
+    const int nb = kLUBlock;
+    int nblk = (n + nb - 1) / nb;
+    for (int bi = 0; bi < nblk; ++bi) {
+        int k0 = bi * nb, kb = std::min(nb, n - k0);
+        gemm<double>(false, kb, m, kb, cz<double>(1), c->Linv + (size_t)bi * nb * nb, nb,
+                     Z + k0, ldz, cz<double>(0), tmp, kb, s);
+        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
+        int rest = n - k0 - kb;
+        if (rest > 0)
+            gemm<double>(false, rest, m, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * c->cap,
+                         c->cap, Z + k0, ldz, cz<double>(1), Z + k0 + kb, ldz, s);
+    }
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        int k0 = bi * nb, kb = std::min(nb, n - k0);
+        gemm<double>(false, kb, m, kb, cz<double>(1), c->Uinv + (size_t)bi * nb * nb, nb,
+                     Z + k0, ldz, cz<double>(0), tmp, kb, s);
+        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
+        if (k0 > 0)
+            gemm<double>(false, k0, m, kb, cz<double>(-1), c->K + (size_t)k0 * c->cap, c->cap,
+                         Z + k0, ldz, cz<double>(1), Z, ldz, s);
+    }
+    c->check_launch();
+}
+
+template <typename T>
+cfie_status factor_impl(cfie_ctx *c) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    alloc_factor<T>(c);
+    const int cap = c->cap;
+    const int b = std::min(c->opt.block, N);
+    cpx<T> *Q = (cpx<T> *)c->Q;
+    cpx<T> *Om = (cpx<T> *)c->w_om, *Y = (cpx<T> *)c->w_y, *Tt = (cpx<T> *)c->w_t;
+    cpx<T> *W1 = (cpx<T> *)c->w_w1, *W2 = (cpx<T> *)c->w_w2, *Z = (cpx<T> *)c->w_z;
+    cpx<T> *S = (cpx<T> *)c->w_s;
+    const double tau = c->opt.compress_tol * c->cc_norm;
+    int ell = 0;
+    uint64_t blk = 0;
+    std::vector<double> nrm(b);
+    c->remainder_est = 0.0;
+    while (ell < cap) {
+        int bb = std::min(b, cap - ell);
+        randn<T>(N, bb, c->opt.seed, blk++, Om, N, s);
+        apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z);
+        if (ell > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                gemm<T>(true, ell, bb, N, cz<T>(1), Q, N, Y, N, cz<T>(0), S, ell, s);
+                gemm<T>(false, N, bb, ell, cz<T>(-1), Q, N, S, ell, cz<T>(1), Y, N, s);
+            }
+        }
+        colnorm2<T>(N, bb, Y, N, c->w_norm, s);
+        HIPCHK(hipMemcpyAsync(nrm.data(), c->w_norm, bb * sizeof(double), hipMemcpyDeviceToHost, s));
+        c->sync();
+        double mx = 0.0;
+        for (int i = 0; i < bb; ++i) mx = std::max(mx, nrm[i]);
+        c->remainder_est = std::sqrt(mx);
+        if (c->remainder_est <= tau) break;
+        orthonormalise<T>(c, Y, bb);
+        axpby<T>(N, bb, cz<T>(1), Y, N, cz<T>(0), Q + (size_t)ell * N, N, s);
+        ell += bb;
+    }
+    c->rank = ell;
+    if (ell == 0) {
+        c->state = 2;
+        return CFIE_OK;
+    }
+    // P = R^H Q, Ut = C_c^{-1} Q
+    c->P = c->alloc_n<cpx<T>>((size_t)N * ell);
+    c->Ut = c->alloc_n<cpx<T>>((size_t)N * ell);
+    cpx<T> *P = (cpx<T> *)c->P, *Ut = (cpx<T> *)c->Ut;
+    for (int j = 0; j < ell; j += b) {
+        int bb = std::min(b, ell - j);
+        apply_RH<T>(c, Q + (size_t)j * N, N, P + (size_t)j * N, N, bb, Tt, W1, W2, Z);
+    }
+    axpby<T>(N, ell, cz<T>(1), Q, N, cz<T>(0), Ut, N, s);
+    launch_circ_apply<T>(c->fft, Ops<T>::dCinv(c), Ut, N, ell, s);
+    // K = I + P^H Ut  (Woodbury capacitance, eq. (9)), always complex128
+    c->K = c->alloc_n<zd>((size_t)cap * cap);
+    if (sizeof(T) == sizeof(double)) {
+        gemm<double>(true, ell, ell, N, cz<double>(1), (const zd *)P, N, (const zd *)Ut, N,
+                     cz<double>(0), c->K, cap, s);
+    } else {
+        cpx<T> *K32 = (cpx<T> *)c->alloc_n<cpx<T>>((size_t)ell * ell);
+        gemm<T>(true, ell, ell, N, cz<T>(1), P, N, Ut, N, cz<T>(0), K32, ell, s);
+        convert<double, T>(ell, ell, K32, ell, c->K, cap, s);
+        c->sync();
+        c->dfree(K32);
+    }
+    launch_add_identity(ell, c->K, cap, s);
+    // blocked LU with partial pivoting
+    c->piv = c->alloc_n<int>(std::max(ell, 1));
+    int nblk = (ell + kLUBlock - 1) / kLUBlock;
+    c->Linv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
+    c->Uinv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
+    zd *tmp = c->alloc_n<zd>((size_t)kLUBlock * std::max(ell, 1));
+    HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
+    for (int bi = 0; bi < nblk; ++bi) {
+        int k0 = bi * kLUBlock, kb = std::min(kLUBlock, ell - k0);
+        launch_lu_panel(ell, k0, kb, c->K, cap, c->piv, c->info, s);
+        launch_swaps<double>(k0, k0 + kb, c->piv, c->K, cap, 0, k0, s);
+        launch_swaps<double>(k0, k0 + kb, c->piv, c->K, cap, k0 + kb, ell, s);
+        zd *Kd = c->K + k0 + (size_t)k0 * cap;
+        launch_tri_inv(kb, Kd, cap, true, c->Linv + (size_t)bi * kLUBlock * kLUBlock, kLUBlock, s);
+        int rest = ell - k0 - kb;
+        if (rest > 0) {
+            zd *U12 = c->K + k0 + (size_t)(k0 + kb) * cap;
+            gemm<double>(false, kb, rest, kb, cz<double>(1), c->Linv + (size_t)bi * kLUBlock * kLUBlock,
+                         kLUBlock, U12, cap, cz<double>(0), tmp, kb, s);
+            axpby<double>(kb, rest, cz<double>(1), tmp, kb, cz<double>(0), U12, cap, s);
+            gemm<double>(false, rest, rest, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * cap,
+                         cap, U12, cap, cz<double>(1), c->K + (k0 + kb) + (size_t)(k0 + kb) * cap,
+                         cap, s);
+        }
+        launch_tri_inv(kb, Kd, cap, false, c->Uinv + (size_t)bi * kLUBlock * kLUBlock, kLUBlock, s);
+        c->check_launch();
+    }
+    int info = 0;
+    HIPCHK(hipMemcpyAsync(&info, c->info, sizeof(int), hipMemcpyDeviceToHost, s));
+    c->sync();
+    c->dfree(tmp);
+    if (info) return fail(c, CFIE_ESINGULAR, "zero pivot in the capacitance matrix");
+    c->state = 2;
+    return CFIE_OK;
+}
+
+// X <- C^{-1} X in precision T (X is N x m in T, ld N); Zbuf: rank x m (zd), tmp
+template <typename T>
+void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, zd *Zd, cpx<T> *ZT, zd *tmp) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    launch_circ_apply<T>(c->fft, Ops<T>::dCinv(c), X, N, m, s);
+    const int r = c->rank;
+    if (r == 0) return;
+    cpx<T> *P = (cpx<T> *)c->P, *Ut = (cpx<T> *)c->Ut;
+    if (sizeof(T) == sizeof(double)) {
+        gemm<double>(true, r, m, N, cz<double>(1), (const zd *)P, N, (const zd *)X, N,
+                     cz<double>(0), Zd, r, s);
+        lu_solve(c, Zd, r, m, tmp);
+        gemm<double>(false, N, m, r, cz<double>(-1), (const zd *)Ut, N, Zd, r, cz<double>(1),
+                     (zd *)X, N, s);
+    } else {
+        gemm<T>(true, r, m, N, cz<T>(1), P, N, X, N, cz<T>(0), ZT, r, s);
+        convert<double, T>(r, m, ZT, r, Zd, r, s);
+        lu_solve(c, Zd, r, m, tmp);
+        convert<T, double>(r, m, Zd, r, ZT, r, s);
+        gemm<T>(false, N, m, r, cz<T>(-1), Ut, N, ZT, r, cz<T>(1), X, N, s);
+    }
+    c->check_launch();
+}
+
+cfie_status solve_fp64(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx, int64_t nrhs) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    const int64_t chunk = 4096;
+    int r = std::max(c->rank, 1);
+    int64_t mc = std::min<int64_t>(nrhs, chunk);
+    zd *work = c->alloc_n<zd>((size_t)N * mc);
+    zd *Zd = c->alloc_n<zd>((size_t)r * mc);
+    zd *tmp = c->alloc_n<zd>((size_t)kLUBlock * mc);
+    for (int64_t j = 0; j < nrhs; j += chunk) {
+        int64_t m = std::min(chunk, nrhs - j);
+        axpby<double>(N, m, cz<double>(1), B + j * ldb, ldb, cz<double>(0), work, N, s);
+        woodbury<double>(c, work, m, Zd, nullptr, tmp);
+        axpby<double>(N, m, cz<double>(1), work, N, cz<double>(0), X + j * ldx, ldx, s);
+    }
+    c->sync();
+    c->dfree(work);
+    c->dfree(Zd);
+    c->dfree(tmp);
+    return CFIE_OK;
+}
+
+cfie_status solve_mixed(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx,
+                        int64_t nrhs) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    const int64_t chunk = 2048;
+    int r = std::max(c->rank, 1);
+    int64_t mc = std::min<int64_t>(nrhs, chunk);
+    zd *Rb = c->alloc_n<zd>((size_t)N * mc);              // residual (FP64)
+    zd *Xw = c->alloc_n<zd>((size_t)N * mc);              // iterate (FP64)
+    zd *Tt = c->alloc_n<zd>((size_t)N * mc);
+    zd *W1 = c->alloc_n<zd>((size_t)N * mc);
+    zd *W2 = c->alloc_n<zd>((size_t)N * mc);
+    zf *R32 = c->alloc_n<zf>((size_t)N * mc);
+    zd *Zd = c->alloc_n<zd>((size_t)r * mc);
+    zf *Z32 = c->alloc_n<zf>((size_t)r * mc);
+    zd *tmp = c->alloc_n<zd>((size_t)kLUBlock * mc);
+    double *b2 = c->alloc_n<double>(mc), *r2 = c->alloc_n<double>(mc), *mx = c->alloc_n<double>(2);
+    cfie_status st = CFIE_OK;
+    int sweeps_max = 0;
+    double worst = 0.0;
+    for (int64_t j = 0; j < nrhs; j += chunk) {
+        int64_t m = std::min(chunk, nrhs - j);
+        const zd *Bj = B + j * ldb;
+        colnorm2<double>(N, m, Bj, ldb, b2, s);
+        axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(0), Rb, N, s);
+        HIPCHK(hipMemsetAsync(Xw, 0, sizeof(zd) * (size_t)N * m, s));
+        int sweep = 0;
+        double rel = 1e300;
+        for (; sweep < std::max(1, c->opt.max_refine); ++sweep) {
+            convert<float, double>(N, m, Rb, N, R32, N, s);
+            woodbury<float>(c, R32, m, Zd, Z32, tmp);
+            convert<double, float>(N, m, R32, N, Tt, N, s);
+            axpby<double>(N, m, cz<double>(1), Tt, N, cz<double>(1), Xw, N, s);
+            // residual in FP64 against the assembled operator
+            apply_C<double>(c, Xw, N, Rb, N, m, Tt, W1, W2);
+            axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(-1), Rb, N, s);
+            colnorm2<double>(N, m, Rb, N, r2, s);
+            launch_ratio_max(m, r2, b2, mx, s);
+            HIPCHK(hipMemcpyAsync(&rel, mx, sizeof(double), hipMemcpyDeviceToHost, s));
+            c->sync();
+            if (rel <= c->opt.refine_tol) { ++sweep; break; }
+        }
+        axpby<double>(N, m, cz<double>(1), Xw, N, cz<double>(0), X + j * ldx, ldx, s);
+        sweeps_max = std::max(sweeps_max, sweep);
+        worst = std::max(worst, rel);
+        if (rel > c->opt.refine_tol) st = CFIE_ENOCONV;
+    }
+    c->sync();
+    void *bufs[] = {Rb, Xw, Tt, W1, W2, R32, Zd, Z32, tmp, b2, r2, mx};
+    for (void *p : bufs) c->dfree(p);
+    c->refine_sweeps = sweeps_max;
+    c->refine_res = worst;
+    if (st == CFIE_ENOCONV) return fail(c, st, "refinement did not reach refine_tol");
+    return CFIE_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI ======
+extern "C" {
+
+void cfie_default_options(cfie_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = CFIE_FP64;
+    o->compress_tol = 1e-10;
+    o->block = 128;
+    o->max_rank = 0;
+    o->seed = 1;
+    o->refine_tol = 1e-8;
+    o->max_refine = 20;
+    o->quad_far = 5;
+    o->quad_near = 10;
+    o->near_band = 6;
+    o->fail_alloc_after = -1;
+}
+
+const char *cfie_status_string(cfie_status s) {
+    switch (s) {
+        case CFIE_OK: return "ok";
+        case CFIE_EINVAL: return "invalid argument";
+        case CFIE_ENOMEM: return "out of device memory";
+        case CFIE_EHIP: return "HIP runtime error";
+        case CFIE_ESTATE: return "call out of order";
+        case CFIE_ESINGULAR: return "singular matrix";
+        case CFIE_ENOCONV: return "refinement did not converge";
+        case CFIE_WNONCONVEX: return "warning: contour is not convex";
+    }
+    return "unknown status";
+}
+
+cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, cfie_ctx **out) {
+    g_create_err.clear();
+    if (!out) { g_create_err = "out is NULL"; return CFIE_EINVAL; }
+    cfie_options o;
+    if (opt) o = *opt; else cfie_default_options(&o);
+    auto bad = [&](const char *m) { g_create_err = m; return CFIE_EINVAL; };
+    if (o.precision != CFIE_FP64 && o.precision != CFIE_MIXED) return bad("precision must be 0 or 1");
+    if (!(o.compress_tol >= 0.0) || !std::isfinite(o.compress_tol)) return bad("compress_tol must be >= 0");
+    if (o.block < 1 || o.block > 512) return bad("block must be in [1, 512]");
+    if (o.max_rank < 0) return bad("max_rank must be >= 0");
+    if (!(o.refine_tol > 0.0)) return bad("refine_tol must be > 0");
+    if (o.max_refine < 1) return bad("max_refine must be >= 1");
+    if (o.quad_far != 3 && o.quad_far != 4 && o.quad_far != 5 && o.quad_far != 6 && o.quad_far != 8)
+        return bad("quad_far must be one of 3, 4, 5, 6, 8");
+    if (o.quad_near < 4 || o.quad_near > 16) return bad("quad_near must be in [4, 16]");
+    if (o.near_band < 1 || o.near_band > 64) return bad("near_band must be in [1, 64]");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        g_create_err = "no such HIP device";
+        return CFIE_EHIP;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        g_create_err = "hipSetDevice failed";
+        return CFIE_EHIP;
+    }
+    cfie_ctx *c = new (std::nothrow) cfie_ctx();
+    if (!c) { g_create_err = "host allocation failed"; return CFIE_ENOMEM; }
+    c->opt = o;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return CFIE_OK;
+}
+
+void cfie_destroy(cfie_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+const char *cfie_last_error(const cfie_ctx *c) {
+    if (!c) return g_create_err.c_str();
+    return c->err.c_str();
+}
+
+cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
+    if (!c) return CFIE_EINVAL;
+    if (!contour) return fail(c, CFIE_EINVAL, "contour is NULL");
+    if (contour->n_nodes < 8) return fail(c, CFIE_EINVAL, "n_nodes must be >= 8");
+    int N = contour->n_nodes;
+    if (N & (N - 1)) return fail(c, CFIE_EINVAL, "n_nodes must be a power of two");
+    if (N > (1 << 16)) return fail(c, CFIE_EINVAL, "n_nodes must be <= 65536");
+    if (!(k > 0.0) || !std::isfinite(k)) return fail(c, CFIE_EINVAL, "k must be finite and > 0");
+    HostGeometry hg;
+    std::string e = build_geometry(*contour, hg);
+    if (!e.empty()) return fail(c, CFIE_EINVAL, e);
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        hipStream_t s = c->stream;
+        // release everything of a previous problem
+        free_factor(c);
+        for (int i = 0; i < 4; ++i) { c->dfree(c->mat[i]); c->mat[i] = nullptr; c->dfree(c->mat32[i]); c->mat32[i] = nullptr; }
+        free_points(c, c->pf); free_points(c, c->pn); free_points(c, c->cf); free_points(c, c->cn);
+        void *old[] = {c->crow, c->mu, c->cvals, c->dC, c->dCH, c->dCinv, c->fC, c->fCH, c->fCinv,
+                       c->absc, c->scal, c->d_xf, c->d_wf, c->d_xn, c->d_wn, c->d_mom, c->d_gcoef};
+        for (void *p : old) c->dfree(p);
+        c->state = 0;
+        c->N = N;
+        c->k = k;
+        c->hg = hg;
+        c->hg.h = hg.L / N;
+        double a = hg.L / (2.0 * kPi);
+        c->kt = mk(k, 0.4 * std::cbrt(k) * std::pow(a, -2.0 / 3.0));
+        double h = hg.L / N;
+        if (cabs(c->kt) * h > 8.0)
+            return fail(c, CFIE_EINVAL, "mesh too coarse: |kt| h > 8 (fewer than 0.8 nodes per wavelength)");
+        c->hc = circle_geometry(a);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s));
+        // quadrature tables
+        gauss_legendre01(c->opt.quad_far, c->xf, c->wf);
+        gauss_legendre01(c->opt.quad_near, c->xn, c->wn);
+        log_moments(c->opt.quad_near, c->moments);
+        c->d_xf = c->alloc_n<double>(c->xf.size()); c->upload(c->d_xf, c->xf.data(), c->xf.size());
+        c->d_wf = c->alloc_n<double>(c->wf.size()); c->upload(c->d_wf, c->wf.data(), c->wf.size());
+        c->d_xn = c->alloc_n<double>(c->xn.size()); c->upload(c->d_xn, c->xn.data(), c->xn.size());
+        c->d_wn = c->alloc_n<double>(c->wn.size()); c->upload(c->d_wn, c->wn.data(), c->wn.size());
+        c->d_mom = c->alloc_n<double>(c->moments.size());
+        c->upload(c->d_mom, c->moments.data(), c->moments.size());
+        ginv_taps(N, h, c->gcoef, c->g_t0);
+        c->d_gcoef = c->alloc_n<double>(c->gcoef.size());
+        c->upload(c->d_gcoef, c->gcoef.data(), c->gcoef.size());
+        // geometry and Gauss points of gamma and gamma_c
+        upload_geom(c, c->hg, c->gd);
+        upload_geom(c, c->hc, c->gc);
+        alloc_points(c, c->pf, c->opt.quad_far);
+        alloc_points(c, c->pn, c->opt.quad_near);
+        alloc_points(c, c->cf, c->opt.quad_far);
+        alloc_points(c, c->cn, c->opt.quad_near);
+        launch_points(c->gd, c->d_xf, c->pf, s);
+        launch_points(c->gd, c->d_xn, c->pn, s);
+        launch_points(c->gc, c->d_xf, c->cf, s);
+        launch_points(c->gc, c->d_xn, c->cn, s);
+        c->check_launch();
+        // dense matrices on gamma
+        size_t nn = (size_t)N * N;
+        for (int i = 0; i < 4; ++i) c->mat[i] = c->alloc_n<zd>(nn);
+        AsmParams p;
+        p.N = N;
+        p.h = h;
+        p.kc.k = k;
+        p.kc.kt = c->kt;
+        p.nb = std::min(c->opt.near_band, N);
+        p.r0 = 0;
+        p.r1 = N;
+        p.ld = N;
+        for (int i = 0; i < 4; ++i) p.out[i] = c->mat[i];
+        launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
+        launch_assemble_near(p, c->pn, c->xn.data(), c->wn.data(), c->d_mom, s);
+        c->check_launch();
+        // first row of each matrix on the circle -> eigenvalues (Sec. V)
+        c->crow = c->alloc_n<zd>((size_t)4 * N);
+        c->mu = c->alloc_n<zd>((size_t)4 * N);
+        AsmParams pc = p;
+        pc.r0 = 0;
+        pc.r1 = 1;
+        pc.ld = 1;
+        for (int i = 0; i < 4; ++i) pc.out[i] = c->crow + (size_t)i * N;
+        launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), s);
+        launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, s);
+        setup_fft(c);
+        // rows of symmetric circulants equal their first columns
+        launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, s);
+        c->cvals = c->alloc_n<zd>(N);
+        c->dC = c->alloc_n<zd>(N); c->dCH = c->alloc_n<zd>(N); c->dCinv = c->alloc_n<zd>(N);
+        c->fC = c->alloc_n<zf>(N); c->fCH = c->alloc_n<zf>(N); c->fCinv = c->alloc_n<zf>(N);
+        c->absc = c->alloc_n<double>(N);
+        c->scal = c->alloc_n<double>(4);
+        launch_circ_eigs(N, c->fft.N1, c->fft.N2, h, c->mu, c->cvals, c->dC, c->dCH, c->dCinv,
+                         c->fC, c->fCH, c->fCinv, c->absc, s);
+        launch_maxmin(N, c->absc, c->scal, s);
+        double mm[2];
+        HIPCHK(hipMemcpyAsync(mm, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (c->opt.precision == CFIE_MIXED) {
+            for (int i = 0; i < 4; ++i) {
+                c->mat32[i] = c->alloc_n<zf>(nn);
+                convert<float, double>(N, N, c->mat[i], N, c->mat32[i], N, s);
+            }
+        }
+        HIPCHK(hipEventRecord(e1, s));
+        c->sync();
+        HIPCHK(hipEventElapsedTime(&c->t_asm, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->cc_norm = mm[0];
+        c->cc_min = mm[1];
+        if (!(c->cc_min > 1e-300)) return fail(c, CFIE_ESINGULAR, "C_c has a zero eigenvalue");
+        c->state = 1;
+        if (!hg.convex) {
+            c->err = "contour is not convex (negative curvature)";
+            return CFIE_WNONCONVEX;
+        }
+        return CFIE_OK;
+    });
+}
+
+cfie_status cfie_factor(cfie_ctx *c) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 1) return fail(c, CFIE_ESTATE, "cfie_factor before cfie_assemble");
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, c->stream));
+        c->state = 1;
+        cfie_status st = c->opt.precision == CFIE_MIXED ? factor_impl<float>(c) : factor_impl<double>(c);
+        HIPCHK(hipEventRecord(e1, c->stream));
+        c->sync();
+        HIPCHK(hipEventElapsedTime(&c->t_fac, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return st;
+    });
+}
+
+cfie_status cfie_solve(cfie_ctx *c, const void *B, int64_t ldb, void *X, int64_t ldx,
+                       int64_t nrhs) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 2) return fail(c, CFIE_ESTATE, "cfie_solve before cfie_factor");
+    if (nrhs < 0) return fail(c, CFIE_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return CFIE_OK;
+    if (!B || !X) return fail(c, CFIE_EINVAL, "NULL B or X");
+    if (ldb < c->N || ldx < c->N) return fail(c, CFIE_EINVAL, "leading dimension < N");
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, c->stream));
+        cfie_status st;
+        if (c->opt.precision == CFIE_MIXED)
+            st = solve_mixed(c, (const zd *)B, ldb, (zd *)X, ldx, nrhs);
+        else
+            st = solve_fp64(c, (const zd *)B, ldb, (zd *)X, ldx, nrhs);
+        HIPCHK(hipEventRecord(e1, c->stream));
+        c->sync();
+        HIPCHK(hipEventElapsedTime(&c->t_sol, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return st;
+    });
+}
+
+cfie_status cfie_plane_wave_rhs(cfie_ctx *c, const double *angles, int64_t nrhs, void *Bv,
+                                int64_t ldb) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 1) return fail(c, CFIE_ESTATE, "cfie_plane_wave_rhs before cfie_assemble");
+    if (nrhs < 0) return fail(c, CFIE_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return CFIE_OK;
+    if (!angles || !Bv) return fail(c, CFIE_EINVAL, "NULL angles or B");
+    if (ldb < c->N) return fail(c, CFIE_EINVAL, "ldb < N");
+    for (int64_t i = 0; i < nrhs; ++i)
+        if (!std::isfinite(angles[i])) return fail(c, CFIE_EINVAL, "non-finite angle");
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        const int N = c->N;
+        hipStream_t s = c->stream;
+        zd *B = (zd *)Bv;
+        double *d_ang = c->alloc_n<double>(nrhs);
+        c->upload(d_ang, angles, nrhs);
+        zd *e = c->alloc_n<zd>((size_t)N * nrhs), *hv = c->alloc_n<zd>((size_t)N * nrhs);
+        zd *ge = c->alloc_n<zd>((size_t)N * nrhs), *gh = c->alloc_n<zd>((size_t)N * nrhs);
+        launch_excitation(c->gd, c->pn, c->d_xn, c->d_wn, c->k, d_ang, nrhs, e, hv, N, s);
+        const int nt = (int)c->gcoef.size();
+        launch_ginv_ex<double>(N, nt, c->g_t0, c->d_gcoef, cz<double>(0), nullptr, 0, cz<double>(1),
+                               e, N, ge, N, nrhs, s);
+        launch_ginv_ex<double>(N, nt, c->g_t0, c->d_gcoef, cz<double>(0), nullptr, 0, cz<double>(1),
+                               hv, N, gh, N, nrhs, s);
+        // b = -i k S^kt G^-1 e' - h/2 - D^kt G^-1 h     (eq. (5), eta cancelled)
+        axpby<double>(N, nrhs, cz<double>(-0.5), hv, N, cz<double>(0), B, ldb, s);
+        gemm<double>(false, N, nrhs, N, cz<double>(-1), c->mat[2], N, gh, N, cz<double>(1), B, ldb, s);
+        gemm<double>(false, N, nrhs, N, mk(0.0, -c->k), c->mat[3], N, ge, N, cz<double>(1), B, ldb, s);
+        c->check_launch();
+        c->sync();
+        c->dfree(d_ang); c->dfree(e); c->dfree(hv); c->dfree(ge); c->dfree(gh);
+        return CFIE_OK;
+    });
+}
+
+cfie_status cfie_apply_C(cfie_ctx *c, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                         int64_t nrhs) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 1) return fail(c, CFIE_ESTATE, "cfie_apply_C before cfie_assemble");
+    if (nrhs < 0) return fail(c, CFIE_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return CFIE_OK;
+    if (!X || !Y) return fail(c, CFIE_EINVAL, "NULL X or Y");
+    if (ldx < c->N || ldy < c->N) return fail(c, CFIE_EINVAL, "leading dimension < N");
+    if (X == Y) return fail(c, CFIE_EINVAL, "X and Y must not alias");
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        const int N = c->N;
+        zd *Tt = c->alloc_n<zd>((size_t)N * nrhs), *W1 = c->alloc_n<zd>((size_t)N * nrhs),
+           *W2 = c->alloc_n<zd>((size_t)N * nrhs);
+        apply_C<double>(c, (const zd *)X, ldx, (zd *)Y, ldy, nrhs, Tt, W1, W2);
+        c->sync();
+        c->dfree(Tt); c->dfree(W1); c->dfree(W2);
+        return CFIE_OK;
+    });
+}
+
+cfie_status cfie_export_matrix(cfie_ctx *c, int which, void *dst, int64_t ld) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 1) return fail(c, CFIE_ESTATE, "nothing assembled yet");
+    if (!dst) return fail(c, CFIE_EINVAL, "dst is NULL");
+    if (ld < c->N) return fail(c, CFIE_EINVAL, "ld < N");
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        const int N = c->N;
+        zd *D = (zd *)dst;
+        hipStream_t s = c->stream;
+        switch (which) {
+            case CFIE_MAT_G: {
+                std::vector<zd> G((size_t)N * N, mk(0.0, 0.0));
+                double h = c->hg.L / N;
+                for (int i = 0; i < N; ++i) {
+                    G[i + (size_t)i * N].x += 2.0 * h / 3.0;
+                    G[((i + 1) % N) + (size_t)i * N].x += h / 6.0;
+                    G[((i + N - 1) % N) + (size_t)i * N].x += h / 6.0;
+                }
+                HIPCHK(hipMemcpy2DAsync(D, ld * sizeof(zd), G.data(), N * sizeof(zd), N * sizeof(zd), N,
+                                        hipMemcpyHostToDevice, s));
+                break;
+            }
+            case CFIE_MAT_DK: case CFIE_MAT_NK: case CFIE_MAT_DKT: case CFIE_MAT_SKT:
+                axpby<double>(N, N, cz<double>(1), c->mat[which - 1], N, cz<double>(0), D, ld, s);
+                break;
+            case CFIE_MAT_CC_EIG:
+                HIPCHK(hipMemcpyAsync(D, c->cvals, N * sizeof(zd), hipMemcpyDeviceToDevice, s));
+                break;
+            case CFIE_MAT_CIRCLE_ROW:
+                axpby<double>(N, 4, cz<double>(1), c->crow, N, cz<double>(0), D, ld, s);
+                break;
+            default:
+                return fail(c, CFIE_EINVAL, "unknown matrix id");
+        }
+        c->check_launch();
+        c->sync();
+        return CFIE_OK;
+    });
+}
+
+cfie_status cfie_query(const cfie_ctx *c, cfie_info *o) {
+    if (!c || !o) return CFIE_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->n_nodes = c->N;
+    o->rank = c->rank;
+    o->perimeter = c->hg.L;
+    o->radius = c->hg.L / (2.0 * kPi);
+    o->k = c->k;
+    o->ktilde_re = c->kt.x;
+    o->ktilde_im = c->kt.y;
+    o->h = c->N ? c->hg.L / c->N : 0.0;
+    o->cc_norm = c->cc_norm;
+    o->remainder_est = c->remainder_est;
+    o->t_assemble_ms = c->t_asm;
+    o->t_factor_ms = c->t_fac;
+    o->t_solve_ms = c->t_sol;
+    o->refine_sweeps = c->refine_sweeps;
+    o->refine_residual = c->refine_res;
+    o->precision = c->opt.precision;
+    o->convex = c->hg.convex ? 1 : 0;
+    return CFIE_OK;
+}
+
+}  // extern "C"

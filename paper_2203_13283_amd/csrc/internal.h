@@ -1,0 +1,106 @@
+// Internal declarations shared by the HIP translation units of libcfie.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cfie.h"
+#include "bessel.h"
+#include "cplx.h"
+
+namespace cfie {
+
+// ------------------------------------------------------------------ geometry (host) -------
+// Contour z(t) = sum_m zhat_m e^{imt}; arc-length density |z'(t)| as a Fourier series
+// c0 + 2 Re sum_{m>=1} c_m e^{imt}.  Nodes s_i = i L / N (uniform in arc length).
+struct HostGeometry {
+    int M = 0;                       // z modes -M..M
+    std::vector<zd> zhat;            // 2M+1
+    double c0 = 0.0;                 // mean speed
+    std::vector<zd> cm;              // c_m, m = 1..Ms
+    double L = 0.0, h = 0.0, radius = 0.0;
+    bool convex = true;
+    double min_curvature = 0.0;
+};
+
+// Fills g from the contour; returns an error text or "" on success.
+std::string build_geometry(const cfie_contour &c, HostGeometry &g);
+HostGeometry circle_geometry(double radius);
+void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w);
+
+// Product-integration weights for the log part of touching element pairs.  For the
+// q-point Gauss grid (xi_g, xi'_h) on [0,1]^2:
+//   mom[kind][c][g*q+h] = int int l_g(xi) l_h(xi') P_c(xi, xi') log(sigma) dxi dxi'
+// kind 0: sigma = |xi - xi'| (same element), 1: sigma = 1 - xi + xi' (source = next
+// element), 2: sigma = 1 + xi - xi' (source = previous element); c = 2a+b for the hat
+// product phi_a(xi) phi_b(xi') (phi_0 = 1 - xi, phi_1 = xi) and c = 4 for no hats.
+void log_moments(int q, std::vector<double> &mom /* 3 * 5 * q * q */);
+
+// ------------------------------------------------------------------ device tables --------
+struct PointTable {                  // per element e and Gauss point g: index e*q + g
+    int q = 0;
+    double *x = nullptr, *y = nullptr, *tx = nullptr, *ty = nullptr, *curv = nullptr;
+};
+
+struct GeomDev {                     // device copies of the Fourier data
+    int M = 0, Ms = 0;
+    zd *zhat = nullptr;              // 2M+1
+    zd *cm = nullptr;                // Ms
+    double c0 = 0.0, L = 0.0, h = 0.0;
+    int N = 0;
+};
+
+struct KernelConsts {                // wavenumbers and derived constants
+    double k;                        // real wavenumber
+    zd kt;                           // complex wavenumber k + i beta
+};
+
+// ------------------------------------------------------------------ launchers ------------
+// Gauss points of all elements (x, y, unit tangent, curvature) from the Fourier data.
+void launch_points(const GeomDev &g, const double *xi, PointTable &pt, hipStream_t s);
+
+// Rows [r0, r1) of Dk, Nk, Dkt, Skt (out[m] + i + j*ld); far part: entries with cyclic
+// |i - j| >= nb + 2 by q_far x q_far Gauss-Legendre.
+struct AsmParams {
+    int N;
+    double h;
+    KernelConsts kc;
+    int nb;                          // near band
+    int r0, r1;
+    int64_t ld;
+    zd *out[4];                      // Dk, Nk, Dkt, Skt
+};
+void launch_assemble_far(const AsmParams &p, const PointTable &far, const double *xi,
+                         const double *w, hipStream_t s);
+// Near part: entries with cyclic |i - j| <= nb + 1; touching element pairs by product
+// integration of the log singularity (moments), others by q_near Gauss-Legendre.
+void launch_assemble_near(const AsmParams &p, const PointTable &near, const double *xi,
+                          const double *w, const double *moments, hipStream_t s);
+
+// Plane-wave right-hand-side vectors e' and h (N x m each).
+void launch_excitation(const GeomDev &g, const PointTable &pt, const double *xi,
+                       const double *w, double k, const double *angles, int64_t m,
+                       zd *e, zd *hvec, int64_t ld, hipStream_t s);
+
+// ------------------------------------------------------------------ FFT ------------------
+struct FFTPlan {
+    int N = 0, N1 = 0, N2 = 0;       // N = N1 * N2, N1 <= 4096 (power of two)
+    double *tw1 = nullptr;           // e^{-2 pi i j / N1}, j < N1   (complex, interleaved)
+    double *twN = nullptr;           // e^{-2 pi i j / N},  j < N    (complex)
+    float *tw1f = nullptr, *twNf = nullptr;
+    int *perm = nullptr;             // natural index of the transposed layout position
+};
+// y = IFFT(d .* FFT(x)) column by column (d in the transposed layout, 1/N folded in).
+template <typename T>
+void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx,
+                       int64_t nb, hipStream_t s);
+
+// complex GEMM: C = alpha * op(A) * B + beta * C, op(A) = A or A^H
+template <typename T>
+void gemm(bool conjA, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A,
+          int64_t lda, const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc,
+          hipStream_t s);
+
+}  // namespace cfie

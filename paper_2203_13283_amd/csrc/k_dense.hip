@@ -1,0 +1,507 @@
+// Dense helper kernels of the factor and solve phases: Gram-matrix products (G is the
+// circulant h [1/6, 2/3, 1/6], its inverse a banded circulant), elementwise updates,
+// the Gaussian sketch generator, column norms, small Cholesky/triangular inverses for the
+// orthonormalisation of sketch blocks, and the blocked LU with partial pivoting of the
+// capacitance matrix I + V^T C_c^{-1} U (Sec. V eq. (9)).
+#include "internal.h"
+
+namespace cfie {
+
+// ------------------------------------------------------------------ G and G^{-1} ---------
+// out = a X + b G^{-1} Y ; G^{-1} has first column ginv[n]; taps u = 0..ntap-1 at offset
+// t = t0 + u: (G^{-1} Y)_i = sum_u coef[u] Y_{(i - t) mod N}
+template <typename T>
+__global__ void k_ginv(int N, int ntap, int t0, const double *__restrict__ coef, cpx<T> a,
+                       const cpx<T> *X, int64_t ldx, cpx<T> b, const cpx<T> *__restrict__ Y,
+                       int64_t ldy, cpx<T> *out, int64_t ldo, int64_t ncol) {
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)N * ncol) return;
+    int i = (int)(tid % N);
+    int64_t c = tid / N;
+    const cpx<T> *y = Y + c * ldy;
+    T sr = 0, si = 0;
+    for (int u = 0; u < ntap; ++u) {
+        int idx = i - (t0 + u);
+        idx %= N;
+        if (idx < 0) idx += N;
+        cpx<T> v = y[idx];
+        T w = (T)coef[u];
+        sr += w * v.x;
+        si += w * v.y;
+    }
+    cpx<T> r = b * mk(sr, si);
+    if (X) r = r + a * X[i + c * ldx];
+    out[i + c * ldo] = r;
+}
+
+// out = a X + b G Y, G = h circ(2/3; 1/6, 1/6)
+template <typename T>
+__global__ void k_gmul(int N, double h, cpx<T> a, const cpx<T> *X, int64_t ldx, cpx<T> b,
+                       const cpx<T> *__restrict__ Y, int64_t ldy, cpx<T> *out, int64_t ldo,
+                       int64_t ncol) {
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)N * ncol) return;
+    int i = (int)(tid % N);
+    int64_t c = tid / N;
+    const cpx<T> *y = Y + c * ldy;
+    int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
+    T c0 = (T)(2.0 * h / 3.0), c1 = (T)(h / 6.0);
+    cpx<T> g = y[i] * c0 + (y[im] + y[ip]) * c1;
+    cpx<T> r = b * g;
+    if (X) r = r + a * X[i + c * ldx];
+    out[i + c * ldo] = r;
+}
+
+void ginv_taps(int N, double h, std::vector<double> &coef, int &t0) {
+    // first column of G^{-1}: (6/h) (rho^n + rho^(N-n)) / (2 sqrt 3 (1 - rho^N)), rho = sqrt3-2
+    const double rho = std::sqrt(3.0) - 2.0;
+    auto g = [&](int n) {
+        n = ((n % N) + N) % N;
+        double rn = std::pow(rho, n), rNn = std::pow(rho, N - n), rN = std::pow(rho, N);
+        return (6.0 / h) * (rn + rNn) / (2.0 * std::sqrt(3.0) * (1.0 - rN));
+    };
+    coef.clear();
+    if (N >= 61) {
+        t0 = -30;
+        for (int t = -30; t <= 30; ++t) coef.push_back(g(t));
+    } else {
+        t0 = 0;
+        for (int t = 0; t < N; ++t) coef.push_back(g(t));
+    }
+}
+
+template <typename T>
+void launch_ginv_ex(int N, int ntap, int t0, const double *coef, cpx<T> a, const cpx<T> *X,
+                    int64_t ldx, cpx<T> b, const cpx<T> *Y, int64_t ldy, cpx<T> *out,
+                    int64_t ldo, int64_t ncol, hipStream_t s) {
+    int64_t n = (int64_t)N * ncol;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ginv<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, ntap,
+                       t0, coef, a, X, ldx, b, Y, ldy, out, ldo, ncol);
+}
+template <typename T>
+void launch_gmul(int N, double h, cpx<T> a, const cpx<T> *X, int64_t ldx, cpx<T> b,
+                 const cpx<T> *Y, int64_t ldy, cpx<T> *out, int64_t ldo, int64_t ncol,
+                 hipStream_t s) {
+    int64_t n = (int64_t)N * ncol;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gmul<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, h, a,
+                       X, ldx, b, Y, ldy, out, ldo, ncol);
+}
+template void launch_ginv_ex<double>(int, int, int, const double *, zd, const zd *, int64_t, zd,
+                                     const zd *, int64_t, zd *, int64_t, int64_t, hipStream_t);
+template void launch_ginv_ex<float>(int, int, int, const double *, zf, const zf *, int64_t, zf,
+                                    const zf *, int64_t, zf *, int64_t, int64_t, hipStream_t);
+template void launch_gmul<double>(int, double, zd, const zd *, int64_t, zd, const zd *, int64_t,
+                                  zd *, int64_t, int64_t, hipStream_t);
+template void launch_gmul<float>(int, double, zf, const zf *, int64_t, zf, const zf *, int64_t,
+                                 zf *, int64_t, int64_t, hipStream_t);
+
+// ------------------------------------------------------------------ elementwise ----------
+// Y = a X + b Y   (m rows, n cols)
+template <typename T>
+__global__ void k_axpby(int64_t m, int64_t n, cpx<T> a, const cpx<T> *X, int64_t ldx, cpx<T> b,
+                        cpx<T> *Y, int64_t ldy) {
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= m * n) return;
+    int64_t i = tid % m, c = tid / m;
+    cpx<T> y = (b.x == (T)0 && b.y == (T)0) ? mk((T)0, (T)0) : b * Y[i + c * ldy];
+    Y[i + c * ldy] = y + a * X[i + c * ldx];
+}
+template <typename T>
+void axpby(int64_t m, int64_t n, cpx<T> a, const cpx<T> *X, int64_t ldx, cpx<T> b, cpx<T> *Y,
+           int64_t ldy, hipStream_t s) {
+    int64_t t = m * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL(k_axpby<T>, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, m, n, a, X,
+                       ldx, b, Y, ldy);
+}
+template void axpby<double>(int64_t, int64_t, zd, const zd *, int64_t, zd, zd *, int64_t,
+                            hipStream_t);
+template void axpby<float>(int64_t, int64_t, zf, const zf *, int64_t, zf, zf *, int64_t,
+                           hipStream_t);
+
+template <typename TO, typename TI>
+__global__ void k_convert(int64_t m, int64_t n, const cpx<TI> *X, int64_t ldx, cpx<TO> *Y,
+                          int64_t ldy) {
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= m * n) return;
+    int64_t i = tid % m, c = tid / m;
+    cpx<TI> v = X[i + c * ldx];
+    Y[i + c * ldy] = mk((TO)v.x, (TO)v.y);
+}
+template <typename TO, typename TI>
+void convert(int64_t m, int64_t n, const cpx<TI> *X, int64_t ldx, cpx<TO> *Y, int64_t ldy,
+             hipStream_t s) {
+    int64_t t = m * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL((k_convert<TO, TI>), dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, m,
+                       n, X, ldx, Y, ldy);
+}
+template void convert<float, double>(int64_t, int64_t, const zd *, int64_t, zf *, int64_t,
+                                     hipStream_t);
+template void convert<double, float>(int64_t, int64_t, const zf *, int64_t, zd *, int64_t,
+                                     hipStream_t);
+template void convert<double, double>(int64_t, int64_t, const zd *, int64_t, zd *, int64_t,
+                                      hipStream_t);
+template void convert<float, float>(int64_t, int64_t, const zf *, int64_t, zf *, int64_t,
+                                    hipStream_t);
+
+// Y (n x m) = X^H (X is m x n)
+template <typename T>
+__global__ void k_conj_transpose(int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
+                                 int64_t ldy) {
+    __shared__ cpx<T> tile[32][33];
+    int64_t bx = (int64_t)blockIdx.x * 32, by = (int64_t)blockIdx.y * 32;
+    int tx = threadIdx.x, ty = threadIdx.y;
+    for (int r = ty; r < 32; r += 8) {
+        int64_t i = bx + tx, j = by + r;
+        if (i < m && j < n) tile[r][tx] = X[i + j * ldx];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        int64_t i = by + tx, j = bx + r;         // Y(i, j) = conj X(j, i)
+        if (i < n && j < m) Y[i + j * ldy] = conj(tile[tx][r]);
+    }
+}
+template <typename T>
+void conj_transpose(int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy,
+                    hipStream_t s) {
+    if (m <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_conj_transpose<T>, dim3((unsigned)((m + 31) / 32), (unsigned)((n + 31) / 32)),
+                       dim3(32, 8), 0, s, m, n, X, ldx, Y, ldy);
+}
+template void conj_transpose<double>(int64_t, int64_t, const zd *, int64_t, zd *, int64_t,
+                                     hipStream_t);
+template void conj_transpose<float>(int64_t, int64_t, const zf *, int64_t, zf *, int64_t,
+                                    hipStream_t);
+
+// ------------------------------------------------------------------ Gaussian sketch ------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter = (element index lo/hi,
+// stream, 0), key = seed.  Two 32-bit outputs make one uniform pair -> Box-Muller.
+__device__ __forceinline__ void philox_round(uint32_t &c0, uint32_t &c1, uint32_t &c2,
+                                             uint32_t &c3, uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
+    uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+}
+__device__ __forceinline__ void philox4x32_10(uint32_t ctr[4], uint32_t k0, uint32_t k1) {
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        philox_round(ctr[0], ctr[1], ctr[2], ctr[3], k0, k1);
+        k0 += W0;
+        k1 += W1;
+    }
+}
+template <typename T>
+__global__ void k_randn(int64_t m, int64_t n, uint64_t seed, uint64_t stream, cpx<T> *X,
+                        int64_t ldx) {
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= m * n) return;
+    int64_t i = tid % m, c = tid / m;
+    uint32_t ctr[4] = {(uint32_t)tid, (uint32_t)(tid >> 32), (uint32_t)stream,
+                       (uint32_t)(stream >> 32)};
+    philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+    // 53-bit uniforms in (0, 1]
+    double u1 = ((double)(((uint64_t)ctr[0] << 21) ^ (ctr[1] >> 11)) + 1.0) * (1.0 / 9007199254740993.0);
+    double u2 = ((double)(((uint64_t)ctr[2] << 21) ^ (ctr[3] >> 11)) + 0.5) * (1.0 / 9007199254740992.0);
+    double r = sqrt(-log(u1));                        // |z|^2 ~ Exp(1): E|z|^2 = 1
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    X[i + c * ldx] = mk((T)(r * cs), (T)(r * sn));
+}
+template <typename T>
+void randn(int64_t m, int64_t n, uint64_t seed, uint64_t stream, cpx<T> *X, int64_t ldx,
+           hipStream_t s) {
+    int64_t t = m * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL(k_randn<T>, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, m, n, seed,
+                       stream, X, ldx);
+}
+template void randn<double>(int64_t, int64_t, uint64_t, uint64_t, zd *, int64_t, hipStream_t);
+template void randn<float>(int64_t, int64_t, uint64_t, uint64_t, zf *, int64_t, hipStream_t);
+
+// ------------------------------------------------------------------ column norms ---------
+// out[c] = sum_i |X_ic|^2 (double), one block per column
+template <typename T>
+__global__ void k_colnorm2(int64_t m, const cpx<T> *X, int64_t ldx, double *out) {
+    __shared__ double red[256];
+    int64_t c = blockIdx.x;
+    const cpx<T> *x = X + c * ldx;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+        cpx<T> v = x[i];
+        s += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+}
+template <typename T>
+void colnorm2(int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, double *out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_colnorm2<T>, dim3((unsigned)n), dim3(256), 0, s, m, X, ldx, out);
+}
+template void colnorm2<double>(int64_t, int64_t, const zd *, int64_t, double *, hipStream_t);
+template void colnorm2<float>(int64_t, int64_t, const zf *, int64_t, double *, hipStream_t);
+
+// ------------------------------------------------------------------ circulant eigenvalues
+// mu: 4 natural-order DFT vectors (Dk, Nk, Dkt, Skt rows of the circle); G has eigenvalue
+// h (2 + cos(2 pi m / N)) / 3.  c_m = (g/2 + dt)(g/2 - d)/g + s n / g  (Sec. V eq. (6)).
+// Writes c (natural) and the diagonals for the FFT layout: dC = c/N, dCH = conj(c)/N,
+// dCinv = 1/(N c), in double and float.
+__global__ void k_circ_eigs(int N, int N1, int N2, double h, const zd *__restrict__ mu,
+                            zd *c, zd *dC, zd *dCH, zd *dCinv, zf *fC, zf *fCH, zf *fCinv,
+                            double *absc) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= N) return;
+    zd md = mu[m], mn = mu[m + N], mdt = mu[m + 2 * N], ms = mu[m + 3 * N];
+    double g = h * (2.0 + cospi(2.0 * m / (double)N)) / 3.0;
+    zd hg = mk(0.5 * g, 0.0);
+    zd cm = (hg + mdt) * (hg - md) * (1.0 / g) + ms * mn * (1.0 / g);
+    c[m] = cm;
+    absc[m] = cabs(cm);
+    // position in the transposed layout of the four-step FFT: m = k2 + N2 k1 -> k1 + N1 k2
+    int k2 = m % N2, k1 = m / N2;
+    int p = k1 + N1 * k2;
+    double invN = 1.0 / N;
+    zd a = cm * invN, b = conj(cm) * invN, ci = cinv(cm) * invN;
+    dC[p] = a;
+    dCH[p] = b;
+    dCinv[p] = ci;
+    fC[p] = mk((float)a.x, (float)a.y);
+    fCH[p] = mk((float)b.x, (float)b.y);
+    fCinv[p] = mk((float)ci.x, (float)ci.y);
+}
+void launch_circ_eigs(int N, int N1, int N2, double h, const zd *mu, zd *c, zd *dC, zd *dCH,
+                      zd *dCinv, zf *fC, zf *fCH, zf *fCinv, double *absc, hipStream_t s) {
+    hipLaunchKernelGGL(k_circ_eigs, dim3((N + 255) / 256), dim3(256), 0, s, N, N1, N2, h, mu, c,
+                       dC, dCH, dCinv, fC, fCH, fCinv, absc);
+}
+
+// max over n doubles (single block)
+__global__ void k_maxmin(int64_t n, const double *x, double *out) {
+    __shared__ double mx[256], mn[256];
+    double a = -1e308, b = 1e308;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        a = fmax(a, x[i]);
+        b = fmin(b, x[i]);
+    }
+    mx[threadIdx.x] = a;
+    mn[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+            mn[threadIdx.x] = fmin(mn[threadIdx.x], mn[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = mx[0];
+        out[1] = mn[0];
+    }
+}
+void launch_maxmin(int64_t n, const double *x, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_maxmin, dim3(1), dim3(256), 0, s, n, x, out);
+}
+
+// ------------------------------------------------------------------ small dense ----------
+// Hermitian positive definite W (b x b, in place, lower part used) -> upper Cholesky
+// factor R with W = R^H R, then Rinv = R^{-1} (upper).  One workgroup.  A shift s is added
+// to the diagonal first (shifted Cholesky QR).  info[0] = 1 on a non-positive pivot.
+__global__ void k_chol_inv(int b, zd *W, int ldw, double shift, zd *Rinv, int ldr, int *info) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < b; i += nt) W[i + i * ldw].x += shift;
+    __syncthreads();
+    // right-looking Cholesky on the upper triangle: R(j, j:) row by row
+    __shared__ double piv;
+    for (int j = 0; j < b; ++j) {
+        if (tid == 0) {
+            double d = W[j + j * ldw].x;
+            if (!(d > 0.0)) { info[0] = 1; d = 1e-300; }
+            piv = sqrt(d);
+        }
+        __syncthreads();
+        double p = piv;
+        // row j of R: R(j, c) = W(j, c) / p for c > j ; R(j, j) = p
+        for (int c = j + tid; c < b; c += nt) {
+            zd v = W[j + c * ldw];
+            W[j + c * ldw] = (c == j) ? mk(p, 0.0) : v * (1.0 / p);
+        }
+        __syncthreads();
+        // trailing update: W(r, c) -= conj(R(j, r)) R(j, c) for j < r <= c
+        int rem = b - j - 1;
+        for (int64_t t = tid; t < (int64_t)rem * rem; t += nt) {
+            int r = j + 1 + (int)(t % rem), c = j + 1 + (int)(t / rem);
+            if (r <= c) W[r + c * ldw] = W[r + c * ldw] - conj(W[j + r * ldw]) * W[j + c * ldw];
+        }
+        __syncthreads();
+    }
+    // Rinv by back substitution, one column per thread: R X = I, X upper
+    for (int c = tid; c < b; c += nt) {
+        for (int r = b - 1; r >= 0; --r) {
+            zd s = mk(r == c ? 1.0 : 0.0, 0.0);
+            if (r > c) { Rinv[r + c * ldr] = mk(0.0, 0.0); continue; }
+            for (int q = r + 1; q <= c; ++q) s = s - W[r + q * ldw] * Rinv[q + c * ldr];
+            Rinv[r + c * ldr] = s * cinv(W[r + r * ldw]);
+        }
+    }
+}
+void launch_chol_inv(int b, zd *W, int ldw, double shift, zd *Rinv, int ldr, int *info,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, s, b, W, ldw, shift, Rinv, ldr, info);
+}
+
+// ---- LU with partial pivoting: panel of columns [k0, k0 + nb) of the n x n matrix A
+// (rows k0..n-1), one workgroup; piv[j] = global row swapped with row j.
+__global__ void k_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ double bestv[1024];
+    __shared__ int besti[1024];
+    for (int jj = 0; jj < nb; ++jj) {
+        int j = k0 + jj;
+        // pivot search in column j, rows j..n-1
+        double bv = -1.0;
+        int bi = j;
+        for (int r = j + tid; r < n; r += nt) {
+            double v = abs2(A[r + (int64_t)j * lda]);
+            if (v > bv) { bv = v; bi = r; }
+        }
+        bestv[tid] = bv;
+        besti[tid] = bi;
+        __syncthreads();
+        for (int w = nt / 2; w > 0; w >>= 1) {
+            if (tid < w) {
+                if (bestv[tid + w] > bestv[tid] ||
+                    (bestv[tid + w] == bestv[tid] && besti[tid + w] < besti[tid])) {
+                    bestv[tid] = bestv[tid + w];
+                    besti[tid] = besti[tid + w];
+                }
+            }
+            __syncthreads();
+        }
+        int p = besti[0];
+        if (tid == 0) {
+            piv[j] = p;
+            if (!(bestv[0] > 0.0)) info[0] = 1;
+        }
+        // swap rows j and p inside the panel
+        if (p != j) {
+            for (int c = k0 + tid; c < k0 + nb; c += nt) {
+                zd t = A[j + (int64_t)c * lda];
+                A[j + (int64_t)c * lda] = A[p + (int64_t)c * lda];
+                A[p + (int64_t)c * lda] = t;
+            }
+        }
+        __syncthreads();
+        zd d = A[j + (int64_t)j * lda];
+        zd dinv = (abs2(d) > 0.0) ? cinv(d) : mk(0.0, 0.0);
+        for (int r = j + 1 + tid; r < n; r += nt) A[r + (int64_t)j * lda] = A[r + (int64_t)j * lda] * dinv;
+        __syncthreads();
+        // rank-1 update of the rest of the panel
+        int rows = n - j - 1, cols = k0 + nb - j - 1;
+        for (int64_t t = tid; t < (int64_t)rows * cols; t += nt) {
+            int r = j + 1 + (int)(t % rows), c = j + 1 + (int)(t / rows);
+            A[r + (int64_t)c * lda] = A[r + (int64_t)c * lda] - A[r + (int64_t)j * lda] * A[j + (int64_t)c * lda];
+        }
+        __syncthreads();
+    }
+}
+void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, s, n, k0, nb, A, lda, piv, info);
+}
+
+// apply the row swaps piv[k0 .. k1) to columns [c0, c1) of A (one thread per column)
+template <typename T>
+__global__ void k_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0,
+                        int64_t c1, bool reverse) {
+    int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    cpx<T> *col = A + c * lda;
+    if (!reverse) {
+        for (int j = k0; j < k1; ++j) {
+            int p = piv[j];
+            if (p != j) { cpx<T> t = col[j]; col[j] = col[p]; col[p] = t; }
+        }
+    } else {
+        for (int j = k1 - 1; j >= k0; --j) {
+            int p = piv[j];
+            if (p != j) { cpx<T> t = col[j]; col[j] = col[p]; col[p] = t; }
+        }
+    }
+}
+template <typename T>
+void launch_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0, int64_t c1,
+                  hipStream_t s) {
+    if (c1 <= c0 || k1 <= k0) return;
+    int64_t n = c1 - c0;
+    hipLaunchKernelGGL(k_swaps<T>, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, k0, k1, piv, A,
+                       lda, c0, c1, false);
+}
+template void launch_swaps<double>(int, int, const int *, zd *, int64_t, int64_t, int64_t,
+                                   hipStream_t);
+
+// inverse of the nb x nb diagonal block at (k0, k0): unit lower (lower = true) or upper
+__global__ void k_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nb) return;
+    if (lower) {
+        for (int r = 0; r < nb; ++r) {
+            zd s = mk(r == c ? 1.0 : 0.0, 0.0);
+            if (r < c) { Inv[r + c * ldi] = mk(0.0, 0.0); continue; }
+            for (int q = c; q < r; ++q) s = s - A[r + (int64_t)q * lda] * Inv[q + c * ldi];
+            Inv[r + c * ldi] = s;
+        }
+    } else {
+        for (int r = nb - 1; r >= 0; --r) {
+            zd s = mk(r == c ? 1.0 : 0.0, 0.0);
+            if (r > c) { Inv[r + c * ldi] = mk(0.0, 0.0); continue; }
+            for (int q = r + 1; q <= c; ++q) s = s - A[r + (int64_t)q * lda] * Inv[q + c * ldi];
+            Inv[r + c * ldi] = s * cinv(A[r + (int64_t)r * lda]);
+        }
+    }
+}
+void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_tri_inv, dim3((nb + 63) / 64), dim3(64), 0, s, nb, A, lda, lower, Inv, ldi);
+}
+
+// identity added to the diagonal: A += I
+__global__ void k_add_identity(int n, zd *A, int64_t lda) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) A[i + (int64_t)i * lda].x += 1.0;
+}
+void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_identity, dim3((n + 255) / 256), dim3(256), 0, s, n, A, lda);
+}
+
+// per-column relative residual: out[c] = sqrt(r2[c] / b2[c]); max written to out[n]
+__global__ void k_ratio_max(int64_t n, const double *r2, const double *b2, double *out) {
+    __shared__ double mx[256];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double v = b2[i] > 0.0 ? sqrt(r2[i] / b2[i]) : sqrt(r2[i]);
+        a = fmax(a, v);
+    }
+    mx[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = mx[0];
+}
+void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_ratio_max, dim3(1), dim3(256), 0, s, n, r2, b2, out);
+}
+
+}  // namespace cfie
