@@ -143,11 +143,20 @@ cfie_status cfie_solve(cfie_ctx *ctx, const void *B_dev, int64_t ldb, void *X_de
 cfie_status cfie_plane_wave_rhs(cfie_ctx *ctx, const double *angles_host, int64_t nrhs,
                                 void *B_dev, int64_t ldb);
 
-/* Y = C X in complex128 from the assembled matrices (eq. (6), applied factor by factor).
- * Device pointers, N x nrhs, column-major.  ESTATE before assemble.  Used for residuals
- * and by the tests. */
-cfie_status cfie_apply_C(cfie_ctx *ctx, const void *X_dev, int64_t ldx, void *Y_dev,
-                         int64_t ldy, int64_t nrhs);
+/* Operators that cfie_apply can apply (Sec. V eqs. (6)-(9)). */
+enum {
+    CFIE_OP_C = 0,        /* C of eq. (6), factor by factor from the assembled matrices  */
+    CFIE_OP_CC = 1,       /* C_c, circulant, by FFT                                        */
+    CFIE_OP_CC_INV = 2,   /* C_c^-1 by FFT                                                 */
+    CFIE_OP_REMAINDER = 3,/* C - C_c                                                        */
+    CFIE_OP_SKELETON = 4  /* U V^T, the compressed remainder (after cfie_factor)            */
+};
+
+/* Y = op X in complex128.  X_dev, Y_dev: device, N x nrhs column-major, ldx, ldy >= N,
+ * must not overlap.  ESTATE before assemble (before factor for CFIE_OP_SKELETON); EINVAL
+ * for an unknown op.  Used for residuals, diagnostics and the tests. */
+cfie_status cfie_apply(cfie_ctx *ctx, int op, const void *X_dev, int64_t ldx, void *Y_dev,
+                       int64_t ldy, int64_t nrhs);
 
 /* Copy one internal matrix (CFIE_MAT_*) to dst_dev (device, complex128, column-major,
  * leading dimension ld >= N).  ESTATE if it does not exist yet. */

@@ -239,51 +239,110 @@ def near_offsets(N: int):
     return out
 
 
+_WORK = {}     # problem shared with forked worker processes
+
+
+def _single_thread_blas():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _far_rows(args):
+    """Far-pair contributions of element rows [e0, e1) to matrix rows e0 .. e1 (mod N)."""
+    e0, e1 = args
+    disc, k, kt, opts = _WORK["disc"], _WORK["k"], _WORK["kt"], _WORK["opts"]
+    N = disc.N
+    E = np.repeat(np.arange(e0, e1), N)
+    F = np.tile(np.arange(N), e1 - e0)
+    off = (F - E) % N
+    sel = np.minimum(off, N - off) >= 8
+    blk = _blocks_regular(disc, E[sel], F[sel], opts.qf, k, kt)
+    nb = e1 - e0
+    out = {}
+    for m in MATS:
+        full = np.zeros((nb * N, 2, 2), dtype=np.complex128)
+        full[sel] = blk[m]
+        full = full.reshape(nb, N, 2, 2)
+        rows = np.zeros((nb + 1, N), dtype=np.complex128)
+        for a in range(2):
+            for b in range(2):
+                rows[a:a + nb] += np.roll(full[:, :, a, b], b, axis=1)
+        out[m] = rows
+    return e0, out
+
+
+def _near_chunk(args):
+    """Near-pair local blocks of offset `off` for the elements E."""
+    off, dist, E = args
+    disc, k, kt, opts = _WORK["disc"], _WORK["k"], _WORK["kt"], _WORK["opts"]
+    N = disc.N
+    F = (E + off) % N
+    if dist == 0:
+        blk = _blocks_touching(disc, E, "coincident", k, kt, opts)
+    elif dist == 1 and off == 1:
+        blk = _blocks_touching(disc, E, "right", k, kt, opts)
+    elif dist == 1:
+        blk = _blocks_touching(disc, E, "left", k, kt, opts)
+    else:
+        q = opts.qn if dist <= 3 else opts.qm
+        blk = _blocks_regular(disc, E, F, q, k, kt)
+    return off, E, blk
+
+
 def assemble(zhat, N: int, k: float, kt: complex, opts: QuadOptions | None = None,
-             row_block: int | None = None):
-    """Dense Dk, Nk, Dkt, Skt (complex128 N x N) and G (float64) on the contour zhat."""
+             row_block: int | None = None, workers: int = 1):
+    """Dense Dk, Nk, Dkt, Skt (complex128 N x N) and G (float64) on the contour zhat.
+
+    workers > 1 spreads the element pairs over forked processes (same arithmetic)."""
     contour = Contour(zhat)
     disc = Discretisation(contour, N)
     h = disc.h
     opts = opts or QuadOptions.for_mesh(max(abs(k), abs(kt)) * h)
+    for q in {opts.qf, opts.qm, opts.qn}:
+        disc.points(q)
+    disc.node_params()
     Ms = {m: np.zeros((N, N), dtype=np.complex128) for m in MATS}
     near = near_offsets(N)
-    # --- far pairs: all (e, f) with cyclic distance >= 8, by row blocks
+    _WORK.update(disc=disc, k=k, kt=kt, opts=opts)
+    far_jobs = []
     if N > 15:
         if row_block is None:
             row_block = max(1, 2_000_000 // (N * opts.qf * opts.qf))
-        allf = np.arange(N)
-        for e0 in range(0, N, row_block):
-            e1 = min(N, e0 + row_block)
-            E = np.repeat(np.arange(e0, e1), N)
-            F = np.tile(allf, e1 - e0)
-            off = (F - E) % N
-            dist = np.minimum(off, N - off)
-            sel = dist >= 8
-            blk = _blocks_regular(disc, E[sel], F[sel], opts.qf, k, kt)
-            nb = e1 - e0
-            for m in MATS:
-                full = np.zeros((nb * N, 2, 2), dtype=np.complex128)
-                full[sel] = blk[m]
-                full = full.reshape(nb, N, 2, 2)
-                for a in range(2):
-                    rows = (np.arange(e0, e1) + a) % N
-                    for b in range(2):
-                        Ms[m][rows, :] += np.roll(full[:, :, a, b], b, axis=1)
-    # --- near pairs
+        far_jobs = [(e0, min(N, e0 + row_block)) for e0 in range(0, N, row_block)]
+    near_jobs = []
     E = np.arange(N)
+    per = max(1, -(-N // max(1, 4 * workers)))
     for off, dist in near.items():
-        F = (E + off) % N
-        if dist == 0:
-            blk = _blocks_touching(disc, E, "coincident", k, kt, opts)
-        elif dist == 1 and off == 1:
-            blk = _blocks_touching(disc, E, "right", k, kt, opts)
-        elif dist == 1:
-            blk = _blocks_touching(disc, E, "left", k, kt, opts)
-        else:
-            q = opts.qn if dist <= 3 else opts.qm
-            blk = _blocks_regular(disc, E, F, q, k, kt)
-        _scatter(Ms, E, F, blk, N)
+        for i0 in range(0, N, per):
+            near_jobs.append((off, dist, E[i0:i0 + per]))
+
+    def add_far(res):
+        e0, out = res
+        for m in MATS:
+            nb = out[m].shape[0] - 1
+            Ms[m][e0:e0 + nb, :] += out[m][:nb]          # rows e0 .. e1-1
+            Ms[m][(e0 + nb) % N, :] += out[m][nb]         # row e1 (wraps to 0 at the end)
+
+    def add_near(res):
+        off, Eb, blk = res
+        _scatter(Ms, Eb, (Eb + off) % N, blk, N)
+
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers, initializer=_single_thread_blas) as pool:
+            for r in pool.imap_unordered(_far_rows, far_jobs):
+                add_far(r)
+            for r in pool.imap_unordered(_near_chunk, near_jobs):
+                add_near(r)
+    else:
+        for j in far_jobs:
+            add_far(_far_rows(j))
+        for j in near_jobs:
+            add_near(_near_chunk(j))
+    _WORK.clear()
     Ms["G"] = gram_by_quadrature(disc)
     Ms["h"] = h
     Ms["L"] = contour.L

@@ -82,14 +82,15 @@ def solve_dense(C, b):
 class Problem:
     """Everything the oracle knows about one (contour, N, k) problem."""
 
-    def __init__(self, zhat, N: int, k: float, assemble_opts=None):
+    def __init__(self, zhat, N: int, k: float, assemble_opts=None, workers: int = 1):
         self.zhat = np.asarray(zhat, dtype=np.complex128)
         self.N = N
         self.k = float(k)
         self.contour = Contour(self.zhat)
         self.L = self.contour.L
         self.kt = ktilde(self.k, self.L)
-        self.M = assemble(self.zhat, N, self.k, self.kt, assemble_opts)
+        self.workers = workers
+        self.M = assemble(self.zhat, N, self.k, self.kt, assemble_opts, workers=workers)
         self.C = form_C(self.M)
         self._Mc = None
         self._Cc = None
@@ -107,7 +108,7 @@ class Problem:
         """Dense matrices on the circle of equal perimeter, same N, k, kt (Sec. V)."""
         if self._Mc is None:
             self._Mc = assemble(equivalent_circle(self.L), self.N, self.k, self.kt,
-                                self._opts)
+                                self._opts, workers=self.workers)
         return self._Mc
 
     @property

@@ -17,10 +17,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW, MAT_DK,
-                   MAT_DKT, MAT_G, MAT_NK, MAT_SKT)
+                   MAT_DKT, MAT_G, MAT_NK, MAT_SKT, OP_C, OP_CC, OP_CC_INV, OP_REMAINDER,
+                   OP_SKELETON)
 
 __all__ = ["Solver", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK", "MAT_NK",
-           "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "load_library"]
+           "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
+           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "load_library"]
 
 
 def load_library():
@@ -138,12 +140,16 @@ class Solver:
             self.N), "cfie_plane_wave_rhs")
         return B
 
-    def apply_C(self, X):
+    def apply(self, op: int, X):
+        """Y = op X for op in OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON."""
         self._check_batch(X, self.N, "X")
         Y = self._batch(X.shape[0])
-        self._check(self._lib.cfie_apply_C(self._h, _ptr(X), self.N, _ptr(Y), self.N,
-                                           X.shape[0]), "cfie_apply_C")
+        self._check(self._lib.cfie_apply(self._h, op, _ptr(X), self.N, _ptr(Y), self.N,
+                                         X.shape[0]), "cfie_apply")
         return Y
+
+    def apply_C(self, X):
+        return self.apply(OP_C, X)
 
     def export_matrix(self, which: int):
         """Matrix as a torch tensor in natural (row, column) indexing."""

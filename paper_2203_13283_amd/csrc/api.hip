@@ -53,6 +53,8 @@ void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int l
 void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s);
 void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out,
                       hipStream_t s);
+void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz,
+                  int *kout, hipStream_t s);
 }  // namespace cfie
 
 using namespace cfie;
@@ -126,7 +128,7 @@ struct cfie_ctx {
     zd *Linv = nullptr, *Uinv = nullptr;                // diagonal block inverses
     void *w_om = nullptr, *w_y = nullptr, *w_t = nullptr, *w_w1 = nullptr, *w_w2 = nullptr,
          *w_z = nullptr, *w_s = nullptr, *w_rinvT = nullptr;
-    zd *w_gram = nullptr, *w_rinv = nullptr;
+    zd *w_gram = nullptr, *w_rinv = nullptr, *w_y64 = nullptr;
     double *w_norm = nullptr;
 
     ~cfie_ctx() {
@@ -191,14 +193,14 @@ template <typename F> cfie_status guarded(cfie_ctx *c, F &&f) {
 void free_factor(cfie_ctx *c) {
     void *bufs[] = {c->Q, c->P, c->Ut, c->K, c->piv, c->info, c->Linv, c->Uinv, c->w_om,
                     c->w_y, c->w_t, c->w_w1, c->w_w2, c->w_z, c->w_s, c->w_rinvT, c->w_gram,
-                    c->w_rinv, c->w_norm};
+                    c->w_rinv, c->w_norm, c->w_y64};
     for (void *p : bufs) c->dfree(p);
     c->Q = c->P = c->Ut = nullptr;
     c->K = nullptr;
     c->piv = c->info = nullptr;
     c->Linv = c->Uinv = nullptr;
     c->w_om = c->w_y = c->w_t = c->w_w1 = c->w_w2 = c->w_z = c->w_s = c->w_rinvT = nullptr;
-    c->w_gram = c->w_rinv = nullptr;
+    c->w_gram = c->w_rinv = c->w_y64 = nullptr;
     c->w_norm = nullptr;
     c->rank = 0;
 }
@@ -338,38 +340,50 @@ void apply_RH(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy,
     c->check_launch();
 }
 
-double unit_roundoff(double) { return 1.1102230246251565e-16; }
-double unit_roundoff(float) { return 5.9604644775390625e-08; }
-
-// orthonormalise the N x b block Y in place (shifted Cholesky QR, then two plain passes)
+// Gram matrix Y^H Y (b x b) in FP64 for a block in precision T
 template <typename T>
-void orthonormalise(cfie_ctx *c, cpx<T> *Y, int b) {
+void gram64(cfie_ctx *c, const cpx<T> *Y, int b, zd *W) {
+    const int N = c->N;
+    if (sizeof(T) == sizeof(double)) {
+        gemm<double>(true, b, b, N, cz<double>(1), (const zd *)Y, N, (const zd *)Y, N,
+                     cz<double>(0), W, b, c->stream);
+    } else {
+        convert<double, T>(N, b, Y, N, c->w_y64, N, c->stream);
+        gemm<double>(true, b, b, N, cz<double>(1), c->w_y64, N, c->w_y64, N, cz<double>(0), W,
+                     b, c->stream);
+    }
+}
+
+// Orthonormalise the N x b sketch block Y in place and return the number k of columns kept
+// (the first k columns of Y on return).  A pivoted Cholesky of the Gram matrix keeps the
+// directions whose norm exceeds max(tau, rel * largest column norm), which also drops
+// directions that are rounding noise; two plain Cholesky-QR passes follow.
+template <typename T>
+int orthonormalise(cfie_ctx *c, cpx<T> *Y, int b, double tau) {
     const int N = c->N;
     hipStream_t s = c->stream;
-    cpx<T> *gramT = (cpx<T> *)c->w_s;                    // b x b scratch in T (first b*b)
     cpx<T> *rinvT = (cpx<T> *)c->w_rinvT;
     cpx<T> *Y2 = (cpx<T> *)c->w_t;
-    for (int pass = 0; pass < 3; ++pass) {
-        gemm<T>(true, b, b, N, cz<T>(1), Y, N, Y, N, cz<T>(0), gramT, b, s);
-        convert<double, T>(b, b, gramT, b, c->w_gram, b, s);
-        double shift = 0.0;
-        if (pass == 0) {
-            // shift = 11 (N b + b (b + 1)) u ||Y||_F^2 (Fukaya et al., shifted CholeskyQR)
-            colnorm2<T>(N, b, Y, N, c->w_norm, s);
-            std::vector<double> nrm(b);
-            HIPCHK(hipMemcpyAsync(nrm.data(), c->w_norm, b * sizeof(double), hipMemcpyDeviceToHost, s));
-            c->sync();
-            double fro = 0.0;
-            for (double v : nrm) fro += v;
-            shift = 11.0 * ((double)N * b + (double)b * (b + 1)) * unit_roundoff((T)0) * fro;
-        }
+    const double rel2 = sizeof(T) == sizeof(double) ? 1e-13 : 1e-6;
+    gram64<T>(c, Y, b, c->w_gram);
+    launch_pchol(b, c->w_gram, b, tau * tau, rel2, c->w_rinv, b, c->info + 1, s);
+    int k = 0;
+    HIPCHK(hipMemcpyAsync(&k, c->info + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    c->sync();
+    if (k <= 0) return 0;
+    convert<T, double>(b, k, c->w_rinv, b, rinvT, b, s);
+    gemm<T>(false, N, k, b, cz<T>(1), Y, N, rinvT, b, cz<T>(0), Y2, N, s);
+    axpby<T>(N, k, cz<T>(1), Y2, N, cz<T>(0), Y, N, s);
+    for (int pass = 0; pass < 2; ++pass) {
+        gram64<T>(c, Y, k, c->w_gram);
         HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
-        launch_chol_inv(b, c->w_gram, b, shift, c->w_rinv, b, c->info, s);
-        convert<T, double>(b, b, c->w_rinv, b, rinvT, b, s);
-        gemm<T>(false, N, b, b, cz<T>(1), Y, N, rinvT, b, cz<T>(0), Y2, N, s);
-        axpby<T>(N, b, cz<T>(1), Y2, N, cz<T>(0), Y, N, s);
-        c->check_launch();
+        launch_chol_inv(k, c->w_gram, k, 0.0, c->w_rinv, k, c->info, s);
+        convert<T, double>(k, k, c->w_rinv, k, rinvT, k, s);
+        gemm<T>(false, N, k, k, cz<T>(1), Y, N, rinvT, k, cz<T>(0), Y2, N, s);
+        axpby<T>(N, k, cz<T>(1), Y2, N, cz<T>(0), Y, N, s);
     }
+    c->check_launch();
+    return k;
 }
 
 template <typename T>
@@ -393,6 +407,7 @@ void alloc_factor(cfie_ctx *c) {
     c->w_rinv = c->alloc_n<zd>((size_t)b * b);
     c->w_norm = c->alloc_n<double>((size_t)std::max(b, 64));
     c->info = c->alloc_n<int>(4);
+    if (sizeof(T) != sizeof(double)) c->w_y64 = c->alloc_n<zd>(nb);
 }
 
 // solve K Z = Z in place with the LU factors (piv, L, U; diagonal block inverses)
@@ -457,9 +472,10 @@ cfie_status factor_impl(cfie_ctx *c) {
         for (int i = 0; i < bb; ++i) mx = std::max(mx, nrm[i]);
         c->remainder_est = std::sqrt(mx);
         if (c->remainder_est <= tau) break;
-        orthonormalise<T>(c, Y, bb);
-        axpby<T>(N, bb, cz<T>(1), Y, N, cz<T>(0), Q + (size_t)ell * N, N, s);
-        ell += bb;
+        int kept = orthonormalise<T>(c, Y, bb, tau);
+        if (kept == 0) break;
+        axpby<T>(N, kept, cz<T>(1), Y, N, cz<T>(0), Q + (size_t)ell * N, N, s);
+        ell += kept;
     }
     c->rank = ell;
     if (ell == 0) {
@@ -917,10 +933,13 @@ cfie_status cfie_plane_wave_rhs(cfie_ctx *c, const double *angles, int64_t nrhs,
     });
 }
 
-cfie_status cfie_apply_C(cfie_ctx *c, const void *X, int64_t ldx, void *Y, int64_t ldy,
-                         int64_t nrhs) {
+cfie_status cfie_apply(cfie_ctx *c, int op, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy, int64_t nrhs) {
     if (!c) return CFIE_EINVAL;
-    if (c->state < 1) return fail(c, CFIE_ESTATE, "cfie_apply_C before cfie_assemble");
+    if (op < CFIE_OP_C || op > CFIE_OP_SKELETON) return fail(c, CFIE_EINVAL, "unknown operator");
+    if (c->state < 1) return fail(c, CFIE_ESTATE, "cfie_apply before cfie_assemble");
+    if (op == CFIE_OP_SKELETON && c->state < 2)
+        return fail(c, CFIE_ESTATE, "skeleton requested before cfie_factor");
     if (nrhs < 0) return fail(c, CFIE_EINVAL, "nrhs must be >= 0");
     if (nrhs == 0) return CFIE_OK;
     if (!X || !Y) return fail(c, CFIE_EINVAL, "NULL X or Y");
@@ -929,11 +948,57 @@ cfie_status cfie_apply_C(cfie_ctx *c, const void *X, int64_t ldx, void *Y, int64
     return guarded(c, [&]() -> cfie_status {
         HIPCHK(hipSetDevice(c->device));
         const int N = c->N;
+        hipStream_t s = c->stream;
+        const zd *Xd = (const zd *)X;
+        zd *Yd = (zd *)Y;
         zd *Tt = c->alloc_n<zd>((size_t)N * nrhs), *W1 = c->alloc_n<zd>((size_t)N * nrhs),
-           *W2 = c->alloc_n<zd>((size_t)N * nrhs);
-        apply_C<double>(c, (const zd *)X, ldx, (zd *)Y, ldy, nrhs, Tt, W1, W2);
+           *W2 = c->alloc_n<zd>((size_t)N * nrhs), *Z = c->alloc_n<zd>((size_t)N * nrhs);
+        switch (op) {
+            case CFIE_OP_C:
+                apply_C<double>(c, Xd, ldx, Yd, ldy, nrhs, Tt, W1, W2);
+                break;
+            case CFIE_OP_CC:
+            case CFIE_OP_CC_INV:
+                axpby<double>(N, nrhs, cz<double>(1), Xd, ldx, cz<double>(0), Z, N, s);
+                launch_circ_apply<double>(c->fft, op == CFIE_OP_CC ? c->dC : c->dCinv, Z, N, nrhs, s);
+                axpby<double>(N, nrhs, cz<double>(1), Z, N, cz<double>(0), Yd, ldy, s);
+                break;
+            case CFIE_OP_REMAINDER:
+                apply_R<double>(c, Xd, ldx, Yd, ldy, nrhs, Tt, W1, W2, Z);
+                break;
+            case CFIE_OP_SKELETON: {
+                // U V^T X = Q (R^H Q)^H X = Q (P^H X); in mixed precision from the FP32 factors
+                int r = c->rank;
+                if (r == 0) {
+                    HIPCHK(hipMemset2DAsync(Yd, ldy * sizeof(zd), 0, N * sizeof(zd), nrhs, s));
+                    break;
+                }
+                zd *S = c->alloc_n<zd>((size_t)r * nrhs);
+                if (c->opt.precision == CFIE_MIXED) {
+                    zf *X32 = c->alloc_n<zf>((size_t)N * nrhs), *S32 = c->alloc_n<zf>((size_t)r * nrhs);
+                    convert<float, double>(N, nrhs, Xd, ldx, X32, N, s);
+                    gemm<float>(true, r, nrhs, N, cz<float>(1), (const zf *)c->P, N, X32, N,
+                                cz<float>(0), S32, r, s);
+                    gemm<float>(false, N, nrhs, r, cz<float>(1), (const zf *)c->Q, N, S32, r,
+                                cz<float>(0), X32, N, s);
+                    convert<double, float>(N, nrhs, X32, N, Yd, ldy, s);
+                    c->sync();
+                    c->dfree(X32);
+                    c->dfree(S32);
+                } else {
+                    gemm<double>(true, r, nrhs, N, cz<double>(1), (const zd *)c->P, N, Xd, ldx,
+                                 cz<double>(0), S, r, s);
+                    gemm<double>(false, N, nrhs, r, cz<double>(1), (const zd *)c->Q, N, S, r,
+                                 cz<double>(0), Yd, ldy, s);
+                }
+                c->sync();
+                c->dfree(S);
+                break;
+            }
+        }
+        c->check_launch();
         c->sync();
-        c->dfree(Tt); c->dfree(W1); c->dfree(W2);
+        c->dfree(Tt); c->dfree(W1); c->dfree(W2); c->dfree(Z);
         return CFIE_OK;
     });
 }

@@ -127,15 +127,22 @@ std::string build_geometry(const cfie_contour &c, HostGeometry &g) {
     g.c0 = c0;
     g.cm.clear();
     int mmax = P / 4;
-    int last = 0;
     std::vector<zd> coef(mmax + 1);
     for (int m = 1; m <= mmax; ++m) {
         zd acc = mk(0.0, 0.0);
         for (int j = 0; j < P; ++j) acc = acc + roots[(long)m * j % P] * speed[j];
         coef[m] = acc * (1.0 / P);
-        if (cabs(coef[m]) > 1e-17 * c0) last = m;
     }
-    if (last >= mmax - 8) return "arc-length density not resolved (contour too irregular)";
+    // rounding floor of the transform from its upper half, where an analytic speed has
+    // decayed below it; keep modes clearly above that floor
+    double noise = 0.0;
+    for (int m = mmax / 2 + 1; m <= mmax; ++m) noise += abs2(coef[m]);
+    noise = std::sqrt(noise / (mmax - mmax / 2));
+    double thr = std::max(1e-17 * c0, 16.0 * noise);
+    int last = 0;
+    for (int m = 1; m <= mmax; ++m)
+        if (cabs(coef[m]) > thr) last = m;
+    if (last >= mmax / 2) return "arc-length density not resolved (contour too irregular)";
     g.cm.assign(coef.begin() + 1, coef.begin() + last + 1);
     g.L = 2.0 * kPi * c0;
     g.radius = g.L / (2.0 * kPi);

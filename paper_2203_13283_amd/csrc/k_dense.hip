@@ -360,6 +360,114 @@ void launch_chol_inv(int b, zd *W, int ldw, double shift, zd *Rinv, int ldr, int
     hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, s, b, W, ldw, shift, Rinv, ldr, info);
 }
 
+// Rank-revealing orthonormaliser for a sketch block: pivoted Cholesky of the Gram matrix
+// W = Y^H Y (b x b, Hermitian, full storage, overwritten).  Pivots are taken while the
+// largest remaining Schur-complement diagonal (squared norm of what a column adds to the
+// span of the columns already taken) exceeds max(thr_abs, thr_rel * max diag).  With k
+// pivots kept and R the k x k factor of the permuted Gram, Z (b x b, ld ldz) receives
+// Z[perm[r], c] = (R^{-1})[r, c] for r, c < k and zeros elsewhere, so that Y Z[:, :k] has
+// orthonormal columns (up to rounding; two plain Cholesky passes follow).  *kout = k.
+__global__ void k_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz,
+                        int *kout) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ int perm[512];
+    __shared__ double bestv[1024];
+    __shared__ int besti[1024];
+    __shared__ int kk;
+    __shared__ double thr;
+    for (int i = tid; i < b; i += nt) perm[i] = i;
+    // threshold from the largest diagonal
+    double mx = 0.0;
+    for (int i = tid; i < b; i += nt) mx = fmax(mx, W[i + i * ldw].x);
+    bestv[tid] = mx;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+        if (tid < w) bestv[tid] = fmax(bestv[tid], bestv[tid + w]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        thr = fmax(thr_abs, thr_rel * bestv[0]);
+        kk = b;
+    }
+    __syncthreads();
+    for (int j = 0; j < b; ++j) {
+        double bv = -1.0;
+        int bi = j;
+        for (int i = j + tid; i < b; i += nt) {
+            double v = W[i + i * ldw].x;
+            if (v > bv) { bv = v; bi = i; }
+        }
+        bestv[tid] = bv;
+        besti[tid] = bi;
+        __syncthreads();
+        for (int w = nt / 2; w > 0; w >>= 1) {
+            if (tid < w && (bestv[tid + w] > bestv[tid] ||
+                            (bestv[tid + w] == bestv[tid] && besti[tid + w] < besti[tid]))) {
+                bestv[tid] = bestv[tid + w];
+                besti[tid] = besti[tid + w];
+            }
+            __syncthreads();
+        }
+        int p = besti[0];
+        bool stop = !(bestv[0] > thr);
+        __syncthreads();
+        if (stop) {
+            if (tid == 0) kk = j;
+            break;
+        }
+        if (p != j) {
+            // symmetric swap of rows and columns j <-> p
+            for (int i = tid; i < b; i += nt) {
+                zd t = W[j + i * ldw];
+                W[j + i * ldw] = W[p + i * ldw];
+                W[p + i * ldw] = t;
+            }
+            __syncthreads();
+            for (int i = tid; i < b; i += nt) {
+                zd t = W[i + j * ldw];
+                W[i + j * ldw] = W[i + p * ldw];
+                W[i + p * ldw] = t;
+            }
+            if (tid == 0) {
+                int t = perm[j];
+                perm[j] = perm[p];
+                perm[p] = t;
+            }
+            __syncthreads();
+        }
+        double r = sqrt(W[j + j * ldw].x);
+        __syncthreads();
+        for (int c = j + tid; c < b; c += nt)
+            W[j + c * ldw] = (c == j) ? mk(r, 0.0) : W[j + c * ldw] * (1.0 / r);
+        __syncthreads();
+        int rem = b - j - 1;
+        for (int64_t t = tid; t < (int64_t)rem * rem; t += nt) {
+            int rr = j + 1 + (int)(t % rem), cc = j + 1 + (int)(t / rem);
+            W[rr + cc * ldw] = W[rr + cc * ldw] - conj(W[j + rr * ldw]) * W[j + cc * ldw];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    const int k = kk;
+    for (int64_t t = tid; t < (int64_t)b * b; t += nt) Z[(t % b) + (t / b) * ldz] = mk(0.0, 0.0);
+    __syncthreads();
+    // R^{-1} by back substitution (one column per thread), scattered to rows perm[r]
+    for (int c = tid; c < k; c += nt) {
+        // temporary column stored directly into Z at permuted rows
+        for (int r = c; r >= 0; --r) {
+            zd s = mk(r == c ? 1.0 : 0.0, 0.0);
+            for (int q = r + 1; q <= c; ++q) s = s - W[r + q * ldw] * Z[perm[q] + c * ldz];
+            Z[perm[r] + c * ldz] = s * (1.0 / W[r + r * ldw].x);
+        }
+    }
+    if (tid == 0) kout[0] = k;
+}
+void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz, int *kout,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(1024), 0, s, b, W, ldw, thr_abs, thr_rel, Z, ldz,
+                       kout);
+}
+
 // ---- LU with partial pivoting: panel of columns [k0, k0 + nb) of the n x n matrix A
 // (rows k0..n-1), one workgroup; piv[j] = global row swapped with row j.
 __global__ void k_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info) {

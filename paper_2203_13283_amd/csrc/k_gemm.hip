@@ -19,6 +19,16 @@ template <typename T> struct MfmaAcc;
 template <> struct MfmaAcc<double> { typedef d4 type; };
 template <> struct MfmaAcc<float> { typedef f4 type; };
 
+// Output layout of the 16x16x4 MFMA (checked on gfx950): lane l, accumulator register r
+// holds D[row][l % 16] with row = l/16 + 4 r for f64 and row = 4 (l/16) + r for f32.
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) {
+    return (lane >> 4) + 4 * r;
+}
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) {
+    return 4 * (lane >> 4) + r;
+}
+
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -138,7 +148,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
                 }
         }
     }
-    // epilogue: lane holds rows 4*(lane/16) + r, column lane%16 of each 16x16 tile
+    // epilogue: column lane%16 of each 16x16 tile, rows from acc_row
     const bool beta_zero = (beta.x == (T)0 && beta.y == (T)0);
 #pragma unroll
     for (int a = 0; a < TI; ++a)
@@ -147,7 +157,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
             int64_t gj = col0 + wcol + b * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int64_t gi = row0 + wrow + a * 16 + 4 * (lane >> 4) + r;
+                int64_t gi = row0 + wrow + a * 16 + acc_row<T>(lane, r);
                 if (gi < m && gj < n) {
                     cpx<T> v = mk((T)accr[a][b][r], (T)acci[a][b][r]);
                     v = alpha * v;

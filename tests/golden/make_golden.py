@@ -1,0 +1,79 @@
+"""Write the oracle reference values used by the full-size GPU parity tests.
+
+Calls only the CPU oracle (oracle/) and the input generators (workloads/).  For each
+workload it stores, in tests/golden/<name>.npz:
+  rows, cols, entries[m]   sampled entries of Dk, Nk, Dkt, Skt (by the oracle's own rules)
+  cc_eig                   eigenvalues of C_c (DFT of the first column of the dense C_c)
+                           -- only where N <= 4096 (the dense circle matrices are needed)
+  cols_rhs                 indices of the stored right-hand sides (angles 2 pi j / m)
+  b, x                     right-hand sides of eq. (5) and dense-LU solutions for them
+  L, k, kt_re, kt_im, N    constants
+
+Run:  python tests/golden/make_golden.py ellipse4096 perturbed16384 [--workers 8]
+(about 2 minutes for ellipse4096 and 40 minutes for perturbed16384 on 8 cores; the
+larger one needs about 40 GB of host memory).
+"""
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+import scipy.linalg as sla
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W  # noqa: E402
+from oracle import assembly as A  # noqa: E402
+from oracle import system as S  # noqa: E402
+
+STORED_COLUMNS = {"ellipse4096": [0, 37, 64, 128, 201, 255],
+                  "perturbed16384": [0, 301, 512, 777]}
+
+
+def make(name: str, workers: int, n_samples: int = 2048):
+    w = W.get(name)
+    N = w.n_nodes
+    contour = S.Contour(w.zhat)
+    L = contour.L
+    kt = S.ktilde(w.k, L)
+    t0 = time.time()
+    M = A.assemble(w.zhat, N, w.k, kt, workers=workers)
+    t_asm = time.time() - t0
+    print(f"{name}: assembly {t_asm:.1f} s", flush=True)
+    rng = np.random.default_rng(1234)
+    rows = rng.integers(0, N, n_samples)
+    cols = np.concatenate([rng.integers(0, N, n_samples // 2),
+                           (rows[n_samples // 2:] + rng.integers(-8, 9, n_samples - n_samples // 2)) % N])
+    entries = {m: M[m][rows, cols].copy() for m in A.MATS}
+    cols_rhs = np.array(STORED_COLUMNS[name])
+    angles = w.angles[cols_rhs]
+    e, hh = S.excitation(w.zhat, N, w.k, angles)
+    b = S.rhs(M, e, hh, w.k)
+    t1 = time.time()
+    C = S.form_C(M)
+    del M
+    lu = sla.lu_factor(C, overwrite_a=True, check_finite=False)
+    x = sla.lu_solve(lu, b)
+    t_lu = time.time() - t1
+    print(f"{name}: form C + LU + solve {t_lu:.1f} s", flush=True)
+    out = dict(rows=rows, cols=cols, cols_rhs=cols_rhs, b=b, x=x, L=L, k=w.k, kt_re=kt.real,
+               kt_im=kt.imag, N=N, t_assemble_s=t_asm, t_lu_s=t_lu)
+    for m in A.MATS:
+        out["entries_" + m] = entries[m]
+    del lu, C
+    if N <= 4096:
+        Mc = A.assemble(S.equivalent_circle(L), N, w.k, kt, workers=workers)
+        out["cc_eig"] = np.fft.fft(S.form_C(Mc)[:, 0])
+    np.savez_compressed(os.path.join(HERE, name + ".npz"), **out)
+    print(f"{name}: written", flush=True)
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="+")
+    ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
+    a = ap.parse_args()
+    for n in a.names:
+        make(n, a.workers)

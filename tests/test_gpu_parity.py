@@ -114,11 +114,16 @@ def test_solve_in_place_and_ragged_batch(cfg1, cfg1_solver):
 
 
 def test_circle_remainder_vanishes():
-    """Circle: C = C_c exactly, the skeleton has rank 0 and the FFT solve is the answer."""
+    """Circle: C = C_c up to rounding (the same rules on the same mesh), so at the FP64
+    tolerance the skeleton has rank 0 and the FFT solve alone is the answer."""
     R, k = 0.9, 12.0
     zh = W.circle_coeffs(R)
-    s = P.Solver(compress_tol=1e-12)
-    s.assemble(zh, 128, k).factor()
+    s = P.Solver(compress_tol=1e-10)
+    s.assemble(zh, 128, k)
+    x = torch.randn((2, 128), dtype=torch.complex128, device="cuda")
+    yc, ycc = s.apply(P.OP_C, x), s.apply(P.OP_CC, x)
+    assert float((yc - ycc).abs().max() / ycc.abs().max()) <= 1e-11
+    s.factor()
     assert s.info()["rank"] == 0
     ang = W.plane_wave_angles(2)
     X = _np(s.solve(s.plane_wave_rhs(ang))).T
