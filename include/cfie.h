@@ -84,6 +84,8 @@ typedef struct {
     int32_t quad_near;    /* Gauss-Legendre points per element, near pairs              */
     int32_t near_band;    /* element pairs at cyclic distance <= near_band are near     */
     int64_t fail_alloc_after; /* test hook: fail the (n+1)-th device allocation; -1 off */
+    int32_t profile;      /* 1: time every GEMM / assembly / FFT launch with HIP events on
+                             the context stream and accumulate work and time (cfie_info) */
 } cfie_options;
 
 typedef struct {
@@ -103,7 +105,17 @@ typedef struct {
     double refine_residual;   /* max_j ||b_j - C x_j|| / ||b_j|| after the last sweep  */
     int32_t precision;
     int32_t convex;           /* 1 if curvature >= 0 everywhere sampled                */
+    /* launch profile (options.profile = 1), accumulated since cfie_create or the last
+     * reset; index: 0 complex128 GEMM, 1 complex64 GEMM, 2 far-pair assembly, 3 near-pair
+     * assembly, 4 circulant FFT apply.  work: flops (GEMM, 8 m n k), Gauss point pairs
+     * (assembly), bytes of one read and one write of the batch (FFT). */
+    int64_t prof_launches[5];
+    double prof_work[5];
+    double prof_ms[5];
 } cfie_info;
+
+/* Zero the accumulated launch profile of ctx. */
+cfie_status cfie_profile_reset(cfie_ctx *ctx);
 
 /* Fill *opt with defaults: FP64, compress_tol 1e-10, block 128, max_rank 0, seed 1,
  * refine_tol 1e-8, max_refine 20, quad_far 5, quad_near 10, near_band 6, no injection. */

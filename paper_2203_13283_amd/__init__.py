@@ -45,7 +45,7 @@ class Solver:
                  block: int = 128, max_rank: int = 0, seed: int = 1,
                  refine_tol: float = 1e-8, max_refine: int = 20, quad_far: int = 5,
                  quad_near: int = 10, near_band: int = 6, fail_alloc_after: int = -1,
-                 device: int = 0, stream=None):
+                 profile: bool = False, device: int = 0, stream=None):
         lib = _lib.load()
         torch = _torch()
         o = _lib.default_options()
@@ -60,6 +60,7 @@ class Solver:
         o.quad_near = quad_near
         o.near_band = near_band
         o.fail_alloc_after = fail_alloc_after
+        o.profile = 1 if profile else 0
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -163,4 +164,17 @@ class Solver:
     def info(self) -> dict:
         i = _lib.Info()
         self._check(self._lib.cfie_query(self._h, ctypes.byref(i)), "cfie_query")
-        return {f: getattr(i, f) for f, _ in i._fields_}
+        out = {}
+        for f, _ in i._fields_:
+            v = getattr(i, f)
+            out[f] = list(v) if f.startswith("prof_") else v
+        return out
+
+    def profile(self) -> dict:
+        """Per-kernel launch totals: {name: (launches, work, ms)}."""
+        inf = self.info()
+        return {n: (inf["prof_launches"][i], inf["prof_work"][i], inf["prof_ms"][i])
+                for i, n in enumerate(_lib.PROF_NAMES)}
+
+    def profile_reset(self):
+        self._check(self._lib.cfie_profile_reset(self._h), "cfie_profile_reset")

@@ -27,7 +27,7 @@ OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON = range(5)
 EXPORTED = [
     "cfie_default_options", "cfie_create", "cfie_assemble", "cfie_factor", "cfie_solve",
     "cfie_plane_wave_rhs", "cfie_apply", "cfie_export_matrix", "cfie_query",
-    "cfie_last_error", "cfie_status_string", "cfie_destroy",
+    "cfie_last_error", "cfie_status_string", "cfie_destroy", "cfie_profile_reset",
 ]
 
 
@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("refine_tol", ctypes.c_double),
                 ("max_refine", ctypes.c_int32), ("quad_far", ctypes.c_int32),
                 ("quad_near", ctypes.c_int32), ("near_band", ctypes.c_int32),
-                ("fail_alloc_after", ctypes.c_int64)]
+                ("fail_alloc_after", ctypes.c_int64), ("profile", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -54,7 +54,10 @@ class Info(ctypes.Structure):
                 ("t_assemble_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("refine_sweeps", ctypes.c_int32),
                 ("refine_residual", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("convex", ctypes.c_int32)]
+                ("convex", ctypes.c_int32), ("prof_launches", ctypes.c_int64 * 5),
+                ("prof_work", ctypes.c_double * 5), ("prof_ms", ctypes.c_double * 5)]
+
+PROF_NAMES = ("zgemm_f64", "zgemm_f32", "assemble_far", "assemble_near", "circ_fft")
 
 
 _lib = None
@@ -93,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.cfie_status_string.restype = ctypes.c_char_p
     lib.cfie_destroy.argtypes = [vp]
     lib.cfie_destroy.restype = None
+    lib.cfie_profile_reset.argtypes = [vp]
+    lib.cfie_profile_reset.restype = i32
     _lib = lib
     return lib
 

@@ -57,6 +57,20 @@ void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, 
                   int *kout, hipStream_t s);
 }  // namespace cfie
 
+namespace cfie {
+thread_local Profiler *g_prof = nullptr;
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+}  // namespace cfie
+
 using namespace cfie;
 
 namespace {
@@ -83,6 +97,10 @@ struct cfie_ctx {
     cfie_options opt;
     int device = 0;
     hipStream_t stream = nullptr;
+    Profiler prof;
+    int64_t prof_n[PROF_KINDS] = {0, 0, 0, 0, 0};
+    double prof_work[PROF_KINDS] = {0, 0, 0, 0, 0};
+    double prof_ms[PROF_KINDS] = {0, 0, 0, 0, 0};
     std::string err;
     int state = 0;                       // 0 created, 1 assembled, 2 factored
     int64_t n_alloc = 0;
@@ -132,6 +150,8 @@ struct cfie_ctx {
     double *w_norm = nullptr;
 
     ~cfie_ctx() {
+        for (auto &r : prof.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : prof.pool) (void)hipEventDestroy(e);
         for (auto &kv : live) (void)hipFree(kv.first);
         live.clear();
         if (stream_owned && stream) (void)hipStreamDestroy(stream);
@@ -176,7 +196,33 @@ cfie_status fail(cfie_ctx *c, cfie_status s, const std::string &m) {
 
 thread_local std::string g_create_err;
 
+// fold the launch records of the last call into the context totals
+void harvest_profile(cfie_ctx *c) {
+    if (c->prof.recs.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &r : c->prof.recs) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            c->prof_n[r.kind] += 1;
+            c->prof_work[r.kind] += r.work;
+            c->prof_ms[r.kind] += ms;
+        }
+        c->prof.pool.push_back(r.a);
+        c->prof.pool.push_back(r.b);
+    }
+    c->prof.recs.clear();
+    (void)hipGetLastError();
+}
+
 template <typename F> cfie_status guarded(cfie_ctx *c, F &&f) {
+    struct Scope {
+        cfie_ctx *c;
+        Scope(cfie_ctx *cc) : c(cc) { g_prof = (c && c->opt.profile) ? &c->prof : nullptr; }
+        ~Scope() {
+            g_prof = nullptr;
+            if (c) harvest_profile(c);
+        }
+    } scope(c);
     try {
         return f();
     } catch (const HipError &e) {
@@ -663,6 +709,7 @@ void cfie_default_options(cfie_options *o) {
     o->quad_near = 10;
     o->near_band = 6;
     o->fail_alloc_after = -1;
+    o->profile = 0;
 }
 
 const char *cfie_status_string(cfie_status s) {
@@ -1044,6 +1091,16 @@ cfie_status cfie_export_matrix(cfie_ctx *c, int which, void *dst, int64_t ld) {
     });
 }
 
+cfie_status cfie_profile_reset(cfie_ctx *c) {
+    if (!c) return CFIE_EINVAL;
+    for (int i = 0; i < PROF_KINDS; ++i) {
+        c->prof_n[i] = 0;
+        c->prof_work[i] = 0.0;
+        c->prof_ms[i] = 0.0;
+    }
+    return CFIE_OK;
+}
+
 cfie_status cfie_query(const cfie_ctx *c, cfie_info *o) {
     if (!c || !o) return CFIE_EINVAL;
     std::memset(o, 0, sizeof(*o));
@@ -1064,6 +1121,11 @@ cfie_status cfie_query(const cfie_ctx *c, cfie_info *o) {
     o->refine_residual = c->refine_res;
     o->precision = c->opt.precision;
     o->convex = c->hg.convex ? 1 : 0;
+    for (int i = 0; i < PROF_KINDS; ++i) {
+        o->prof_launches[i] = c->prof_n[i];
+        o->prof_work[i] = c->prof_work[i];
+        o->prof_ms[i] = c->prof_ms[i];
+    }
     return CFIE_OK;
 }
 

@@ -12,6 +12,44 @@
 
 namespace cfie {
 
+// ------------------------------------------------------------------ launch profiling ------
+// When a context is created with profile != 0, every API call installs a Profiler for the
+// calling thread; the hot kernels then bracket their launches with HIP events on their
+// stream and record the algorithmic work of the launch (flops for GEMMs, point pairs for
+// the assembly).  Totals are read back with cfie_query.
+struct LaunchRec {
+    int kind;                        // PROF_* below
+    double work;
+    hipEvent_t a, b;
+};
+enum { PROF_GEMM64 = 0, PROF_GEMM32 = 1, PROF_FAR = 2, PROF_NEAR = 3, PROF_FFT = 4, PROF_KINDS = 5 };
+struct Profiler {
+    std::vector<LaunchRec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+};
+extern thread_local Profiler *g_prof;
+struct ProfScope {                   // brackets one launch when profiling is on
+    Profiler *p;
+    LaunchRec r;
+    hipStream_t s;
+    ProfScope(int kind, double work, hipStream_t st) : p(g_prof), s(st) {
+        if (p) {
+            r.kind = kind;
+            r.work = work;
+            r.a = p->get();
+            r.b = p->get();
+            (void)hipEventRecord(r.a, s);
+        }
+    }
+    ~ProfScope() {
+        if (p) {
+            (void)hipEventRecord(r.b, s);
+            p->recs.push_back(r);
+        }
+    }
+};
+
 // ------------------------------------------------------------------ geometry (host) -------
 // Contour z(t) = sum_m zhat_m e^{imt}; arc-length density |z'(t)| as a Fourier series
 // c0 + 2 Re sum_{m>=1} c_m e^{imt}.  Nodes s_i = i L / N (uniform in arc length).

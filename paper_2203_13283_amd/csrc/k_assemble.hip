@@ -292,6 +292,10 @@ void launch_assemble_far(const AsmParams &p, const PointTable &far, const double
     int n_col_tiles = (p.N + kFarCols - 1) / kFarCols;
     long waves = (long)n_row_tiles * n_col_tiles;
     int blocks = (int)((waves + 3) / 4);
+    // algorithmic work: Gauss point pairs of the well-separated element pairs of the rows
+    double far_pairs = (double)nrows * (double)(p.N - std::min(p.N, 2 * p.nb + 1)) *
+                       (double)far.q * far.q;
+    ProfScope prof(PROF_FAR, far_pairs, s);
 #define CFIE_FAR_CASE(QQ)                                                                   \
     case QQ: {                                                                             \
         QuadConsts<QQ> qc;                                                                 \
@@ -481,6 +485,7 @@ void launch_assemble_near(const AsmParams &p, const PointTable &near, const doub
     int nrows = p.r1 - p.r0;
     long n = (long)nrows * (2 * p.nb + 3);
     int bs = 64;
+    ProfScope prof(PROF_NEAR, 4.0 * n * near.q * near.q, s);
     hipLaunchKernelGGL(k_near, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, p.N, nc,
                        near.q, p.nb, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2], p.out[3],
                        near.x, near.y, near.tx, near.ty, near.curv, moments);

@@ -118,6 +118,8 @@ void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx
                        hipStream_t s) {
     if (nb <= 0) return;
     const int bs = 256;
+    // algorithmic work: bytes of one read and one write of the batch
+    ProfScope prof(PROF_FFT, 2.0 * sizeof(cpx<T>) * (double)p.N * (double)nb, s);
     if (p.N2 > 1) {
         int64_t n = (int64_t)p.N1 * nb;
         hipLaunchKernelGGL(k_fft_stepA<T>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s,

@@ -178,6 +178,8 @@ void gemm(bool conjA, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T
         // C = beta C : run the kernel with an empty K loop
     }
     constexpr int TI = 2, TJ = 2;
+    ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
+                   8.0 * (double)m * (double)n * (double)k, s);
     dim3 grid((unsigned)((m + 32 * TI - 1) / (32 * TI)), (unsigned)((n + 32 * TJ - 1) / (32 * TJ)));
     if (conjA)
         hipLaunchKernelGGL((k_zgemm<T, true, TI, TJ>), grid, dim3(256), 0, s, m, n, k, alpha, A,
