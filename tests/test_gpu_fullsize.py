@@ -1,0 +1,86 @@
+"""Full-size parity against stored oracle references (GPU tests, through the C ABI).
+
+References are written by tests/golden/make_golden.py, which calls only the oracle: sampled
+entries of the four assembled matrices, the right-hand sides of eq. (5) and dense-LU
+solutions for a few plane-wave angles.  The HIP path runs in the launch configuration that
+bench.py times (block 256, default quadrature).  Bars: matrix entries within 1e-11 of the
+largest sampled entry; right-hand sides 1e-11; FP64 solve rel.err <= 1e-10 at
+epsilon = 1e-10 (ellipse4096) and <= 1e-6 at the bench's epsilon = 1e-6 (perturbed16384);
+mixed precision <= 1e-6 after refinement.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2203_13283_amd")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (tests/golden/make_golden.py {name})")
+    return np.load(path)
+
+
+def _rel_err(x, ref):
+    return float(np.max(np.linalg.norm(x - ref, axis=0) / np.linalg.norm(ref, axis=0)))
+
+
+def _check_case(name, eps_fp64, tol_fp64):
+    w = W.get(name)
+    g = _golden(name)
+    assert int(g["N"]) == w.n_nodes and float(g["k"]) == w.k
+    s = P.Solver(compress_tol=eps_fp64, block=256)
+    s.assemble(w.zhat, w.n_nodes, w.k)
+    info = s.info()
+    assert abs(info["ktilde_im"] - float(g["kt_im"])) <= 1e-13 * float(g["kt_im"])
+    rows = torch.as_tensor(g["rows"], device="cuda")
+    cols = torch.as_tensor(g["cols"], device="cuda")
+    for which, key in ((P.MAT_DK, "Dk"), (P.MAT_NK, "Nk"), (P.MAT_DKT, "Dkt"),
+                       (P.MAT_SKT, "Skt")):
+        A = s.export_matrix(which)
+        got = A[rows, cols].cpu().numpy()
+        del A
+        ref = g["entries_" + key]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"{name} {key}: sampled entries {err:.2e}")
+        assert err <= 1e-11, key
+    if "cc_eig" in g:
+        c = s.export_matrix(P.MAT_CC_EIG).cpu().numpy()[0]
+        ref = g["cc_eig"]
+        assert np.abs(c - ref).max() / np.abs(ref).max() <= 1e-11
+    ang = w.angles[g["cols_rhs"]]
+    B = s.plane_wave_rhs(ang)
+    eb = _rel_err(B.cpu().numpy().T, g["b"])
+    print(f"{name}: rhs {eb:.2e}")
+    assert eb <= 1e-11
+    s.factor()
+    X = s.solve(B).cpu().numpy().T
+    e64 = _rel_err(X, g["x"])
+    print(f"{name}: fp64 eps={eps_fp64} rank {s.info()['rank']} rel.err {e64:.2e}")
+    assert e64 <= tol_fp64
+    del s
+    torch.cuda.empty_cache()
+    sm = P.Solver(precision=P.CFIE_MIXED, compress_tol=1e-3, block=256, refine_tol=1e-8)
+    sm.assemble(w.zhat, w.n_nodes, w.k).factor()
+    Xm = sm.solve(sm.plane_wave_rhs(ang)).cpu().numpy().T
+    em = _rel_err(Xm, g["x"])
+    im = sm.info()
+    print(f"{name}: mixed rank {im['rank']} sweeps {im['refine_sweeps']} rel.err {em:.2e}")
+    assert em <= 1e-6
+
+
+def test_ellipse4096_against_oracle():
+    _check_case("ellipse4096", 1e-10, 1e-10)
+
+
+def test_perturbed16384_against_oracle():
+    _check_case("perturbed16384", 1e-6, 1e-6)
