@@ -55,6 +55,11 @@ void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out
                       hipStream_t s);
 void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz,
                   int *kout, hipStream_t s);
+template <typename T>
+void launch_polar_coef(int k, const zd *G, int ldg, cpx<T> *M, int ldm, hipStream_t s);
+template <typename T>
+void conj_transpose(bool conj_, int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
+                    int64_t ldy, hipStream_t s);
 }  // namespace cfie
 
 namespace cfie {
@@ -132,6 +137,8 @@ struct cfie_ctx {
     // matrices
     zd *mat[4] = {nullptr, nullptr, nullptr, nullptr};   // Dk, Nk, Dkt, Skt
     zf *mat32[4] = {nullptr, nullptr, nullptr, nullptr};
+    zd *matT[2] = {nullptr, nullptr};                    // Dk^T, Dkt^T
+    zf *matT32[2] = {nullptr, nullptr};
     zd *crow = nullptr, *mu = nullptr, *cvals = nullptr;
     zd *dC = nullptr, *dCH = nullptr, *dCinv = nullptr;
     zf *fC = nullptr, *fCH = nullptr, *fCinv = nullptr;
@@ -140,7 +147,8 @@ struct cfie_ctx {
 
     // factor
     int cap = 0;
-    void *Q = nullptr, *P = nullptr, *Ut = nullptr;    // N x cap (zd or zf)
+    void *Q = nullptr, *Ut = nullptr;                  // N x cap (zd or zf)
+    void *P = nullptr;                                  // V^T = Q^H (C - C_c): rank x N
     zd *K = nullptr;                                    // cap x cap
     int *piv = nullptr, *info = nullptr;
     zd *Linv = nullptr, *Uinv = nullptr;                // diagonal block inverses
@@ -320,12 +328,14 @@ template <typename T> cpx<T> cz(double a, double b = 0.0) { return mk((T)a, (T)b
 template <typename T> struct Ops;
 template <> struct Ops<double> {
     static zd *mat(cfie_ctx *c, int i) { return c->mat[i]; }
+    static zd *matT(cfie_ctx *c, int i) { return c->matT[i]; }
     static const zd *dC(cfie_ctx *c) { return c->dC; }
     static const zd *dCH(cfie_ctx *c) { return c->dCH; }
     static const zd *dCinv(cfie_ctx *c) { return c->dCinv; }
 };
 template <> struct Ops<float> {
     static zf *mat(cfie_ctx *c, int i) { return c->mat32[i]; }
+    static zf *matT(cfie_ctx *c, int i) { return c->matT32[i]; }
     static const zf *dC(cfie_ctx *c) { return c->fC; }
     static const zf *dCH(cfie_ctx *c) { return c->fCH; }
     static const zf *dCinv(cfie_ctx *c) { return c->fCinv; }
@@ -340,14 +350,14 @@ void apply_C(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, 
     const double h = c->hg.L / N;
     hipStream_t s = c->stream;
     const int nt = (int)c->gcoef.size();
-    gemm<T>(false, N, m, N, cz<T>(1), Ops<T>::mat(c, 0), N, X, ldx, cz<T>(0), Tt, N, s);
+    gemm<T>(GEMM_N, N, m, N, cz<T>(1), Ops<T>::mat(c, 0), N, X, ldx, cz<T>(0), Tt, N, s);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0.5), X, ldx, cz<T>(-1), Tt, N, W1, N, m, s);
-    gemm<T>(false, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, X, ldx, cz<T>(0), Tt, N, s);
+    gemm<T>(GEMM_N, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, X, ldx, cz<T>(0), Tt, N, s);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(1),
                       Tt, N, W2, N, m, s);
     launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), W1, N, Y, ldy, m, s);
-    gemm<T>(false, N, m, N, cz<T>(1), Ops<T>::mat(c, 2), N, W1, N, cz<T>(1), Y, ldy, s);
-    gemm<T>(false, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, W2, N, cz<T>(1), Y, ldy, s);
+    gemm<T>(GEMM_N, N, m, N, cz<T>(1), Ops<T>::mat(c, 2), N, W1, N, cz<T>(1), Y, ldy, s);
+    gemm<T>(GEMM_N, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, W2, N, cz<T>(1), Y, ldy, s);
     c->check_launch();
 }
 
@@ -364,7 +374,9 @@ void apply_R(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, 
 }
 
 // Y = (C - C_c)^H X = (G/2 - Dk^H) V1 + Nk^H V2 - C_c^H X,
-// V1 = X/2 + G^{-1} Dkt^H X, V2 = G^{-1} Skt^H X
+// V1 = X/2 + G^{-1} Dkt^H X, V2 = G^{-1} Skt^H X.
+// Every product is a non-transposed GEMM: Skt and Nk are symmetric (reciprocity of the
+// bilinear forms), so their adjoints are their conjugates; Dk and Dkt are kept transposed.
 template <typename T>
 void apply_RH(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
               cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z) {
@@ -372,14 +384,14 @@ void apply_RH(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy,
     const double h = c->hg.L / N;
     hipStream_t s = c->stream;
     const int nt = (int)c->gcoef.size();
-    gemm<T>(true, N, m, N, cz<T>(1), Ops<T>::mat(c, 2), N, X, ldx, cz<T>(0), Tt, N, s);
+    gemm<T>(GEMM_R, N, m, N, cz<T>(1), Ops<T>::matT(c, 1), N, X, ldx, cz<T>(0), Tt, N, s);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0.5), X, ldx, cz<T>(1), Tt, N, W1, N, m, s);
-    gemm<T>(true, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, X, ldx, cz<T>(0), Tt, N, s);
+    gemm<T>(GEMM_R, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, X, ldx, cz<T>(0), Tt, N, s);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(1),
                       Tt, N, W2, N, m, s);
     launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), W1, N, Y, ldy, m, s);
-    gemm<T>(true, N, m, N, cz<T>(-1), Ops<T>::mat(c, 0), N, W1, N, cz<T>(1), Y, ldy, s);
-    gemm<T>(true, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, W2, N, cz<T>(1), Y, ldy, s);
+    gemm<T>(GEMM_R, N, m, N, cz<T>(-1), Ops<T>::matT(c, 0), N, W1, N, cz<T>(1), Y, ldy, s);
+    gemm<T>(GEMM_R, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, W2, N, cz<T>(1), Y, ldy, s);
     axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, s);
     launch_circ_apply<T>(c->fft, Ops<T>::dCH(c), Z, N, m, s);
     axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, s);
@@ -391,11 +403,11 @@ template <typename T>
 void gram64(cfie_ctx *c, const cpx<T> *Y, int b, zd *W) {
     const int N = c->N;
     if (sizeof(T) == sizeof(double)) {
-        gemm<double>(true, b, b, N, cz<double>(1), (const zd *)Y, N, (const zd *)Y, N,
+        gemm<double>(GEMM_C, b, b, N, cz<double>(1), (const zd *)Y, N, (const zd *)Y, N,
                      cz<double>(0), W, b, c->stream);
     } else {
         convert<double, T>(N, b, Y, N, c->w_y64, N, c->stream);
-        gemm<double>(true, b, b, N, cz<double>(1), c->w_y64, N, c->w_y64, N, cz<double>(0), W,
+        gemm<double>(GEMM_C, b, b, N, cz<double>(1), c->w_y64, N, c->w_y64, N, cz<double>(0), W,
                      b, c->stream);
     }
 }
@@ -418,14 +430,16 @@ int orthonormalise(cfie_ctx *c, cpx<T> *Y, int b, double tau) {
     c->sync();
     if (k <= 0) return 0;
     convert<T, double>(b, k, c->w_rinv, b, rinvT, b, s);
-    gemm<T>(false, N, k, b, cz<T>(1), Y, N, rinvT, b, cz<T>(0), Y2, N, s);
+    gemm<T>(GEMM_N, N, k, b, cz<T>(1), Y, N, rinvT, b, cz<T>(0), Y2, N, s);
     axpby<T>(N, k, cz<T>(1), Y2, N, cz<T>(0), Y, N, s);
-    for (int pass = 0; pass < 2; ++pass) {
+    // Newton-Schulz steps towards the orthonormal polar factor: Y <- Y (3 I - Y^H Y) / 2.
+    // After the pivoted step ||Y^H Y - I|| is at most ~1e-3 (FP64) or ~1e-1 (FP32 data),
+    // and each step squares it.
+    const int steps = sizeof(T) == sizeof(double) ? 3 : 4;
+    for (int it = 0; it < steps; ++it) {
         gram64<T>(c, Y, k, c->w_gram);
-        HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
-        launch_chol_inv(k, c->w_gram, k, 0.0, c->w_rinv, k, c->info, s);
-        convert<T, double>(k, k, c->w_rinv, k, rinvT, k, s);
-        gemm<T>(false, N, k, k, cz<T>(1), Y, N, rinvT, k, cz<T>(0), Y2, N, s);
+        launch_polar_coef<T>(k, c->w_gram, k, rinvT, k, s);
+        gemm<T>(GEMM_N, N, k, k, cz<T>(1), Y, N, rinvT, k, cz<T>(0), Y2, N, s);
         axpby<T>(N, k, cz<T>(1), Y2, N, cz<T>(0), Y, N, s);
     }
     c->check_launch();
@@ -465,21 +479,21 @@ void lu_solve(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
     int nblk = (n + nb - 1) / nb;
     for (int bi = 0; bi < nblk; ++bi) {
         int k0 = bi * nb, kb = std::min(nb, n - k0);
-        gemm<double>(false, kb, m, kb, cz<double>(1), c->Linv + (size_t)bi * nb * nb, nb,
+        gemm<double>(GEMM_N, kb, m, kb, cz<double>(1), c->Linv + (size_t)bi * nb * nb, nb,
                      Z + k0, ldz, cz<double>(0), tmp, kb, s);
         axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
         int rest = n - k0 - kb;
         if (rest > 0)
-            gemm<double>(false, rest, m, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * c->cap,
+            gemm<double>(GEMM_N, rest, m, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * c->cap,
                          c->cap, Z + k0, ldz, cz<double>(1), Z + k0 + kb, ldz, s);
     }
     for (int bi = nblk - 1; bi >= 0; --bi) {
         int k0 = bi * nb, kb = std::min(nb, n - k0);
-        gemm<double>(false, kb, m, kb, cz<double>(1), c->Uinv + (size_t)bi * nb * nb, nb,
+        gemm<double>(GEMM_N, kb, m, kb, cz<double>(1), c->Uinv + (size_t)bi * nb * nb, nb,
                      Z + k0, ldz, cz<double>(0), tmp, kb, s);
         axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
         if (k0 > 0)
-            gemm<double>(false, k0, m, kb, cz<double>(-1), c->K + (size_t)k0 * c->cap, c->cap,
+            gemm<double>(GEMM_N, k0, m, kb, cz<double>(-1), c->K + (size_t)k0 * c->cap, c->cap,
                          Z + k0, ldz, cz<double>(1), Z, ldz, s);
     }
     c->check_launch();
@@ -507,8 +521,8 @@ cfie_status factor_impl(cfie_ctx *c) {
         apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z);
         if (ell > 0) {
             for (int pass = 0; pass < 2; ++pass) {
-                gemm<T>(true, ell, bb, N, cz<T>(1), Q, N, Y, N, cz<T>(0), S, ell, s);
-                gemm<T>(false, N, bb, ell, cz<T>(-1), Q, N, S, ell, cz<T>(1), Y, N, s);
+                gemm<T>(GEMM_C, ell, bb, N, cz<T>(1), Q, N, Y, N, cz<T>(0), S, ell, s);
+                gemm<T>(GEMM_N, N, bb, ell, cz<T>(-1), Q, N, S, ell, cz<T>(1), Y, N, s);
             }
         }
         colnorm2<T>(N, bb, Y, N, c->w_norm, s);
@@ -528,24 +542,29 @@ cfie_status factor_impl(cfie_ctx *c) {
         c->state = 2;
         return CFIE_OK;
     }
-    // P = R^H Q, Ut = C_c^{-1} Q
-    c->P = c->alloc_n<cpx<T>>((size_t)N * ell);
-    c->Ut = c->alloc_n<cpx<T>>((size_t)N * ell);
-    cpx<T> *P = (cpx<T> *)c->P, *Ut = (cpx<T> *)c->Ut;
+    // V^T = Q^H (C - C_c) = ((C - C_c)^H Q)^H, stored as an ell x N matrix; Ut = C_c^{-1} Q
+    cpx<T> *RHQ = (cpx<T> *)c->alloc_n<cpx<T>>((size_t)N * ell);
     for (int j = 0; j < ell; j += b) {
         int bb = std::min(b, ell - j);
-        apply_RH<T>(c, Q + (size_t)j * N, N, P + (size_t)j * N, N, bb, Tt, W1, W2, Z);
+        apply_RH<T>(c, Q + (size_t)j * N, N, RHQ + (size_t)j * N, N, bb, Tt, W1, W2, Z);
     }
+    c->P = c->alloc_n<cpx<T>>((size_t)N * ell);
+    cpx<T> *P = (cpx<T> *)c->P;
+    conj_transpose<T>(true, N, ell, RHQ, N, P, ell, s);
+    c->sync();
+    c->dfree(RHQ);
+    c->Ut = c->alloc_n<cpx<T>>((size_t)N * ell);
+    cpx<T> *Ut = (cpx<T> *)c->Ut;
     axpby<T>(N, ell, cz<T>(1), Q, N, cz<T>(0), Ut, N, s);
     launch_circ_apply<T>(c->fft, Ops<T>::dCinv(c), Ut, N, ell, s);
     // K = I + P^H Ut  (Woodbury capacitance, eq. (9)), always complex128
     c->K = c->alloc_n<zd>((size_t)cap * cap);
     if (sizeof(T) == sizeof(double)) {
-        gemm<double>(true, ell, ell, N, cz<double>(1), (const zd *)P, N, (const zd *)Ut, N,
+        gemm<double>(GEMM_N, ell, ell, N, cz<double>(1), (const zd *)P, ell, (const zd *)Ut, N,
                      cz<double>(0), c->K, cap, s);
     } else {
         cpx<T> *K32 = (cpx<T> *)c->alloc_n<cpx<T>>((size_t)ell * ell);
-        gemm<T>(true, ell, ell, N, cz<T>(1), P, N, Ut, N, cz<T>(0), K32, ell, s);
+        gemm<T>(GEMM_N, ell, ell, N, cz<T>(1), P, ell, Ut, N, cz<T>(0), K32, ell, s);
         convert<double, T>(ell, ell, K32, ell, c->K, cap, s);
         c->sync();
         c->dfree(K32);
@@ -568,10 +587,10 @@ cfie_status factor_impl(cfie_ctx *c) {
         int rest = ell - k0 - kb;
         if (rest > 0) {
             zd *U12 = c->K + k0 + (size_t)(k0 + kb) * cap;
-            gemm<double>(false, kb, rest, kb, cz<double>(1), c->Linv + (size_t)bi * kLUBlock * kLUBlock,
+            gemm<double>(GEMM_N, kb, rest, kb, cz<double>(1), c->Linv + (size_t)bi * kLUBlock * kLUBlock,
                          kLUBlock, U12, cap, cz<double>(0), tmp, kb, s);
             axpby<double>(kb, rest, cz<double>(1), tmp, kb, cz<double>(0), U12, cap, s);
-            gemm<double>(false, rest, rest, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * cap,
+            gemm<double>(GEMM_N, rest, rest, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * cap,
                          cap, U12, cap, cz<double>(1), c->K + (k0 + kb) + (size_t)(k0 + kb) * cap,
                          cap, s);
         }
@@ -597,17 +616,17 @@ void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, zd *Zd, cpx<T> *ZT, zd *tmp) {
     if (r == 0) return;
     cpx<T> *P = (cpx<T> *)c->P, *Ut = (cpx<T> *)c->Ut;
     if (sizeof(T) == sizeof(double)) {
-        gemm<double>(true, r, m, N, cz<double>(1), (const zd *)P, N, (const zd *)X, N,
+        gemm<double>(GEMM_N, r, m, N, cz<double>(1), (const zd *)P, r, (const zd *)X, N,
                      cz<double>(0), Zd, r, s);
         lu_solve(c, Zd, r, m, tmp);
-        gemm<double>(false, N, m, r, cz<double>(-1), (const zd *)Ut, N, Zd, r, cz<double>(1),
+        gemm<double>(GEMM_N, N, m, r, cz<double>(-1), (const zd *)Ut, N, Zd, r, cz<double>(1),
                      (zd *)X, N, s);
     } else {
-        gemm<T>(true, r, m, N, cz<T>(1), P, N, X, N, cz<T>(0), ZT, r, s);
+        gemm<T>(GEMM_N, r, m, N, cz<T>(1), P, r, X, N, cz<T>(0), ZT, r, s);
         convert<double, T>(r, m, ZT, r, Zd, r, s);
         lu_solve(c, Zd, r, m, tmp);
         convert<T, double>(r, m, Zd, r, ZT, r, s);
-        gemm<T>(false, N, m, r, cz<T>(-1), Ut, N, ZT, r, cz<T>(1), X, N, s);
+        gemm<T>(GEMM_N, N, m, r, cz<T>(-1), Ut, N, ZT, r, cz<T>(1), X, N, s);
     }
     c->check_launch();
 }
@@ -790,6 +809,7 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         // release everything of a previous problem
         free_factor(c);
         for (int i = 0; i < 4; ++i) { c->dfree(c->mat[i]); c->mat[i] = nullptr; c->dfree(c->mat32[i]); c->mat32[i] = nullptr; }
+        for (int i = 0; i < 2; ++i) { c->dfree(c->matT[i]); c->matT[i] = nullptr; c->dfree(c->matT32[i]); c->matT32[i] = nullptr; }
         free_points(c, c->pf); free_points(c, c->pn); free_points(c, c->cf); free_points(c, c->cn);
         void *old[] = {c->crow, c->mu, c->cvals, c->dC, c->dCH, c->dCinv, c->fC, c->fCH, c->fCinv,
                        c->absc, c->scal, c->d_xf, c->d_wf, c->d_xn, c->d_wn, c->d_mom, c->d_gcoef};
@@ -873,10 +893,19 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         launch_maxmin(N, c->absc, c->scal, s);
         double mm[2];
         HIPCHK(hipMemcpyAsync(mm, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        // transposes of the two double-layer matrices for the adjoint sketch
+        for (int i = 0; i < 2; ++i) {
+            c->matT[i] = c->alloc_n<zd>(nn);
+            conj_transpose<double>(false, N, N, c->mat[2 * i], N, c->matT[i], N, s);
+        }
         if (c->opt.precision == CFIE_MIXED) {
             for (int i = 0; i < 4; ++i) {
                 c->mat32[i] = c->alloc_n<zf>(nn);
                 convert<float, double>(N, N, c->mat[i], N, c->mat32[i], N, s);
+            }
+            for (int i = 0; i < 2; ++i) {
+                c->matT32[i] = c->alloc_n<zf>(nn);
+                convert<float, double>(N, N, c->matT[i], N, c->matT32[i], N, s);
             }
         }
         HIPCHK(hipEventRecord(e1, s));
@@ -971,8 +1000,8 @@ cfie_status cfie_plane_wave_rhs(cfie_ctx *c, const double *angles, int64_t nrhs,
                                hv, N, gh, N, nrhs, s);
         // b = -i k S^kt G^-1 e' - h/2 - D^kt G^-1 h     (eq. (5), eta cancelled)
         axpby<double>(N, nrhs, cz<double>(-0.5), hv, N, cz<double>(0), B, ldb, s);
-        gemm<double>(false, N, nrhs, N, cz<double>(-1), c->mat[2], N, gh, N, cz<double>(1), B, ldb, s);
-        gemm<double>(false, N, nrhs, N, mk(0.0, -c->k), c->mat[3], N, ge, N, cz<double>(1), B, ldb, s);
+        gemm<double>(GEMM_N, N, nrhs, N, cz<double>(-1), c->mat[2], N, gh, N, cz<double>(1), B, ldb, s);
+        gemm<double>(GEMM_N, N, nrhs, N, mk(0.0, -c->k), c->mat[3], N, ge, N, cz<double>(1), B, ldb, s);
         c->check_launch();
         c->sync();
         c->dfree(d_ang); c->dfree(e); c->dfree(hv); c->dfree(ge); c->dfree(gh);
@@ -1024,18 +1053,18 @@ cfie_status cfie_apply(cfie_ctx *c, int op, const void *X, int64_t ldx, void *Y,
                 if (c->opt.precision == CFIE_MIXED) {
                     zf *X32 = c->alloc_n<zf>((size_t)N * nrhs), *S32 = c->alloc_n<zf>((size_t)r * nrhs);
                     convert<float, double>(N, nrhs, Xd, ldx, X32, N, s);
-                    gemm<float>(true, r, nrhs, N, cz<float>(1), (const zf *)c->P, N, X32, N,
+                    gemm<float>(GEMM_N, r, nrhs, N, cz<float>(1), (const zf *)c->P, r, X32, N,
                                 cz<float>(0), S32, r, s);
-                    gemm<float>(false, N, nrhs, r, cz<float>(1), (const zf *)c->Q, N, S32, r,
+                    gemm<float>(GEMM_N, N, nrhs, r, cz<float>(1), (const zf *)c->Q, N, S32, r,
                                 cz<float>(0), X32, N, s);
                     convert<double, float>(N, nrhs, X32, N, Yd, ldy, s);
                     c->sync();
                     c->dfree(X32);
                     c->dfree(S32);
                 } else {
-                    gemm<double>(true, r, nrhs, N, cz<double>(1), (const zd *)c->P, N, Xd, ldx,
+                    gemm<double>(GEMM_N, r, nrhs, N, cz<double>(1), (const zd *)c->P, r, Xd, ldx,
                                  cz<double>(0), S, r, s);
-                    gemm<double>(false, N, nrhs, r, cz<double>(1), (const zd *)c->Q, N, S, r,
+                    gemm<double>(GEMM_N, N, nrhs, r, cz<double>(1), (const zd *)c->Q, N, S, r,
                                  cz<double>(0), Yd, ldy, s);
                 }
                 c->sync();

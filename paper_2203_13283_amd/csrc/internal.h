@@ -135,10 +135,11 @@ template <typename T>
 void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx,
                        int64_t nb, hipStream_t s);
 
-// complex GEMM: C = alpha * op(A) * B + beta * C, op(A) = A or A^H
+// complex GEMM: C = alpha * op(A) * B + beta * C, op(A) = A (GEMM_N), A^H (GEMM_C) or the
+// elementwise conjugate of A (GEMM_R)
+enum { GEMM_N = 0, GEMM_C = 1, GEMM_R = 2 };
 template <typename T>
-void gemm(bool conjA, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A,
-          int64_t lda, const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc,
-          hipStream_t s);
+void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A, int64_t lda,
+          const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s);
 
 }  // namespace cfie

@@ -147,8 +147,8 @@ template void convert<double, double>(int64_t, int64_t, const zd *, int64_t, zd 
 template void convert<float, float>(int64_t, int64_t, const zf *, int64_t, zf *, int64_t,
                                     hipStream_t);
 
-// Y (n x m) = X^H (X is m x n)
-template <typename T>
+// Y (n x m) = X^H (CONJ) or X^T (X is m x n)
+template <typename T, bool CONJ>
 __global__ void k_conj_transpose(int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
                                  int64_t ldy) {
     __shared__ cpx<T> tile[32][33];
@@ -161,19 +161,22 @@ __global__ void k_conj_transpose(int64_t m, int64_t n, const cpx<T> *X, int64_t 
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         int64_t i = by + tx, j = bx + r;         // Y(i, j) = conj X(j, i)
-        if (i < n && j < m) Y[i + j * ldy] = conj(tile[tx][r]);
+        if (i < n && j < m) Y[i + j * ldy] = CONJ ? conj(tile[tx][r]) : tile[tx][r];
     }
 }
 template <typename T>
-void conj_transpose(int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy,
-                    hipStream_t s) {
+void conj_transpose(bool conj_, int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
+                    int64_t ldy, hipStream_t s) {
     if (m <= 0 || n <= 0) return;
-    hipLaunchKernelGGL(k_conj_transpose<T>, dim3((unsigned)((m + 31) / 32), (unsigned)((n + 31) / 32)),
-                       dim3(32, 8), 0, s, m, n, X, ldx, Y, ldy);
+    dim3 grid((unsigned)((m + 31) / 32), (unsigned)((n + 31) / 32));
+    if (conj_)
+        hipLaunchKernelGGL((k_conj_transpose<T, true>), grid, dim3(32, 8), 0, s, m, n, X, ldx, Y, ldy);
+    else
+        hipLaunchKernelGGL((k_conj_transpose<T, false>), grid, dim3(32, 8), 0, s, m, n, X, ldx, Y, ldy);
 }
-template void conj_transpose<double>(int64_t, int64_t, const zd *, int64_t, zd *, int64_t,
+template void conj_transpose<double>(bool, int64_t, int64_t, const zd *, int64_t, zd *, int64_t,
                                      hipStream_t);
-template void conj_transpose<float>(int64_t, int64_t, const zf *, int64_t, zf *, int64_t,
+template void conj_transpose<float>(bool, int64_t, int64_t, const zf *, int64_t, zf *, int64_t,
                                     hipStream_t);
 
 // ------------------------------------------------------------------ Gaussian sketch ------
@@ -467,6 +470,23 @@ void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, 
     hipLaunchKernelGGL(k_pchol, dim3(1), dim3(1024), 0, s, b, W, ldw, thr_abs, thr_rel, Z, ldz,
                        kout);
 }
+
+// M = (3 I - G) / 2 in precision T (one Newton-Schulz step towards the polar factor)
+template <typename T>
+__global__ void k_polar_coef(int k, const zd *G, int ldg, cpx<T> *M, int ldm) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k * k) return;
+    int i = t % k, j = t / k;
+    zd g = G[i + (int64_t)j * ldg];
+    zd v = mk((i == j ? 1.5 : 0.0) - 0.5 * g.x, -0.5 * g.y);
+    M[i + (int64_t)j * ldm] = mk((T)v.x, (T)v.y);
+}
+template <typename T>
+void launch_polar_coef(int k, const zd *G, int ldg, cpx<T> *M, int ldm, hipStream_t s) {
+    hipLaunchKernelGGL(k_polar_coef<T>, dim3((k * k + 255) / 256), dim3(256), 0, s, k, G, ldg, M, ldm);
+}
+template void launch_polar_coef<double>(int, const zd *, int, zd *, int, hipStream_t);
+template void launch_polar_coef<float>(int, const zd *, int, zf *, int, hipStream_t);
 
 // ---- LU with partial pivoting: panel of columns [k0, k0 + nb) of the n x n matrix A
 // (rows k0..n-1), one workgroup; piv[j] = global row swapped with row j.

@@ -5,9 +5,13 @@
 //
 // The complex product is four real products per k-step on split real/imaginary tiles held
 // in LDS: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br, with the 16x16x4 MFMA (f64 or f32).
-// Block tile BM x BN with BK = 16, 256 threads = 4 wavefronts, each wavefront a
-// (BM/2) x (BN/2) sub-tile made of 16x16 MFMA tiles.  Global loads for the next K-slice are
-// issued before the MFMAs of the current one (register double buffering).
+// Block tile BM x BN = 32 TI x 32 TJ with a K-slice of BKT, 256 threads = 4 wavefronts,
+// each wavefront a (BM/2) x (BN/2) sub-tile of TI x TJ MFMA tiles of 16 x 16.  Global loads
+// of the next K-slice are issued before the MFMAs of the current one.
+//
+// Shapes with few output tiles and a long K (Gram matrices Y^H Y, projections Q^H Y) are
+// split along K over blockIdx.z: each slice writes its partial product to a workspace and a
+// second kernel sums the slices in a fixed order (deterministic) and applies alpha, beta.
 #include "internal.h"
 
 namespace cfie {
@@ -36,19 +40,25 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int BK = 16;
-
-// BM = 32 * TI, BN = 32 * TJ (each wavefront: TI x TJ MFMA tiles of 16 x 16)
-template <typename T, bool CONJA, int TI, int TJ>
+template <typename T, int OPA, int TI, int TJ, int BKT>
 __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdim,
-                                               cpx<T> alpha, const cpx<T> *__restrict__ A,
-                                               int64_t lda, const cpx<T> *__restrict__ B,
-                                               int64_t ldb, cpx<T> beta, cpx<T> *C,
-                                               int64_t ldc) {
+                                               int64_t kchunk, cpx<T> alpha,
+                                               const cpx<T> *__restrict__ A, int64_t lda,
+                                               const cpx<T> *__restrict__ B, int64_t ldb,
+                                               cpx<T> beta, cpx<T> *C, int64_t ldc,
+                                               cpx<T> *W) {
+    constexpr bool CONJA = OPA == 1;
     constexpr int BM = 32 * TI, BN = 32 * TJ;
-    constexpr int PAD = 2;
-    __shared__ T As[2][BK][BM + PAD];     // [re/im][k][i]
-    __shared__ T Bs[2][BK][BN + PAD];     // [re/im][k][j]
+    // LDS tiles split into real and imaginary parts.  The layout follows the order in which
+    // the global loads arrive so that the stores are free of bank conflicts: A is [k][i]
+    // (rows contiguous) for op(A) = A and [i][k] (k contiguous) for op(A) = A^H; B is
+    // always [j][k].  The k-contiguous layouts are padded by one element per row so that
+    // the 16 lanes reading one MFMA fragment hit distinct banks.
+    constexpr int AK = CONJA ? BM : BKT, AI = CONJA ? BKT + 1 : BM + 2;
+    __shared__ T As[2][AK * AI];
+    __shared__ T Bs[2][BN * (BKT + 1)];
+    auto aidx = [&](int kk, int i) { return CONJA ? i * AI + kk : kk * AI + i; };
+    auto bidx = [&](int kk, int j) { return j * (BKT + 1) + kk; };
     typedef typename MfmaAcc<T>::type acc_t;
 
     const int tid = threadIdx.x;
@@ -58,6 +68,8 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
     const int wcol = (wv >> 1) * (BN / 2);
     const int64_t row0 = (int64_t)blockIdx.x * BM;
     const int64_t col0 = (int64_t)blockIdx.y * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = min(kdim, kbeg + kchunk);
 
     acc_t accr[TI][TJ], acci[TI][TJ];
 #pragma unroll
@@ -68,9 +80,8 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
             acci[a][b] = acc_t{0, 0, 0, 0};
         }
 
-    // per-thread staging registers: A tile BM*BK elements, B tile BK*BN, over 256 threads
-    constexpr int NA = BM * BK / 256;
-    constexpr int NB = BN * BK / 256;
+    constexpr int NA = BM * BKT / 256;
+    constexpr int NB = BN * BKT / 256;
     cpx<T> ra[NA], rb[NB];
 
     auto load_tiles = [&](int64_t k0) {
@@ -79,22 +90,22 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
             int e = tid + 256 * r;
             int i, kk;
             if (!CONJA) { i = e % BM; kk = e / BM; }      // contiguous along rows
-            else { kk = e % BK; i = e / BK; }              // contiguous along k
+            else { kk = e % BKT; i = e / BKT; }            // contiguous along k
             int64_t gi = row0 + i, gk = k0 + kk;
             cpx<T> v = mk((T)0, (T)0);
-            if (gi < m && gk < kdim) {
+            if (gi < m && gk < kend) {
                 v = CONJA ? A[gk + gi * lda] : A[gi + gk * lda];
-                if (CONJA) v.y = -v.y;
+                if (OPA != 0) v.y = -v.y;
             }
             ra[r] = v;
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
             int e = tid + 256 * r;
-            int kk = e % BK, j = e / BK;
+            int kk = e % BKT, j = e / BKT;
             int64_t gj = col0 + j, gk = k0 + kk;
             cpx<T> v = mk((T)0, (T)0);
-            if (gj < n && gk < kdim) v = B[gk + gj * ldb];
+            if (gj < n && gk < kend) v = B[gk + gj * ldb];
             rb[r] = v;
         }
     };
@@ -104,52 +115,54 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
             int e = tid + 256 * r;
             int i, kk;
             if (!CONJA) { i = e % BM; kk = e / BM; }
-            else { kk = e % BK; i = e / BK; }
-            As[0][kk][i] = ra[r].x;
-            As[1][kk][i] = ra[r].y;
+            else { kk = e % BKT; i = e / BKT; }
+            As[0][aidx(kk, i)] = ra[r].x;
+            As[1][aidx(kk, i)] = ra[r].y;
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
             int e = tid + 256 * r;
-            int kk = e % BK, j = e / BK;
-            Bs[0][kk][j] = rb[r].x;
-            Bs[1][kk][j] = rb[r].y;
+            int kk = e % BKT, j = e / BKT;
+            Bs[0][bidx(kk, j)] = rb[r].x;
+            Bs[1][bidx(kk, j)] = rb[r].y;
         }
     };
 
-    load_tiles(0);
-    for (int64_t k0 = 0; k0 < kdim; k0 += BK) {
+    if (kbeg < kend) load_tiles(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BKT) {
         __syncthreads();
         store_tiles();
         __syncthreads();
-        if (k0 + BK < kdim) load_tiles(k0 + BK);
+        if (k0 + BKT < kend) load_tiles(k0 + BKT);
 #pragma unroll
-        for (int k4 = 0; k4 < BK; k4 += 4) {
+        for (int k4 = 0; k4 < BKT; k4 += 4) {
             const int kk = k4 + (lane >> 4);
             T ar[TI], ai[TI], br[TJ], bi[TJ];
 #pragma unroll
             for (int a = 0; a < TI; ++a) {
-                ar[a] = As[0][kk][wrow + a * 16 + (lane & 15)];
-                ai[a] = As[1][kk][wrow + a * 16 + (lane & 15)];
+                ar[a] = As[0][aidx(kk, wrow + a * 16 + (lane & 15))];
+                ai[a] = As[1][aidx(kk, wrow + a * 16 + (lane & 15))];
             }
 #pragma unroll
             for (int b = 0; b < TJ; ++b) {
-                br[b] = Bs[0][kk][wcol + b * 16 + (lane & 15)];
-                bi[b] = Bs[1][kk][wcol + b * 16 + (lane & 15)];
+                br[b] = Bs[0][bidx(kk, wcol + b * 16 + (lane & 15))];
+                bi[b] = Bs[1][bidx(kk, wcol + b * 16 + (lane & 15))];
             }
 #pragma unroll
-            for (int a = 0; a < TI; ++a)
+            for (int a = 0; a < TI; ++a) {
+                T nai = -ai[a];
 #pragma unroll
                 for (int b = 0; b < TJ; ++b) {
                     accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
-                    accr[a][b] = mfma(-ai[a], bi[b], accr[a][b]);
+                    accr[a][b] = mfma(nai, bi[b], accr[a][b]);
                     acci[a][b] = mfma(ar[a], bi[b], acci[a][b]);
                     acci[a][b] = mfma(ai[a], br[b], acci[a][b]);
                 }
+            }
         }
     }
-    // epilogue: column lane%16 of each 16x16 tile, rows from acc_row
     const bool beta_zero = (beta.x == (T)0 && beta.y == (T)0);
+    cpx<T> *Wz = W ? W + (int64_t)blockIdx.z * m * n : nullptr;
 #pragma unroll
     for (int a = 0; a < TI; ++a)
 #pragma unroll
@@ -160,38 +173,107 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
                 int64_t gi = row0 + wrow + a * 16 + acc_row<T>(lane, r);
                 if (gi < m && gj < n) {
                     cpx<T> v = mk((T)accr[a][b][r], (T)acci[a][b][r]);
-                    v = alpha * v;
-                    cpx<T> *p = C + gi + gj * ldc;
-                    if (!beta_zero) v = v + beta * (*p);
-                    *p = v;
+                    if (Wz) {
+                        Wz[gi + gj * m] = v;                     // partial of this K-slice
+                    } else {
+                        v = alpha * v;
+                        cpx<T> *p = C + gi + gj * ldc;
+                        if (!beta_zero) v = v + beta * (*p);
+                        *p = v;
+                    }
                 }
             }
         }
 }
 
+// C = alpha * sum_z W[z] + beta * C, slices summed in order
 template <typename T>
-void gemm(bool conjA, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A,
-          int64_t lda, const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc,
-          hipStream_t s) {
-    if (m <= 0 || n <= 0) return;
-    if (k <= 0) {
-        // C = beta C : run the kernel with an empty K loop
-    }
-    constexpr int TI = 2, TJ = 2;
-    ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
-                   8.0 * (double)m * (double)n * (double)k, s);
-    dim3 grid((unsigned)((m + 32 * TI - 1) / (32 * TI)), (unsigned)((n + 32 * TJ - 1) / (32 * TJ)));
-    if (conjA)
-        hipLaunchKernelGGL((k_zgemm<T, true, TI, TJ>), grid, dim3(256), 0, s, m, n, k, alpha, A,
-                           lda, B, ldb, beta, C, ldc);
-    else
-        hipLaunchKernelGGL((k_zgemm<T, false, TI, TJ>), grid, dim3(256), 0, s, m, n, k, alpha,
-                           A, lda, B, ldb, beta, C, ldc);
+__global__ void k_splitk_reduce(int64_t m, int64_t n, int S, const cpx<T> *__restrict__ W,
+                                cpx<T> alpha, cpx<T> beta, cpx<T> *C, int64_t ldc) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * n) return;
+    int64_t i = t % m, j = t / m;
+    cpx<T> acc = W[t];
+    for (int z = 1; z < S; ++z) acc = acc + W[(int64_t)z * m * n + t];
+    cpx<T> v = alpha * acc;
+    cpx<T> *p = C + i + j * ldc;
+    if (!(beta.x == (T)0 && beta.y == (T)0)) v = v + beta * (*p);
+    *p = v;
 }
 
-template void gemm<double>(bool, int64_t, int64_t, int64_t, zd, const zd *, int64_t,
+namespace {
+// grow-only device workspace for split-K partial products (one per process and device)
+struct SplitKWorkspace {
+    void *ptr[16] = {nullptr};
+    size_t bytes[16] = {0};
+};
+SplitKWorkspace g_ws;
+
+void *splitk_ws(size_t need, hipStream_t s) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 16) return nullptr;
+    if (g_ws.bytes[dev] < need) {
+        (void)hipStreamSynchronize(s);
+        if (g_ws.ptr[dev]) (void)hipFree(g_ws.ptr[dev]);
+        g_ws.ptr[dev] = nullptr;
+        g_ws.bytes[dev] = 0;
+        size_t nb = need + need / 2;
+        if (hipMalloc(&g_ws.ptr[dev], nb) != hipSuccess) {
+            (void)hipGetLastError();
+            g_ws.ptr[dev] = nullptr;
+            return nullptr;
+        }
+        g_ws.bytes[dev] = nb;
+    }
+    return g_ws.ptr[dev];
+}
+
+template <typename T, int OPA, int TI, int TJ, int BKT>
+void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *A, int64_t lda,
+            const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s) {
+    constexpr int BM = 32 * TI, BN = 32 * TJ;
+    int64_t kchunk = k;
+    cpx<T> *W = nullptr;
+    if (S > 1) {
+        kchunk = ((k + S - 1) / S + BKT - 1) / BKT * BKT;
+        S = (int)((k + kchunk - 1) / kchunk);
+        W = (cpx<T> *)splitk_ws((size_t)S * m * n * sizeof(cpx<T>), s);
+        if (!W) { S = 1; kchunk = k; }
+    }
+    dim3 grid((unsigned)((m + BM - 1) / BM), (unsigned)((n + BN - 1) / BN), (unsigned)S);
+    hipLaunchKernelGGL((k_zgemm<T, OPA, TI, TJ, BKT>), grid, dim3(256), 0, s, m, n, k, kchunk,
+                       alpha, A, lda, B, ldb, beta, C, ldc, S > 1 ? W : nullptr);
+    if (S > 1) {
+        int64_t t = m * n;
+        hipLaunchKernelGGL(k_splitk_reduce<T>, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s,
+                           m, n, S, (const cpx<T> *)W, alpha, beta, C, ldc);
+    }
+}
+}  // namespace
+
+template <typename T>
+void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A, int64_t lda,
+          const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || n <= 0) return;
+    ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
+                   8.0 * (double)m * (double)n * (double)std::max<int64_t>(k, 0), s);
+    // 64 x 64 tiles at two wavefronts per SIMD measured fastest on gfx950 for every shape
+    // of the solver; K is split when the output has too few tiles to fill 256 CUs
+    const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
+    int S = 1;
+    if (tiles < 192 && k >= 4096) {
+        S = (int)std::min<int64_t>((512 + tiles - 1) / tiles, k / 512);
+        S = std::max(1, std::min(S, 64));
+    }
+    if (op == GEMM_C) launch<T, 1, 2, 2, 16>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    else if (op == GEMM_R) launch<T, 2, 2, 2, 16>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    else launch<T, 0, 2, 2, 16>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
+}
+
+template void gemm<double>(int, int64_t, int64_t, int64_t, zd, const zd *, int64_t,
                            const zd *, int64_t, zd, zd *, int64_t, hipStream_t);
-template void gemm<float>(bool, int64_t, int64_t, int64_t, zf, const zf *, int64_t,
+template void gemm<float>(int, int64_t, int64_t, int64_t, zf, const zf *, int64_t,
                           const zf *, int64_t, zf, zf *, int64_t, hipStream_t);
 
 }  // namespace cfie

@@ -185,3 +185,19 @@ def test_state_machine_and_errors(cfg1):
     with pytest.raises(P.CfieError) as e:
         s2.assemble(w.zhat, 64, 3.0)
     assert e.value.status == 2
+
+
+def test_skeleton_approximates_remainder(cfg1):
+    """U V^T approximates C - C_c to the compression tolerance (Sec. V eq. (7))."""
+    w, _ = cfg1
+    eps = 1e-6
+    s = P.Solver(compress_tol=eps)
+    s.assemble(w.zhat, w.n_nodes, w.k).factor()
+    info = s.info()
+    assert 0 < info["rank"] < w.n_nodes
+    x = torch.randn((6, w.n_nodes), dtype=torch.complex128, device="cuda")
+    d = s.apply(P.OP_REMAINDER, x) - s.apply(P.OP_SKELETON, x)
+    ratio = float((d.abs().pow(2).sum(1).sqrt() / x.abs().pow(2).sum(1).sqrt()).max())
+    tau = eps * info["cc_norm"]
+    print(f"skeleton: rank {info['rank']} ||(R - UV^T) x|| / ||x|| = {ratio:.2e}, tau {tau:.2e}")
+    assert ratio <= 10 * tau
