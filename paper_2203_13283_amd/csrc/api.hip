@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -149,6 +150,9 @@ struct cfie_ctx {
     int cap = 0;
     void *Q = nullptr, *Ut = nullptr;                  // N x cap (zd or zf)
     void *P = nullptr;                                  // V^T = Q^H (C - C_c): rank x N
+    void *Wf = nullptr;                                 // K^{-1} V^T: rank x N
+    void *ws[4] = {nullptr, nullptr, nullptr, nullptr}; // grow-only solve workspaces
+    size_t ws_bytes[4] = {0, 0, 0, 0};
     zd *K = nullptr;                                    // cap x cap
     int *piv = nullptr, *info = nullptr;
     zd *Linv = nullptr, *Uinv = nullptr;                // diagonal block inverses
@@ -188,6 +192,18 @@ struct cfie_ctx {
         }
     }
     template <typename T> T *alloc_n(size_t n) { return (T *)dalloc(n * sizeof(T)); }
+    // grow-only scratch that survives between calls (solve batches of the same size reuse it)
+    template <typename T> T *scratch(int slot, size_t n) {
+        size_t need = n * sizeof(T);
+        if (ws_bytes[slot] < need) {
+            dfree(ws[slot]);
+            ws[slot] = nullptr;
+            ws_bytes[slot] = 0;
+            ws[slot] = dalloc(need);
+            ws_bytes[slot] = need;
+        }
+        return (T *)ws[slot];
+    }
     template <typename T> void upload(T *d, const T *h, size_t n) {
         HIPCHK(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, stream));
     }
@@ -245,11 +261,11 @@ template <typename F> cfie_status guarded(cfie_ctx *c, F &&f) {
 }
 
 void free_factor(cfie_ctx *c) {
-    void *bufs[] = {c->Q, c->P, c->Ut, c->K, c->piv, c->info, c->Linv, c->Uinv, c->w_om,
+    void *bufs[] = {c->Q, c->P, c->Wf, c->Ut, c->K, c->piv, c->info, c->Linv, c->Uinv, c->w_om,
                     c->w_y, c->w_t, c->w_w1, c->w_w2, c->w_z, c->w_s, c->w_rinvT, c->w_gram,
                     c->w_rinv, c->w_norm, c->w_y64};
     for (void *p : bufs) c->dfree(p);
-    c->Q = c->P = c->Ut = nullptr;
+    c->Q = c->P = c->Ut = c->Wf = nullptr;
     c->K = nullptr;
     c->piv = c->info = nullptr;
     c->Linv = c->Uinv = nullptr;
@@ -602,32 +618,40 @@ cfie_status factor_impl(cfie_ctx *c) {
     c->sync();
     c->dfree(tmp);
     if (info) return fail(c, CFIE_ESINGULAR, "zero pivot in the capacitance matrix");
+    // K^{-1} V^T (ell x N) by the complex128 LU factors, once per factorisation, so that a
+    // solve is C_c^{-1} by FFT and two GEMMs
+    {
+        zd *W64 = c->alloc_n<zd>((size_t)ell * N);
+        zd *tmpN = c->alloc_n<zd>((size_t)kLUBlock * N);
+        convert<double, T>(ell, N, P, ell, W64, ell, s);
+        lu_solve(c, W64, ell, N, tmpN);
+        if (sizeof(T) == sizeof(double)) {
+            c->Wf = W64;
+        } else {
+            c->Wf = c->alloc_n<cpx<T>>((size_t)ell * N);
+            convert<T, double>(ell, N, W64, ell, (cpx<T> *)c->Wf, ell, s);
+            c->sync();
+            c->dfree(W64);
+        }
+        c->sync();
+        c->dfree(tmpN);
+    }
     c->state = 2;
     return CFIE_OK;
 }
 
-// X <- C^{-1} X in precision T (X is N x m in T, ld N); Zbuf: rank x m (zd), tmp
+// X <- C^{-1} X in precision T (X is N x m in T, ld N) by eq. (9):
+// X = C_c^{-1} X - U~ (K^{-1} V^T) C_c^{-1} X, with U~ = C_c^{-1} U; Z: rank x m scratch
 template <typename T>
-void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, zd *Zd, cpx<T> *ZT, zd *tmp) {
+void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, cpx<T> *Z) {
     const int N = c->N;
     hipStream_t s = c->stream;
     launch_circ_apply<T>(c->fft, Ops<T>::dCinv(c), X, N, m, s);
     const int r = c->rank;
     if (r == 0) return;
-    cpx<T> *P = (cpx<T> *)c->P, *Ut = (cpx<T> *)c->Ut;
-    if (sizeof(T) == sizeof(double)) {
-        gemm<double>(GEMM_N, r, m, N, cz<double>(1), (const zd *)P, r, (const zd *)X, N,
-                     cz<double>(0), Zd, r, s);
-        lu_solve(c, Zd, r, m, tmp);
-        gemm<double>(GEMM_N, N, m, r, cz<double>(-1), (const zd *)Ut, N, Zd, r, cz<double>(1),
-                     (zd *)X, N, s);
-    } else {
-        gemm<T>(GEMM_N, r, m, N, cz<T>(1), P, r, X, N, cz<T>(0), ZT, r, s);
-        convert<double, T>(r, m, ZT, r, Zd, r, s);
-        lu_solve(c, Zd, r, m, tmp);
-        convert<T, double>(r, m, Zd, r, ZT, r, s);
-        gemm<T>(GEMM_N, N, m, r, cz<T>(-1), Ut, N, ZT, r, cz<T>(1), X, N, s);
-    }
+    const cpx<T> *Wf = (const cpx<T> *)c->Wf, *Ut = (const cpx<T> *)c->Ut;
+    gemm<T>(GEMM_N, r, m, N, cz<T>(1), Wf, r, X, N, cz<T>(0), Z, r, s);
+    gemm<T>(GEMM_N, N, m, r, cz<T>(-1), Ut, N, Z, r, cz<T>(1), X, N, s);
     c->check_launch();
 }
 
@@ -637,19 +661,19 @@ cfie_status solve_fp64(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx
     const int64_t chunk = 4096;
     int r = std::max(c->rank, 1);
     int64_t mc = std::min<int64_t>(nrhs, chunk);
-    zd *work = c->alloc_n<zd>((size_t)N * mc);
-    zd *Zd = c->alloc_n<zd>((size_t)r * mc);
-    zd *tmp = c->alloc_n<zd>((size_t)kLUBlock * mc);
+    // operate in place in X when it is packed (ld = N), else through a packed workspace
+    const bool direct = (ldx == N);
+    zd *work = direct ? nullptr : c->scratch<zd>(0, (size_t)N * mc);
+    zd *Zd = c->scratch<zd>(1, (size_t)r * mc);
     for (int64_t j = 0; j < nrhs; j += chunk) {
         int64_t m = std::min(chunk, nrhs - j);
-        axpby<double>(N, m, cz<double>(1), B + j * ldb, ldb, cz<double>(0), work, N, s);
-        woodbury<double>(c, work, m, Zd, nullptr, tmp);
-        axpby<double>(N, m, cz<double>(1), work, N, cz<double>(0), X + j * ldx, ldx, s);
+        zd *Xj = direct ? X + j * ldx : work;
+        if (!(direct && B == X))
+            axpby<double>(N, m, cz<double>(1), B + j * ldb, ldb, cz<double>(0), Xj, N, s);
+        woodbury<double>(c, Xj, m, Zd);
+        if (!direct) axpby<double>(N, m, cz<double>(1), work, N, cz<double>(0), X + j * ldx, ldx, s);
     }
     c->sync();
-    c->dfree(work);
-    c->dfree(Zd);
-    c->dfree(tmp);
     return CFIE_OK;
 }
 
@@ -683,7 +707,7 @@ cfie_status solve_mixed(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ld
         double rel = 1e300;
         for (; sweep < std::max(1, c->opt.max_refine); ++sweep) {
             convert<float, double>(N, m, Rb, N, R32, N, s);
-            woodbury<float>(c, R32, m, Zd, Z32, tmp);
+            woodbury<float>(c, R32, m, Z32);
             convert<double, float>(N, m, R32, N, Tt, N, s);
             axpby<double>(N, m, cz<double>(1), Tt, N, cz<double>(1), Xw, N, s);
             // residual in FP64 against the assembled operator
@@ -832,7 +856,19 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         // quadrature tables
         gauss_legendre01(c->opt.quad_far, c->xf, c->wf);
         gauss_legendre01(c->opt.quad_near, c->xn, c->wn);
-        log_moments(c->opt.quad_near, c->moments);
+        {
+            // the moments depend on the rule only: computed once per process and rule
+            static std::mutex mu;
+            static std::map<int, std::vector<double>> cache;
+            std::lock_guard<std::mutex> lock(mu);
+            auto it = cache.find(c->opt.quad_near);
+            if (it == cache.end()) {
+                std::vector<double> mom;
+                log_moments(c->opt.quad_near, mom);
+                it = cache.emplace(c->opt.quad_near, std::move(mom)).first;
+            }
+            c->moments = it->second;
+        }
         c->d_xf = c->alloc_n<double>(c->xf.size()); c->upload(c->d_xf, c->xf.data(), c->xf.size());
         c->d_wf = c->alloc_n<double>(c->wf.size()); c->upload(c->d_wf, c->wf.data(), c->wf.size());
         c->d_xn = c->alloc_n<double>(c->xn.size()); c->upload(c->d_xn, c->xn.data(), c->xn.size());
