@@ -138,8 +138,6 @@ struct cfie_ctx {
     // matrices
     zd *mat[4] = {nullptr, nullptr, nullptr, nullptr};   // Dk, Nk, Dkt, Skt
     zf *mat32[4] = {nullptr, nullptr, nullptr, nullptr};
-    zd *matT[2] = {nullptr, nullptr};                    // Dk^T, Dkt^T
-    zf *matT32[2] = {nullptr, nullptr};
     zd *crow = nullptr, *mu = nullptr, *cvals = nullptr;
     zd *dC = nullptr, *dCH = nullptr, *dCinv = nullptr;
     zf *fC = nullptr, *fCH = nullptr, *fCinv = nullptr;
@@ -344,14 +342,12 @@ template <typename T> cpx<T> cz(double a, double b = 0.0) { return mk((T)a, (T)b
 template <typename T> struct Ops;
 template <> struct Ops<double> {
     static zd *mat(cfie_ctx *c, int i) { return c->mat[i]; }
-    static zd *matT(cfie_ctx *c, int i) { return c->matT[i]; }
     static const zd *dC(cfie_ctx *c) { return c->dC; }
     static const zd *dCH(cfie_ctx *c) { return c->dCH; }
     static const zd *dCinv(cfie_ctx *c) { return c->dCinv; }
 };
 template <> struct Ops<float> {
     static zf *mat(cfie_ctx *c, int i) { return c->mat32[i]; }
-    static zf *matT(cfie_ctx *c, int i) { return c->matT32[i]; }
     static const zf *dC(cfie_ctx *c) { return c->fC; }
     static const zf *dCH(cfie_ctx *c) { return c->fCH; }
     static const zf *dCinv(cfie_ctx *c) { return c->fCinv; }
@@ -391,8 +387,6 @@ void apply_R(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, 
 
 // Y = (C - C_c)^H X = (G/2 - Dk^H) V1 + Nk^H V2 - C_c^H X,
 // V1 = X/2 + G^{-1} Dkt^H X, V2 = G^{-1} Skt^H X.
-// Every product is a non-transposed GEMM: Skt and Nk are symmetric (reciprocity of the
-// bilinear forms), so their adjoints are their conjugates; Dk and Dkt are kept transposed.
 template <typename T>
 void apply_RH(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
               cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z) {
@@ -400,14 +394,14 @@ void apply_RH(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy,
     const double h = c->hg.L / N;
     hipStream_t s = c->stream;
     const int nt = (int)c->gcoef.size();
-    gemm<T>(GEMM_R, N, m, N, cz<T>(1), Ops<T>::matT(c, 1), N, X, ldx, cz<T>(0), Tt, N, s);
+    gemm<T>(GEMM_C, N, m, N, cz<T>(1), Ops<T>::mat(c, 2), N, X, ldx, cz<T>(0), Tt, N, s);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0.5), X, ldx, cz<T>(1), Tt, N, W1, N, m, s);
-    gemm<T>(GEMM_R, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, X, ldx, cz<T>(0), Tt, N, s);
+    gemm<T>(GEMM_C, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, X, ldx, cz<T>(0), Tt, N, s);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(1),
                       Tt, N, W2, N, m, s);
     launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), W1, N, Y, ldy, m, s);
-    gemm<T>(GEMM_R, N, m, N, cz<T>(-1), Ops<T>::matT(c, 0), N, W1, N, cz<T>(1), Y, ldy, s);
-    gemm<T>(GEMM_R, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, W2, N, cz<T>(1), Y, ldy, s);
+    gemm<T>(GEMM_C, N, m, N, cz<T>(-1), Ops<T>::mat(c, 0), N, W1, N, cz<T>(1), Y, ldy, s);
+    gemm<T>(GEMM_C, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, W2, N, cz<T>(1), Y, ldy, s);
     axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, s);
     launch_circ_apply<T>(c->fft, Ops<T>::dCH(c), Z, N, m, s);
     axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, s);
@@ -833,7 +827,6 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         // release everything of a previous problem
         free_factor(c);
         for (int i = 0; i < 4; ++i) { c->dfree(c->mat[i]); c->mat[i] = nullptr; c->dfree(c->mat32[i]); c->mat32[i] = nullptr; }
-        for (int i = 0; i < 2; ++i) { c->dfree(c->matT[i]); c->matT[i] = nullptr; c->dfree(c->matT32[i]); c->matT32[i] = nullptr; }
         free_points(c, c->pf); free_points(c, c->pn); free_points(c, c->cf); free_points(c, c->cn);
         void *old[] = {c->crow, c->mu, c->cvals, c->dC, c->dCH, c->dCinv, c->fC, c->fCH, c->fCinv,
                        c->absc, c->scal, c->d_xf, c->d_wf, c->d_xn, c->d_wn, c->d_mom, c->d_gcoef};
@@ -929,19 +922,10 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         launch_maxmin(N, c->absc, c->scal, s);
         double mm[2];
         HIPCHK(hipMemcpyAsync(mm, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        // transposes of the two double-layer matrices for the adjoint sketch
-        for (int i = 0; i < 2; ++i) {
-            c->matT[i] = c->alloc_n<zd>(nn);
-            conj_transpose<double>(false, N, N, c->mat[2 * i], N, c->matT[i], N, s);
-        }
         if (c->opt.precision == CFIE_MIXED) {
             for (int i = 0; i < 4; ++i) {
                 c->mat32[i] = c->alloc_n<zf>(nn);
                 convert<float, double>(N, N, c->mat[i], N, c->mat32[i], N, s);
-            }
-            for (int i = 0; i < 2; ++i) {
-                c->matT32[i] = c->alloc_n<zf>(nn);
-                convert<float, double>(N, N, c->matT[i], N, c->matT32[i], N, s);
             }
         }
         HIPCHK(hipEventRecord(e1, s));

@@ -95,7 +95,6 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
             cpx<T> v = mk((T)0, (T)0);
             if (gi < m && gk < kend) {
                 v = CONJA ? A[gk + gi * lda] : A[gi + gk * lda];
-                if (OPA != 0) v.y = -v.y;
             }
             ra[r] = v;
         }
@@ -150,13 +149,17 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
             }
 #pragma unroll
             for (int a = 0; a < TI; ++a) {
+                // conj(A) (op A^H and op conj(A)) flips the sign of the Ai products; the sign
+                // is applied here rather than on the loaded values (measured faster)
                 T nai = -ai[a];
+                T s_r = OPA != 0 ? ai[a] : nai;   // coefficient of Bi in the real part
+                T s_i = OPA != 0 ? nai : ai[a];   // coefficient of Br in the imaginary part
 #pragma unroll
                 for (int b = 0; b < TJ; ++b) {
                     accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
-                    accr[a][b] = mfma(nai, bi[b], accr[a][b]);
+                    accr[a][b] = mfma(s_r, bi[b], accr[a][b]);
                     acci[a][b] = mfma(ar[a], bi[b], acci[a][b]);
-                    acci[a][b] = mfma(ai[a], br[b], acci[a][b]);
+                    acci[a][b] = mfma(s_i, br[b], acci[a][b]);
                 }
             }
         }
