@@ -3,8 +3,11 @@
 // sketch of the remainder C - C_c (Sec. V eq. (7)), the capacitance matrix of eq. (9) and
 // the Woodbury correction, and the FP64 residual of the refinement.
 //
-// The complex product is four real products per k-step on split real/imaginary tiles held
-// in LDS: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br, with the 16x16x4 MFMA (f64 or f32).
+// The complex product runs on split real/imaginary tiles held in LDS with the 16x16x4 MFMA
+// (f64 or f32), either as four real products per k-step (Cr += Ar Br - Ai Bi,
+// Ci += Ar Bi + Ai Br) or as three (the 3M form: P1 = Ar Br, P2 = Ai Bi,
+// P3 = (Ar + Ai)(Br + Bi), Cr = P1 - P2, Ci = P3 - P1 - P2), which takes a quarter fewer
+// matrix-core operations for a normwise error of the same order.
 // Block tile BM x BN = 32 TI x 32 TJ with a K-slice of BKT, 256 threads = 4 wavefronts,
 // each wavefront a (BM/2) x (BN/2) sub-tile of TI x TJ MFMA tiles of 16 x 16.  Global loads
 // of the next K-slice are issued before the MFMAs of the current one.
@@ -13,6 +16,8 @@
 // split along K over blockIdx.z: each slice writes its partial product to a workspace and a
 // second kernel sums the slices in a fixed order (deterministic) and applies alpha, beta.
 #include "internal.h"
+
+#include <type_traits>
 
 namespace cfie {
 
@@ -40,7 +45,7 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <typename T, int OPA, int TI, int TJ, int BKT>
+template <typename T, int OPA, int TI, int TJ, int BKT, bool G3>
 __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdim,
                                                int64_t kchunk, cpx<T> alpha,
                                                const cpx<T> *__restrict__ A, int64_t lda,
@@ -71,41 +76,56 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
     const int64_t kend = min(kdim, kbeg + kchunk);
 
-    acc_t accr[TI][TJ], acci[TI][TJ];
+    // 4M: accr, acci are the real and imaginary parts; 3M: accr = P1, acci = P2, acc3 = P3
+    acc_t accr[TI][TJ], acci[TI][TJ], acc3[G3 ? TI : 1][G3 ? TJ : 1];
 #pragma unroll
     for (int a = 0; a < TI; ++a)
 #pragma unroll
         for (int b = 0; b < TJ; ++b) {
             accr[a][b] = acc_t{0, 0, 0, 0};
             acci[a][b] = acc_t{0, 0, 0, 0};
+            if constexpr (G3) acc3[a][b] = acc_t{0, 0, 0, 0};
         }
 
     constexpr int NA = BM * BKT / 256;
     constexpr int NB = BN * BKT / 256;
     cpx<T> ra[NA], rb[NB];
 
-    auto load_tiles = [&](int64_t k0) {
+    // Global loads of one K-slice into registers.  Rows of op(A) and columns of B beyond the
+    // matrix are clamped onto the last one: they only feed outputs that are never stored.
+    // Only the ragged last slice (CHECKK) zeroes what lies beyond kend.  The full slices
+    // run without control flow, which keeps the accumulators in the matrix-core registers.
+    auto load_tiles = [&](int64_t k0, auto checkk) {
+        constexpr bool CHECKK = decltype(checkk)::value;
 #pragma unroll
         for (int r = 0; r < NA; ++r) {
             int e = tid + 256 * r;
             int i, kk;
             if (!CONJA) { i = e % BM; kk = e / BM; }      // contiguous along rows
             else { kk = e % BKT; i = e / BKT; }            // contiguous along k
-            int64_t gi = row0 + i, gk = k0 + kk;
-            cpx<T> v = mk((T)0, (T)0);
-            if (gi < m && gk < kend) {
-                v = CONJA ? A[gk + gi * lda] : A[gi + gk * lda];
+            int64_t gi = min(row0 + i, m - 1), gk = k0 + kk;
+            if constexpr (CHECKK) {
+                const bool in = gk < kend;
+                gk = min(gk, kend - 1);
+                cpx<T> v = CONJA ? A[gk + gi * lda] : A[gi + gk * lda];
+                ra[r] = in ? v : mk((T)0, (T)0);
+            } else {
+                ra[r] = CONJA ? A[gk + gi * lda] : A[gi + gk * lda];
             }
-            ra[r] = v;
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
             int e = tid + 256 * r;
             int kk = e % BKT, j = e / BKT;
-            int64_t gj = col0 + j, gk = k0 + kk;
-            cpx<T> v = mk((T)0, (T)0);
-            if (gj < n && gk < kend) v = B[gk + gj * ldb];
-            rb[r] = v;
+            int64_t gj = min(col0 + j, n - 1), gk = k0 + kk;
+            if constexpr (CHECKK) {
+                const bool in = gk < kend;
+                gk = min(gk, kend - 1);
+                cpx<T> v = B[gk + gj * ldb];
+                rb[r] = in ? v : mk((T)0, (T)0);
+            } else {
+                rb[r] = B[gk + gj * ldb];
+            }
         }
     };
     auto store_tiles = [&]() {
@@ -126,13 +146,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
             Bs[1][bidx(kk, j)] = rb[r].y;
         }
     };
-
-    if (kbeg < kend) load_tiles(kbeg);
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BKT) {
-        __syncthreads();
-        store_tiles();
-        __syncthreads();
-        if (k0 + BKT < kend) load_tiles(k0 + BKT);
+    auto mma_slice = [&]() {
 #pragma unroll
         for (int k4 = 0; k4 < BKT; k4 += 4) {
             const int kk = k4 + (lane >> 4);
@@ -147,22 +161,68 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
                 br[b] = Bs[0][bidx(kk, wcol + b * 16 + (lane & 15))];
                 bi[b] = Bs[1][bidx(kk, wcol + b * 16 + (lane & 15))];
             }
+            if constexpr (G3) {
+                // conj(A) (op A^H and op conj(A)): P3 takes Ar - Ai and the signs of P2 flip
+                // in the epilogue, so no operand is negated
+                T sb[TJ];
 #pragma unroll
-            for (int a = 0; a < TI; ++a) {
-                // conj(A) (op A^H and op conj(A)) flips the sign of the Ai products; the sign
-                // is applied here rather than on the loaded values (measured faster)
-                T nai = -ai[a];
-                T s_r = OPA != 0 ? ai[a] : nai;   // coefficient of Bi in the real part
-                T s_i = OPA != 0 ? nai : ai[a];   // coefficient of Br in the imaginary part
+                for (int b = 0; b < TJ; ++b) sb[b] = br[b] + bi[b];
 #pragma unroll
-                for (int b = 0; b < TJ; ++b) {
-                    accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
-                    accr[a][b] = mfma(s_r, bi[b], accr[a][b]);
-                    acci[a][b] = mfma(ar[a], bi[b], acci[a][b]);
-                    acci[a][b] = mfma(s_i, br[b], acci[a][b]);
+                for (int a = 0; a < TI; ++a) {
+                    T sa = OPA != 0 ? ar[a] - ai[a] : ar[a] + ai[a];
+#pragma unroll
+                    for (int b = 0; b < TJ; ++b) {
+                        accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
+                        acci[a][b] = mfma(ai[a], bi[b], acci[a][b]);
+                        acc3[a][b] = mfma(sa, sb[b], acc3[a][b]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < TI; ++a) {
+                    // conj(A) flips the sign of the Ai products; the sign is applied here
+                    // rather than on the loaded values (measured faster)
+                    T nai = -ai[a];
+                    T s_r = OPA != 0 ? ai[a] : nai;   // coefficient of Bi in the real part
+                    T s_i = OPA != 0 ? nai : ai[a];   // coefficient of Br in the imaginary part
+#pragma unroll
+                    for (int b = 0; b < TJ; ++b) {
+                        accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
+                        accr[a][b] = mfma(s_r, bi[b], accr[a][b]);
+                        acci[a][b] = mfma(ar[a], bi[b], acci[a][b]);
+                        acci[a][b] = mfma(s_i, br[b], acci[a][b]);
+                    }
                 }
             }
         }
+    };
+
+    typedef std::integral_constant<bool, false> no_t;
+    typedef std::integral_constant<bool, true> yes_t;
+    const int64_t nfull = kend > kbeg ? (kend - kbeg) / BKT : 0;
+    const bool tail = kend > kbeg && (kend - kbeg) % BKT != 0;
+    if (nfull > 0) load_tiles(kbeg, no_t{});
+    for (int64_t s = 0; s + 1 < nfull; ++s) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        load_tiles(kbeg + (s + 1) * BKT, no_t{});
+        mma_slice();
+    }
+    if (nfull > 0) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        if (tail) load_tiles(kbeg + nfull * BKT, yes_t{});
+        mma_slice();
+    } else if (tail) {
+        load_tiles(kbeg, yes_t{});
+    }
+    if (tail) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        mma_slice();
     }
     const bool beta_zero = (beta.x == (T)0 && beta.y == (T)0);
     cpx<T> *Wz = W ? W + (int64_t)blockIdx.z * m * n : nullptr;
@@ -175,7 +235,13 @@ __global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdi
             for (int r = 0; r < 4; ++r) {
                 int64_t gi = row0 + wrow + a * 16 + acc_row<T>(lane, r);
                 if (gi < m && gj < n) {
-                    cpx<T> v = mk((T)accr[a][b][r], (T)acci[a][b][r]);
+                    cpx<T> v;
+                    if constexpr (G3) {
+                        T p1 = accr[a][b][r], p2 = acci[a][b][r], p3 = acc3[a][b][r];
+                        v = OPA != 0 ? mk(p1 + p2, p3 - p1 + p2) : mk(p1 - p2, p3 - p1 - p2);
+                    } else {
+                        v = mk((T)accr[a][b][r], (T)acci[a][b][r]);
+                    }
                     if (Wz) {
                         Wz[gi + gj * m] = v;                     // partial of this K-slice
                     } else {
@@ -232,7 +298,7 @@ void *splitk_ws(size_t need, hipStream_t s) {
     return g_ws.ptr[dev];
 }
 
-template <typename T, int OPA, int TI, int TJ, int BKT>
+template <typename T, int OPA, int TI, int TJ, int BKT, bool G3 = true>
 void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *A, int64_t lda,
             const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s) {
     constexpr int BM = 32 * TI, BN = 32 * TJ;
@@ -245,7 +311,7 @@ void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *
         if (!W) { S = 1; kchunk = k; }
     }
     dim3 grid((unsigned)((m + BM - 1) / BM), (unsigned)((n + BN - 1) / BN), (unsigned)S);
-    hipLaunchKernelGGL((k_zgemm<T, OPA, TI, TJ, BKT>), grid, dim3(256), 0, s, m, n, k, kchunk,
+    hipLaunchKernelGGL((k_zgemm<T, OPA, TI, TJ, BKT, G3>), grid, dim3(256), 0, s, m, n, k, kchunk,
                        alpha, A, lda, B, ldb, beta, C, ldc, S > 1 ? W : nullptr);
     if (S > 1) {
         int64_t t = m * n;
@@ -261,8 +327,8 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
     if (m <= 0 || n <= 0) return;
     ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
                    8.0 * (double)m * (double)n * (double)std::max<int64_t>(k, 0), s);
-    // 64 x 64 tiles at two wavefronts per SIMD measured fastest on gfx950 for every shape
-    // of the solver; K is split when the output has too few tiles to fill 256 CUs
+    // 64 x 64 tiles in the 3M form measured fastest on gfx950 for every shape of the
+    // solver; K is split when the output has too few tiles to fill 256 CUs
     const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
     int S = 1;
     if (tiles < 192 && k >= 4096) {
