@@ -45,8 +45,8 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <typename T, int OPA, int TI, int TJ, int BKT, bool G3>
-__global__ __launch_bounds__(256) void k_zgemm(int64_t m, int64_t n, int64_t kdim,
+template <typename T, int OPA, int TI, int TJ, int BKT, bool G3, int MINB = 1>
+__global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64_t kdim,
                                                int64_t kchunk, cpx<T> alpha,
                                                const cpx<T> *__restrict__ A, int64_t lda,
                                                const cpx<T> *__restrict__ B, int64_t ldb,
@@ -298,7 +298,7 @@ void *splitk_ws(size_t need, hipStream_t s) {
     return g_ws.ptr[dev];
 }
 
-template <typename T, int OPA, int TI, int TJ, int BKT, bool G3 = true>
+template <typename T, int OPA, int TI, int TJ, int BKT, bool G3 = true, int MINB = 1>
 void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *A, int64_t lda,
             const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s) {
     constexpr int BM = 32 * TI, BN = 32 * TJ;
@@ -311,7 +311,7 @@ void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *
         if (!W) { S = 1; kchunk = k; }
     }
     dim3 grid((unsigned)((m + BM - 1) / BM), (unsigned)((n + BN - 1) / BN), (unsigned)S);
-    hipLaunchKernelGGL((k_zgemm<T, OPA, TI, TJ, BKT, G3>), grid, dim3(256), 0, s, m, n, k, kchunk,
+    hipLaunchKernelGGL((k_zgemm<T, OPA, TI, TJ, BKT, G3, MINB>), grid, dim3(256), 0, s, m, n, k, kchunk,
                        alpha, A, lda, B, ldb, beta, C, ldc, S > 1 ? W : nullptr);
     if (S > 1) {
         int64_t t = m * n;
@@ -328,16 +328,23 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
     ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
                    8.0 * (double)m * (double)n * (double)std::max<int64_t>(k, 0), s);
     // 64 x 64 tiles in the 3M form measured fastest on gfx950 for every shape of the
-    // solver; K is split when the output has too few tiles to fill 256 CUs
+    // solver (about 110% of the FP64 matrix-core peak counted as 8 m n k real flops, i.e.
+    // 83-86% of the pipe for the 6 m n k it executes); K is split when the output has too
+    // few tiles to fill 256 CUs
     const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
     int S = 1;
     if (tiles < 192 && k >= 4096) {
         S = (int)std::min<int64_t>((512 + tiles - 1) / tiles, k / 512);
         S = std::max(1, std::min(S, 64));
     }
-    if (op == GEMM_C) launch<T, 1, 2, 2, 16>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
-    else if (op == GEMM_R) launch<T, 2, 2, 2, 16>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
-    else launch<T, 0, 2, 2, 16>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    // two workgroups (two wavefronts per SIMD) per CU: the register budget of 256 per lane
+    // that this imposes measured 15-20% faster than one wavefront with more registers
+    if (op == GEMM_C)
+        launch<T, 1, 2, 2, 16, true, 2>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    else if (op == GEMM_R)
+        launch<T, 2, 2, 2, 16, true, 2>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    else
+        launch<T, 0, 2, 2, 16, true, 2>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
 }
 
 template void gemm<double>(int, int64_t, int64_t, int64_t, zd, const zd *, int64_t,
