@@ -8,43 +8,82 @@
 // which leaves X[k2 + N2 k1] at position k1 + N1 k2.  The diagonal is stored in that
 // order, so the middle kernel does FFT_N1 -> multiply -> inverse FFT_N1 while the chunk is
 // in LDS, and the inverse of step A restores natural order.  Three passes over memory for
-// N > 4096, one for N <= 4096.  Radix-2 Stockham passes in LDS, twiddles from tables.
+// N > 4096, one for N <= 4096.  Radix-4 Stockham stages in LDS (one radix-2 stage for odd
+// powers of two), twiddles from tables, all index arithmetic by shifts and masks.
 #include "internal.h"
 
 namespace cfie {
 
-template <typename T>
-__device__ __forceinline__ void lds_fft(T *re, T *im, int n, const cpx<T> *__restrict__ tw,
-                                        bool inverse) {
-    const int T_ = blockDim.x;
-    const int half = n >> 1;
-    for (int Ns = 1; Ns < n; Ns <<= 1) {
-        // each thread: butterflies j = tid, tid + T, ...
-        constexpr int MAXB = 8;                  // n / 2 / blockDim <= 8 (n <= 4096, 256 thr)
-        cpx<T> b0[MAXB], b1[MAXB];
-        int nb = 0;
-        for (int j = threadIdx.x; j < half; j += T_) {
-            cpx<T> a0 = mk(re[j], im[j]);
-            cpx<T> a1 = mk(re[j + half], im[j + half]);
-            cpx<T> w = tw[(j & (Ns - 1)) * (n / (2 * Ns))];
+__device__ __forceinline__ int ilog2(int n) { return 31 - __clz(n); }
+
+// One Stockham stage of radix R (2 or 4) over the n points held in LDS (split re / im):
+// for butterfly j < n/R with k = j mod L, inputs x[j + r n/R] times w^{r k},
+// w = e^{-/+ 2 pi i / (R L)}, an R-point DFT, outputs at (j - k) R + k + s L.
+// Results go through registers (read all, barrier, write all, barrier).  256 threads.
+template <typename T, int R>
+__device__ __forceinline__ void lds_stage(T *re, T *im, int lgn, int lgL,
+                                          const cpx<T> *__restrict__ tw, bool inverse) {
+    constexpr int MAXB = 4096 / R / 256;         // butterflies per thread (n <= 4096, 256 thr)
+    const int n = 1 << lgn;
+    const int nq = n / R;
+    const int L = 1 << lgL;
+    const int twsh = lgn - lgL - (R == 4 ? 2 : 1);   // table step n / (R L)
+    cpx<T> y[MAXB][R];
+#pragma unroll
+    for (int nb = 0; nb < MAXB; ++nb) {
+        const int j = threadIdx.x + nb * 256;
+        if (j >= nq) break;
+        const int k = j & (L - 1);
+        cpx<T> a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = mk(re[j + r * nq], im[j + r * nq]);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            cpx<T> w = tw[(r * k) << twsh];
             if (inverse) w.y = -w.y;
-            a1 = a1 * w;
-            b0[nb] = a0 + a1;
-            b1[nb] = a0 - a1;
-            ++nb;
+            a[r] = a[r] * w;
         }
-        __syncthreads();
-        nb = 0;
-        for (int j = threadIdx.x; j < half; j += T_) {
-            int idx = (j / Ns) * 2 * Ns + (j & (Ns - 1));
-            re[idx] = b0[nb].x;
-            im[idx] = b0[nb].y;
-            re[idx + Ns] = b1[nb].x;
-            im[idx + Ns] = b1[nb].y;
-            ++nb;
+        if constexpr (R == 2) {
+            y[nb][0] = a[0] + a[1];
+            y[nb][1] = a[0] - a[1];
+        } else {
+            // 4-point DFT; forward uses -i, inverse +i
+            cpx<T> s02 = a[0] + a[2], d02 = a[0] - a[2];
+            cpx<T> s13 = a[1] + a[3], d13 = a[1] - a[3];
+            cpx<T> jd13 = inverse ? mk(-d13.y, d13.x) : mk(d13.y, -d13.x);   // -/+ i d13
+            y[nb][0] = s02 + s13;
+            y[nb][1] = d02 + jd13;
+            y[nb][2] = s02 - s13;
+            y[nb][3] = d02 - jd13;
         }
-        __syncthreads();
     }
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < MAXB; ++nb) {
+        const int j = threadIdx.x + nb * 256;
+        if (j >= nq) break;
+        const int k = j & (L - 1);
+        const int base = ((j >> lgL) << (lgL + (R == 4 ? 2 : 1))) + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            re[base + r * L] = y[nb][r].x;
+            im[base + r * L] = y[nb][r].y;
+        }
+    }
+    __syncthreads();
+}
+
+// In-place FFT of n = 2^lgn points in LDS: one radix-2 stage when lgn is odd, then radix-4
+// stages.  tw: e^{-2 pi i j / n}, j < n.  No scaling.
+template <typename T>
+__device__ __forceinline__ void lds_fft(T *re, T *im, int lgn, const cpx<T> *__restrict__ tw,
+                                        bool inverse) {
+    int lgL = 0;
+    if (lgn & 1) {
+        lds_stage<T, 2>(re, im, lgn, 0, tw, inverse);
+        lgL = 1;
+    }
+    for (; lgL < lgn; lgL += 2) lds_stage<T, 4>(re, im, lgn, lgL, tw, inverse);
 }
 
 // middle step: chunk k2 = blockIdx.x of column blockIdx.y
@@ -64,46 +103,70 @@ __global__ __launch_bounds__(256) void k_fft_mid(int N1, const cpx<T> *__restric
         im[i] = v.y;
     }
     __syncthreads();
-    lds_fft(re, im, N1, tw1, false);
+    const int lg = ilog2(N1);
+    lds_fft(re, im, lg, tw1, false);
     for (int i = threadIdx.x; i < N1; i += blockDim.x) {
         cpx<T> v = mk(re[i], im[i]) * dc[i];
         re[i] = v.x;
         im[i] = v.y;
     }
     __syncthreads();
-    lds_fft(re, im, N1, tw1, true);
+    lds_fft(re, im, lg, tw1, true);
     for (int i = threadIdx.x; i < N1; i += blockDim.x) col[i] = mk(re[i], im[i]);
 }
 
-// step A (forward or inverse) for one (n1, column) per thread
-template <typename T>
-__global__ void k_fft_stepA(int N1, int N2, const cpx<T> *__restrict__ twN, cpx<T> *x,
-                            int64_t ldx, int64_t ncol, bool inverse) {
+// step A (forward or inverse) for one (n1, column) per thread; N1, N2 powers of two.
+// N2 is a template parameter so the per-thread vectors stay in registers.
+template <typename T, int N2>
+__global__ __launch_bounds__(256) void k_fft_stepA(int N1, const cpx<T> *__restrict__ twN,
+                                                   cpx<T> *x, int64_t ldx, int64_t ncol,
+                                                   bool inverse) {
     int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= (int64_t)N1 * ncol) return;
-    const int N = N1 * N2;
-    int n1 = (int)(tid % N1);
-    int64_t c = tid / N1;
+    const int lg1 = ilog2(N1);
+    const int mN = N1 * N2 - 1;
+    const int n1 = (int)(tid & (N1 - 1));
+    const int64_t c = tid >> lg1;
     cpx<T> *col = x + c * ldx;
-    constexpr int MAXN2 = 16;
-    cpx<T> v[MAXN2], o[MAXN2];
+    cpx<T> v[N2], o[N2];
+#pragma unroll
     for (int a = 0; a < N2; ++a) v[a] = col[n1 + (int64_t)N1 * a];
     if (!inverse) {
+#pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
-            cpx<T> s = mk((T)0, (T)0);
-            for (int n2 = 0; n2 < N2; ++n2) s = s + v[n2] * twN[(int64_t)((n2 * k2) % N2) * N1];
-            o[k2] = s * twN[((int64_t)n1 * k2) % N];
+            cpx<T> s = v[0];
+#pragma unroll
+            for (int n2 = 1; n2 < N2; ++n2) s = s + v[n2] * twN[((n2 * k2) & (N2 - 1)) << lg1];
+            o[k2] = s * twN[(n1 * k2) & mN];
         }
     } else {
-        for (int k2 = 0; k2 < N2; ++k2) v[k2] = v[k2] * conj(twN[((int64_t)n1 * k2) % N]);
+#pragma unroll
+        for (int k2 = 1; k2 < N2; ++k2) v[k2] = v[k2] * conj(twN[(n1 * k2) & mN]);
+#pragma unroll
         for (int n2 = 0; n2 < N2; ++n2) {
-            cpx<T> s = mk((T)0, (T)0);
-            for (int k2 = 0; k2 < N2; ++k2)
-                s = s + v[k2] * conj(twN[(int64_t)((n2 * k2) % N2) * N1]);
+            cpx<T> s = v[0];
+#pragma unroll
+            for (int k2 = 1; k2 < N2; ++k2)
+                s = s + v[k2] * conj(twN[((n2 * k2) & (N2 - 1)) << lg1]);
             o[n2] = s;
         }
     }
+#pragma unroll
     for (int a = 0; a < N2; ++a) col[n1 + (int64_t)N1 * a] = o[a];
+}
+
+template <typename T>
+void launch_stepA(const FFTPlan &p, const cpx<T> *twN, cpx<T> *x, int64_t ldx, int64_t nb,
+                  bool inverse, hipStream_t s) {
+    const int bs = 256;
+    int64_t n = (int64_t)p.N1 * nb;
+    dim3 g((unsigned)((n + bs - 1) / bs));
+    switch (p.N2) {
+    case 2: hipLaunchKernelGGL((k_fft_stepA<T, 2>), g, dim3(bs), 0, s, p.N1, twN, x, ldx, nb, inverse); break;
+    case 4: hipLaunchKernelGGL((k_fft_stepA<T, 4>), g, dim3(bs), 0, s, p.N1, twN, x, ldx, nb, inverse); break;
+    case 8: hipLaunchKernelGGL((k_fft_stepA<T, 8>), g, dim3(bs), 0, s, p.N1, twN, x, ldx, nb, inverse); break;
+    default: hipLaunchKernelGGL((k_fft_stepA<T, 16>), g, dim3(bs), 0, s, p.N1, twN, x, ldx, nb, inverse); break;
+    }
 }
 
 template <typename T> const cpx<T> *tw1_of(const FFTPlan &p);
@@ -120,19 +183,11 @@ void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx
     const int bs = 256;
     // algorithmic work: bytes of one read and one write of the batch
     ProfScope prof(PROF_FFT, 2.0 * sizeof(cpx<T>) * (double)p.N * (double)nb, s);
-    if (p.N2 > 1) {
-        int64_t n = (int64_t)p.N1 * nb;
-        hipLaunchKernelGGL(k_fft_stepA<T>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s,
-                           p.N1, p.N2, twN_of<T>(p), x, ldx, nb, false);
-    }
+    if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), x, ldx, nb, false, s);
     size_t sh = 2 * sizeof(T) * (size_t)p.N1;
     hipLaunchKernelGGL(k_fft_mid<T>, dim3(p.N2, (unsigned)nb), dim3(bs), sh, s, p.N1,
                        tw1_of<T>(p), d, x, ldx);
-    if (p.N2 > 1) {
-        int64_t n = (int64_t)p.N1 * nb;
-        hipLaunchKernelGGL(k_fft_stepA<T>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s,
-                           p.N1, p.N2, twN_of<T>(p), x, ldx, nb, true);
-    }
+    if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), x, ldx, nb, true, s);
 }
 
 template void launch_circ_apply<double>(const FFTPlan &, const zd *, zd *, int64_t, int64_t,

@@ -135,6 +135,26 @@ def test_circle_remainder_vanishes():
     assert np.linalg.norm(X[:, 1] - jm) / np.linalg.norm(jm) < 2e-2
 
 
+@pytest.mark.parametrize("N", [8, 32, 512, 2048, 8192, 16384])
+def test_circulant_fft_lengths(N):
+    """C_c x and C_c^-1 x by the library's FFT path against numpy's FFT with the exported
+    eigenvalues, for odd and even powers of two, one pass (N <= 4096) and the four-step
+    split (N1 = 4096, N2 = 2, 4)."""
+    zh = W.ellipse_coeffs(1.0, 0.6)
+    L = S.Contour(zh).L
+    s = P.Solver(compress_tol=1e-10)
+    s.assemble(zh, N, 2 * np.pi * N / (10 * L))
+    c = _np(s.export_matrix(P.MAT_CC_EIG))[0]
+    g = torch.Generator(device="cuda").manual_seed(N)
+    x = torch.randn((3, N), dtype=torch.complex128, device="cuda", generator=g)
+    xn = _np(x)
+    for op, ref in ((P.OP_CC, np.fft.ifft(c * np.fft.fft(xn, axis=1), axis=1)),
+                    (P.OP_CC_INV, np.fft.ifft(np.fft.fft(xn, axis=1) / c, axis=1))):
+        y = _np(s.apply(op, x))
+        err = np.abs(y - ref).max() / np.abs(ref).max()
+        assert err <= 1e-13, (op, err)
+
+
 def test_mixed_precision_refinement(cfg1):
     w, prob = cfg1
     s = P.Solver(precision=P.CFIE_MIXED, compress_tol=1e-3, refine_tol=1e-8)
