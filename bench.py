@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--cpu-baseline", action=argparse.BooleanOptionalAction, default=True)
     ap.add_argument("--profile", action=argparse.BooleanOptionalAction, default=True,
                     help="HIP-event timing of every hot launch inside the library")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the steps, copy a MIB-mebibyte device buffer once (a kernel of "
+                         "known HBM traffic, the reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -128,6 +131,26 @@ def cpu_baseline(w):
             "sample_cpu_s": round(t4 - t0, 1)}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary, or None when
+    the summary is missing or was taken on a different version of the kernel's source."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", f"{kernel}_perturbed16384.md")
+    src = os.path.join(ROOT, "paper_2203_13283_amd", "csrc",
+                       {"zgemm_f64": "k_gemm.hip", "zgemm_f32": "k_gemm.hip"}.get(kernel, ""))
+    if not (os.path.exists(prof) and os.path.isfile(src)):
+        return None
+    vals = {}
+    for line in open(prof):
+        k, _, v = line.strip().partition(": ")
+        if k in ("traffic_bytes_per_launch", "source_sha256"):
+            vals[k] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -142,6 +165,12 @@ def main():
     import paper_2203_13283_amd as P
     prec = P.CFIE_FP64 if a.precision == "fp64" else P.CFIE_MIXED
     eps = a.eps if a.eps is not None else (1e-5 if prec == P.CFIE_FP64 else 1e-3)
+    if a.calibrate_copy > 0:
+        src = torch.ones(a.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(a.warmup):
         s, B, X, _t = step(P, w, prec, eps, False)
         del s, B, X
@@ -210,7 +239,11 @@ def main():
         scale = 1e-12 if unit == "TFLOP/s" else 1e-9
         achieved = d["work_per_launch"] * scale / (d["avg_launch_ms"] / 1e3)
         out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
-                           "unit": unit, "frac": achieved / peak, "traffic": None}
+                           "unit": unit, "frac": achieved / peak,
+                           "traffic": measured_traffic(dom)}
+        if dom.startswith("zgemm"):
+            # the 3M complex product executes 6 m n k of the 8 m n k counted above
+            out["roofline"]["mfma_pipe_frac"] = 0.75 * achieved / peak
     if a.compare:
         other = P.CFIE_MIXED if prec == P.CFIE_FP64 else P.CFIE_FP64
         eps_o = 1e-3 if other == P.CFIE_MIXED else 1e-5

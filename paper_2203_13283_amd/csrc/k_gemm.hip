@@ -13,7 +13,7 @@
 // of the next K-slice are issued before the MFMAs of the current one.
 //
 // Shapes with few output tiles and a long K (Gram matrices Y^H Y, projections Q^H Y) are
-// split along K over blockIdx.z: each slice writes its partial product to a workspace and a
+// split along K over slices of the grid: each writes its partial product to a workspace and a
 // second kernel sums the slices in a fixed order (deterministic) and applies alpha, beta.
 #include "internal.h"
 
@@ -71,9 +71,29 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
     const int wv = tid >> 6;
     const int wrow = (wv & 1) * (BM / 2);
     const int wcol = (wv >> 1) * (BN / 2);
-    const int64_t row0 = (int64_t)blockIdx.x * BM;
-    const int64_t col0 = (int64_t)blockIdx.y * BN;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    // Tile of this workgroup.  The grid is one-dimensional over (K-slice, tile).  Workgroups
+    // are dealt round-robin to the 8 XCDs (workgroup id mod 8), each with its own L2, so the
+    // id is first mapped to a logical index that gives every XCD a contiguous run; logical
+    // indices then walk groups of GROUP_M row panels column by column, so the workgroups
+    // resident on one XCD share both their A row panels and their B column panels in L2.
+    constexpr int NXCD = 8, GROUP_M = 8;
+    const int64_t tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+    const int64_t ntile = tiles_m * tiles_n;
+    const int64_t total = (int64_t)gridDim.x;
+    int64_t lg;
+    {
+        const int64_t g = blockIdx.x, x = g % NXCD, loc = g / NXCD;
+        const int64_t q = total / NXCD, r = total % NXCD;
+        lg = x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
+    }
+    const int64_t zslice = lg / ntile, t = lg % ntile;
+    const int64_t gsz = (int64_t)GROUP_M * tiles_n;
+    const int64_t fm = (t / gsz) * GROUP_M;
+    const int64_t gm = min((int64_t)GROUP_M, tiles_m - fm);
+    const int64_t tm = fm + (t % gsz) % gm, tn = (t % gsz) / gm;
+    const int64_t row0 = tm * BM;
+    const int64_t col0 = tn * BN;
+    const int64_t kbeg = zslice * kchunk;
     const int64_t kend = min(kdim, kbeg + kchunk);
 
     // 4M: accr, acci are the real and imaginary parts; 3M: accr = P1, acci = P2, acc3 = P3
@@ -225,7 +245,7 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
         mma_slice();
     }
     const bool beta_zero = (beta.x == (T)0 && beta.y == (T)0);
-    cpx<T> *Wz = W ? W + (int64_t)blockIdx.z * m * n : nullptr;
+    cpx<T> *Wz = W ? W + zslice * m * n : nullptr;
 #pragma unroll
     for (int a = 0; a < TI; ++a)
 #pragma unroll
@@ -310,7 +330,8 @@ void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *
         W = (cpx<T> *)splitk_ws((size_t)S * m * n * sizeof(cpx<T>), s);
         if (!W) { S = 1; kchunk = k; }
     }
-    dim3 grid((unsigned)((m + BM - 1) / BM), (unsigned)((n + BN - 1) / BN), (unsigned)S);
+    const int64_t ntile = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+    dim3 grid((unsigned)(ntile * S));
     hipLaunchKernelGGL((k_zgemm<T, OPA, TI, TJ, BKT, G3, MINB>), grid, dim3(256), 0, s, m, n, k, kchunk,
                        alpha, A, lda, B, ldb, beta, C, ldc, S > 1 ? W : nullptr);
     if (S > 1) {
