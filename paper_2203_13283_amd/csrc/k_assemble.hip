@@ -78,56 +78,100 @@ void launch_points(const GeomDev &g, const double *xi, PointTable &pt, hipStream
 }
 
 // ------------------------------------------------------------------ kernel values ---------
+// Large-argument Hankel expansion (DLMF 10.17.5): H_nu(z) = sqrt(2/(pi z)) e^{i(z - nu pi/2 -
+// pi/4)} F_nu(z), F_nu(z) = sum_n a_n(nu) (i/z)^n, a_n(nu) = prod_{j<=n} (4nu^2 - (2j-1)^2)/(8j).
+// Truncated after T terms: T = 8, 12, 22 keep the first omitted term below 3e-17 relative for
+// |z| >= 200, 50, 22.  For the real argument x = k R the even and odd terms give F = P + i Q
+// with P, Q polynomials in 1/x^2; for kt R the series is a complex Horner in w = i/(kt R).
+// The coefficients are compile-time constants.
+constexpr int kSerMax = 22;
+struct SerCoef {
+    double a[2][kSerMax];            // a_n(nu)
+    double p[2][kSerMax / 2];        // (-1)^j a_2j(nu)
+    double q[2][kSerMax / 2];        // (-1)^j a_2j+1(nu)
+};
+constexpr SerCoef make_ser() {
+    SerCoef c{};
+    for (int nu = 0; nu < 2; ++nu) {
+        double an = 1.0;
+        for (int n = 0; n < kSerMax; ++n) {
+            if (n > 0) {
+                double m = (double)(2 * n - 1);
+                an *= (4.0 * nu * nu - m * m) / (8.0 * n);
+            }
+            c.a[nu][n] = an;
+            double sg = ((n / 2) % 2) ? -1.0 : 1.0;
+            if (n % 2 == 0) c.p[nu][n / 2] = sg * an;
+            else c.q[nu][n / 2] = sg * an;
+        }
+    }
+    return c;
+}
+constexpr SerCoef kSer = make_ser();
+
 struct PairConsts {
-    double k, beta;                  // kt = k + i beta
-    zd kt;
+    double k, beta, invk;            // kt = k + i beta
+    zd kt, iwk;                      // iwk = i / kt
     zd Cg, CD, CS, CDt;              // prefactors of the large-argument forms
     zd ik4, ikt4;                    // i k / 4, i kt / 4
 };
 
+// Large-argument kernels (k R >= 22 for this lane) with a T-term series.
+template <int T>
+__device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R, double nu,
+                                                  zd &gk, zd &Dk, zd &St, zd &Dt) {
+    const double invR = 1.0 / R;
+    double sn, cs;
+    sincos(c.k * R, &sn, &cs);
+    const double rs = rsqrt(R);
+    const zd E = mk(cs * rs, sn * rs);                   // e^{ikR} R^{-1/2}
+    const zd Et = E * exp(-c.beta * R);
+    const double y = invR * c.invk, y2 = y * y;
+    double P0 = kSer.p[0][T / 2 - 1], Q0 = kSer.q[0][T / 2 - 1];
+    double P1 = kSer.p[1][T / 2 - 1], Q1 = kSer.q[1][T / 2 - 1];
+#pragma unroll
+    for (int j = T / 2 - 2; j >= 0; --j) {
+        P0 = fma(P0, y2, kSer.p[0][j]);
+        Q0 = fma(Q0, y2, kSer.q[0][j]);
+        P1 = fma(P1, y2, kSer.p[1][j]);
+        Q1 = fma(Q1, y2, kSer.q[1][j]);
+    }
+    const zd w = c.iwk * invR;                           // i / (kt R)
+    zd s0 = mk(kSer.a[0][T - 1], 0.0), s1 = mk(kSer.a[1][T - 1], 0.0);
+#pragma unroll
+    for (int n = T - 2; n >= 0; --n) {
+        s0 = mk(fma(s0.x, w.x, fma(-s0.y, w.y, kSer.a[0][n])), fma(s0.x, w.y, s0.y * w.x));
+        s1 = mk(fma(s1.x, w.x, fma(-s1.y, w.y, kSer.a[1][n])), fma(s1.x, w.y, s1.y * w.x));
+    }
+    gk = c.Cg * E * mk(P0, Q0 * y);
+    Dk = c.CD * E * mk(P1, Q1 * y) * nu;
+    St = c.CS * Et * s0;
+    Dt = c.CDt * Et * s1 * nu;
+}
+
+// Any argument: ascending series / Miller recurrence below k R = 22 (kept out of line so
+// that the register allocation of the far kernel's main loop is not sized for it).
+__device__ __attribute__((noinline)) void pair_kernels_small(const PairConsts &c, double R,
+                                                             double nu, zd &gk, zd &Dk,
+                                                             zd &St, zd &Dt) {
+    zd H0, H1;
+    hankel01(mk(c.k * R, 0.0), H0, H1);
+    gk = cmul_i(H0) * 0.25;
+    Dk = c.ik4 * H1 * nu;
+    hankel01(c.kt * R, H0, H1);
+    St = cmul_i(H0) * 0.25;
+    Dt = c.ikt4 * H1 * nu;
+}
+
 // Point-pair kernels: gk = (i/4) H0(kR), Dk = (ik/4) H1(kR) nu, St = (i/4) H0(ktR),
-// Dt = (ikt/4) H1(ktR) nu, with nu = (r - r').n' / R.
+// Dt = (ikt/4) H1(ktR) nu, with nu = (r - r').n' / R.  Per-thread choice of the form.
 __device__ __forceinline__ void pair_kernels(const PairConsts &c, double R, double nu,
                                              zd &gk, zd &Dk, zd &St, zd &Dt) {
-    double kR = c.k * R;
-    if (kR >= kAsymMin) {
-        double invR = 1.0 / R;
-        double sn, cs;
-        sincos(kR, &sn, &cs);
-        double rs = sqrt(invR);
-        zd E = mk(cs * rs, sn * rs);                    // e^{ikR} R^{-1/2}
-        zd Et = E * exp(-c.beta * R);
-        // real-argument series: w1 = i q1, q1 = 1 / (kR)
-        double q1 = invR / c.k;
-        zd w2 = cmul_i(cinv(c.kt)) * invR;              // i / (kt R)
-        zd t0 = mk(1.0, 0.0), t1 = t0, p0 = t0, p1 = t0;
-        zd u0 = t0, u1 = t0, s0 = t0, s1 = t0;
-        for (int n = 1; n < 64; ++n) {
-            double m = (double)(2 * n - 1);
-            double r0 = -m * m / (8.0 * n), r1 = (4.0 - m * m) / (8.0 * n);
-            t0 = mk(-t0.y, t0.x) * (r0 * q1);
-            t1 = mk(-t1.y, t1.x) * (r1 * q1);
-            u0 = u0 * w2 * r0;
-            u1 = u1 * w2 * r1;
-            p0 = p0 + t0;
-            p1 = p1 + t1;
-            s0 = s0 + u0;
-            s1 = s1 + u1;
-            if (abs2(t0) + abs2(t1) + abs2(u0) + abs2(u1) < 1e-34) break;
-        }
-        gk = c.Cg * E * p0;
-        Dk = c.CD * E * p1 * nu;
-        St = c.CS * Et * s0;
-        Dt = c.CDt * Et * s1 * nu;
-    } else {
-        zd H0, H1;
-        hankel01(mk(kR, 0.0), H0, H1);
-        gk = cmul_i(H0) * 0.25;
-        Dk = c.ik4 * H1 * nu;
-        hankel01(c.kt * R, H0, H1);
-        St = cmul_i(H0) * 0.25;
-        Dt = c.ikt4 * H1 * nu;
-    }
+    const double kR = c.k * R;
+    if (kR >= 200.0) pair_kernels_asym<8>(c, R, nu, gk, Dk, St, Dt);
+    else if (kR >= 50.0) pair_kernels_asym<12>(c, R, nu, gk, Dk, St, Dt);
+    else if (kR >= kAsymMin) pair_kernels_asym<kSerMax>(c, R, nu, gk, Dk, St, Dt);
+    else pair_kernels_small(c, R, nu, gk, Dk, St, Dt);
 }
 
 static PairConsts make_consts(const KernelConsts &kc) {
@@ -135,6 +179,8 @@ static PairConsts make_consts(const KernelConsts &kc) {
     c.k = kc.k;
     c.kt = kc.kt;
     c.beta = kc.kt.y;
+    c.invk = 1.0 / kc.k;
+    c.iwk = cmul_i(cinv(kc.kt));
     const double r2 = 0.70710678118654752440;
     zd em1 = mk(r2, -r2);                                // e^{-i pi/4}
     zd em3 = mk(-r2, -r2);                               // e^{-3 i pi/4}
@@ -158,14 +204,83 @@ struct QuadConsts {
     double xi[Q], w[Q];
 };
 
-template <int Q>
-__global__ __launch_bounds__(256) void k_far(int N, double h, PairConsts c, int nb, int r0,
-                                             int r1, int64_t ld, zd *o0, zd *o1, zd *o2,
-                                             zd *o3, const double *__restrict__ PX,
-                                             const double *__restrict__ PY,
-                                             const double *__restrict__ PTX,
-                                             const double *__restrict__ PTY, QuadConsts<Q> qc,
-                                             int n_row_tiles) {
+// 2x2 block of element pair (e, f) for the four matrices, accumulated point pair by point
+// pair: A_b[m][a] += K_m(g, hh) h^2 w_g w_hh phi_a(xi_g) phi_b(xi_hh) (b = 0 into acc0, the
+// node column f; b = 1 into acc1, the node column f + 1), and for N^k the Maue term
+// K (s_a s_b w_g w_hh - k^2 n.n' h^2 w_g w_hh phi_a phi_b) with s_a = +/-1 the sign of
+// phi_a'.  Lanes with on = false add nothing (their kernel is evaluated at a harmless
+// separation).  KERNEL(R, nu, gk, Dk, St, Dt) evaluates the point-pair kernels.
+template <int Q, typename KERNEL>
+__device__ __forceinline__ void far_block(const double *rp, int fe, bool on, double rsafe,
+                                          double h, double k2, const double *__restrict__ PX,
+                                          const double *__restrict__ PY,
+                                          const double *__restrict__ PTX,
+                                          const double *__restrict__ PTY,
+                                          const QuadConsts<Q> &qc, zd (&acc0)[4][2],
+                                          zd (&acc1)[4][2], KERNEL kern) {
+    // rp: this lane's row-element points in LDS, [4][Q] with stride 256 (x, y, tx, ty)
+    const double msk = on ? 1.0 : 0.0;
+#pragma unroll 1
+    for (int hh = 0; hh < Q; ++hh) {
+        const double xs = PX[fe * Q + hh], ys = PY[fe * Q + hh];
+        const double txs = PTX[fe * Q + hh], tys = PTY[fe * Q + hh];
+        const double xh = qc.xi[hh], wh = qc.w[hh];
+        const double wb0 = msk * h * wh * (1.0 - xh), wb1 = msk * h * wh * xh;
+#pragma unroll 1
+        for (int g = 0; g < Q; ++g) {
+            double dx = rp[(0 * Q + g) * 256] - xs, dy = rp[(1 * Q + g) * 256] - ys;
+            dx = on ? dx : rsafe;
+            dy = on ? dy : 0.0;
+            const double R = sqrt(dx * dx + dy * dy);
+            const double nu = (dx * tys - dy * txs) / R;
+            const double nn = rp[(3 * Q + g) * 256] * tys + rp[(2 * Q + g) * 256] * txs;
+            zd gk, Dk, St, Dt;
+            kern(R, nu, gk, Dk, St, Dt);
+            const double xg = qc.xi[g], wg = qc.w[g];
+            const double wa[2] = {h * wg * (1.0 - xg), h * wg * xg};
+            const double wgh = msk * wg * wh;
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa) {
+                const double w0 = wa[aa] * wb0, w1 = wa[aa] * wb1;
+                acc0[0][aa] = acc0[0][aa] + Dk * w0;
+                acc1[0][aa] = acc1[0][aa] + Dk * w1;
+                acc0[2][aa] = acc0[2][aa] + Dt * w0;
+                acc1[2][aa] = acc1[2][aa] + Dt * w1;
+                acc0[3][aa] = acc0[3][aa] + St * w0;
+                acc1[3][aa] = acc1[3][aa] + St * w1;
+                // s_a s_b: + for a == b
+                acc0[1][aa] = acc0[1][aa] + gk * ((aa == 0 ? wgh : -wgh) - k2 * nn * w0);
+                acc1[1][aa] = acc1[1][aa] + gk * ((aa == 1 ? wgh : -wgh) - k2 * nn * w1);
+            }
+        }
+    }
+}
+
+// Lower bound of k R over the Gauss point pairs of two elements whose reference points
+// (Gauss point Q/2, within arc length h of every Gauss point of its element) are dxr, dyr
+// apart.  Rounded operations only, so that both far passes take the same decision.
+__device__ __forceinline__ double far_kRmin(double k, double h, double dxr, double dyr) {
+    return __dmul_rn(k, __dsub_rn(__dsqrt_rn(__dadd_rn(__dmul_rn(dxr, dxr), __dmul_rn(dyr, dyr))),
+                                  __dmul_rn(2.0, h)));
+}
+constexpr double kFarFast = 200.0;    // k R above which the 8-term series is used
+
+// One wavefront: 63 output rows (lane l holds element i0 - 1 + l) and kFarCols node
+// columns, walking the element columns f.  Two passes over the same tiles:
+//   SLOW = false: element pairs whose k R >= kFarFast for every point pair (by far_kRmin)
+//                 with the 8-term large-argument series; writes every entry of the tile;
+//   SLOW = true : the remaining element pairs outside the near band (any argument, per
+//                 lane forms) added to the entries they touch.
+// Entry (i, j) is owned by one lane in each pass, so the sum is deterministic.
+template <int Q, bool SLOW>
+__global__ __launch_bounds__(256, SLOW ? 1 : 2) void k_far(int N, double h, PairConsts c,
+                                                           int nb, int r0, int r1, int64_t ld,
+                                                           zd *o0, zd *o1, zd *o2, zd *o3,
+                                                           const double *__restrict__ PX,
+                                                           const double *__restrict__ PY,
+                                                           const double *__restrict__ PTX,
+                                                           const double *__restrict__ PTY,
+                                                           QuadConsts<Q> qc, int n_row_tiles) {
     const int lane = threadIdx.x & 63;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int n_col_tiles = (N + kFarCols - 1) / kFarCols;
@@ -177,109 +292,78 @@ __global__ __launch_bounds__(256) void k_far(int N, double h, PairConsts c, int 
     const int jend = min(N, j0 + kFarCols);
     int e = i0 - 1 + lane;
     e = (e % N + N) % N;
-    double xo[Q], yo[Q], txo[Q], tyo[Q];
+    // the row element's Gauss points live in LDS (one column of 4 Q doubles per thread)
+    __shared__ double rows_lds[4 * Q * 256];
+    double *rp = rows_lds + threadIdx.x;
 #pragma unroll
     for (int g = 0; g < Q; ++g) {
-        xo[g] = PX[e * Q + g];
-        yo[g] = PY[e * Q + g];
-        txo[g] = PTX[e * Q + g];
-        tyo[g] = PTY[e * Q + g];
+        rp[(0 * Q + g) * 256] = PX[e * Q + g];
+        rp[(1 * Q + g) * 256] = PY[e * Q + g];
+        rp[(2 * Q + g) * 256] = PTX[e * Q + g];
+        rp[(3 * Q + g) * 256] = PTY[e * Q + g];
     }
-    double Wa[2][Q];                                  // h w_g phi_a(xi_g)
-#pragma unroll
-    for (int g = 0; g < Q; ++g) {
-        Wa[0][g] = h * qc.w[g] * (1.0 - qc.xi[g]);
-        Wa[1][g] = h * qc.w[g] * qc.xi[g];
-    }
+    const double xref = rp[(0 * Q + Q / 2) * 256], yref = rp[(1 * Q + Q / 2) * 256];
     const double k2 = c.k * c.k;
-    // carry[m][a]: contribution of element column f-1 (b = 1) to node column f
-    zd carry[4][2];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) carry[m][0] = carry[m][1] = mk(0.0, 0.0);
+    const double rsafe = 1000.0 * c.invk;             // k R = 1000 for lanes that add nothing
     const int out_row = i0 + lane;                    // row produced by this lane (a = 1 part)
     const bool row_ok = lane < 63 && out_row < r1 && out_row < N;
+    // acc0[m][a]: node column f (b = 0 of element f plus b = 1 of element f - 1);
+    // acc1[m][a]: node column f + 1 (b = 1 of element f)
+    zd acc0[4][2], acc1[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc0[m][0] = acc0[m][1] = acc1[m][0] = acc1[m][1] = mk(0.0, 0.0);
+    bool used_prev = false;                           // SLOW: this lane added at column f - 1
     for (int f = j0 - 1; f < jend; ++f) {
         int fe = (f % N + N) % N;
         int off = fe - e;
         off = ((off % N) + N) % N;
-        int dist = min(off, N - off);
-        zd B[4][2][2];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) B[m][a][0] = B[m][a][1] = mk(0.0, 0.0);
-        if (dist > nb) {
-            double xs[Q], ys[Q], txs[Q], tys[Q];
-#pragma unroll
-            for (int hh = 0; hh < Q; ++hh) {
-                xs[hh] = PX[fe * Q + hh];
-                ys[hh] = PY[fe * Q + hh];
-                txs[hh] = PTX[fe * Q + hh];
-                tys[hh] = PTY[fe * Q + hh];
+        const bool on = min(off, N - off) > nb;       // near-band pairs: near kernel
+        const double kRmin = far_kRmin(c.k, h, xref - PX[fe * Q + Q / 2],
+                                       yref - PY[fe * Q + Q / 2]);
+        const bool fast = kRmin >= kFarFast;
+        const bool use = on && (SLOW ? !fast : fast);
+        if (__any(use)) {
+            if constexpr (SLOW) {
+                auto KG = [&](double R, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
+                    pair_kernels(c, R, nu, g0, g1, g2, g3);
+                };
+                far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, KG);
+            } else {
+                auto K8 = [&](double R, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
+                    pair_kernels_asym<8>(c, R, nu, g0, g1, g2, g3);
+                };
+                far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K8);
             }
-            for (int g = 0; g < Q; ++g) {
-                zd TS[2], TD[2], TT[2], TN1[2], TN0;
-                TS[0] = TS[1] = TD[0] = TD[1] = TT[0] = TT[1] = TN1[0] = TN1[1] = TN0 =
-                    mk(0.0, 0.0);
-#pragma unroll
-                for (int hh = 0; hh < Q; ++hh) {
-                    double dx = xo[g] - xs[hh], dy = yo[g] - ys[hh];
-                    double R = sqrt(dx * dx + dy * dy);
-                    double nu = (dx * tys[hh] - dy * txs[hh]) / R;
-                    double nn = tyo[g] * tys[hh] + txo[g] * txs[hh];
-                    zd gk, Dk, St, Dt;
-                    pair_kernels(c, R, nu, gk, Dk, St, Dt);
-                    double wb0 = Wa[0][hh], wb1 = Wa[1][hh];
-                    TS[0] = TS[0] + St * wb0;
-                    TS[1] = TS[1] + St * wb1;
-                    TD[0] = TD[0] + Dk * wb0;
-                    TD[1] = TD[1] + Dk * wb1;
-                    TT[0] = TT[0] + Dt * wb0;
-                    TT[1] = TT[1] + Dt * wb1;
-                    TN0 = TN0 + gk * qc.w[hh];
-                    zd gn = gk * nn;
-                    TN1[0] = TN1[0] + gn * wb0;
-                    TN1[1] = TN1[1] + gn * wb1;
-                }
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    double wa = Wa[a][g];
-                    double sa = a ? 1.0 : -1.0;
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        double sb = b ? 1.0 : -1.0;
-                        B[0][a][b] = B[0][a][b] + TD[b] * wa;
-                        B[2][a][b] = B[2][a][b] + TT[b] * wa;
-                        B[3][a][b] = B[3][a][b] + TS[b] * wa;
-                        B[1][a][b] = B[1][a][b] + TN0 * (sa * sb * qc.w[g]) -
-                                     TN1[b] * (k2 * wa);
-                    }
-                }
-            }
-        }
-        // node column f: carry (b = 1 of column f-1) + b = 0 of column f
-        zd col[4][2];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            col[m][0] = carry[m][0] + B[m][0][0];
-            col[m][1] = carry[m][1] + B[m][1][0];
-            carry[m][0] = B[m][0][1];
-            carry[m][1] = B[m][1][1];
         }
         if (f >= j0) {
             int j = f;
             int dij = out_row - j;
             dij = ((dij % N) + N) % N;
             int dd = min(dij, N - dij);
+            // SLOW: the entry changes if any of its element pairs (e, f-1), (e, f),
+            // (e+1, f-1), (e+1, f) was added in this pass
+            const int mine = (use || used_prev) ? 1 : 0;
+            const bool touched = SLOW ? (mine | __shfl_down(mine, 1)) != 0 : true;
             zd *outs[4] = {o0, o1, o2, o3};
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 // row out_row = e + 1: own a = 1 part + a = 0 part of lane + 1
-                double nx = __shfl_down(col[m][0].x, 1);
-                double ny = __shfl_down(col[m][0].y, 1);
-                zd v = col[m][1] + mk(nx, ny);
-                if (row_ok && dd >= nb + 2) outs[m][(int64_t)out_row + (int64_t)j * ld] = v;
+                double nx = __shfl_down(acc0[m][0].x, 1);
+                double ny = __shfl_down(acc0[m][0].y, 1);
+                zd v = acc0[m][1] + mk(nx, ny);
+                if (row_ok && dd >= nb + 2 && touched) {
+                    zd *dst = outs[m] + (int64_t)out_row + (int64_t)j * ld;
+                    if (SLOW) v = v + *dst;
+                    *dst = v;
+                }
             }
+        }
+        used_prev = use;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            acc0[m][0] = acc1[m][0];
+            acc0[m][1] = acc1[m][1];
+            acc1[m][0] = acc1[m][1] = mk(0.0, 0.0);
         }
     }
 }
@@ -300,9 +384,12 @@ void launch_assemble_far(const AsmParams &p, const PointTable &far, const double
     case QQ: {                                                                             \
         QuadConsts<QQ> qc;                                                                 \
         for (int i = 0; i < QQ; ++i) { qc.xi[i] = xi[i]; qc.w[i] = w[i]; }                 \
-        hipLaunchKernelGGL(k_far<QQ>, dim3(blocks), dim3(256), 0, s, p.N, p.h, c, p.nb,    \
-                           p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2], p.out[3], far.x,  \
-                           far.y, far.tx, far.ty, qc, n_row_tiles);                        \
+        hipLaunchKernelGGL((k_far<QQ, false>), dim3(blocks), dim3(256), 0, s, p.N, p.h, c, \
+                           p.nb, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2], p.out[3],  \
+                           far.x, far.y, far.tx, far.ty, qc, n_row_tiles);                 \
+        hipLaunchKernelGGL((k_far<QQ, true>), dim3(blocks), dim3(256), 0, s, p.N, p.h, c,  \
+                           p.nb, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2], p.out[3],  \
+                           far.x, far.y, far.tx, far.ty, qc, n_row_tiles);                 \
         break;                                                                             \
     }
     switch (far.q) {
