@@ -54,7 +54,7 @@ void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int l
 void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s);
 void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out,
                       hipStream_t s);
-void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz,
+void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz, zd *M,
                   int *kout, hipStream_t s);
 template <typename T>
 void launch_polar_coef(int k, const zd *G, int ldg, cpx<T> *M, int ldm, hipStream_t s);
@@ -156,7 +156,7 @@ struct cfie_ctx {
     zd *Linv = nullptr, *Uinv = nullptr;                // diagonal block inverses
     void *w_om = nullptr, *w_y = nullptr, *w_t = nullptr, *w_w1 = nullptr, *w_w2 = nullptr,
          *w_z = nullptr, *w_s = nullptr, *w_rinvT = nullptr;
-    zd *w_gram = nullptr, *w_rinv = nullptr, *w_y64 = nullptr;
+    zd *w_gram = nullptr, *w_rinv = nullptr, *w_y64 = nullptr, *w_pchm = nullptr;
     double *w_norm = nullptr;
 
     ~cfie_ctx() {
@@ -261,14 +261,14 @@ template <typename F> cfie_status guarded(cfie_ctx *c, F &&f) {
 void free_factor(cfie_ctx *c) {
     void *bufs[] = {c->Q, c->P, c->Wf, c->Ut, c->K, c->piv, c->info, c->Linv, c->Uinv, c->w_om,
                     c->w_y, c->w_t, c->w_w1, c->w_w2, c->w_z, c->w_s, c->w_rinvT, c->w_gram,
-                    c->w_rinv, c->w_norm, c->w_y64};
+                    c->w_rinv, c->w_norm, c->w_y64, c->w_pchm};
     for (void *p : bufs) c->dfree(p);
     c->Q = c->P = c->Ut = c->Wf = nullptr;
     c->K = nullptr;
     c->piv = c->info = nullptr;
     c->Linv = c->Uinv = nullptr;
     c->w_om = c->w_y = c->w_t = c->w_w1 = c->w_w2 = c->w_z = c->w_s = c->w_rinvT = nullptr;
-    c->w_gram = c->w_rinv = c->w_y64 = nullptr;
+    c->w_gram = c->w_rinv = c->w_y64 = c->w_pchm = nullptr;
     c->w_norm = nullptr;
     c->rank = 0;
 }
@@ -434,7 +434,7 @@ int orthonormalise(cfie_ctx *c, cpx<T> *Y, int b, double tau) {
     cpx<T> *Y2 = (cpx<T> *)c->w_t;
     const double rel2 = sizeof(T) == sizeof(double) ? 1e-13 : 1e-6;
     gram64<T>(c, Y, b, c->w_gram);
-    launch_pchol(b, c->w_gram, b, tau * tau, rel2, c->w_rinv, b, c->info + 1, s);
+    launch_pchol(b, c->w_gram, b, tau * tau, rel2, c->w_rinv, b, c->w_pchm, c->info + 1, s);
     int k = 0;
     HIPCHK(hipMemcpyAsync(&k, c->info + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     c->sync();
@@ -475,6 +475,7 @@ void alloc_factor(cfie_ctx *c) {
     c->w_rinvT = c->alloc_n<cpx<T>>((size_t)b * b);
     c->w_gram = c->alloc_n<zd>((size_t)b * b);
     c->w_rinv = c->alloc_n<zd>((size_t)b * b);
+    c->w_pchm = c->alloc_n<zd>((size_t)b * b);
     c->w_norm = c->alloc_n<double>((size_t)std::max(b, 64));
     c->info = c->alloc_n<int>(4);
     if (sizeof(T) != sizeof(double)) c->w_y64 = c->alloc_n<zd>(nb);

@@ -465,10 +465,132 @@ __global__ void k_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, z
     }
     if (tid == 0) kout[0] = k;
 }
-void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz, int *kout,
-                  hipStream_t s) {
-    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(1024), 0, s, b, W, ldw, thr_abs, thr_rel, Z, ldz,
-                       kout);
+// Panel-blocked form of the same factorisation (b <= 512, one workgroup of 1024 threads).
+// No rows or columns are moved: with p_j the j-th pivot (largest remaining Schur-complement
+// diagonal d), the pivot row is r^(j)_c = (W_j[p_j, c]) / sqrt(d_p) where W_j is W minus the
+// rank-one terms of the earlier pivots, and the columns of Z are built alongside by
+// z_j = (e_p - sum_{i<j} z_i r^(i)_p) / sqrt(d_p) (Gram-Schmidt in the coefficients of Y), so
+// that Y z_j is the j-th orthonormal direction.  The earlier pivots' terms are applied to W
+// and to M = -sum z_i r^(i) in rank-NB updates at the end of each panel of NB pivots; within
+// a panel the pivot rows and z vectors of the panel are kept in LDS.  M: b x b workspace.
+constexpr int kPcholLds = 4096;                 // complex entries per panel store
+__global__ __launch_bounds__(1024) void k_pchol_panel(int b, zd *W, int ldw, double thr_abs,
+                                                      double thr_rel, zd *Z, int ldz, zd *M,
+                                                      int *kout) {
+    const int tid = threadIdx.x;
+    const int NB = b <= 256 ? 16 : 8;
+    __shared__ zd Rp[kPcholLds];                 // Rp[i * b + c]: pivot rows of the panel
+    __shared__ zd Zp[kPcholLds];                 // Zp[i * b + r]: z vectors of the panel
+    __shared__ double d[512];
+    __shared__ int taken[512];
+    __shared__ double wv[16];
+    __shared__ int wi[16];
+    __shared__ double thr;
+    // M = 0, diagonal, threshold from the largest diagonal
+    for (int t = tid; t < b * b; t += 1024) M[t] = mk(0.0, 0.0);
+    double mx = 0.0;
+    if (tid < b) {
+        d[tid] = W[tid + (int64_t)tid * ldw].x;
+        taken[tid] = 0;
+        mx = d[tid];
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if ((tid & 63) == 0) wv[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double m = 0.0;
+        for (int w = 0; w < 16; ++w) m = fmax(m, wv[w]);
+        thr = fmax(thr_abs, thr_rel * m);
+    }
+    __syncthreads();
+    int k = 0;
+    int j0 = 0;                                   // first pivot of the current panel
+    while (k < b) {
+        // ---- pivot: largest untaken d (ties: smallest index)
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        if (tid < b && !taken[tid]) { bv = d[tid]; bi = tid; }
+        for (int o = 32; o > 0; o >>= 1) {
+            double ov = __shfl_xor(bv, o);
+            int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if ((tid & 63) == 0) { wv[tid >> 6] = bv; wi[tid >> 6] = bi; }
+        __syncthreads();
+        bv = wv[0];
+        bi = wi[0];
+        for (int w = 1; w < 16; ++w)
+            if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
+        const bool stop = !(bv > thr);
+        const int p = bi;
+        const int jp = k - j0;
+        if (!stop) {
+            const double sd = sqrt(bv), isd = 1.0 / sd;
+            if (tid < b) {
+                // pivot row, from column p of the (panel-start) updated W: W[p, c] = conj(W[c, p])
+                const int cc = tid;
+                zd r = mk(0.0, 0.0);
+                if (cc == p) {
+                    r = mk(sd, 0.0);
+                } else if (!taken[cc]) {
+                    r = conj(W[cc + (int64_t)p * ldw]);
+                    for (int i = 0; i < jp; ++i) r = r - conj(Rp[i * b + p]) * Rp[i * b + cc];
+                    r = r * isd;
+                }
+                // z_j: row = tid
+                const int rr = tid;
+                zd z = M[rr + (int64_t)p * b];
+                if (rr == p) z = z + mk(1.0, 0.0);
+                for (int i = 0; i < jp; ++i) z = z - Zp[i * b + rr] * Rp[i * b + p];
+                z = z * isd;
+                Zp[jp * b + rr] = z;
+                Z[rr + (int64_t)k * ldz] = z;
+                Rp[jp * b + cc] = r;
+            }
+        }
+        __syncthreads();
+        if (!stop && tid < b) {
+            if (tid == p) taken[p] = 1;
+            else if (!taken[tid]) d[tid] -= abs2(Rp[jp * b + tid]);
+        }
+        if (!stop) ++k;
+        // ---- end of panel: W -= Rp^H Rp and M -= Zp Rp over the whole b x b
+        const int np = k - j0;
+        if (np == NB || (stop && np > 0) || (k == b && np > 0)) {
+            __syncthreads();
+            if (!(stop || k == b)) {
+                for (int64_t t = tid; t < (int64_t)b * b; t += 1024) {
+                    const int rr = (int)(t % b), cc = (int)(t / b);
+                    zd w = W[rr + (int64_t)cc * ldw], m = M[t];
+                    for (int i = 0; i < np; ++i) {
+                        const zd rc = Rp[i * b + cc];
+                        w = w - conj(Rp[i * b + rr]) * rc;
+                        m = m - Zp[i * b + rr] * rc;
+                    }
+                    W[rr + (int64_t)cc * ldw] = w;
+                    M[t] = m;
+                }
+            }
+            j0 = k;
+            __syncthreads();
+        }
+        if (stop) break;
+        __syncthreads();
+    }
+    // unused columns of Z are zero
+    for (int64_t t = tid; t < (int64_t)b * (b - k); t += 1024)
+        Z[(t % b) + (int64_t)(k + t / b) * ldz] = mk(0.0, 0.0);
+    if (tid == 0) kout[0] = k;
+}
+
+void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz, zd *M,
+                  int *kout, hipStream_t s) {
+    if (b <= 512 && M)
+        hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(1024), 0, s, b, W, ldw, thr_abs,
+                           thr_rel, Z, ldz, M, kout);
+    else
+        hipLaunchKernelGGL(k_pchol, dim3(1), dim3(1024), 0, s, b, W, ldw, thr_abs, thr_rel, Z,
+                           ldz, kout);
 }
 
 // M = (3 I - G) / 2 in precision T (one Newton-Schulz step towards the polar factor)
