@@ -131,9 +131,10 @@ def cpu_baseline(w):
             "sample_cpu_s": round(t4 - t0, 1)}
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, launches_per_step):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary, or None when
-    the summary is missing or was taken on a different version of the kernel's source."""
+    the summary is missing, was taken on a different version of the kernel's source, or on a
+    step with a different number of launches of it (a different mix of shapes)."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", f"{kernel}_perturbed16384.md")
     src = os.path.join(ROOT, "paper_2203_13283_amd", "csrc",
@@ -143,10 +144,12 @@ def measured_traffic(kernel):
     vals = {}
     for line in open(prof):
         k, _, v = line.strip().partition(": ")
-        if k in ("traffic_bytes_per_launch", "source_sha256"):
+        if k in ("traffic_bytes_per_launch", "source_sha256", "launches_per_step"):
             vals[k] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if vals.get("source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    if vals.get("launches_per_step") != str(launches_per_step):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -240,7 +243,7 @@ def main():
         achieved = d["work_per_launch"] * scale / (d["avg_launch_ms"] / 1e3)
         out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
                            "unit": unit, "frac": achieved / peak,
-                           "traffic": measured_traffic(dom)}
+                           "traffic": measured_traffic(dom, d["launches"] // a.steps)}
         if dom.startswith("zgemm"):
             # the 3M complex product executes 6 m n k of the 8 m n k counted above
             out["roofline"]["mfma_pipe_frac"] = 0.75 * achieved / peak

@@ -81,7 +81,8 @@ using namespace cfie;
 
 namespace {
 
-constexpr int kLUBlock = 64;
+constexpr int kLUBlock = 64;          // diagonal blocks inverted for the triangular solves
+constexpr int kLUPanel = 16;          // columns per LU panel
 
 struct HipError {
     cfie_status st;
@@ -581,37 +582,46 @@ cfie_status factor_impl(cfie_ctx *c) {
         c->dfree(K32);
     }
     launch_add_identity(ell, c->K, cap, s);
-    // blocked LU with partial pivoting
+    // blocked LU with partial pivoting: panels of kLUPanel columns, trailing updates by GEMM;
+    // then the inverses of the kLUBlock x kLUBlock diagonal blocks of L and U for the solves
     c->piv = c->alloc_n<int>(std::max(ell, 1));
     int nblk = (ell + kLUBlock - 1) / kLUBlock;
     c->Linv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
     c->Uinv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
-    zd *tmp = c->alloc_n<zd>((size_t)kLUBlock * std::max(ell, 1));
+    zd *tmp = c->alloc_n<zd>((size_t)kLUPanel * std::max(ell, 1));
+    zd *Lp = c->alloc_n<zd>((size_t)kLUPanel * kLUPanel);
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
-    for (int bi = 0; bi < nblk; ++bi) {
-        int k0 = bi * kLUBlock, kb = std::min(kLUBlock, ell - k0);
+    for (int k0 = 0; k0 < ell; k0 += kLUPanel) {
+        const int kb = std::min(kLUPanel, ell - k0);
         launch_lu_panel(ell, k0, kb, c->K, cap, c->piv, c->info, s);
         launch_swaps<double>(k0, k0 + kb, c->piv, c->K, cap, 0, k0, s);
         launch_swaps<double>(k0, k0 + kb, c->piv, c->K, cap, k0 + kb, ell, s);
-        zd *Kd = c->K + k0 + (size_t)k0 * cap;
-        launch_tri_inv(kb, Kd, cap, true, c->Linv + (size_t)bi * kLUBlock * kLUBlock, kLUBlock, s);
-        int rest = ell - k0 - kb;
+        const int rest = ell - k0 - kb;
         if (rest > 0) {
+            zd *Kd = c->K + k0 + (size_t)k0 * cap;
+            launch_tri_inv(kb, Kd, cap, true, Lp, kLUPanel, s);
             zd *U12 = c->K + k0 + (size_t)(k0 + kb) * cap;
-            gemm<double>(GEMM_N, kb, rest, kb, cz<double>(1), c->Linv + (size_t)bi * kLUBlock * kLUBlock,
-                         kLUBlock, U12, cap, cz<double>(0), tmp, kb, s);
+            gemm<double>(GEMM_N, kb, rest, kb, cz<double>(1), Lp, kLUPanel, U12, cap,
+                         cz<double>(0), tmp, kb, s);
             axpby<double>(kb, rest, cz<double>(1), tmp, kb, cz<double>(0), U12, cap, s);
             gemm<double>(GEMM_N, rest, rest, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * cap,
                          cap, U12, cap, cz<double>(1), c->K + (k0 + kb) + (size_t)(k0 + kb) * cap,
                          cap, s);
         }
-        launch_tri_inv(kb, Kd, cap, false, c->Uinv + (size_t)bi * kLUBlock * kLUBlock, kLUBlock, s);
         c->check_launch();
     }
+    for (int bi = 0; bi < nblk; ++bi) {
+        const int k0 = bi * kLUBlock, kb = std::min(kLUBlock, ell - k0);
+        zd *Kd = c->K + k0 + (size_t)k0 * cap;
+        launch_tri_inv(kb, Kd, cap, true, c->Linv + (size_t)bi * kLUBlock * kLUBlock, kLUBlock, s);
+        launch_tri_inv(kb, Kd, cap, false, c->Uinv + (size_t)bi * kLUBlock * kLUBlock, kLUBlock, s);
+    }
+    c->check_launch();
     int info = 0;
     HIPCHK(hipMemcpyAsync(&info, c->info, sizeof(int), hipMemcpyDeviceToHost, s));
     c->sync();
     c->dfree(tmp);
+    c->dfree(Lp);
     if (info) return fail(c, CFIE_ESINGULAR, "zero pivot in the capacitance matrix");
     // K^{-1} V^T (ell x N) by the complex128 LU factors, once per factorisation, so that a
     // solve is C_c^{-1} by FFT and two GEMMs

@@ -611,56 +611,54 @@ template void launch_polar_coef<double>(int, const zd *, int, zd *, int, hipStre
 template void launch_polar_coef<float>(int, const zd *, int, zf *, int, hipStream_t);
 
 // ---- LU with partial pivoting: panel of columns [k0, k0 + nb) of the n x n matrix A
-// (rows k0..n-1), one workgroup; piv[j] = global row swapped with row j.
-__global__ void k_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    __shared__ double bestv[1024];
-    __shared__ int besti[1024];
+// (rows k0..n-1), one workgroup of 1024 threads; piv[j] = global row swapped with row j.
+// Pivot search by wavefront shuffles and one exchange through LDS (ties: smallest row).
+__global__ __launch_bounds__(1024) void k_lu_panel(int n, int k0, int nb, zd *A, int64_t lda,
+                                                   int *piv, int *info) {
+    const int tid = threadIdx.x;
+    __shared__ double wv[16];
+    __shared__ int wi[16];
     for (int jj = 0; jj < nb; ++jj) {
-        int j = k0 + jj;
-        // pivot search in column j, rows j..n-1
+        const int j = k0 + jj;
         double bv = -1.0;
-        int bi = j;
-        for (int r = j + tid; r < n; r += nt) {
-            double v = abs2(A[r + (int64_t)j * lda]);
+        int bi = 0x7fffffff;
+        for (int r = j + tid; r < n; r += 1024) {
+            const double v = abs2(A[r + (int64_t)j * lda]);
             if (v > bv) { bv = v; bi = r; }
         }
-        bestv[tid] = bv;
-        besti[tid] = bi;
-        __syncthreads();
-        for (int w = nt / 2; w > 0; w >>= 1) {
-            if (tid < w) {
-                if (bestv[tid + w] > bestv[tid] ||
-                    (bestv[tid + w] == bestv[tid] && besti[tid + w] < besti[tid])) {
-                    bestv[tid] = bestv[tid + w];
-                    besti[tid] = besti[tid + w];
-                }
-            }
-            __syncthreads();
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
         }
-        int p = besti[0];
+        if ((tid & 63) == 0) { wv[tid >> 6] = bv; wi[tid >> 6] = bi; }
+        __syncthreads();
+        bv = wv[0];
+        bi = wi[0];
+        for (int w = 1; w < 16; ++w)
+            if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
+        const int p = bi < n ? bi : j;
         if (tid == 0) {
             piv[j] = p;
-            if (!(bestv[0] > 0.0)) info[0] = 1;
+            if (!(bv > 0.0)) info[0] = 1;
         }
-        // swap rows j and p inside the panel
-        if (p != j) {
-            for (int c = k0 + tid; c < k0 + nb; c += nt) {
-                zd t = A[j + (int64_t)c * lda];
-                A[j + (int64_t)c * lda] = A[p + (int64_t)c * lda];
-                A[p + (int64_t)c * lda] = t;
-            }
+        // swap rows j and p inside the panel (one thread per column)
+        if (p != j && tid < nb) {
+            const int c = k0 + tid;
+            zd t = A[j + (int64_t)c * lda];
+            A[j + (int64_t)c * lda] = A[p + (int64_t)c * lda];
+            A[p + (int64_t)c * lda] = t;
         }
         __syncthreads();
-        zd d = A[j + (int64_t)j * lda];
-        zd dinv = (abs2(d) > 0.0) ? cinv(d) : mk(0.0, 0.0);
-        for (int r = j + 1 + tid; r < n; r += nt) A[r + (int64_t)j * lda] = A[r + (int64_t)j * lda] * dinv;
-        __syncthreads();
-        // rank-1 update of the rest of the panel
-        int rows = n - j - 1, cols = k0 + nb - j - 1;
-        for (int64_t t = tid; t < (int64_t)rows * cols; t += nt) {
-            int r = j + 1 + (int)(t % rows), c = j + 1 + (int)(t / rows);
-            A[r + (int64_t)c * lda] = A[r + (int64_t)c * lda] - A[r + (int64_t)j * lda] * A[j + (int64_t)c * lda];
+        const zd d = A[j + (int64_t)j * lda];
+        const zd dinv = (abs2(d) > 0.0) ? cinv(d) : mk(0.0, 0.0);
+        // scale the column and apply the rank-one update to the rest of the panel, row by row
+        const int cols = k0 + nb - j - 1;
+        for (int r = j + 1 + tid; r < n; r += 1024) {
+            const zd l = A[r + (int64_t)j * lda] * dinv;
+            A[r + (int64_t)j * lda] = l;
+            for (int c = j + 1; c < j + 1 + cols; ++c)
+                A[r + (int64_t)c * lda] = A[r + (int64_t)c * lda] - l * A[j + (int64_t)c * lda];
         }
         __syncthreads();
     }
@@ -700,29 +698,42 @@ void launch_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_
 template void launch_swaps<double>(int, int, const int *, zd *, int64_t, int64_t, int64_t,
                                    hipStream_t);
 
-// inverse of the nb x nb diagonal block at (k0, k0): unit lower (lower = true) or upper
-__global__ void k_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nb) return;
-    if (lower) {
-        for (int r = 0; r < nb; ++r) {
-            zd s = mk(r == c ? 1.0 : 0.0, 0.0);
-            if (r < c) { Inv[r + c * ldi] = mk(0.0, 0.0); continue; }
-            for (int q = c; q < r; ++q) s = s - A[r + (int64_t)q * lda] * Inv[q + c * ldi];
-            Inv[r + c * ldi] = s;
-        }
-    } else {
-        for (int r = nb - 1; r >= 0; --r) {
-            zd s = mk(r == c ? 1.0 : 0.0, 0.0);
-            if (r > c) { Inv[r + c * ldi] = mk(0.0, 0.0); continue; }
-            for (int q = r + 1; q <= c; ++q) s = s - A[r + (int64_t)q * lda] * Inv[q + c * ldi];
-            Inv[r + c * ldi] = s * cinv(A[r + (int64_t)r * lda]);
+// inverse of the nb x nb (nb <= 64) diagonal block at A: unit lower (lower = true) or upper.
+// The block is staged in LDS; one thread per column of the inverse (element (r, c) of the
+// inverse at X[c + 65 r], so that the threads of a step touch consecutive words).
+__global__ __launch_bounds__(64) void k_tri_inv(int nb, const zd *A, int64_t lda, bool lower,
+                                                zd *Inv, int ldi) {
+    __shared__ zd Ab[64 * 65];
+    __shared__ zd X[64 * 65];
+    const int c = threadIdx.x;
+    for (int q = 0; q < nb; ++q)
+        if (c < nb) Ab[c + q * 65] = A[c + (int64_t)q * lda];
+    __syncthreads();
+    if (c < nb) {
+        if (lower) {
+            for (int r = 0; r < nb; ++r) {
+                zd sum = mk(r == c ? 1.0 : 0.0, 0.0);
+                if (r > c)
+                    for (int q = c; q < r; ++q) sum = sum - Ab[r + q * 65] * X[c + q * 65];
+                X[c + r * 65] = r < c ? mk(0.0, 0.0) : sum;
+            }
+        } else {
+            for (int r = nb - 1; r >= 0; --r) {
+                zd sum = mk(r == c ? 1.0 : 0.0, 0.0);
+                if (r <= c)
+                    for (int q = r + 1; q <= c; ++q) sum = sum - Ab[r + q * 65] * X[c + q * 65];
+                X[c + r * 65] = r > c ? mk(0.0, 0.0) : sum * cinv(Ab[r + r * 65]);
+            }
         }
     }
+    __syncthreads();
+    // Inv[r, q] = X[q + 65 r]: thread c writes row c
+    for (int q = 0; q < nb; ++q)
+        if (c < nb) Inv[c + q * ldi] = X[q + c * 65];
 }
 void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_inv, dim3((nb + 63) / 64), dim3(64), 0, s, nb, A, lda, lower, Inv, ldi);
+    hipLaunchKernelGGL(k_tri_inv, dim3(1), dim3(64), 0, s, nb, A, lda, lower, Inv, ldi);
 }
 
 // identity added to the diagonal: A += I
