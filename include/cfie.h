@@ -72,8 +72,11 @@ typedef struct {
 typedef struct {
     int32_t precision;    /* CFIE_FP64 or CFIE_MIXED (complex64 skeleton, GEMMs and FFTs,
                              complex128 capacitance LU, FP64 iterative refinement)      */
-    double compress_tol;  /* epsilon: keep the sketch until the remainder's estimated
-                             norm is below epsilon * ||C_c||_2 (||C_c||_2 = max |c_m|)  */
+    double compress_tol;  /* epsilon, tau = epsilon * ||C_c||_2 (||C_c||_2 = max |c_m|):
+                             sketch blocks are added until a block's projected columns all
+                             have norm <= tau, or a block keeps at most block - 16
+                             directions of norm > tau (the remaining range has then been
+                             sampled with 16 or more columns of oversampling)            */
     int32_t block;        /* columns added to the sketch per adaptive step (b)         */
     int32_t max_rank;     /* cap on the skeleton rank; 0 = N                            */
     uint64_t seed;        /* seed of the Gaussian sketch (Philox4x32-10 counter stream) */
@@ -135,7 +138,8 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream,
 cfie_status cfie_assemble(cfie_ctx *ctx, const cfie_contour *contour, double k);
 
 /* Steps A4-A5 (Sec. V eqs. (7)-(9)): randomized skeleton C - C_c ~ U V^T grown in blocks
- * until the remainder estimate drops below compress_tol * ||C_c||_2 (or max_rank / N),
+ * until the remainder estimate drops below compress_tol * ||C_c||_2 or a block is found
+ * rank-deficient at that level (see cfie_options.compress_tol; or max_rank / N),
  * then the capacitance matrix K = I + V^T C_c^-1 U and its LU factorisation with partial
  * pivoting (complex128).  ESTATE before assemble; ESINGULAR on a zero pivot. */
 cfie_status cfie_factor(cfie_ctx *ctx);

@@ -548,6 +548,10 @@ cfie_status factor_impl(cfie_ctx *c) {
         if (kept == 0) break;
         axpby<T>(N, kept, cz<T>(1), Y, N, cz<T>(0), Q + (size_t)ell * N, N, s);
         ell += kept;
+        // a Gaussian block that kept at most bb - 16 directions above tau has sampled the
+        // remaining range with at least 16 columns of oversampling: the remainder left after
+        // it exceeds tau only with negligible probability, so no further block is drawn
+        if (bb >= 32 && kept <= bb - 16) break;
     }
     c->rank = ell;
     if (ell == 0) {
