@@ -645,6 +645,9 @@ cfie_status factor_impl(cfie_ctx *c) {
         c->sync();
         c->dfree(tmpN);
     }
+    // the FP64 solve's rank x m workspace, sized with the factorisation for batches of up to
+    // 1024 right-hand sides (larger batches grow it on first use)
+    if (sizeof(T) == sizeof(double)) (void)c->scratch<zd>(1, (size_t)ell * 1024);
     c->state = 2;
     return CFIE_OK;
 }
