@@ -16,5 +16,6 @@ Modules:
   quadrature  Gauss-Legendre and tanh-sinh rules
   assembly  dense Galerkin matrices S, D, N (Maue form) and G
   system    C of eq. (6), the right-hand side of eq. (5), dense LU solve, circle counterpart
+  diagnostics  singular values of C and C - C_c labelled by spatial frequency, exact rank
 """
-from . import geometry, quadrature, assembly, system  # noqa: F401
+from . import geometry, quadrature, assembly, system, diagnostics  # noqa: F401

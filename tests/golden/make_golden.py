@@ -9,7 +9,9 @@ workload it stores, in tests/golden/<name>.npz:
   b, x                     right-hand sides of eq. (5) and dense-LU solutions for them
   L, k, kt_re, kt_im, N    constants
 
-Run:  python tests/golden/make_golden.py ellipse4096 perturbed16384 [--workers 8]
+Also spectra<N>: singular values of C and C - C_c with their spatial-frequency labels.
+
+Run:  python tests/golden/make_golden.py ellipse4096 perturbed16384 spectra512 [--workers 8]
 (about 2 minutes for ellipse4096 and 40 minutes for perturbed16384 on 8 cores; the
 larger one needs about 40 GB of host memory).
 """
@@ -70,10 +72,30 @@ def make(name: str, workers: int, n_samples: int = 2048):
     print(f"{name}: written", flush=True)
 
 
+def make_spectra(N: int, workers: int):
+    """Singular values of C and C - C_c on the 2:1 ellipse (semi-axes 2 and 1) at 10 nodes
+    per wavelength, labelled by spatial frequency (Sec. III Fig. 3, Sec. V Fig. 4)."""
+    import math
+    from oracle import diagnostics as Dg
+    zh = W.ellipse_coeffs(2.0, 1.0)
+    L = S.Contour(zh).L
+    k = 2 * math.pi * N / (10 * L)
+    pr = S.Problem(zh, N, k, workers=workers)
+    sC, mC = Dg.labelled_spectrum(pr.C)
+    sR, mR = Dg.labelled_spectrum(pr.C - pr.Cc)
+    cc = np.fft.fft(pr.Cc[:, 0])
+    np.savez_compressed(os.path.join(HERE, f"spectra_ellipse{N}.npz"), N=N, k=k, L=L, sC=sC,
+                        mC=mC, sR=sR, mR=mR, cc_max=np.abs(cc).max())
+    print(f"spectra_ellipse{N}: written", flush=True)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("names", nargs="+")
     ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
     a = ap.parse_args()
     for n in a.names:
-        make(n, a.workers)
+        if n.startswith("spectra"):
+            make_spectra(int(n[len("spectra"):]), a.workers)
+        else:
+            make(n, a.workers)

@@ -83,6 +83,24 @@ def test_circle_matrices_are_circulant(circle64):
         assert np.max(np.abs(sh - X)) <= 1e-13 * np.max(np.abs(X)), name
 
 
+def test_labelled_spectrum_of_circulant(circle64):
+    """On the circle C is circulant and normal: its singular values are |c_m| and each
+    singular vector is a Fourier mode, so the labels are the mode numbers (up to the sign,
+    c_m = c_-m)."""
+    from oracle import diagnostics as Dg
+    _, _, _, M = circle64
+    C = S.form_C(M)
+    s, m = Dg.labelled_spectrum(C)
+    c = np.fft.fft(C[:, 0])
+    N = C.shape[0]
+    freq = np.fft.fftfreq(N, 1.0 / N).astype(int)
+    assert np.max(np.abs(s - np.sort(np.abs(c))[::-1])) <= 1e-12 * s[0]
+    by_mode = {int(abs(f)): abs(v) for f, v in zip(freq, c)}
+    for sv, lab in zip(s, m):
+        assert abs(by_mode[int(abs(lab))] - sv) <= 1e-10 * s[0], (sv, lab)
+    assert Dg.exact_rank(s, s[3]) == 3
+
+
 # ---------------------------------------------------------------- invariants (T5, T6) -------
 @pytest.fixture(scope="module")
 def ellipse64():
