@@ -64,7 +64,8 @@ enum {
 };
 
 typedef struct {
-    int32_t n_nodes;      /* N >= 8 nodes = elements, uniform in arc length from t = 0 */
+    int32_t n_nodes;      /* N >= 8 nodes = elements, uniform in arc length from t = 0;
+                             N <= 65536 for powers of two, else N <= 32768             */
     int32_t n_modes;      /* M >= 1: z(t) = sum_{m=-M..M} zhat[m+M] e^{imt}, CCW       */
     const double *zhat;   /* host, 2*(2M+1) doubles (re, im); read during the call only */
 } cfie_contour;
@@ -132,7 +133,8 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream,
 
 /* Steps A1-A3 (Sec. II eq. (4), Sec. V): geometry of gamma and of its equivalent circle,
  * dense assembly of D^k, N^k, D^kt, S^kt on gamma (complex128, library-owned, 64 N^2
- * bytes), and the N eigenvalues c_m of C_c.  EINVAL: N < 8, k <= 0 or not finite, M < 1,
+ * bytes), and the N eigenvalues c_m of C_c.  EINVAL: N < 8 or above the limits of
+ * cfie_contour.n_nodes, k <= 0 or not finite, M < 1,
  * non-finite coefficients, clockwise or self-intersecting contour.  WNONCONVEX: the
  * contour is not convex (the algebra is unaffected).  Invalidates a previous factor. */
 cfie_status cfie_assemble(cfie_ctx *ctx, const cfie_contour *contour, double k);

@@ -305,39 +305,63 @@ void upload_geom(cfie_ctx *c, const HostGeometry &h, GeomDev &g) {
 
 void setup_fft(cfie_ctx *c) {
     FFTPlan &p = c->fft;
-    c->dfree(p.tw1); c->dfree(p.twN); c->dfree(p.tw1f); c->dfree(p.twNf);
-    int N = c->N;
+    if (p.twN != p.twM) c->dfree(p.twN);
+    c->dfree(p.tw1); c->dfree(p.twM); c->dfree(p.tw1f); c->dfree(p.twMf);
+    p.twN = nullptr;
+    const int N = c->N;
     p.N = N;
-    p.N1 = std::min(N, 4096);
-    p.N2 = N / p.N1;
-    std::vector<double> t1(2 * (size_t)p.N1), tN(2 * (size_t)N);
-    std::vector<float> t1f(2 * (size_t)p.N1), tNf(2 * (size_t)N);
-    for (int j = 0; j < p.N1; ++j) {
-        // exact reduction of the angle: e^{-2 pi i j / n} via sin/cos of pi * (2j/n)
-        double a = -2.0 * kPi * (double)j / p.N1;
-        t1[2 * j] = std::cos(a);
-        t1[2 * j + 1] = std::sin(a);
-        t1f[2 * j] = (float)t1[2 * j];
-        t1f[2 * j + 1] = (float)t1[2 * j + 1];
-    }
-    for (int j = 0; j < N; ++j) {
-        double a = -2.0 * kPi * (double)j / N;
-        tN[2 * j] = std::cos(a);
-        tN[2 * j + 1] = std::sin(a);
-        tNf[2 * j] = (float)tN[2 * j];
-        tNf[2 * j + 1] = (float)tN[2 * j + 1];
-    }
+    int M = 1;
+    if ((N & (N - 1)) == 0) M = N;
+    else while (M < 2 * N - 1) M <<= 1;
+    p.M = M;
+    p.N1 = std::min(M, 4096);
+    p.N2 = M / p.N1;
+    auto table = [](int n, std::vector<double> &t, std::vector<float> &tf) {
+        t.assign(2 * (size_t)n, 0.0);
+        tf.assign(2 * (size_t)n, 0.0f);
+        for (int j = 0; j < n; ++j) {
+            double a = -2.0 * kPi * (double)j / n;
+            t[2 * j] = std::cos(a);
+            t[2 * j + 1] = std::sin(a);
+            tf[2 * j] = (float)t[2 * j];
+            tf[2 * j + 1] = (float)t[2 * j + 1];
+        }
+    };
+    std::vector<double> t1, tM, tN;
+    std::vector<float> t1f, tMf, tNf;
+    table(p.N1, t1, t1f);
+    table(M, tM, tMf);
     p.tw1 = c->alloc_n<double>(t1.size());
-    p.twN = c->alloc_n<double>(tN.size());
+    p.twM = c->alloc_n<double>(tM.size());
     p.tw1f = c->alloc_n<float>(t1f.size());
-    p.twNf = c->alloc_n<float>(tNf.size());
+    p.twMf = c->alloc_n<float>(tMf.size());
     c->upload(p.tw1, t1.data(), t1.size());
-    c->upload(p.twN, tN.data(), tN.size());
+    c->upload(p.twM, tM.data(), tM.size());
     c->upload(p.tw1f, t1f.data(), t1f.size());
-    c->upload(p.twNf, tNf.data(), tNf.size());
+    c->upload(p.twMf, tMf.data(), tMf.size());
+    if (M == N) {
+        p.twN = p.twM;
+    } else {
+        table(N, tN, tNf);
+        p.twN = c->alloc_n<double>(tN.size());
+        c->upload(p.twN, tN.data(), tN.size());
+    }
 }
 
 template <typename T> cpx<T> cz(double a, double b = 0.0) { return mk((T)a, (T)b); }
+
+// y = C x for a circulant given by its diagonal d (length fft.M, transposed layout): one
+// FFT pass at the length N when N is a power of two, else a zero-padded linear convolution
+// of length M through a grow-only workspace
+template <typename T>
+void circ_apply(cfie_ctx *c, const cpx<T> *d, cpx<T> *X, int64_t ldx, int64_t m) {
+    if (c->fft.M == c->N) {
+        launch_circ_apply<T>(c->fft, d, X, ldx, m, c->stream);
+    } else {
+        cpx<T> *P = c->scratch<cpx<T>>(3, (size_t)c->fft.M * (size_t)m);
+        launch_circ_apply_padded<T>(c->fft, d, X, ldx, m, P, c->stream);
+    }
+}
 
 // ---------------------------------------------------------------- operator applications ---
 template <typename T> struct Ops;
@@ -381,7 +405,7 @@ void apply_R(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, 
     const int N = c->N;
     apply_C<T>(c, X, ldx, Y, ldy, m, Tt, W1, W2);
     axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, c->stream);
-    launch_circ_apply<T>(c->fft, Ops<T>::dC(c), Z, N, m, c->stream);
+    circ_apply<T>(c, Ops<T>::dC(c), Z, N, m);
     axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, c->stream);
     c->check_launch();
 }
@@ -404,7 +428,7 @@ void apply_RH(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy,
     gemm<T>(GEMM_C, N, m, N, cz<T>(-1), Ops<T>::mat(c, 0), N, W1, N, cz<T>(1), Y, ldy, s);
     gemm<T>(GEMM_C, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, W2, N, cz<T>(1), Y, ldy, s);
     axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, s);
-    launch_circ_apply<T>(c->fft, Ops<T>::dCH(c), Z, N, m, s);
+    circ_apply<T>(c, Ops<T>::dCH(c), Z, N, m);
     axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, s);
     c->check_launch();
 }
@@ -572,7 +596,7 @@ cfie_status factor_impl(cfie_ctx *c) {
     c->Ut = c->alloc_n<cpx<T>>((size_t)N * ell);
     cpx<T> *Ut = (cpx<T> *)c->Ut;
     axpby<T>(N, ell, cz<T>(1), Q, N, cz<T>(0), Ut, N, s);
-    launch_circ_apply<T>(c->fft, Ops<T>::dCinv(c), Ut, N, ell, s);
+    circ_apply<T>(c, Ops<T>::dCinv(c), Ut, N, ell);
     // K = I + P^H Ut  (Woodbury capacitance, eq. (9)), always complex128
     c->K = c->alloc_n<zd>((size_t)cap * cap);
     if (sizeof(T) == sizeof(double)) {
@@ -658,7 +682,7 @@ template <typename T>
 void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, cpx<T> *Z) {
     const int N = c->N;
     hipStream_t s = c->stream;
-    launch_circ_apply<T>(c->fft, Ops<T>::dCinv(c), X, N, m, s);
+    circ_apply<T>(c, Ops<T>::dCinv(c), X, N, m);
     const int r = c->rank;
     if (r == 0) return;
     const cpx<T> *Wf = (const cpx<T> *)c->Wf, *Ut = (const cpx<T> *)c->Ut;
@@ -833,8 +857,10 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
     if (!contour) return fail(c, CFIE_EINVAL, "contour is NULL");
     if (contour->n_nodes < 8) return fail(c, CFIE_EINVAL, "n_nodes must be >= 8");
     int N = contour->n_nodes;
-    if (N & (N - 1)) return fail(c, CFIE_EINVAL, "n_nodes must be a power of two");
-    if (N > (1 << 16)) return fail(c, CFIE_EINVAL, "n_nodes must be <= 65536");
+    if ((N & (N - 1)) == 0 && N > (1 << 16))
+        return fail(c, CFIE_EINVAL, "n_nodes must be <= 65536");
+    if ((N & (N - 1)) != 0 && N > (1 << 15))
+        return fail(c, CFIE_EINVAL, "n_nodes that is not a power of two must be <= 32768");
     if (!(k > 0.0) || !std::isfinite(k)) return fail(c, CFIE_EINVAL, "k must be finite and > 0");
     HostGeometry hg;
     std::string e = build_geometry(*contour, hg);
@@ -931,12 +957,29 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         // rows of symmetric circulants equal their first columns
         launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, s);
         c->cvals = c->alloc_n<zd>(N);
-        c->dC = c->alloc_n<zd>(N); c->dCH = c->alloc_n<zd>(N); c->dCinv = c->alloc_n<zd>(N);
-        c->fC = c->alloc_n<zf>(N); c->fCH = c->alloc_n<zf>(N); c->fCinv = c->alloc_n<zf>(N);
+        const int M = c->fft.M;
+        c->dC = c->alloc_n<zd>(M); c->dCH = c->alloc_n<zd>(M); c->dCinv = c->alloc_n<zd>(M);
+        c->fC = c->alloc_n<zf>(M); c->fCH = c->alloc_n<zf>(M); c->fCinv = c->alloc_n<zf>(M);
         c->absc = c->alloc_n<double>(N);
         c->scal = c->alloc_n<double>(4);
-        launch_circ_eigs(N, c->fft.N1, c->fft.N2, h, c->mu, c->cvals, c->dC, c->dCH, c->dCinv,
-                         c->fC, c->fCH, c->fCinv, c->absc, s);
+        if (M == N) {
+            launch_circ_eigs(N, c->fft.N1, c->fft.N2, h, c->mu, c->cvals, c->dC, c->dCH,
+                             c->dCinv, c->fC, c->fCH, c->fCinv, c->absc, s);
+        } else {
+            // natural-order eigenvalues / N, then the padded convolution diagonals
+            zd *nat = c->alloc_n<zd>(3 * (size_t)N);
+            zf *natf = c->alloc_n<zf>(3 * (size_t)N);
+            zd *work = c->alloc_n<zd>(3 * (size_t)M);
+            launch_circ_eigs(N, N, 1, h, c->mu, c->cvals, nat, nat + N, nat + 2 * (size_t)N,
+                             natf, natf + N, natf + 2 * (size_t)N, c->absc, s);
+            launch_padded_diagonal(c->fft, nat, work, c->dC, c->fC, s);
+            launch_padded_diagonal(c->fft, nat + N, work, c->dCH, c->fCH, s);
+            launch_padded_diagonal(c->fft, nat + 2 * (size_t)N, work, c->dCinv, c->fCinv, s);
+            c->sync();
+            c->dfree(nat);
+            c->dfree(natf);
+            c->dfree(work);
+        }
         launch_maxmin(N, c->absc, c->scal, s);
         double mm[2];
         HIPCHK(hipMemcpyAsync(mm, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1074,7 +1117,7 @@ cfie_status cfie_apply(cfie_ctx *c, int op, const void *X, int64_t ldx, void *Y,
             case CFIE_OP_CC:
             case CFIE_OP_CC_INV:
                 axpby<double>(N, nrhs, cz<double>(1), Xd, ldx, cz<double>(0), Z, N, s);
-                launch_circ_apply<double>(c->fft, op == CFIE_OP_CC ? c->dC : c->dCinv, Z, N, nrhs, s);
+                circ_apply<double>(c, op == CFIE_OP_CC ? c->dC : c->dCinv, Z, N, nrhs);
                 axpby<double>(N, nrhs, cz<double>(1), Z, N, cz<double>(0), Yd, ldy, s);
                 break;
             case CFIE_OP_REMAINDER:

@@ -124,16 +124,31 @@ void launch_excitation(const GeomDev &g, const PointTable &pt, const double *xi,
 
 // ------------------------------------------------------------------ FFT ------------------
 struct FFTPlan {
-    int N = 0, N1 = 0, N2 = 0;       // N = N1 * N2, N1 <= 4096 (power of two)
+    int N = 0;                       // length of the circulant
+    // transform length M = N1 * N2 (power of two, N1 <= 4096): M = N for powers of two;
+    // otherwise the smallest power of two >= 2N - 1, and circulant products are computed
+    // as zero-padded linear convolutions of length M
+    int M = 0, N1 = 0, N2 = 0;
     double *tw1 = nullptr;           // e^{-2 pi i j / N1}, j < N1   (complex, interleaved)
-    double *twN = nullptr;           // e^{-2 pi i j / N},  j < N    (complex)
-    float *tw1f = nullptr, *twNf = nullptr;
-    int *perm = nullptr;             // natural index of the transposed layout position
+    double *twM = nullptr;           // e^{-2 pi i j / M},  j < M    (complex)
+    float *tw1f = nullptr, *twMf = nullptr;
+    double *twN = nullptr;           // e^{-2 pi i j / N},  j < N    (aliases twM when M == N)
 };
-// y = IFFT(d .* FFT(x)) column by column (d in the transposed layout, 1/N folded in).
+// y = IFFT(d .* FFT(x)) column by column at the transform length M (d in the transposed
+// layout of length M, 1/M folded in).
 template <typename T>
 void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx,
                        int64_t nb, hipStream_t s);
+// the same for M > N: x (N x nb, ld ldx) zero-padded into P (M x nb), transformed, and the
+// first N rows copied back
+template <typename T>
+void launch_circ_apply_padded(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx,
+                              int64_t nb, cpx<T> *P, hipStream_t s);
+// diagonal of length M in the transposed layout from the natural-order eigenvalues d_m / N
+// (m < N) of a circulant of length N: its first column by an inverse DFT, wrapped to length
+// M, transformed and scaled by 1/M (direct DFTs; once per assembly)
+void launch_padded_diagonal(const FFTPlan &p, const zd *eig_over_N, zd *work, zd *dT, zf *fT,
+                            hipStream_t s);
 
 // complex GEMM: C = alpha * op(A) * B + beta * C, op(A) = A (GEMM_N), A^H (GEMM_C) or the
 // elementwise conjugate of A (GEMM_R)

@@ -173,8 +173,8 @@ template <typename T> const cpx<T> *tw1_of(const FFTPlan &p);
 template <> const zd *tw1_of<double>(const FFTPlan &p) { return (const zd *)p.tw1; }
 template <> const zf *tw1_of<float>(const FFTPlan &p) { return (const zf *)p.tw1f; }
 template <typename T> const cpx<T> *twN_of(const FFTPlan &p);
-template <> const zd *twN_of<double>(const FFTPlan &p) { return (const zd *)p.twN; }
-template <> const zf *twN_of<float>(const FFTPlan &p) { return (const zf *)p.twNf; }
+template <> const zd *twN_of<double>(const FFTPlan &p) { return (const zd *)p.twM; }
+template <> const zf *twN_of<float>(const FFTPlan &p) { return (const zf *)p.twMf; }
 
 template <typename T>
 void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx, int64_t nb,
@@ -182,7 +182,7 @@ void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx
     if (nb <= 0) return;
     const int bs = 256;
     // algorithmic work: bytes of one read and one write of the batch
-    ProfScope prof(PROF_FFT, 2.0 * sizeof(cpx<T>) * (double)p.N * (double)nb, s);
+    ProfScope prof(PROF_FFT, 2.0 * sizeof(cpx<T>) * (double)p.M * (double)nb, s);
     if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), x, ldx, nb, false, s);
     size_t sh = 2 * sizeof(T) * (size_t)p.N1;
     hipLaunchKernelGGL(k_fft_mid<T>, dim3(p.N2, (unsigned)nb), dim3(bs), sh, s, p.N1,
@@ -195,23 +195,100 @@ template void launch_circ_apply<double>(const FFTPlan &, const zd *, zd *, int64
 template void launch_circ_apply<float>(const FFTPlan &, const zf *, zf *, int64_t, int64_t,
                                        hipStream_t);
 
-// natural-order DFT by direct summation (a handful of length-N vectors, once per assembly)
-__global__ void k_dft_direct(int N, const zd *__restrict__ x, int64_t ldx, zd *y, int64_t ldy,
-                             const zd *__restrict__ twN) {
+template <typename T>
+__global__ void k_pad(int N, int M, int64_t nb, const cpx<T> *__restrict__ x, int64_t ldx,
+                      cpx<T> *P) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)M * nb) return;
+    int64_t i = t % M, j = t / M;
+    P[t] = i < N ? x[i + j * ldx] : mk((T)0, (T)0);
+}
+template <typename T>
+__global__ void k_unpad(int N, int M, int64_t nb, const cpx<T> *__restrict__ P, cpx<T> *x,
+                        int64_t ldx) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)N * nb) return;
+    int64_t i = t % N, j = t / N;
+    x[i + j * ldx] = P[i + j * M];
+}
+
+template <typename T>
+void launch_circ_apply_padded(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx,
+                              int64_t nb, cpx<T> *P, hipStream_t s) {
+    if (nb <= 0) return;
+    const int bs = 256;
+    int64_t nM = (int64_t)p.M * nb, nN = (int64_t)p.N * nb;
+    hipLaunchKernelGGL(k_pad<T>, dim3((unsigned)((nM + bs - 1) / bs)), dim3(bs), 0, s, p.N, p.M,
+                       nb, (const cpx<T> *)x, ldx, P);
+    launch_circ_apply<T>(p, d, P, p.M, nb, s);
+    hipLaunchKernelGGL(k_unpad<T>, dim3((unsigned)((nN + bs - 1) / bs)), dim3(bs), 0, s, p.N,
+                       p.M, nb, (const cpx<T> *)P, x, ldx);
+}
+template void launch_circ_apply_padded<double>(const FFTPlan &, const zd *, zd *, int64_t,
+                                               int64_t, zd *, hipStream_t);
+template void launch_circ_apply_padded<float>(const FFTPlan &, const zf *, zf *, int64_t,
+                                              int64_t, zf *, hipStream_t);
+
+// DFT by direct summation: y_m = scale sum_p x_p w^{m p} with w = tw[1] (tw: the n-th roots
+// of unity, e^{-2 pi i j / n}), conjugated for inverse; the table index advances by m
+// modulo n without division
+__global__ void k_dft_direct(int n, const zd *__restrict__ x, int64_t ldx, zd *y, int64_t ldy,
+                             const zd *__restrict__ tw, bool inverse, double scale) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     int c = blockIdx.y;
-    if (m >= N) return;
+    if (m >= n) return;
     const zd *xc = x + (int64_t)c * ldx;
     zd acc = mk(0.0, 0.0);
-    for (int p = 0; p < N; ++p) acc = acc + xc[p] * twN[((int64_t)m * p) % N];
-    y[m + (int64_t)c * ldy] = acc;
+    int idx = 0;
+    for (int q = 0; q < n; ++q) {
+        zd w = tw[idx];
+        if (inverse) w.y = -w.y;
+        acc = acc + xc[q] * w;
+        idx += m;
+        if (idx >= n) idx -= n;
+    }
+    y[m + (int64_t)c * ldy] = acc * scale;
 }
 
 void launch_dft_direct_tw(int N, const zd *x, int64_t ldx, zd *y, int64_t ldy, int ncol,
                           const zd *twN, hipStream_t s) {
     int bs = 256;
     hipLaunchKernelGGL(k_dft_direct, dim3((N + bs - 1) / bs, ncol), dim3(bs), 0, s, N, x, ldx, y,
-                       ldy, twN);
+                       ldy, twN, false, 1.0);
+}
+
+// kappa of length N (first column) -> wrapped kernel of length M: [0, N) and [M - N + 1, M)
+__global__ void k_wrap(int N, int M, const zd *__restrict__ kap, zd *out) {
+    int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= M) return;
+    out[u] = u < N ? kap[u] : (u > M - N ? kap[u - M + N] : mk(0.0, 0.0));
+}
+// natural order (length M) -> transposed layout of the four-step FFT, FP64 and FP32
+__global__ void k_diag_transpose(int M, int N1, int N2, const zd *__restrict__ nat, zd *dT,
+                                 zf *fT) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M) return;
+    int k2 = q % N2, k1 = q / N2;
+    int pos = k1 + N1 * k2;
+    zd v = nat[q];
+    dT[pos] = v;
+    fT[pos] = mk((float)v.x, (float)v.y);
+}
+
+void launch_padded_diagonal(const FFTPlan &p, const zd *eig_over_N, zd *work, zd *dT, zf *fT,
+                            hipStream_t s) {
+    // work: 3 M entries (kappa, wrapped kernel, its transform)
+    const int bs = 256;
+    zd *kap = work, *wrp = work + p.M, *hat = work + 2 * (size_t)p.M;
+    hipLaunchKernelGGL(k_dft_direct, dim3((p.N + bs - 1) / bs, 1), dim3(bs), 0, s, p.N,
+                       eig_over_N, (int64_t)p.N, kap, (int64_t)p.N, (const zd *)p.twN, true, 1.0);
+    hipLaunchKernelGGL(k_wrap, dim3((p.M + bs - 1) / bs), dim3(bs), 0, s, p.N, p.M,
+                       (const zd *)kap, wrp);
+    hipLaunchKernelGGL(k_dft_direct, dim3((p.M + bs - 1) / bs, 1), dim3(bs), 0, s, p.M,
+                       (const zd *)wrp, (int64_t)p.M, hat, (int64_t)p.M, (const zd *)p.twM, false,
+                       1.0 / p.M);
+    hipLaunchKernelGGL(k_diag_transpose, dim3((p.M + bs - 1) / bs), dim3(bs), 0, s, p.M, p.N1,
+                       p.N2, (const zd *)hat, dT, fT);
 }
 
 }  // namespace cfie

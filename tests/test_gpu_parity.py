@@ -135,11 +135,12 @@ def test_circle_remainder_vanishes():
     assert np.linalg.norm(X[:, 1] - jm) / np.linalg.norm(jm) < 2e-2
 
 
-@pytest.mark.parametrize("N", [8, 32, 512, 2048, 8192, 16384])
+@pytest.mark.parametrize("N", [8, 32, 512, 2048, 8192, 16384, 9, 100, 1000, 3000, 6000])
 def test_circulant_fft_lengths(N):
     """C_c x and C_c^-1 x by the library's FFT path against numpy's FFT with the exported
-    eigenvalues, for odd and even powers of two, one pass (N <= 4096) and the four-step
-    split (N1 = 4096, N2 = 2, 4)."""
+    eigenvalues: odd and even powers of two, one pass (N <= 4096) and the four-step split
+    (N1 = 4096, N2 = 2, 4); other lengths through the zero-padded convolution (transform
+    lengths 32 ... 16384)."""
     zh = W.ellipse_coeffs(1.0, 0.6)
     L = S.Contour(zh).L
     s = P.Solver(compress_tol=1e-10)
@@ -153,6 +154,24 @@ def test_circulant_fft_lengths(N):
         y = _np(s.apply(op, x))
         err = np.abs(y - ref).max() / np.abs(ref).max()
         assert err <= 1e-13, (op, err)
+
+
+@pytest.mark.parametrize("N", [200, 333])
+def test_solve_non_power_of_two(N):
+    """Lengths that are not powers of two (circulant products by zero-padded convolution):
+    the full path against the oracle's dense LU, FP64 at epsilon = 1e-10 and mixed."""
+    zh = W.ellipse_coeffs(1.0, 0.6)
+    k = 2 * np.pi * N / (10 * S.Contour(zh).L)
+    prob = S.Problem(zh, N, k)
+    ang = W.plane_wave_angles(4)
+    x_ref = prob.solve(prob.rhs(ang))
+    for prec, eps, tol in ((P.CFIE_FP64, 1e-10, 1e-10), (P.CFIE_MIXED, 1e-3, 1e-6)):
+        s = P.Solver(precision=prec, compress_tol=eps, block=64)
+        s.assemble(zh, N, k).factor()
+        X = _np(s.solve(s.plane_wave_rhs(ang))).T
+        err = S.rel_err(X, x_ref)
+        print(f"N={N} precision {prec}: rank {s.info()['rank']} rel.err {err:.2e}")
+        assert err <= tol
 
 
 def test_mixed_precision_refinement(cfg1):
