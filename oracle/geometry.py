@@ -82,8 +82,11 @@ class Contour:
         c = np.fft.rfft(speed) / n_fine
         c0 = c[0].real
         mags = np.abs(c)
-        # keep the speed's Fourier modes down to tail_tol relative to the mean
-        last = np.nonzero(mags > tail_tol * c0)[0].max()
+        # keep the speed's Fourier modes down to tail_tol relative to the mean, or to twice
+        # the rounding noise of the sampled speed (the largest magnitude in the upper half
+        # of the sampled spectrum, where the smooth density has none) if that is higher
+        noise = mags[n_fine // 4:].max()
+        last = np.nonzero(mags > max(tail_tol * c0, 2.0 * noise))[0].max()
         if last > n_fine // 4:
             raise ValueError("arc-length density not resolved; contour too irregular")
         self.speed_c0 = c0
