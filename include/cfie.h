@@ -191,6 +191,32 @@ const char *cfie_status_string(cfie_status s);
 /* Release every device buffer of ctx.  NULL is ignored. */
 void cfie_destroy(cfie_ctx *ctx);
 
+/* One problem of a batch: a contour, its wavenumber and its plane waves (Sec. II-V). */
+typedef struct {
+    cfie_contour contour;     /* as for cfie_assemble; read during the call only          */
+    double k;                 /* wavenumber                                                */
+    const double *angles_host;/* host, nrhs plane-wave directions (cfie_plane_wave_rhs)    */
+    int64_t nrhs;             /* >= 0                                                      */
+    void *X_dev;              /* device, complex128, N x nrhs column-major (ld = N):
+                                 receives the solutions j = C^-1 b of eq. (5)             */
+    /* filled by the call */
+    int32_t status;           /* cfie_status of this problem                               */
+    int32_t rank;             /* skeleton rank                                             */
+    double refine_residual;   /* mixed precision: final max relative residual              */
+    double t_ms;              /* host wall time of this problem (assemble..solve)          */
+} cfie_batch_item;
+
+/* Solve many independent problems (uneven N, their own right-hand-side sets) on one device:
+ * each item runs the whole path (cfie_assemble, cfie_factor, cfie_plane_wave_rhs,
+ * cfie_solve) with the options opt, and the items are spread, largest first, over n_streams
+ * HIP streams (default priority, created and destroyed by the call) driven by as many host
+ * threads, so that the small problems of a batch run concurrently on the device.  Each
+ * item's device buffers are released when it completes.  Returns CFIE_OK when every item
+ * returned OK or a warning, else the first error; per-item results in items[i].  EINVAL for
+ * n_items < 0, n_streams < 1 or > 16, or a NULL items array with n_items > 0. */
+cfie_status cfie_solve_batch(const cfie_options *opt, int device, int n_streams,
+                             cfie_batch_item *items, int64_t n_items);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,8 @@
     B = s.plane_wave_rhs(angles)        # step A8: right-hand sides of the preconditioned CFIE
     X = s.solve(B)                      # step A6 (+ A7 refinement in mixed precision)
 
+    X_list, results = solve_batch(problems)   # many contours of uneven N at once
+
 Batches are (m, N) complex128 CUDA tensors (row j = right-hand side j).  The compute runs
 in libcfie.so; torch is used for device memory and the current stream only.
 """
@@ -20,8 +22,8 @@ from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW,
                    MAT_DKT, MAT_G, MAT_NK, MAT_SKT, OP_C, OP_CC, OP_CC_INV, OP_REMAINDER,
                    OP_SKELETON)
 
-__all__ = ["Solver", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK", "MAT_NK",
-           "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
+__all__ = ["Solver", "solve_batch", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
+           "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
            "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "load_library"]
 
 
@@ -178,3 +180,52 @@ class Solver:
 
     def profile_reset(self):
         self._check(self._lib.cfie_profile_reset(self._h), "cfie_profile_reset")
+
+
+def solve_batch(problems, precision: int = CFIE_FP64, compress_tol: float = 1e-10,
+                block: int = 128, refine_tol: float = 1e-8, n_streams: int = 4,
+                device: int = 0, **options):
+    """Solve independent problems concurrently (cfie_solve_batch).
+
+    problems: sequence of dicts with keys zhat (Fourier coefficients of the contour), n_nodes,
+    k and angles (plane-wave directions).  Returns (solutions, results): solutions[i] is a
+    (len(angles), n_nodes) complex128 CUDA tensor, results[i] a dict with status, rank,
+    refine_residual and t_ms.  The whole path of every problem runs in the library."""
+    torch = _torch()
+    lib = _lib.load()
+    o = _lib.default_options()
+    o.precision = precision
+    o.compress_tol = compress_tol
+    o.block = block
+    o.refine_tol = refine_tol
+    for key, val in options.items():
+        setattr(o, key, val)
+    n = len(problems)
+    items = (_lib.BatchItem * n)()
+    keep = []
+    sols = []
+    for i, pr in enumerate(problems):
+        zh = np.ascontiguousarray(np.asarray(pr["zhat"], dtype=np.complex128))
+        zbuf = np.ascontiguousarray(np.stack([zh.real, zh.imag], axis=-1).reshape(-1))
+        ang = np.ascontiguousarray(np.asarray(pr["angles"], dtype=np.float64))
+        N = int(pr["n_nodes"])
+        X = torch.empty((ang.size, N), dtype=torch.complex128, device=f"cuda:{device}")
+        keep += [zbuf, ang]
+        sols.append(X)
+        it = items[i]
+        it.contour.n_nodes = N
+        it.contour.n_modes = (zh.size - 1) // 2
+        it.contour.zhat = zbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        it.k = float(pr["k"])
+        it.angles_host = ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        it.nrhs = ang.size
+        it.X_dev = X.data_ptr() if ang.size else None
+    torch.cuda.synchronize(device)
+    st = lib.cfie_solve_batch(ctypes.byref(o), device, n_streams, items, n)
+    results = [dict(status=items[i].status, rank=items[i].rank,
+                    refine_residual=items[i].refine_residual, t_ms=items[i].t_ms)
+               for i in range(n)]
+    if st != 0:
+        bad = [i for i in range(n) if results[i]["status"] not in (0, 100)]
+        raise CfieError(st, "cfie_solve_batch", f"items {bad} failed")
+    return sols, results

@@ -28,6 +28,7 @@ EXPORTED = [
     "cfie_default_options", "cfie_create", "cfie_assemble", "cfie_factor", "cfie_solve",
     "cfie_plane_wave_rhs", "cfie_apply", "cfie_export_matrix", "cfie_query",
     "cfie_last_error", "cfie_status_string", "cfie_destroy", "cfie_profile_reset",
+    "cfie_solve_batch",
 ]
 
 
@@ -58,6 +59,14 @@ class Info(ctypes.Structure):
                 ("prof_work", ctypes.c_double * 5), ("prof_ms", ctypes.c_double * 5)]
 
 PROF_NAMES = ("zgemm_f64", "zgemm_f32", "assemble_far", "assemble_near", "circ_fft")
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("contour", Contour), ("k", ctypes.c_double),
+                ("angles_host", ctypes.POINTER(ctypes.c_double)), ("nrhs", ctypes.c_int64),
+                ("X_dev", ctypes.c_void_p), ("status", ctypes.c_int32),
+                ("rank", ctypes.c_int32), ("refine_residual", ctypes.c_double),
+                ("t_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -98,6 +107,9 @@ def load(path: str = LIB_PATH):
     lib.cfie_destroy.restype = None
     lib.cfie_profile_reset.argtypes = [vp]
     lib.cfie_profile_reset.restype = i32
+    lib.cfie_solve_batch.argtypes = [ctypes.POINTER(Options), ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(BatchItem), i64]
+    lib.cfie_solve_batch.restype = i32
     _lib = lib
     return lib
 

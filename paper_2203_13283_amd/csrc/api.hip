@@ -15,6 +15,10 @@
 
 #include "internal.h"
 
+#include <atomic>
+#include <chrono>
+#include <thread>
+
 namespace cfie {
 // launchers defined in the kernel translation units
 void ginv_taps(int N, double h, std::vector<double> &coef, int &t0);
@@ -840,10 +844,90 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, c
     return CFIE_OK;
 }
 
+cfie_status cfie_solve_batch(const cfie_options *opt, int device, int n_streams,
+                             cfie_batch_item *items, int64_t n_items) {
+    if (n_items < 0 || n_streams < 1 || n_streams > 16 || (n_items > 0 && !items))
+        return CFIE_EINVAL;
+    if (n_items == 0) return CFIE_OK;
+    if (hipSetDevice(device) != hipSuccess) return CFIE_EHIP;
+    // largest problems first (work ~ N^2 (assembly, sketch) + N nrhs)
+    std::vector<int64_t> order((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
+    auto work = [&](int64_t i) {
+        double n = (double)items[i].contour.n_nodes;
+        return n * n + n * (double)std::max<int64_t>(items[i].nrhs, 0);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return work(a) > work(b); });
+    for (int64_t i = 0; i < n_items; ++i) {
+        items[i].status = CFIE_EINVAL;
+        items[i].rank = 0;
+        items[i].refine_residual = 0.0;
+        items[i].t_ms = 0.0;
+    }
+    const int ns = (int)std::min<int64_t>(n_streams, n_items);
+    std::vector<hipStream_t> streams((size_t)ns, nullptr);
+    for (int t = 0; t < ns; ++t) {
+        if (hipStreamCreateWithFlags(&streams[(size_t)t], hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int u = 0; u < t; ++u) (void)hipStreamDestroy(streams[(size_t)u]);
+            return CFIE_EHIP;
+        }
+    }
+    std::atomic<int64_t> next{0};
+    auto worker = [&](int t) {
+        (void)hipSetDevice(device);
+        for (;;) {
+            const int64_t q = next.fetch_add(1);
+            if (q >= n_items) break;
+            cfie_batch_item &it = items[order[(size_t)q]];
+            auto t0 = std::chrono::steady_clock::now();
+            cfie_ctx *c = nullptr;
+            cfie_status st = cfie_create(opt, device, streams[(size_t)t], &c);
+            if (st == CFIE_OK) {
+                st = cfie_assemble(c, &it.contour, it.k);
+                if (st == CFIE_OK || st >= 100) {
+                    cfie_status sf = cfie_factor(c);
+                    if (sf != CFIE_OK) st = sf;
+                }
+                if ((st == CFIE_OK || st >= 100) && it.nrhs > 0) {
+                    const int64_t N = it.contour.n_nodes;
+                    cfie_status sr = cfie_plane_wave_rhs(c, it.angles_host, it.nrhs, it.X_dev, N);
+                    if (sr == CFIE_OK) sr = cfie_solve(c, it.X_dev, N, it.X_dev, N, it.nrhs);
+                    if (sr != CFIE_OK) st = sr;
+                }
+                cfie_info inf;
+                if (cfie_query(c, &inf) == CFIE_OK) {
+                    it.rank = inf.rank;
+                    it.refine_residual = inf.refine_residual;
+                }
+                cfie_destroy(c);
+            }
+            it.status = st;
+            it.t_ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t0).count();
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 0; t < ns; ++t) th.emplace_back(worker, t);
+    for (auto &x : th) x.join();
+    for (int t = 0; t < ns; ++t) {
+        (void)hipStreamSynchronize(streams[(size_t)t]);
+        splitk_release(device, streams[(size_t)t]);
+        (void)hipStreamDestroy(streams[(size_t)t]);
+    }
+    cfie_status worst = CFIE_OK;
+    for (int64_t i = 0; i < n_items; ++i)
+        if (items[i].status != CFIE_OK && items[i].status < 100 && worst == CFIE_OK)
+            worst = (cfie_status)items[i].status;
+    return worst;
+}
+
 void cfie_destroy(cfie_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->stream) splitk_release(c->device, c->stream);
     delete c;
 }
 

@@ -17,7 +17,10 @@
 // second kernel sums the slices in a fixed order (deterministic) and applies alpha, beta.
 #include "internal.h"
 
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 namespace cfie {
 
@@ -290,34 +293,46 @@ __global__ void k_splitk_reduce(int64_t m, int64_t n, int S, const cpx<T> *__res
     *p = v;
 }
 
+// grow-only device workspaces for split-K partial products, one per (device, stream) so that
+// contexts on different streams can run from different host threads
 namespace {
-// grow-only device workspace for split-K partial products (one per process and device)
-struct SplitKWorkspace {
-    void *ptr[16] = {nullptr};
-    size_t bytes[16] = {0};
-};
-SplitKWorkspace g_ws;
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_ws;
 
 void *splitk_ws(size_t need, hipStream_t s) {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    if (dev < 0 || dev >= 16) return nullptr;
-    if (g_ws.bytes[dev] < need) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    auto &e = g_ws[{dev, s}];
+    if (e.second < need) {
         (void)hipStreamSynchronize(s);
-        if (g_ws.ptr[dev]) (void)hipFree(g_ws.ptr[dev]);
-        g_ws.ptr[dev] = nullptr;
-        g_ws.bytes[dev] = 0;
+        if (e.first) (void)hipFree(e.first);
+        e.first = nullptr;
+        e.second = 0;
         size_t nb = need + need / 2;
-        if (hipMalloc(&g_ws.ptr[dev], nb) != hipSuccess) {
+        if (hipMalloc(&e.first, nb) != hipSuccess) {
             (void)hipGetLastError();
-            g_ws.ptr[dev] = nullptr;
+            e.first = nullptr;
             return nullptr;
         }
-        g_ws.bytes[dev] = nb;
+        e.second = nb;
     }
-    return g_ws.ptr[dev];
+    return e.first;
+}
+}  // namespace
+
+void splitk_release(int device, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    auto it = g_ws.find({device, s});
+    if (it == g_ws.end()) return;
+    if (it->second.first) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(it->second.first);
+    }
+    g_ws.erase(it);
 }
 
+namespace {
 template <typename T, int OPA, int TI, int TJ, int BKT, bool G3 = true, int MINB = 1>
 void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *A, int64_t lda,
             const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s) {

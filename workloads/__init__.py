@@ -26,6 +26,7 @@ __all__ = [
     "perturbed_circle_coeffs",
     "circle_coeffs",
     "plane_wave_angles",
+    "batch_problems",
     "WORKLOADS",
     "get",
 ]
@@ -109,3 +110,59 @@ WORKLOADS = {
 
 def get(name: str) -> Workload:
     return WORKLOADS[name]
+
+
+def _perimeter(zhat: np.ndarray, n: int = 4096) -> float:
+    """Length of z(t) by the periodic trapezoid rule on |z'(t)| (spectrally accurate)."""
+    M = (zhat.size - 1) // 2
+    t = 2.0 * math.pi * np.arange(n) / n
+    m = np.arange(-M, M + 1)
+    dz = (1j * m * zhat)[None, :] * np.exp(1j * np.outer(t, m))
+    return float(np.abs(dz.sum(axis=1)).mean() * 2.0 * math.pi)
+
+
+def _convex(zhat: np.ndarray, n: int = 4096) -> bool:
+    """Im(conj(z') z'') > 0 on n samples (counter-clockwise and convex)."""
+    M = (zhat.size - 1) // 2
+    t = 2.0 * math.pi * np.arange(n) / n
+    m = np.arange(-M, M + 1)
+    E = np.exp(1j * np.outer(t, m))
+    d1 = (E * (1j * m * zhat)[None, :]).sum(axis=1)
+    d2 = (E * (-(m ** 2) * zhat)[None, :]).sum(axis=1)
+    return bool(np.all(np.imag(np.conj(d1) * d2) > 0.0))
+
+
+def batch_problems(count: int = 64, seed: int = 0, n_range=(512, 8192), rhs_range=(32, 512),
+                   nodes_per_wavelength: float = 10.0):
+    """Seeded batch of perturbed ellipses of uneven size.
+
+    Per problem, from numpy.random.default_rng(seed) in this order: semi-axes a ~ U(0.8, 1.2)
+    and b ~ U(0.4, 0.8); radial perturbation 1 + sum_{m=2..8} c_m cos(m t + phi_m) of the
+    ellipse z = a cos t + i b sin t with c_m ~ U(0, 0.02/m^2) (one vector) and
+    phi_m ~ U(0, 2 pi) (one vector), redrawn until the contour is convex; N log-uniform in
+    n_range (rounded); the number of plane waves uniform in rhs_range; k from the perimeter L
+    at nodes_per_wavelength: k = 2 pi N / (nodes_per_wavelength L).  The contour's Fourier
+    coefficients (modes -9..9) come from 64 samples of the band-limited z(t).
+    Returns a list of dicts with zhat, n_nodes, k, angles."""
+    rng = np.random.default_rng(seed)
+    ms = np.arange(2, 9)
+    out = []
+    for _ in range(count):
+        a = rng.uniform(0.8, 1.2)
+        b = rng.uniform(0.4, 0.8)
+        while True:
+            c = rng.uniform(0.0, 0.02 / ms.astype(np.float64) ** 2)
+            phi = rng.uniform(0.0, 2.0 * math.pi, size=ms.size)
+            t = 2.0 * math.pi * np.arange(64) / 64
+            r = 1.0 + (c[:, None] * np.cos(np.outer(ms, t) + phi[:, None])).sum(axis=0)
+            z = (a * np.cos(t) + 1j * b * np.sin(t)) * r
+            f = np.fft.fft(z) / 64
+            M = 9
+            zhat = np.concatenate([f[-M:], f[:M + 1]]).astype(np.complex128)
+            if _convex(zhat):
+                break
+        N = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        m = int(rng.integers(rhs_range[0], rhs_range[1] + 1))
+        k = 2.0 * math.pi * N / (nodes_per_wavelength * _perimeter(zhat))
+        out.append(dict(zhat=zhat, n_nodes=N, k=k, angles=plane_wave_angles(m)))
+    return out
