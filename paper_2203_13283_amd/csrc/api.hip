@@ -167,8 +167,9 @@ struct cfie_ctx {
     ~cfie_ctx() {
         for (auto &r : prof.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : prof.pool) (void)hipEventDestroy(e);
-        for (auto &kv : live) (void)hipFree(kv.first);
+        for (auto &kv : live) (void)hipFreeAsync(kv.first, stream);
         live.clear();
+        (void)hipStreamSynchronize(stream);
         if (stream_owned && stream) (void)hipStreamDestroy(stream);
     }
     bool stream_owned = false;
@@ -177,11 +178,14 @@ struct cfie_ctx {
         if (opt.fail_alloc_after >= 0 && n_alloc >= opt.fail_alloc_after)
             throw HipError{CFIE_ENOMEM, "injected allocation failure"};
         ++n_alloc;
+        // stream-ordered allocation: no device-wide synchronisation, so that contexts on
+        // different streams (batched solves) keep running concurrently
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+        hipError_t e = hipMallocAsync(&p, bytes ? bytes : 16, stream);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            throw HipError{CFIE_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+            throw HipError{CFIE_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                            " bytes failed"};
         }
         live[p] = bytes;
         return p;
@@ -190,7 +194,7 @@ struct cfie_ctx {
         if (!p) return;
         auto it = live.find(p);
         if (it != live.end()) {
-            (void)hipFree(p);
+            (void)hipFreeAsync(p, stream);
             live.erase(it);
         }
     }
