@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="perturbed16384")
+    ap.add_argument("--workload", default="perturbed16384",
+                    help="perturbed16384 (the metric), ellipse4096, ellipse256, or batch64")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--eps", type=float, default=None,
                     help="compression tolerance (default 1e-5 fp64, 1e-3 mixed)")
@@ -154,12 +155,71 @@ def measured_traffic(kernel, launches_per_step):
     return float(vals["traffic_bytes_per_launch"])
 
 
+def batch_main(a):
+    """--workload batch64: 64 seeded perturbed ellipses, N log-uniform in [512, 8192], 32-512
+    plane waves each, every problem's whole path (assembly, factor, right-hand sides, solve)
+    through cfie_solve_batch over four streams.  value = aggregate right-hand sides solved per
+    second of wall time for the whole batch (setup included)."""
+    import torch
+    import workloads as W
+    import paper_2203_13283_amd as P
+    probs = W.batch_problems()
+    prec = P.CFIE_FP64 if a.precision == "fp64" else P.CFIE_MIXED
+    eps = a.eps if a.eps is not None else (1e-6 if prec == P.CFIE_FP64 else 1e-3)
+    nrhs = sum(p["angles"].size for p in probs)
+    for _ in range(a.warmup):
+        P.solve_batch(probs[:4], precision=prec, compress_tol=eps, block=128)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(a.steps):
+        t0 = time.perf_counter()
+        sols, res = P.solve_batch(probs, precision=prec, compress_tol=eps, block=128,
+                                  refine_tol=1e-8, n_streams=4)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    med = sorted(times)[len(times) // 2]
+    # accuracy of the last batch: FP64 residual of a few columns of three problems
+    worst = 0.0
+    for i in (0, len(probs) // 2, len(probs) - 1):
+        pr = probs[i]
+        s = P.Solver(compress_tol=eps, block=128)
+        s.assemble(pr["zhat"], pr["n_nodes"], pr["k"])
+        X = sols[i][:4].contiguous()
+        B = s.plane_wave_rhs(pr["angles"][:4])
+        R = s.apply(P.OP_C, X) - B
+        worst = max(worst, float((R.abs().pow(2).sum(1).sqrt() /
+                                  B.abs().pow(2).sum(1).sqrt()).max()))
+        del s
+    Ns = [p["n_nodes"] for p in probs]
+    out = {
+        "metric": "batched preconditioned-CFIE RHS solves/s (64 contours, uneven N, setup "
+                  "included)",
+        "value": nrhs / med, "unit": "RHS/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * med, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == P.CFIE_FP64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": "batch64: seeded perturbed ellipses a~U(0.8,1.2), "
+                               "b~U(0.4,0.8), N log-uniform in [512, 8192], 32-512 plane "
+                               "waves, 10 nodes/wavelength",
+                   "problems": len(probs), "N_min": min(Ns), "N_max": max(Ns),
+                   "nrhs_total": nrhs, "compress_tol": eps, "streams": 4,
+                   "precision": a.precision},
+        "problems_per_s": len(probs) / med,
+        "rel_residual_sampled": worst,
+        "max_rank": max(r["rank"] for r in res),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this "
               "build (the solver has no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batch64":
+        batch_main(a)
+        return
     import workloads as W
     w = W.get(a.workload)
     # the CPU leg runs first, before this process touches the GPU (its oracle workers fork)
