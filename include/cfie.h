@@ -154,6 +154,14 @@ cfie_status cfie_factor(cfie_ctx *ctx);
 cfie_status cfie_solve(cfie_ctx *ctx, const void *B_dev, int64_t ldb, void *X_dev,
                        int64_t ldx, int64_t nrhs);
 
+/* Adjoint solve X = C^-H B for nrhs right-hand sides with the same factorisation: with
+ * C = C_c + U V^T (Sec. V eqs. (7)-(9)), C^H = C_c^H + V U^H and the Woodbury identity holds
+ * with the capacitance matrix K^H and C_c^-H (conjugate eigenvalues), so no new factor is
+ * needed.  Used for adjoint sensitivities (g^H C^-1 b = (C^-H g)^H b).  Arguments, aliasing
+ * and errors as for cfie_solve; mixed precision refines against C^H in FP64. */
+cfie_status cfie_solve_adjoint(cfie_ctx *ctx, const void *B_dev, int64_t ldb, void *X_dev,
+                               int64_t ldx, int64_t nrhs);
+
 /* Step A8 (Sec. II eq. (4), Sec. III eq. (5)): right-hand sides b of eq. (5) for unit TE
  * plane waves H_z^inc = exp(i k d.r), d = (cos alpha_j, sin alpha_j); eta cancels.
  * angles_host: host, nrhs doubles.  B_dev: device, complex128, N x nrhs, ldb >= N.
@@ -167,7 +175,8 @@ enum {
     CFIE_OP_CC = 1,       /* C_c, circulant, by FFT                                        */
     CFIE_OP_CC_INV = 2,   /* C_c^-1 by FFT                                                 */
     CFIE_OP_REMAINDER = 3,/* C - C_c                                                        */
-    CFIE_OP_SKELETON = 4  /* U V^T, the compressed remainder (after cfie_factor)            */
+    CFIE_OP_SKELETON = 4, /* U V^T, the compressed remainder (after cfie_factor)            */
+    CFIE_OP_C_ADJ = 5     /* C^H, the adjoint of C, factor by factor                           */
 };
 
 /* Y = op X in complex128.  X_dev, Y_dev: device, N x nrhs column-major, ldx, ldy >= N,

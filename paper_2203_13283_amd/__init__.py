@@ -19,12 +19,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW, MAT_DK,
-                   MAT_DKT, MAT_G, MAT_NK, MAT_SKT, OP_C, OP_CC, OP_CC_INV, OP_REMAINDER,
-                   OP_SKELETON)
+                   MAT_DKT, MAT_G, MAT_NK, MAT_SKT, OP_C, OP_C_ADJ, OP_CC, OP_CC_INV,
+                   OP_REMAINDER, OP_SKELETON)
 
 __all__ = ["Solver", "solve_batch", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
            "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
-           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "load_library"]
+           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library"]
 
 
 def load_library():
@@ -135,6 +135,16 @@ class Solver:
                     "cfie_solve")
         return X
 
+    def solve_adjoint(self, B, out=None):
+        """X = C^-H B with the same factorisation (cfie_solve_adjoint)."""
+        self._check_batch(B, self.N, "B")
+        m = B.shape[0]
+        X = out if out is not None else self._batch(m)
+        self._check_batch(X, self.N, "X")
+        self._check(self._lib.cfie_solve_adjoint(self._h, _ptr(B), self.N, _ptr(X), self.N,
+                                                 m), "cfie_solve_adjoint")
+        return X
+
     def plane_wave_rhs(self, angles, out=None):
         a = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
         B = out if out is not None else self._batch(a.size)
@@ -144,7 +154,7 @@ class Solver:
         return B
 
     def apply(self, op: int, X):
-        """Y = op X for op in OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON."""
+        """Y = op X for op in OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON, OP_C_ADJ."""
         self._check_batch(X, self.N, "X")
         Y = self._batch(X.shape[0])
         self._check(self._lib.cfie_apply(self._h, op, _ptr(X), self.N, _ptr(Y), self.N,

@@ -22,13 +22,13 @@ CFIE_OK, CFIE_EINVAL, CFIE_ENOMEM, CFIE_EHIP, CFIE_ESTATE = 0, 1, 2, 3, 4
 CFIE_ESINGULAR, CFIE_ENOCONV, CFIE_WNONCONVEX = 5, 6, 100
 CFIE_FP64, CFIE_MIXED = 0, 1
 MAT_G, MAT_DK, MAT_NK, MAT_DKT, MAT_SKT, MAT_CC_EIG, MAT_CIRCLE_ROW = range(7)
-OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON = range(5)
+OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON, OP_C_ADJ = range(6)
 
 EXPORTED = [
     "cfie_default_options", "cfie_create", "cfie_assemble", "cfie_factor", "cfie_solve",
     "cfie_plane_wave_rhs", "cfie_apply", "cfie_export_matrix", "cfie_query",
     "cfie_last_error", "cfie_status_string", "cfie_destroy", "cfie_profile_reset",
-    "cfie_solve_batch",
+    "cfie_solve_batch", "cfie_solve_adjoint",
 ]
 
 
@@ -91,6 +91,8 @@ def load(path: str = LIB_PATH):
     lib.cfie_factor.restype = i32
     lib.cfie_solve.argtypes = [vp, vp, i64, vp, i64, i64]
     lib.cfie_solve.restype = i32
+    lib.cfie_solve_adjoint.argtypes = [vp, vp, i64, vp, i64, i64]
+    lib.cfie_solve_adjoint.restype = i32
     lib.cfie_plane_wave_rhs.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64, vp, i64]
     lib.cfie_plane_wave_rhs.restype = i32
     lib.cfie_apply.argtypes = [vp, ctypes.c_int, vp, i64, vp, i64, i64]

@@ -42,7 +42,8 @@ void randn(int64_t m, int64_t n, uint64_t seed, uint64_t stream, cpx<T> *X, int6
 template <typename T>
 void colnorm2(int64_t m, int64_t n, const cpx<T> *X, int64_t ldx, double *out, hipStream_t s);
 void launch_circ_eigs(int N, int N1, int N2, double h, const zd *mu, zd *c, zd *dC, zd *dCH,
-                      zd *dCinv, zf *fC, zf *fCH, zf *fCinv, double *absc, hipStream_t s);
+                      zd *dCinv, zd *dCinvH, zf *fC, zf *fCH, zf *fCinv, zf *fCinvH,
+                      double *absc, hipStream_t s);
 void launch_maxmin(int64_t n, const double *x, double *out, hipStream_t s);
 void launch_dft_direct_tw(int N, const zd *x, int64_t ldx, zd *y, int64_t ldy, int ncol,
                           const zd *twN, hipStream_t s);
@@ -53,6 +54,9 @@ void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *i
 template <typename T>
 void launch_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0,
                   int64_t c1, hipStream_t s);
+template <typename T>
+void launch_swaps_reverse(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0,
+                          int64_t c1, hipStream_t s);
 void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
                     hipStream_t s);
 void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s);
@@ -144,8 +148,8 @@ struct cfie_ctx {
     zd *mat[4] = {nullptr, nullptr, nullptr, nullptr};   // Dk, Nk, Dkt, Skt
     zf *mat32[4] = {nullptr, nullptr, nullptr, nullptr};
     zd *crow = nullptr, *mu = nullptr, *cvals = nullptr;
-    zd *dC = nullptr, *dCH = nullptr, *dCinv = nullptr;
-    zf *fC = nullptr, *fCH = nullptr, *fCinv = nullptr;
+    zd *dC = nullptr, *dCH = nullptr, *dCinv = nullptr, *dCinvH = nullptr;
+    zf *fC = nullptr, *fCH = nullptr, *fCinv = nullptr, *fCinvH = nullptr;
     double *absc = nullptr, *scal = nullptr;
     FFTPlan fft;
 
@@ -378,12 +382,14 @@ template <> struct Ops<double> {
     static const zd *dC(cfie_ctx *c) { return c->dC; }
     static const zd *dCH(cfie_ctx *c) { return c->dCH; }
     static const zd *dCinv(cfie_ctx *c) { return c->dCinv; }
+    static const zd *dCinvH(cfie_ctx *c) { return c->dCinvH; }
 };
 template <> struct Ops<float> {
     static zf *mat(cfie_ctx *c, int i) { return c->mat32[i]; }
     static const zf *dC(cfie_ctx *c) { return c->fC; }
     static const zf *dCH(cfie_ctx *c) { return c->fCH; }
     static const zf *dCinv(cfie_ctx *c) { return c->fCinv; }
+    static const zf *dCinvH(cfie_ctx *c) { return c->fCinvH; }
 };
 
 // Y = C X, C = (G/2 + Dkt) G^{-1} (G/2 - Dk) + Skt G^{-1} Nk   (eq. (6))
@@ -543,6 +549,36 @@ void lu_solve(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
     c->check_launch();
 }
 
+// solve K^H Z = Z in place with the LU factors of K (P K = L U, so K^H = U^H L^H P):
+// forward substitution with U^H, backward with L^H, then the row swaps in reverse order
+void lu_solve_adj(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
+    const int n = c->rank;
+    hipStream_t s = c->stream;
+    const int nb = kLUBlock;
+    const int nblk = (n + nb - 1) / nb;
+    for (int bi = 0; bi < nblk; ++bi) {
+        int k0 = bi * nb, kb = std::min(nb, n - k0);
+        gemm<double>(GEMM_C, kb, m, kb, cz<double>(1), c->Uinv + (size_t)bi * nb * nb, nb,
+                     Z + k0, ldz, cz<double>(0), tmp, kb, s);
+        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
+        int rest = n - k0 - kb;
+        if (rest > 0)
+            gemm<double>(GEMM_C, rest, m, kb, cz<double>(-1), c->K + k0 + (size_t)(k0 + kb) * c->cap,
+                         c->cap, Z + k0, ldz, cz<double>(1), Z + k0 + kb, ldz, s);
+    }
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        int k0 = bi * nb, kb = std::min(nb, n - k0);
+        gemm<double>(GEMM_C, kb, m, kb, cz<double>(1), c->Linv + (size_t)bi * nb * nb, nb,
+                     Z + k0, ldz, cz<double>(0), tmp, kb, s);
+        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
+        if (k0 > 0)
+            gemm<double>(GEMM_C, k0, m, kb, cz<double>(-1), c->K + k0, c->cap, Z + k0, ldz,
+                         cz<double>(1), Z, ldz, s);
+    }
+    launch_swaps_reverse<double>(0, n, c->piv, Z, ldz, 0, m, s);
+    c->check_launch();
+}
+
 template <typename T>
 cfie_status factor_impl(cfie_ctx *c) {
     const int N = c->N;
@@ -697,6 +733,116 @@ void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, cpx<T> *Z) {
     gemm<T>(GEMM_N, r, m, N, cz<T>(1), Wf, r, X, N, cz<T>(0), Z, r, s);
     gemm<T>(GEMM_N, N, m, r, cz<T>(-1), Ut, N, Z, r, cz<T>(1), X, N, s);
     c->check_launch();
+}
+
+// X <- C^{-H} X in precision T (X is N x m in T, ld N): with C = C_c + Q V^T,
+// C^H = C_c^H + (V^T)^H Q^H and the capacitance matrix of the adjoint Woodbury identity is
+// I + Q^H C_c^{-H} (V^T)^H = K^H, so
+// X = C_c^{-H} (X - (V^T)^H K^{-H} Q^H C_c^{-H} X).  Zr: rank x m (T), Z64: rank x m FP64,
+// Tn: N x m (T), tmp: 64 x m FP64.
+template <typename T>
+void woodbury_adj(cfie_ctx *c, cpx<T> *X, int64_t m, cpx<T> *Zr, zd *Z64, cpx<T> *Tn,
+                  zd *tmp) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    const int r = c->rank;
+    if (r == 0) {
+        circ_apply<T>(c, Ops<T>::dCinvH(c), X, N, m);
+        return;
+    }
+    const cpx<T> *Q = (const cpx<T> *)c->Q, *Vt = (const cpx<T> *)c->P;
+    axpby<T>(N, m, cz<T>(1), X, N, cz<T>(0), Tn, N, s);
+    circ_apply<T>(c, Ops<T>::dCinvH(c), Tn, N, m);
+    gemm<T>(GEMM_C, r, m, N, cz<T>(1), Q, N, Tn, N, cz<T>(0), Zr, r, s);
+    convert<double, T>(r, m, Zr, r, Z64, r, s);
+    lu_solve_adj(c, Z64, r, m, tmp);
+    convert<T, double>(r, m, Z64, r, Zr, r, s);
+    gemm<T>(GEMM_C, N, m, r, cz<T>(-1), Vt, r, Zr, r, cz<T>(1), X, N, s);
+    circ_apply<T>(c, Ops<T>::dCinvH(c), X, N, m);
+    c->check_launch();
+}
+
+// Y = C^H X = (C - C_c)^H X + C_c^H X in precision T
+template <typename T>
+void apply_CH(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
+              cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z) {
+    const int N = c->N;
+    apply_RH<T>(c, X, ldx, Y, ldy, m, Tt, W1, W2, Z);
+    axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, c->stream);
+    circ_apply<T>(c, Ops<T>::dCH(c), Z, N, m);
+    axpby<T>(N, m, cz<T>(1), Z, N, cz<T>(1), Y, ldy, c->stream);
+}
+
+// adjoint solves C^H X = B: FP64 directly; mixed precision with FP64 refinement against C^H
+cfie_status solve_adjoint(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx,
+                          int64_t nrhs) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    const bool mixed = c->opt.precision == CFIE_MIXED;
+    const int64_t chunk = 1024;
+    const int r = std::max(c->rank, 1);
+    const int64_t mc = std::min<int64_t>(nrhs, chunk);
+    zd *Xw = c->alloc_n<zd>((size_t)N * mc), *Tn = c->alloc_n<zd>((size_t)N * mc);
+    zd *Z64 = c->alloc_n<zd>((size_t)r * mc), *Zr = c->alloc_n<zd>((size_t)r * mc);
+    zd *tmp = c->alloc_n<zd>((size_t)kLUBlock * mc);
+    zd *Rb = nullptr, *W1 = nullptr, *W2 = nullptr, *Tt = nullptr;
+    zf *R32 = nullptr, *T32 = nullptr, *Zr32 = nullptr;
+    double *b2 = nullptr, *r2 = nullptr, *mx = nullptr;
+    if (mixed) {
+        Rb = c->alloc_n<zd>((size_t)N * mc);
+        W1 = c->alloc_n<zd>((size_t)N * mc);
+        W2 = c->alloc_n<zd>((size_t)N * mc);
+        Tt = c->alloc_n<zd>((size_t)N * mc);
+        R32 = c->alloc_n<zf>((size_t)N * mc);
+        T32 = c->alloc_n<zf>((size_t)N * mc);
+        Zr32 = c->alloc_n<zf>((size_t)r * mc);
+        b2 = c->alloc_n<double>(mc);
+        r2 = c->alloc_n<double>(mc);
+        mx = c->alloc_n<double>(2);
+    }
+    cfie_status st = CFIE_OK;
+    int sweeps_max = 0;
+    double worst = 0.0;
+    for (int64_t j = 0; j < nrhs; j += chunk) {
+        const int64_t m = std::min(chunk, nrhs - j);
+        const zd *Bj = B + j * ldb;
+        if (!mixed) {
+            axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(0), Xw, N, s);
+            woodbury_adj<double>(c, Xw, m, Zr, Z64, Tn, tmp);
+        } else {
+            colnorm2<double>(N, m, Bj, ldb, b2, s);
+            axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(0), Rb, N, s);
+            HIPCHK(hipMemsetAsync(Xw, 0, sizeof(zd) * (size_t)N * m, s));
+            int sweep = 0;
+            double rel = 1e300;
+            for (; sweep < std::max(1, c->opt.max_refine); ++sweep) {
+                convert<float, double>(N, m, Rb, N, R32, N, s);
+                woodbury_adj<float>(c, R32, m, Zr32, Z64, T32, tmp);
+                convert<double, float>(N, m, R32, N, Tn, N, s);
+                axpby<double>(N, m, cz<double>(1), Tn, N, cz<double>(1), Xw, N, s);
+                apply_CH<double>(c, Xw, N, Rb, N, m, Tt, W1, W2, Tn);
+                axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(-1), Rb, N, s);
+                colnorm2<double>(N, m, Rb, N, r2, s);
+                launch_ratio_max(m, r2, b2, mx, s);
+                HIPCHK(hipMemcpyAsync(&rel, mx, sizeof(double), hipMemcpyDeviceToHost, s));
+                c->sync();
+                if (rel <= c->opt.refine_tol) { ++sweep; break; }
+            }
+            sweeps_max = std::max(sweeps_max, sweep);
+            worst = std::max(worst, rel);
+            if (rel > c->opt.refine_tol) st = CFIE_ENOCONV;
+        }
+        axpby<double>(N, m, cz<double>(1), Xw, N, cz<double>(0), X + j * ldx, ldx, s);
+    }
+    c->sync();
+    void *bufs[] = {Xw, Tn, Z64, Zr, tmp, Rb, W1, W2, Tt, R32, T32, Zr32, b2, r2, mx};
+    for (void *p : bufs) c->dfree(p);
+    if (mixed) {
+        c->refine_sweeps = sweeps_max;
+        c->refine_res = worst;
+        if (st == CFIE_ENOCONV) return fail(c, CFIE_ENOCONV, "refinement did not converge");
+    }
+    return st;
 }
 
 cfie_status solve_fp64(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx, int64_t nrhs) {
@@ -960,7 +1106,8 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         free_factor(c);
         for (int i = 0; i < 4; ++i) { c->dfree(c->mat[i]); c->mat[i] = nullptr; c->dfree(c->mat32[i]); c->mat32[i] = nullptr; }
         free_points(c, c->pf); free_points(c, c->pn); free_points(c, c->cf); free_points(c, c->cn);
-        void *old[] = {c->crow, c->mu, c->cvals, c->dC, c->dCH, c->dCinv, c->fC, c->fCH, c->fCinv,
+        void *old[] = {c->crow, c->mu, c->cvals, c->dC, c->dCH, c->dCinv, c->dCinvH, c->fC,
+                       c->fCH, c->fCinv, c->fCinvH,
                        c->absc, c->scal, c->d_xf, c->d_wf, c->d_xn, c->d_wn, c->d_mom, c->d_gcoef};
         for (void *p : old) c->dfree(p);
         c->state = 0;
@@ -1047,22 +1194,27 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         c->cvals = c->alloc_n<zd>(N);
         const int M = c->fft.M;
         c->dC = c->alloc_n<zd>(M); c->dCH = c->alloc_n<zd>(M); c->dCinv = c->alloc_n<zd>(M);
+        c->dCinvH = c->alloc_n<zd>(M);
         c->fC = c->alloc_n<zf>(M); c->fCH = c->alloc_n<zf>(M); c->fCinv = c->alloc_n<zf>(M);
+        c->fCinvH = c->alloc_n<zf>(M);
         c->absc = c->alloc_n<double>(N);
         c->scal = c->alloc_n<double>(4);
         if (M == N) {
             launch_circ_eigs(N, c->fft.N1, c->fft.N2, h, c->mu, c->cvals, c->dC, c->dCH,
-                             c->dCinv, c->fC, c->fCH, c->fCinv, c->absc, s);
+                             c->dCinv, c->dCinvH, c->fC, c->fCH, c->fCinv, c->fCinvH, c->absc,
+                             s);
         } else {
             // natural-order eigenvalues / N, then the padded convolution diagonals
-            zd *nat = c->alloc_n<zd>(3 * (size_t)N);
-            zf *natf = c->alloc_n<zf>(3 * (size_t)N);
+            zd *nat = c->alloc_n<zd>(4 * (size_t)N);
+            zf *natf = c->alloc_n<zf>(4 * (size_t)N);
             zd *work = c->alloc_n<zd>(3 * (size_t)M);
             launch_circ_eigs(N, N, 1, h, c->mu, c->cvals, nat, nat + N, nat + 2 * (size_t)N,
-                             natf, natf + N, natf + 2 * (size_t)N, c->absc, s);
+                             nat + 3 * (size_t)N, natf, natf + N, natf + 2 * (size_t)N,
+                             natf + 3 * (size_t)N, c->absc, s);
             launch_padded_diagonal(c->fft, nat, work, c->dC, c->fC, s);
             launch_padded_diagonal(c->fft, nat + N, work, c->dCH, c->fCH, s);
             launch_padded_diagonal(c->fft, nat + 2 * (size_t)N, work, c->dCinv, c->fCinv, s);
+            launch_padded_diagonal(c->fft, nat + 3 * (size_t)N, work, c->dCinvH, c->fCinvH, s);
             c->sync();
             c->dfree(nat);
             c->dfree(natf);
@@ -1142,6 +1294,20 @@ cfie_status cfie_solve(cfie_ctx *c, const void *B, int64_t ldb, void *X, int64_t
     });
 }
 
+cfie_status cfie_solve_adjoint(cfie_ctx *c, const void *B, int64_t ldb, void *X,
+                               int64_t ldx, int64_t nrhs) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 2) return fail(c, CFIE_ESTATE, "cfie_solve_adjoint before cfie_factor");
+    if (nrhs < 0) return fail(c, CFIE_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return CFIE_OK;
+    if (!B || !X) return fail(c, CFIE_EINVAL, "NULL B or X");
+    if (ldb < c->N || ldx < c->N) return fail(c, CFIE_EINVAL, "leading dimension < N");
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        return solve_adjoint(c, (const zd *)B, ldb, (zd *)X, ldx, nrhs);
+    });
+}
+
 cfie_status cfie_plane_wave_rhs(cfie_ctx *c, const double *angles, int64_t nrhs, void *Bv,
                                 int64_t ldb) {
     if (!c) return CFIE_EINVAL;
@@ -1181,7 +1347,7 @@ cfie_status cfie_plane_wave_rhs(cfie_ctx *c, const double *angles, int64_t nrhs,
 cfie_status cfie_apply(cfie_ctx *c, int op, const void *X, int64_t ldx, void *Y,
                        int64_t ldy, int64_t nrhs) {
     if (!c) return CFIE_EINVAL;
-    if (op < CFIE_OP_C || op > CFIE_OP_SKELETON) return fail(c, CFIE_EINVAL, "unknown operator");
+    if (op < CFIE_OP_C || op > CFIE_OP_C_ADJ) return fail(c, CFIE_EINVAL, "unknown operator");
     if (c->state < 1) return fail(c, CFIE_ESTATE, "cfie_apply before cfie_assemble");
     if (op == CFIE_OP_SKELETON && c->state < 2)
         return fail(c, CFIE_ESTATE, "skeleton requested before cfie_factor");
@@ -1201,6 +1367,9 @@ cfie_status cfie_apply(cfie_ctx *c, int op, const void *X, int64_t ldx, void *Y,
         switch (op) {
             case CFIE_OP_C:
                 apply_C<double>(c, Xd, ldx, Yd, ldy, nrhs, Tt, W1, W2);
+                break;
+            case CFIE_OP_C_ADJ:
+                apply_CH<double>(c, Xd, ldx, Yd, ldy, nrhs, Tt, W1, W2, Z);
                 break;
             case CFIE_OP_CC:
             case CFIE_OP_CC_INV:

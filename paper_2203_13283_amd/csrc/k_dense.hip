@@ -261,8 +261,8 @@ template void colnorm2<float>(int64_t, int64_t, const zf *, int64_t, double *, h
 // Writes c (natural) and the diagonals for the FFT layout: dC = c/N, dCH = conj(c)/N,
 // dCinv = 1/(N c), in double and float.
 __global__ void k_circ_eigs(int N, int N1, int N2, double h, const zd *__restrict__ mu,
-                            zd *c, zd *dC, zd *dCH, zd *dCinv, zf *fC, zf *fCH, zf *fCinv,
-                            double *absc) {
+                            zd *c, zd *dC, zd *dCH, zd *dCinv, zd *dCinvH, zf *fC, zf *fCH,
+                            zf *fCinv, zf *fCinvH, double *absc) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= N) return;
     zd md = mu[m], mn = mu[m + N], mdt = mu[m + 2 * N], ms = mu[m + 3 * N];
@@ -276,17 +276,21 @@ __global__ void k_circ_eigs(int N, int N1, int N2, double h, const zd *__restric
     int p = k1 + N1 * k2;
     double invN = 1.0 / N;
     zd a = cm * invN, b = conj(cm) * invN, ci = cinv(cm) * invN;
+    const zd cih = conj(ci);
     dC[p] = a;
     dCH[p] = b;
     dCinv[p] = ci;
+    dCinvH[p] = cih;
     fC[p] = mk((float)a.x, (float)a.y);
     fCH[p] = mk((float)b.x, (float)b.y);
     fCinv[p] = mk((float)ci.x, (float)ci.y);
+    fCinvH[p] = mk((float)cih.x, (float)cih.y);
 }
 void launch_circ_eigs(int N, int N1, int N2, double h, const zd *mu, zd *c, zd *dC, zd *dCH,
-                      zd *dCinv, zf *fC, zf *fCH, zf *fCinv, double *absc, hipStream_t s) {
+                      zd *dCinv, zd *dCinvH, zf *fC, zf *fCH, zf *fCinv, zf *fCinvH,
+                      double *absc, hipStream_t s) {
     hipLaunchKernelGGL(k_circ_eigs, dim3((N + 255) / 256), dim3(256), 0, s, N, N1, N2, h, mu, c,
-                       dC, dCH, dCinv, fC, fCH, fCinv, absc);
+                       dC, dCH, dCinv, dCinvH, fC, fCH, fCinv, fCinvH, absc);
 }
 
 // max over n doubles (single block)
@@ -695,6 +699,17 @@ void launch_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_
     hipLaunchKernelGGL(k_swaps<T>, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, k0, k1, piv, A,
                        lda, c0, c1, false);
 }
+// the inverse permutation: the swaps of piv[k0 .. k1) in reverse order
+template <typename T>
+void launch_swaps_reverse(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0,
+                          int64_t c1, hipStream_t s) {
+    if (c1 <= c0 || k1 <= k0) return;
+    int64_t n = c1 - c0;
+    hipLaunchKernelGGL(k_swaps<T>, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, k0, k1,
+                       piv, A, lda, c0, c1, true);
+}
+template void launch_swaps_reverse<double>(int, int, const int *, zd *, int64_t, int64_t,
+                                           int64_t, hipStream_t);
 template void launch_swaps<double>(int, int, const int *, zd *, int64_t, int64_t, int64_t,
                                    hipStream_t);
 

@@ -113,6 +113,34 @@ def test_solve_in_place_and_ragged_batch(cfg1, cfg1_solver):
     assert S.rel_err(_np(X).T, x_ref) <= 1e-10
 
 
+def test_adjoint_solve_matches_dense_lu(cfg1, cfg1_solver):
+    """C^H x = g with the same factorisation (adjoint Woodbury, conjugate circulant
+    eigenvalues, K^H from the LU of K) against a dense LU of the oracle's C^H; the adjoint
+    operator against the oracle's C^H; the adjoint identity g^H C^-1 b = (C^-H g)^H b."""
+    w, prob = cfg1
+    s = cfg1_solver
+    s.factor()
+    g = torch.randn((3, w.n_nodes), dtype=torch.complex128, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(5))
+    lam = _np(s.solve_adjoint(g)).T
+    ref = np.linalg.solve(prob.C.conj().T, _np(g).T)
+    err = S.rel_err(lam, ref)
+    print(f"adjoint fp64: rel.err {err:.2e}")
+    assert err <= 1e-10
+    y = _np(s.apply(P.OP_C_ADJ, g)).T
+    assert np.abs(y - prob.C.conj().T @ _np(g).T).max() <= 1e-12 * np.abs(y).max()
+    B = s.plane_wave_rhs(w.angles[:3])
+    X = _np(s.solve(B)).T
+    lhs = np.einsum("ij,ij->j", _np(g).T.conj(), X)
+    rhs = np.einsum("ij,ij->j", lam.conj(), _np(B).T)
+    assert np.abs(lhs - rhs).max() <= 1e-11 * np.abs(lhs).max()
+    sm = P.Solver(precision=P.CFIE_MIXED, compress_tol=1e-3, refine_tol=1e-9)
+    sm.assemble(w.zhat, w.n_nodes, w.k).factor()
+    errm = S.rel_err(_np(sm.solve_adjoint(g)).T, ref)
+    print(f"adjoint mixed: sweeps {sm.info()['refine_sweeps']} rel.err {errm:.2e}")
+    assert errm <= 1e-6
+
+
 def test_circle_remainder_vanishes():
     """Circle: C = C_c up to rounding (the same rules on the same mesh), so at the FP64
     tolerance the skeleton has rank 0 and the FFT solve alone is the answer."""
