@@ -93,9 +93,9 @@ def accuracy(P, s, w, B, X):
 def cpu_baseline(w):
     """The CPU oracle on a bounded sample of this workload, scaled to it.
 
-    Sample: the oracle's dense assembly at N_s = 1024 nodes of the same contour and the same
+    Sample: the oracle's dense assembly at N_s = 2048 nodes of the same contour and the same
     nodes per wavelength, then its dense C, LU and triangular solves for 64 right-hand
-    sides.  Scaling to N: assembly ~ N^2 (pairs of elements), form C + LU ~ N^3, solve ~ N^2
+    sides (about 20 s of CPU work on 16 cores).  Scaling to N: assembly ~ N^2 (pairs of elements), form C + LU ~ N^3, solve ~ N^2
     per right-hand side."""
     import numpy as np
     import scipy.linalg as sla
@@ -103,7 +103,7 @@ def cpu_baseline(w):
     from oracle import system as S
     # the GPU machine grants this job a share of 16 host cores
     cores = max(1, min(16, os.cpu_count() or 1))
-    Ns = 1024
+    Ns = 2048
     ks = w.k * Ns / w.n_nodes
     L = S.Contour(w.zhat).L
     kts = S.ktilde(ks, L)
