@@ -14,6 +14,11 @@
   Laplace parts (R / 2|n| for S, |n| / 2R for N) are summed exactly with Hurwitz zeta.
 * The exact PEC-cylinder (Mie) current for TE incidence H_z^inc = e^{ik d.r}:
     j_t(phi) = -H_z^tot = -sum_n i^n 2i / (pi k R H_n'(kR)) e^{in(phi - alpha)}.
+* Its far field: H_z^s ~ e^{ikr} r^{-1/2} F(phi) with
+    F(phi) = sqrt(2/(pi k)) e^{-i pi/4} sum_n b_n e^{in(phi - alpha)},  b_n = -J_n'(kR)/H_n'(kR)
+  (large-argument form of H_n in the scattered field sum_n i^n b_n H_n(kr) e^{in(phi-alpha)}),
+  and its radius derivative from Bessel's equation, f'' = -f'/x - (1 - n^2/x^2) f, and the
+  Wronskian J_n H_n' - J_n' H_n = 2i/(pi x):  d b_n/dx = (1 - n^2/x^2) (2i/(pi x)) / H_n'^2.
 * Gram matrix: G = h circ(2/3, 1/6, ..., 1/6); its inverse has first column
   (6/h) (rho^n + rho^{N-n}) / (2 sqrt 3 (1 - rho^N)),  rho = sqrt 3 - 2.
 """
@@ -170,6 +175,22 @@ def mie_current(k, R, phi, alpha, nmax=None):
     coef = (1j ** n) * 2j / (np.pi * x * Hp)
     ph = np.exp(1j * np.outer(np.asarray(phi) - alpha, n))
     return -(ph @ coef)
+
+
+def mie_far_field(k, R, phi, alpha, nmax=None):
+    """(F, dF/dR) of the PEC circle of radius R for the TE plane wave from direction alpha."""
+    x = k * R
+    if nmax is None:
+        nmax = int(abs(x) + 40 + 4 * abs(x) ** (1 / 3))
+    n = np.arange(-nmax, nmax + 1)
+    sg = np.where(n < 0, (-1.0) ** np.abs(n), 1.0)
+    Jp = sps.jvp(np.abs(n), x) * sg
+    Hp = sps.h1vp(np.abs(n), x) * sg
+    c = np.sqrt(2.0 / (np.pi * k)) * np.exp(-0.25j * np.pi)
+    E = np.exp(1j * np.outer(np.asarray(phi, dtype=np.float64) - alpha, n))
+    F = c * (E @ (-Jp / Hp))
+    dF = c * (E @ (k * (1.0 - n ** 2 / x ** 2) * (2j / (np.pi * x)) / Hp ** 2))
+    return F, dF
 
 
 def gram_inverse_column(N, h):

@@ -9,9 +9,14 @@ workload it stores, in tests/golden/<name>.npz:
   b, x                     right-hand sides of eq. (5) and dense-LU solutions for them
   L, k, kt_re, kt_im, N    constants
 
-Also spectra<N>: singular values of C and C - C_c with their spatial-frequency labels.
+Also spectra<N>: singular values of C and C - C_c with their spatial-frequency labels, and
+shapegrad<N>: the backscatter loss of the shape-differentiation workload at N nodes (shape
+modes 1..8, four incident waves, 181 observation angles each), its far fields and the
+reference gradient with respect to the 16 shape coefficients (central differences with two
+Richardson extrapolations of the oracle's dense solve).
 
-Run:  python tests/golden/make_golden.py ellipse4096 perturbed16384 spectra512 [--workers 8]
+Run:  python tests/golden/make_golden.py ellipse4096 perturbed16384 spectra512 shapegrad128
+      [--workers 8]
 (about 2 minutes for ellipse4096 and 40 minutes for perturbed16384 on 8 cores; the
 larger one needs about 40 GB of host memory).
 """
@@ -89,6 +94,26 @@ def make_spectra(N: int, workers: int):
     print(f"spectra_ellipse{N}: written", flush=True)
 
 
+def make_shapegrad(N: int, workers: int, mmax: int = 8, n_inc: int = 4, fd_step: float = 1e-3):
+    from oracle import gradient as G
+    pr = W.shape_problem(N=N, mmax=mmax, n_inc=n_inc)
+    s, t = pr["s"], pr["t"]
+    p0 = np.concatenate([s, t])
+
+    def loss(p):
+        return G.backscatter_loss(W.shape_to_zhat(p[:mmax], p[mmax:]), N, pr["k"],
+                                  pr["angles"], pr["obs"], workers=workers)[0]
+
+    t0 = time.time()
+    L0, F = G.backscatter_loss(pr["zhat"], N, pr["k"], pr["angles"], pr["obs"], workers=workers)
+    grad = G.richardson_gradient(loss, p0, fd_step)
+    print(f"shapegrad{N}: loss {L0:.6e}, gradient in {time.time() - t0:.0f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, f"shapegrad{N}.npz"), N=N, mmax=mmax, k=pr["k"],
+                        s=s, t=t, zhat=pr["zhat"], angles=pr["angles"], obs=pr["obs"], L=L0,
+                        F=F, grad=grad, fd_step=fd_step)
+    print(f"shapegrad{N}: written", flush=True)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("names", nargs="+")
@@ -97,5 +122,7 @@ if __name__ == "__main__":
     for n in a.names:
         if n.startswith("spectra"):
             make_spectra(int(n[len("spectra"):]), a.workers)
+        elif n.startswith("shapegrad"):
+            make_shapegrad(int(n[len("shapegrad"):]), a.workers)
         else:
             make(n, a.workers)

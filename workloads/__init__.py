@@ -27,6 +27,11 @@ __all__ = [
     "circle_coeffs",
     "plane_wave_angles",
     "batch_problems",
+    "shape_coeffs",
+    "shape_to_zhat",
+    "shape_jacobian",
+    "backscatter_angles",
+    "shape_problem",
     "WORKLOADS",
     "get",
 ]
@@ -166,3 +171,68 @@ def batch_problems(count: int = 64, seed: int = 0, n_range=(512, 8192), rhs_rang
         k = 2.0 * math.pi * N / (nodes_per_wavelength * _perimeter(zhat))
         out.append(dict(zhat=zhat, n_nodes=N, k=k, angles=plane_wave_angles(m)))
     return out
+
+def shape_coeffs(seed: int = 0, mmax: int = 64, amp: float = 0.01):
+    """Shape coefficients of r(theta) = 1 + sum_{m=1..mmax} s_m cos(m theta) + t_m sin(m theta)
+    with s_m, t_m ~ N(0, (amp/m)^2): s drawn as one vector, then t, from
+    numpy.random.default_rng(seed).  Returns (s, t)."""
+    rng = np.random.default_rng(seed)
+    ms = np.arange(1, mmax + 1, dtype=np.float64)
+    s = rng.normal(0.0, 1.0, mmax) * (amp / ms)
+    t = rng.normal(0.0, 1.0, mmax) * (amp / ms)
+    return s, t
+
+
+def shape_to_zhat(s, t) -> np.ndarray:
+    """z(theta) = r(theta) e^{i theta} for the radial series of shape_coeffs, as Fourier
+    modes -(mmax-1) .. mmax+1 (M = mmax + 1): cos(m th) e^{i th} = (e^{i(m+1)th} +
+    e^{-i(m-1)th})/2 and sin(m th) e^{i th} = (e^{i(m+1)th} - e^{-i(m-1)th})/(2i)."""
+    s = np.asarray(s, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    mmax = s.size
+    M = mmax + 1
+    zhat = np.zeros(2 * M + 1, dtype=np.complex128)
+    zhat[M + 1] += 1.0
+    for m in range(1, mmax + 1):
+        zhat[M + 1 + m] += 0.5 * (s[m - 1] - 1j * t[m - 1])
+        zhat[M + 1 - m] += 0.5 * (s[m - 1] + 1j * t[m - 1])
+    return zhat
+
+
+def shape_jacobian(mmax: int) -> np.ndarray:
+    """d(Re zhat, Im zhat interleaved) / d(s_1..s_mmax, t_1..t_mmax): the real
+    (2 (2M+1)) x (2 mmax) matrix of the linear map shape_to_zhat (M = mmax + 1)."""
+    M = mmax + 1
+    J = np.zeros((2 * (2 * M + 1), 2 * mmax))
+    for m in range(1, mmax + 1):
+        up, dn = M + 1 + m, M + 1 - m
+        J[2 * up, m - 1] += 0.5
+        J[2 * dn, m - 1] += 0.5
+        J[2 * up + 1, mmax + m - 1] += -0.5
+        J[2 * dn + 1, mmax + m - 1] += 0.5
+    return J
+
+
+def backscatter_angles(inc_angles, n_obs: int = 181) -> np.ndarray:
+    """Observation angles around the backscatter direction of each incident wave: for the
+    wave propagating along alpha_j, n_obs angles alpha_j + pi + (o - (n_obs-1)/2) pi/(n_obs-1),
+    o = 0..n_obs-1 (the half circle facing the source, 1 degree apart for 181 angles, the
+    exact backscatter direction in the middle).  Returns a (m, n_obs) array."""
+    a = np.asarray(inc_angles, dtype=np.float64)
+    o = np.arange(n_obs, dtype=np.float64)
+    step = math.pi / max(n_obs - 1, 1)
+    return a[:, None] + math.pi + (o[None, :] - (n_obs - 1) / 2.0) * step
+
+
+def shape_problem(N: int = 8192, mmax: int = 64, seed: int = 0, n_inc: int = 16,
+                  n_obs: int = 181, amp: float = 0.01, nodes_per_wavelength: float = 10.0):
+    """The shape-differentiation workload: the seeded contour of shape_coeffs, N nodes, k at
+    nodes_per_wavelength for the seed's perimeter, n_inc plane waves at 2 pi j / n_inc and
+    n_obs backscatter observation angles per wave.  Returns a dict with s, t, zhat, n_nodes,
+    k, angles (incident), obs (n_inc x n_obs)."""
+    s, t = shape_coeffs(seed, mmax, amp)
+    zhat = shape_to_zhat(s, t)
+    k = 2.0 * math.pi * N / (nodes_per_wavelength * _perimeter(zhat, 8192))
+    ang = plane_wave_angles(n_inc)
+    return dict(s=s, t=t, zhat=zhat, n_nodes=N, k=k, angles=ang,
+                obs=backscatter_angles(ang, n_obs))
