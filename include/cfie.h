@@ -169,6 +169,39 @@ cfie_status cfie_solve_adjoint(cfie_ctx *ctx, const void *B_dev, int64_t ldb, vo
 cfie_status cfie_plane_wave_rhs(cfie_ctx *ctx, const double *angles_host, int64_t nrhs,
                                 void *B_dev, int64_t ldb);
 
+/* Far-field pattern of the field scattered by the surface currents X (Sec. II: the unknown
+ * of eq. (5) is the tangential current j_t = sum_i x_i lambda_i; with H_z^tot = -j_t on
+ * gamma, Green's representation and the large-argument form of H0 give
+ * H_z^s ~ exp(i k r) r^(-1/2) F(phi)), for the directions dhat = (cos phi, sin phi):
+ *   F(phi) = -sqrt(k/(8 pi)) exp(-i pi/4) int j_t(s) (dhat.n) exp(-i k dhat.r(s)) ds.
+ * X_dev: device, complex128, N x nrhs column-major (ldx >= N).  obs_angles_host: host,
+ * n_obs doubles.  F_dev: device, complex128, n_obs x nrhs column-major (ldf >= n_obs):
+ * F[o + j ldf] is the far field of column j in direction o.  ESTATE before assemble;
+ * EINVAL for negative sizes, NULL pointers or non-finite angles. */
+cfie_status cfie_far_field(cfie_ctx *ctx, const void *X_dev, int64_t ldx, int64_t nrhs,
+                           const double *obs_angles_host, int64_t n_obs, void *F_dev,
+                           int64_t ldf);
+
+/* Reverse-mode derivative, with respect to the contour coefficients, of a real function L of
+ * the far fields F = cfie_far_field(X, obs) of the solutions X = C^-1 b of eq. (5) for the
+ * plane waves inc_angles_host (as from cfie_plane_wave_rhs and cfie_solve).
+ *   dF_dev: dL/dRe F + i dL/dIm F, device, complex128, n_obs x nrhs (lddf >= n_obs);
+ *   grad_host: host, 2 (2M+1) doubles: grad[2m] = dL/dRe zhat[m], grad[2m+1] = dL/dIm zhat[m]
+ *   in the order of cfie_contour.zhat.
+ * It is the derivative of the discrete problem that cfie_assemble defines (nodes uniform in
+ * arc length, its quadrature rules, kt through the perimeter): the adjoint lambda = C^-H g
+ * comes from cfie_solve_adjoint with the same factorisation; backward kernels of the
+ * assembly, of the plane-wave vectors and of the far-field functional give the derivatives
+ * with respect to the Gauss points, the element length and kt, which are chained through the
+ * arc-length parametrisation to zhat.  C_c does not enter (C^-1 b does not depend on it).
+ * Work space: four N x N complex128 matrices of loss weights.  ESTATE before factor; EINVAL
+ * for negative sizes, NULL pointers or non-finite angles; nrhs == 0 or n_obs == 0 gives a zero
+ * gradient. */
+cfie_status cfie_shape_gradient(cfie_ctx *ctx, const double *inc_angles_host, int64_t nrhs,
+                                const void *X_dev, int64_t ldx,
+                                const double *obs_angles_host, int64_t n_obs,
+                                const void *dF_dev, int64_t lddf, double *grad_host);
+
 /* Operators that cfie_apply can apply (Sec. V eqs. (6)-(9)). */
 enum {
     CFIE_OP_C = 0,        /* C of eq. (6), factor by factor from the assembled matrices  */

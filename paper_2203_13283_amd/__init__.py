@@ -7,6 +7,9 @@
     X = s.solve(B)                      # step A6 (+ A7 refinement in mixed precision)
 
     X_list, results = solve_batch(problems)   # many contours of uneven N at once
+    F = s.far_field(X, obs)             # far field of the currents (m, n_obs)
+    g = s.shape_gradient(angles, X, obs, dF)  # d loss / d zhat for dF = d loss / d F
+    F = far_field_of_shape(zhat_ri, N, k, angles, obs)   # the same as a torch.autograd op
 
 Batches are (m, N) complex128 CUDA tensors (row j = right-hand side j).  The compute runs
 in libcfie.so; torch is used for device memory and the current stream only.
@@ -22,7 +25,7 @@ from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW,
                    MAT_DKT, MAT_G, MAT_NK, MAT_SKT, OP_C, OP_C_ADJ, OP_CC, OP_CC_INV,
                    OP_REMAINDER, OP_SKELETON)
 
-__all__ = ["Solver", "solve_batch", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
+__all__ = ["Solver", "solve_batch", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
            "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
            "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library"]
 
@@ -120,6 +123,7 @@ class Solver:
         self._check(self._lib.cfie_assemble(self._h, ctypes.byref(c), float(k)),
                     "cfie_assemble")
         self.N = n_nodes
+        self._modes = z.size
         return self
 
     def factor(self):
@@ -152,6 +156,43 @@ class Solver:
             self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size, _ptr(B),
             self.N), "cfie_plane_wave_rhs")
         return B
+
+    def far_field(self, X, obs_angles, out=None):
+        """Far field F[j, o] of the currents X[j] in the directions obs_angles
+        (cfie_far_field); X is (m, N) complex128, the result (m, n_obs) complex128."""
+        torch = _torch()
+        self._check_batch(X, self.N, "X")
+        a = np.ascontiguousarray(np.asarray(obs_angles, dtype=np.float64).ravel())
+        m = X.shape[0]
+        F = out if out is not None else torch.empty((m, a.size), dtype=torch.complex128,
+                                                    device=self.device)
+        if F.shape != (m, a.size) or F.dtype != torch.complex128 or not F.is_contiguous():
+            raise ValueError("F must be a contiguous (m, n_obs) complex128 tensor")
+        self._check(self._lib.cfie_far_field(
+            self._h, _ptr(X), self.N, m, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            a.size, _ptr(F), a.size), "cfie_far_field")
+        return F
+
+    def shape_gradient(self, inc_angles, X, obs_angles, dF):
+        """d loss / d zhat (real view: (2M+1, 2) float64 array of d/dRe, d/dIm) for a real
+        loss of F = far_field(X, obs_angles), X the solutions for the plane waves inc_angles,
+        given dF = d loss/d Re F + i d loss/d Im F as an (m, n_obs) complex128 tensor
+        (cfie_shape_gradient)."""
+        torch = _torch()
+        self._check_batch(X, self.N, "X")
+        inc = np.ascontiguousarray(np.asarray(inc_angles, dtype=np.float64).ravel())
+        obs = np.ascontiguousarray(np.asarray(obs_angles, dtype=np.float64).ravel())
+        m = X.shape[0]
+        if inc.size != m:
+            raise ValueError("one incident angle per row of X")
+        if dF.shape != (m, obs.size) or dF.dtype != torch.complex128 or not dF.is_contiguous():
+            raise ValueError("dF must be a contiguous (m, n_obs) complex128 tensor")
+        grad = np.zeros((self._modes, 2))
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self._lib.cfie_shape_gradient(
+            self._h, inc.ctypes.data_as(dp), m, _ptr(X), self.N, obs.ctypes.data_as(dp),
+            obs.size, _ptr(dF), obs.size, grad.ctypes.data_as(dp)), "cfie_shape_gradient")
+        return grad
 
     def apply(self, op: int, X):
         """Y = op X for op in OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON, OP_C_ADJ."""
@@ -190,6 +231,52 @@ class Solver:
 
     def profile_reset(self):
         self._check(self._lib.cfie_profile_reset(self._h), "cfie_profile_reset")
+
+
+class _FarFieldOfShape:
+    """torch.autograd.Function built lazily (torch is imported on first use)."""
+    fn = None
+
+    @classmethod
+    def get(cls):
+        if cls.fn is None:
+            torch = _torch()
+
+            class FarFieldOfShape(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, zhat_ri, n_nodes, k, inc_angles, obs_angles, options):
+                    z = zhat_ri.detach().cpu().numpy()
+                    zhat = z[:, 0] + 1j * z[:, 1]
+                    s = Solver(**(options or {}))
+                    s.assemble(zhat, int(n_nodes), float(k))
+                    s.factor()
+                    X = s.solve(s.plane_wave_rhs(inc_angles))
+                    F = s.far_field(X, obs_angles)
+                    ctx.state = (s, X, np.asarray(inc_angles), np.asarray(obs_angles),
+                                 zhat_ri.dtype, zhat_ri.device)
+                    return F
+
+                @staticmethod
+                def backward(ctx, dF):
+                    s, X, inc, obs, dt, dev = ctx.state
+                    g = s.shape_gradient(inc, X, obs, dF.contiguous())
+                    ctx.state = None
+                    return torch.as_tensor(g, dtype=dt, device=dev), None, None, None, None, None
+
+            cls.fn = FarFieldOfShape
+        return cls.fn
+
+
+def far_field_of_shape(zhat_ri, n_nodes: int, k: float, inc_angles, obs_angles, **options):
+    """Differentiable far field of the scattered field for the contour zhat_ri.
+
+    zhat_ri: (2M+1, 2) float64 tensor of the contour's Fourier coefficients (real and
+    imaginary parts); returns F (m, n_obs) complex128 on the GPU, F[j, o] the far field of
+    the plane wave inc_angles[j] in the direction obs_angles[o].  The forward pass runs the
+    whole solver (assemble, factor, right-hand sides, solve, far field); the backward pass is
+    cfie_shape_gradient (adjoint solve with the same factorisation and the backward kernels
+    of the assembly)."""
+    return _FarFieldOfShape.get().apply(zhat_ri, n_nodes, k, inc_angles, obs_angles, options)
 
 
 def solve_batch(problems, precision: int = CFIE_FP64, compress_tol: float = 1e-10,

@@ -28,7 +28,7 @@ EXPORTED = [
     "cfie_default_options", "cfie_create", "cfie_assemble", "cfie_factor", "cfie_solve",
     "cfie_plane_wave_rhs", "cfie_apply", "cfie_export_matrix", "cfie_query",
     "cfie_last_error", "cfie_status_string", "cfie_destroy", "cfie_profile_reset",
-    "cfie_solve_batch", "cfie_solve_adjoint",
+    "cfie_solve_batch", "cfie_solve_adjoint", "cfie_far_field", "cfie_shape_gradient",
 ]
 
 
@@ -112,6 +112,11 @@ def load(path: str = LIB_PATH):
     lib.cfie_solve_batch.argtypes = [ctypes.POINTER(Options), ctypes.c_int, ctypes.c_int,
                                      ctypes.POINTER(BatchItem), i64]
     lib.cfie_solve_batch.restype = i32
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.cfie_far_field.argtypes = [vp, vp, i64, i64, dp, i64, vp, i64]
+    lib.cfie_far_field.restype = i32
+    lib.cfie_shape_gradient.argtypes = [vp, dp, i64, vp, i64, dp, i64, vp, i64, dp]
+    lib.cfie_shape_gradient.restype = i32
     _lib = lib
     return lib
 

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcfie.so")
 SOURCES = ["api.hip", "geometry.cpp", "k_assemble.hip", "k_fft.hip", "k_gemm.hip",
-           "k_dense.hip"]
+           "k_dense.hip",
+           "k_shape_grad.hip"]
 ARCH = os.environ.get("CFIE_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

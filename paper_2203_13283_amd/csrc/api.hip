@@ -1344,6 +1344,207 @@ cfie_status cfie_plane_wave_rhs(cfie_ctx *c, const double *angles, int64_t nrhs,
     });
 }
 
+// F = c_F E'(obs + pi)^T X: the far field of the currents X in the directions obs, with
+// c_F = sqrt(k/(8 pi)) e^{-i pi/4} and e'_i(obs + pi) = -int lambda_i (dhat.n) e^{-ik dhat.r}.
+static zd far_field_const(double k) {
+    const double r2 = 0.70710678118654752440;
+    return mk(r2, -r2) * std::sqrt(k / (8.0 * kPi));
+}
+
+cfie_status cfie_far_field(cfie_ctx *c, const void *X, int64_t ldx, int64_t nrhs,
+                           const double *obs, int64_t n_obs, void *F, int64_t ldf) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 1) return fail(c, CFIE_ESTATE, "cfie_far_field before cfie_assemble");
+    if (nrhs < 0 || n_obs < 0) return fail(c, CFIE_EINVAL, "nrhs and n_obs must be >= 0");
+    if (nrhs == 0 || n_obs == 0) return CFIE_OK;
+    if (!X || !F || !obs) return fail(c, CFIE_EINVAL, "NULL X, F or angles");
+    if (ldx < c->N || ldf < n_obs) return fail(c, CFIE_EINVAL, "leading dimension too small");
+    for (int64_t i = 0; i < n_obs; ++i)
+        if (!std::isfinite(obs[i])) return fail(c, CFIE_EINVAL, "non-finite angle");
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        const int N = c->N;
+        hipStream_t s = c->stream;
+        std::vector<double> ang(n_obs);
+        for (int64_t i = 0; i < n_obs; ++i) ang[i] = obs[i] + kPi;
+        double *d_ang = c->alloc_n<double>(n_obs);
+        c->upload(d_ang, ang.data(), n_obs);
+        zd *Eo = c->alloc_n<zd>((size_t)N * n_obs);
+        launch_excitation(c->gd, c->pn, c->d_xn, c->d_wn, c->k, d_ang, n_obs, Eo, nullptr, N, s);
+        launch_conj_scale(N, n_obs, Eo, N, Eo, N, mk(1.0, 0.0), s);
+        gemm<double>(GEMM_C, n_obs, nrhs, N, far_field_const(c->k), Eo, N, (const zd *)X, ldx,
+                     cz<double>(0), (zd *)F, ldf, s);
+        c->check_launch();
+        c->sync();
+        c->dfree(d_ang);
+        c->dfree(Eo);
+        return CFIE_OK;
+    });
+}
+
+cfie_status cfie_shape_gradient(cfie_ctx *c, const double *inc, int64_t nrhs, const void *Xv,
+                                int64_t ldx, const double *obs, int64_t n_obs, const void *dFv,
+                                int64_t lddf, double *grad) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 2) return fail(c, CFIE_ESTATE, "cfie_shape_gradient before cfie_factor");
+    if (nrhs < 0 || n_obs < 0) return fail(c, CFIE_EINVAL, "nrhs and n_obs must be >= 0");
+    if (!grad) return fail(c, CFIE_EINVAL, "NULL gradient");
+    if (nrhs > 0 && n_obs > 0 && (!inc || !Xv || !obs || !dFv))
+        return fail(c, CFIE_EINVAL, "NULL angles, X or dF");
+    if (ldx < c->N || lddf < n_obs) return fail(c, CFIE_EINVAL, "leading dimension too small");
+    for (int64_t i = 0; i < nrhs; ++i)
+        if (!std::isfinite(inc[i])) return fail(c, CFIE_EINVAL, "non-finite angle");
+    for (int64_t i = 0; i < n_obs; ++i)
+        if (!std::isfinite(obs[i])) return fail(c, CFIE_EINVAL, "non-finite angle");
+    const int M = c->hg.M;
+    for (int i = 0; i < 2 * (2 * M + 1); ++i) grad[i] = 0.0;
+    if (nrhs == 0 || n_obs == 0) return CFIE_OK;
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        const int N = c->N;
+        const int64_t m = nrhs;
+        hipStream_t s = c->stream;
+        const double h = c->hg.L / N;
+        const double k = c->k;
+        const zd cF = far_field_const(k);
+        const zd *X = (const zd *)Xv;
+        const zd *dF = (const zd *)dFv;
+        const int nt = (int)c->gcoef.size();
+        auto ginv = [&](const zd *Y, zd *out) {
+            launch_ginv_ex<double>(N, nt, c->g_t0, c->d_gcoef, cz<double>(0), nullptr, 0,
+                                   cz<double>(1), Y, N, out, N, m, s);
+        };
+        const size_t nm = (size_t)N * m;
+        // plane-wave vectors of the incident and (reversed) observation directions
+        std::vector<double> ango(n_obs);
+        for (int64_t i = 0; i < n_obs; ++i) ango[i] = obs[i] + kPi;
+        double *d_inc = c->alloc_n<double>(m), *d_obs = c->alloc_n<double>(n_obs);
+        c->upload(d_inc, inc, m);
+        c->upload(d_obs, ango.data(), n_obs);
+        zd *E = c->alloc_n<zd>(nm), *H = c->alloc_n<zd>(nm);
+        zd *w1 = c->alloc_n<zd>(nm), *w2 = c->alloc_n<zd>(nm);
+        zd *Eo = c->alloc_n<zd>((size_t)N * n_obs);
+        launch_excitation(c->gd, c->pn, c->d_xn, c->d_wn, k, d_inc, m, E, H, N, s);
+        launch_excitation(c->gd, c->pn, c->d_xn, c->d_wn, k, d_obs, n_obs, Eo, nullptr, N, s);
+        ginv(E, w1);
+        ginv(H, w2);
+        // adjoint right-hand side g = conj(c_F) conj(E_o) dF and lambda = C^-H g
+        zd *lam = c->alloc_n<zd>(nm), *T = c->alloc_n<zd>(nm);
+        gemm<double>(GEMM_R, N, m, n_obs, conj(cF), Eo, N, dF, lddf, cz<double>(0), T, N, s);
+        cfie_status st = solve_adjoint(c, T, N, lam, N, m);
+        if (st != CFIE_OK && st != CFIE_ENOCONV) return st;
+        // y1 = G^-1 Dk x, y2 = G^-1 Nk x, z1 = G^-1 Dkt^H lambda, z2 = G^-1 Skt^H lambda
+        zd *y1 = c->alloc_n<zd>(nm), *y2 = c->alloc_n<zd>(nm);
+        zd *z1 = c->alloc_n<zd>(nm), *z2 = c->alloc_n<zd>(nm);
+        gemm<double>(GEMM_N, N, m, N, cz<double>(1), c->mat[0], N, X, ldx, cz<double>(0), T, N, s);
+        ginv(T, y1);
+        gemm<double>(GEMM_N, N, m, N, cz<double>(1), c->mat[1], N, X, ldx, cz<double>(0), T, N, s);
+        ginv(T, y2);
+        gemm<double>(GEMM_C, N, m, N, cz<double>(1), c->mat[2], N, lam, N, cz<double>(0), T, N, s);
+        ginv(T, z1);
+        gemm<double>(GEMM_C, N, m, N, cz<double>(1), c->mat[3], N, lam, N, cz<double>(0), T, N, s);
+        ginv(T, z2);
+        // loss weights Omega_M = conj(A_M) B_M^T of the four assembled matrices:
+        //   Dk: A = lambda/2 + z1, B = x;          Nk: A = z2, B = -x;
+        //   Dkt: A = lambda, B = y1 - x/2 - w2;     Skt: A = lambda, B = -(y2 + i k w1)
+        zd *v = c->alloc_n<zd>(nm), *Bt = c->alloc_n<zd>(nm);
+        axpby<double>(N, m, cz<double>(0.5), lam, N, cz<double>(0), v, N, s);
+        axpby<double>(N, m, cz<double>(1), z1, N, cz<double>(1), v, N, s);
+        const size_t nn = (size_t)N * N;
+        zd *Om[4];
+        for (int i = 0; i < 4; ++i) Om[i] = c->alloc_n<zd>(nn);
+        launch_transpose(N, m, X, ldx, Bt, m, cz<double>(1), false, s);
+        gemm<double>(GEMM_R, N, N, m, cz<double>(1), v, N, Bt, m, cz<double>(0), Om[0], N, s);
+        gemm<double>(GEMM_R, N, N, m, cz<double>(-1), z2, N, Bt, m, cz<double>(0), Om[1], N, s);
+        axpby<double>(N, m, cz<double>(-0.5), X, ldx, cz<double>(0), T, N, s);
+        axpby<double>(N, m, cz<double>(1), y1, N, cz<double>(1), T, N, s);
+        axpby<double>(N, m, cz<double>(-1), w2, N, cz<double>(1), T, N, s);
+        launch_transpose(N, m, T, N, Bt, m, cz<double>(1), false, s);
+        gemm<double>(GEMM_R, N, N, m, cz<double>(1), lam, N, Bt, m, cz<double>(0), Om[2], N, s);
+        axpby<double>(N, m, mk(0.0, k), w1, N, cz<double>(0), T, N, s);
+        axpby<double>(N, m, cz<double>(1), y2, N, cz<double>(1), T, N, s);
+        launch_transpose(N, m, T, N, Bt, m, cz<double>(-1), false, s);
+        gemm<double>(GEMM_R, N, N, m, cz<double>(1), lam, N, Bt, m, cz<double>(0), Om[3], N, s);
+        // observation weights omega_o = c_F X dF^H (N x n_obs)
+        zd *dFh = c->alloc_n<zd>((size_t)m * n_obs), *Wo = c->alloc_n<zd>((size_t)N * n_obs);
+        launch_transpose(n_obs, m, dF, lddf, dFh, m, cz<double>(1), true, s);
+        gemm<double>(GEMM_N, N, n_obs, m, cF, X, ldx, dFh, m, cz<double>(0), Wo, N, s);
+        // backward kernels
+        const int qf = c->pf.q, qn = c->pn.q;
+        const int64_t npf = (int64_t)N * qf, npn = (int64_t)N * qn;
+        const int n_strips = (N + 127) / 128;
+        double *adjf = c->alloc_n<double>(4 * npf), *adjn = c->alloc_n<double>(5 * npn);
+        double *part = c->alloc_n<double>((size_t)n_strips * 4 * npf);
+        const int n_eg = (N + 63) / 64;
+        double *sp_far = c->alloc_n<double>(2 * (size_t)n_eg * n_strips);
+        const int bn = (int)((npn + 127) / 128), be = (int)((npn + 255) / 256);
+        double *sp_near = c->alloc_n<double>(2 * (size_t)bn);
+        double *sp_exc = c->alloc_n<double>(2 * (size_t)be);
+        const int bg = (int)((nm + 255) / 256);
+        double *sp_g = c->alloc_n<double>(5 * (size_t)bg);
+        KernelConsts kc;
+        kc.k = k;
+        kc.kt = c->kt;
+        const int nb = std::min(c->opt.near_band, N);
+        const zd *const Omc[4] = {Om[0], Om[1], Om[2], Om[3]};
+        int n_waves = 0;
+        launch_grad_far(N, h, kc, nb, Omc, N, c->pf, c->xf.data(), c->wf.data(), part, sp_far,
+                        adjf, n_waves, s);
+        launch_grad_near(N, h, kc, nb, Omc, N, c->pn, c->xn.data(), c->wn.data(), c->d_mom, adjn,
+                         sp_near, s);
+        launch_grad_exc(N, h, k, c->pn, c->d_xn, c->d_wn, d_inc, m, z2, N, mk(0.0, -k), true, v,
+                        N, cz<double>(-1), true, adjn, sp_exc, s);
+        launch_grad_exc(N, h, k, c->pn, c->d_xn, c->d_wn, d_obs, n_obs, Wo, N, cz<double>(1),
+                        false, nullptr, 0, cz<double>(0), false, adjn, sp_exc + be, s);
+        // explicit h in G = h circ(2/3, 1/6, ..., 1/6):
+        // Re[-lambda^H G x/4 - z1^H G y1 + z2^H G y2 + i k z2^H G w1 + z1^H G w2] / h
+        launch_gdot(N, m, h, lam, N, X, ldx, cz<double>(-0.25 / h), sp_g, s);
+        launch_gdot(N, m, h, z1, N, y1, N, cz<double>(-1.0 / h), sp_g + bg, s);
+        launch_gdot(N, m, h, z2, N, y2, N, cz<double>(1.0 / h), sp_g + 2 * bg, s);
+        launch_gdot(N, m, h, z2, N, w1, N, mk(0.0, k / h), sp_g + 3 * bg, s);
+        launch_gdot(N, m, h, z1, N, w2, N, cz<double>(1.0 / h), sp_g + 4 * bg, s);
+        // chain to the contour coefficients
+        double *Pf = c->alloc_n<double>(10 * npf), *Pn = c->alloc_n<double>(10 * npn);
+        launch_grad_prep(c->gd, c->pf, c->d_xf, adjf, false, Pf, s);
+        launch_grad_prep(c->gd, c->pn, c->d_xn, adjn, true, Pn, s);
+        const int Ms = (int)c->hg.cm.size();
+        const int nmodes = 2 * M + Ms + 2;
+        zd *modes = c->alloc_n<zd>(nmodes);
+        launch_grad_modes(M, Ms, npf, Pf, npn, Pn, modes, s);
+        c->check_launch();
+        std::vector<double> hsf(2 * (size_t)n_waves), hsn(2 * (size_t)bn), hse(2 * (size_t)be),
+            hsg(5 * (size_t)bg);
+        std::vector<zd> hm(nmodes);
+        HIPCHK(hipMemcpyAsync(hsf.data(), sp_far, hsf.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hsn.data(), sp_near, hsn.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hse.data(), sp_exc, hse.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hsg.data(), sp_g, hsg.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hm.data(), modes, nmodes * sizeof(zd), hipMemcpyDeviceToHost, s));
+        c->sync();
+        double hbar = 0.0, bbar = 0.0;
+        for (int i = 0; i < n_waves; ++i) { hbar += hsf[2 * i]; bbar += hsf[2 * i + 1]; }
+        for (int i = 0; i < bn; ++i) { hbar += hsn[2 * i]; bbar += hsn[2 * i + 1]; }
+        for (double x : hse) hbar += x;
+        for (double x : hsg) hbar += x;
+        // h = L / N = 2 pi c0 / N;  beta = 0.4 k^(1/3) a^(-2/3), a = L / (2 pi) = c0
+        const double c0 = c->hg.c0;
+        double c0bar = hm[2 * M + Ms + 1].x + hbar * 2.0 * kPi / N +
+                       bbar * (-2.0 / 3.0) * c->kt.y / c0;
+        std::vector<zd> zbar(hm.begin(), hm.begin() + 2 * M + 1);
+        std::vector<zd> cmbar(hm.begin() + 2 * M + 1, hm.begin() + 2 * M + 1 + Ms);
+        speed_coeffs_adjoint(c->hg, c0bar, cmbar, zbar);
+        for (int i = 0; i < 2 * M + 1; ++i) {
+            grad[2 * i] = zbar[i].x;
+            grad[2 * i + 1] = zbar[i].y;
+        }
+        void *bufs[] = {d_inc, d_obs, E, H, w1, w2, Eo, lam, T, y1, y2, z1, z2, v, Bt, Om[0],
+                        Om[1], Om[2], Om[3], dFh, Wo, adjf, adjn, part, sp_far, sp_near, sp_exc,
+                        sp_g, Pf, Pn, modes};
+        for (void *p : bufs) c->dfree(p);
+        return st;
+    });
+}
+
 cfie_status cfie_apply(cfie_ctx *c, int op, const void *X, int64_t ldx, void *Y,
                        int64_t ldy, int64_t nrhs) {
     if (!c) return CFIE_EINVAL;

@@ -152,6 +152,40 @@ std::string build_geometry(const cfie_contour &c, HostGeometry &g) {
     return "";
 }
 
+// The speed coefficients are c0 = (1/P) sum_j |z'(tau_j)| and c_m = (1/P) sum_j |z'(tau_j)|
+// e^{-i m tau_j} on the P-point grid tau_j = 2 pi j / P of build_geometry (m = 1..Ms, the
+// retained modes), and d|z'| = Re(conj(T) dz') with the unit tangent T.  With the loss
+// differential Re(conj(cbar_m) dc_m) + c0bar dc0, the sample adjoints are
+//   spbar_j = (c0bar + sum_m Re(conj(cbar_m) e^{-i m tau_j})) / P
+// and zbar_m += sum_j spbar_j T_j conj(i m e^{i m tau_j}).
+void speed_coeffs_adjoint(const HostGeometry &g, double c0bar, const std::vector<zd> &cmbar,
+                          std::vector<zd> &zbar) {
+    int P = 4096;
+    while (P < 64 * (2 * g.M + 1)) P *= 2;
+    const int Ms = (int)g.cm.size();
+    std::vector<zd> roots(P);
+    for (int j = 0; j < P; ++j)
+        roots[j] = mk(std::cos(2.0 * kPi * j / P), -std::sin(2.0 * kPi * j / P));
+    for (int j = 0; j < P; ++j) {
+        double sb = c0bar;
+        for (int m = 1; m <= Ms && m <= (int)cmbar.size(); ++m) {
+            zd E = roots[(long)m * j % P];
+            sb += (conj(cmbar[m - 1]) * E).x;
+        }
+        sb /= P;
+        if (sb == 0.0) continue;
+        zd d1 = zeval(g.zhat, g.M, 2.0 * kPi * j / P, 1);
+        double sp = cabs(d1);
+        zd T = d1 * (1.0 / sp);
+        for (int m = -g.M; m <= g.M; ++m) {
+            // conj(i m e^{i m tau}) = -i m e^{-i m tau}
+            zd E = roots[(long)(((m % P) + P) % P) * j % P];
+            zd w = cmul_i(E) * (-(double)m);
+            zbar[m + g.M] = zbar[m + g.M] + T * w * sb;
+        }
+    }
+}
+
 HostGeometry circle_geometry(double radius) {
     HostGeometry g;
     g.M = 1;

@@ -117,10 +117,44 @@ void launch_assemble_far(const AsmParams &p, const PointTable &far, const double
 void launch_assemble_near(const AsmParams &p, const PointTable &near, const double *xi,
                           const double *w, const double *moments, hipStream_t s);
 
-// Plane-wave right-hand-side vectors e' and h (N x m each).
+// Plane-wave right-hand-side vectors e' and h (N x m each; hvec may be NULL).
 void launch_excitation(const GeomDev &g, const PointTable &pt, const double *xi,
                        const double *w, double k, const double *angles, int64_t m,
                        zd *e, zd *hvec, int64_t ld, hipStream_t s);
+
+// ------------------------------------------------------------------ shape derivative -----
+// Backward passes of the assembly (far and near element pairs), of the plane-wave vectors and
+// of the point evaluation; Om = loss weights of (Dk, Nk, Dkt, Skt), column-major, ld.
+// far: adj (4 x N q_far) = d loss / d(x, y, tx, ty) of the far table; part: n_strips x 4 x
+// N q_far work space (n_strips = ceil(N / 128)); spart: 2 per wave (d/dh, d/dbeta), n_waves
+// returned.
+void launch_grad_far(int N, double h, const KernelConsts &kc, int nb, const zd *const Om[4],
+                     int64_t ld, const PointTable &pt, const double *xi, const double *w,
+                     double *part, double *spart, double *adj, int &n_waves, hipStream_t s);
+// near: adj (5 x N q_near, with curvature) written; spart: 2 per block; returns the blocks
+int launch_grad_near(int N, double h, const KernelConsts &kc, int nb, const zd *const Om[4],
+                     int64_t ld, const PointTable &pt, const double *xi, const double *w,
+                     const double *moments, double *adj, double *spart, hipStream_t s);
+// plane-wave vectors: adds to adj[0..3]; spart: d/dh per block; returns the blocks
+int launch_grad_exc(int N, double h, double k, const PointTable &pt, const double *xi,
+                    const double *w, const double *angles, int64_t m, const zd *WE,
+                    int64_t lde, zd aE, bool cE, const zd *WH, int64_t ldh, zd aH, bool cH,
+                    double *adj, double *spart, hipStream_t s);
+// per point: t, 2 pi sigma - t, (d/dt)/s'(t), adjoints of z, z', z'' (10 doubles)
+void launch_grad_prep(const GeomDev &g, const PointTable &pt, const double *xi,
+                      const double *adj, bool has_curv, double *out, hipStream_t s);
+// reductions onto the modes of z (2M+1), of the speed (Ms) and onto c0 (1)
+void launch_grad_modes(int M, int Ms, int64_t n1, const double *P1, int64_t n2,
+                       const double *P2, zd *out, hipStream_t s);
+int launch_gdot(int N, int64_t m, double h, const zd *A, int64_t lda, const zd *B, int64_t ldb,
+                zd coef, double *part, hipStream_t s);
+void launch_transpose(int64_t rows, int64_t cols, const zd *src, int64_t lds, zd *dst,
+                      int64_t ldd, zd alpha, bool cj, hipStream_t s);
+void launch_conj_scale(int64_t rows, int64_t cols, const zd *src, int64_t lds, zd *dst,
+                       int64_t ldd, zd alpha, hipStream_t s);
+// adjoint of the speed coefficients (c0, c_1..c_Ms) of build_geometry onto zbar (2M+1, +=)
+void speed_coeffs_adjoint(const HostGeometry &g, double c0bar, const std::vector<zd> &cmbar,
+                          std::vector<zd> &zbar);
 
 // ------------------------------------------------------------------ FFT ------------------
 struct FFTPlan {

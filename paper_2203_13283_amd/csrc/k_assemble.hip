@@ -18,6 +18,7 @@
 // smooth: B by Gauss-Legendre on the q x q grid, A by product integration with the
 // precomputed moments int int l_g l_h phi_a phi_b log(sigma).
 #include "internal.h"
+#include "pair_kernels.h"
 
 namespace cfie {
 
@@ -29,39 +30,9 @@ __global__ void k_points(int N, int q, double h, double L, double c0, int Ms, co
     if (idx >= N * q) return;
     int e = idx / q, g = idx - e * q;
     double s = ((double)e + xi[g]) * h;
-    double t = 2.0 * kPi * s / L;
-    int extra = 2;
-    for (int it = 0; it < 60; ++it) {
-        double sn, cs;
-        sincos(t, &sn, &cs);
-        zd E1 = mk(cs, sn), E = E1;
-        double st = c0 * t, sp = c0;
-        for (int m = 1; m <= Ms; ++m) {
-            zd c = cm[m - 1];
-            zd cE = c * E;
-            sp += 2.0 * cE.x;
-            st += 2.0 * (cE.y - c.y) / (double)m;     // 2 Re(c (E - 1) / (i m))
-            E = E * E1;
-        }
-        double dt = (st - s) / sp;
-        t -= dt;
-        if (fabs(dt) < 1e-14) {
-            if (--extra == 0) break;
-        }
-    }
-    double sn, cs;
-    sincos(t, &sn, &cs);
-    zd E1 = mk(cs, sn);
-    sincos(-(double)M * t, &sn, &cs);
-    zd E = mk(cs, sn);
-    zd z = mk(0.0, 0.0), d1 = mk(0.0, 0.0), d2 = mk(0.0, 0.0);
-    for (int m = -M; m <= M; ++m) {
-        zd v = zhat[m + M] * E;
-        z = z + v;
-        d1 = d1 + cmul_i(v) * (double)m;
-        d2 = d2 - v * ((double)m * (double)m);
-        E = E * E1;
-    }
+    double t = arc_param(s, L, c0, Ms, cm);
+    zd z, d1, d2, d3;
+    contour_derivs(t, M, zhat, z, d1, d2, d3);
     double sp = sqrt(d1.x * d1.x + d1.y * d1.y);
     X[idx] = z.x;
     Y[idx] = z.y;
@@ -75,125 +46,6 @@ void launch_points(const GeomDev &g, const double *xi, PointTable &pt, hipStream
     int bs = 256;
     hipLaunchKernelGGL(k_points, dim3((n + bs - 1) / bs), dim3(bs), 0, s, g.N, pt.q, g.h, g.L,
                        g.c0, g.Ms, g.cm, g.M, g.zhat, xi, pt.x, pt.y, pt.tx, pt.ty, pt.curv);
-}
-
-// ------------------------------------------------------------------ kernel values ---------
-// Large-argument Hankel expansion (DLMF 10.17.5): H_nu(z) = sqrt(2/(pi z)) e^{i(z - nu pi/2 -
-// pi/4)} F_nu(z), F_nu(z) = sum_n a_n(nu) (i/z)^n, a_n(nu) = prod_{j<=n} (4nu^2 - (2j-1)^2)/(8j).
-// Truncated after T terms: T = 8, 12, 22 keep the first omitted term below 3e-17 relative for
-// |z| >= 200, 50, 22.  For the real argument x = k R the even and odd terms give F = P + i Q
-// with P, Q polynomials in 1/x^2; for kt R the series is a complex Horner in w = i/(kt R).
-// The coefficients are compile-time constants.
-constexpr int kSerMax = 22;
-struct SerCoef {
-    double a[2][kSerMax];            // a_n(nu)
-    double p[2][kSerMax / 2];        // (-1)^j a_2j(nu)
-    double q[2][kSerMax / 2];        // (-1)^j a_2j+1(nu)
-};
-constexpr SerCoef make_ser() {
-    SerCoef c{};
-    for (int nu = 0; nu < 2; ++nu) {
-        double an = 1.0;
-        for (int n = 0; n < kSerMax; ++n) {
-            if (n > 0) {
-                double m = (double)(2 * n - 1);
-                an *= (4.0 * nu * nu - m * m) / (8.0 * n);
-            }
-            c.a[nu][n] = an;
-            double sg = ((n / 2) % 2) ? -1.0 : 1.0;
-            if (n % 2 == 0) c.p[nu][n / 2] = sg * an;
-            else c.q[nu][n / 2] = sg * an;
-        }
-    }
-    return c;
-}
-constexpr SerCoef kSer = make_ser();
-
-struct PairConsts {
-    double k, beta, invk;            // kt = k + i beta
-    zd kt, iwk;                      // iwk = i / kt
-    zd Cg, CD, CS, CDt;              // prefactors of the large-argument forms
-    zd ik4, ikt4;                    // i k / 4, i kt / 4
-};
-
-// Large-argument kernels (k R >= 22 for this lane) with a T-term series.
-template <int T>
-__device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R, double nu,
-                                                  zd &gk, zd &Dk, zd &St, zd &Dt) {
-    const double invR = 1.0 / R;
-    double sn, cs;
-    sincos(c.k * R, &sn, &cs);
-    const double rs = rsqrt(R);
-    const zd E = mk(cs * rs, sn * rs);                   // e^{ikR} R^{-1/2}
-    const zd Et = E * exp(-c.beta * R);
-    const double y = invR * c.invk, y2 = y * y;
-    double P0 = kSer.p[0][T / 2 - 1], Q0 = kSer.q[0][T / 2 - 1];
-    double P1 = kSer.p[1][T / 2 - 1], Q1 = kSer.q[1][T / 2 - 1];
-#pragma unroll
-    for (int j = T / 2 - 2; j >= 0; --j) {
-        P0 = fma(P0, y2, kSer.p[0][j]);
-        Q0 = fma(Q0, y2, kSer.q[0][j]);
-        P1 = fma(P1, y2, kSer.p[1][j]);
-        Q1 = fma(Q1, y2, kSer.q[1][j]);
-    }
-    const zd w = c.iwk * invR;                           // i / (kt R)
-    zd s0 = mk(kSer.a[0][T - 1], 0.0), s1 = mk(kSer.a[1][T - 1], 0.0);
-#pragma unroll
-    for (int n = T - 2; n >= 0; --n) {
-        s0 = mk(fma(s0.x, w.x, fma(-s0.y, w.y, kSer.a[0][n])), fma(s0.x, w.y, s0.y * w.x));
-        s1 = mk(fma(s1.x, w.x, fma(-s1.y, w.y, kSer.a[1][n])), fma(s1.x, w.y, s1.y * w.x));
-    }
-    gk = c.Cg * E * mk(P0, Q0 * y);
-    Dk = c.CD * E * mk(P1, Q1 * y) * nu;
-    St = c.CS * Et * s0;
-    Dt = c.CDt * Et * s1 * nu;
-}
-
-// Any argument: ascending series / Miller recurrence below k R = 22 (kept out of line so
-// that the register allocation of the far kernel's main loop is not sized for it).
-__device__ __attribute__((noinline)) void pair_kernels_small(const PairConsts &c, double R,
-                                                             double nu, zd &gk, zd &Dk,
-                                                             zd &St, zd &Dt) {
-    zd H0, H1;
-    hankel01(mk(c.k * R, 0.0), H0, H1);
-    gk = cmul_i(H0) * 0.25;
-    Dk = c.ik4 * H1 * nu;
-    hankel01(c.kt * R, H0, H1);
-    St = cmul_i(H0) * 0.25;
-    Dt = c.ikt4 * H1 * nu;
-}
-
-// Point-pair kernels: gk = (i/4) H0(kR), Dk = (ik/4) H1(kR) nu, St = (i/4) H0(ktR),
-// Dt = (ikt/4) H1(ktR) nu, with nu = (r - r').n' / R.  Per-thread choice of the form.
-__device__ __forceinline__ void pair_kernels(const PairConsts &c, double R, double nu,
-                                             zd &gk, zd &Dk, zd &St, zd &Dt) {
-    const double kR = c.k * R;
-    if (kR >= 200.0) pair_kernels_asym<8>(c, R, nu, gk, Dk, St, Dt);
-    else if (kR >= 50.0) pair_kernels_asym<12>(c, R, nu, gk, Dk, St, Dt);
-    else if (kR >= kAsymMin) pair_kernels_asym<kSerMax>(c, R, nu, gk, Dk, St, Dt);
-    else pair_kernels_small(c, R, nu, gk, Dk, St, Dt);
-}
-
-static PairConsts make_consts(const KernelConsts &kc) {
-    PairConsts c;
-    c.k = kc.k;
-    c.kt = kc.kt;
-    c.beta = kc.kt.y;
-    c.invk = 1.0 / kc.k;
-    c.iwk = cmul_i(cinv(kc.kt));
-    const double r2 = 0.70710678118654752440;
-    zd em1 = mk(r2, -r2);                                // e^{-i pi/4}
-    zd em3 = mk(-r2, -r2);                               // e^{-3 i pi/4}
-    zd pk = mk(std::sqrt(2.0 / (kPi * kc.k)), 0.0);      // sqrt(2/(pi k))
-    zd pt = csqrt(cinv(kc.kt) * (2.0 / kPi));             // sqrt(2/(pi kt))
-    zd i4 = mk(0.0, 0.25);
-    c.ik4 = mk(0.0, 0.25 * kc.k);
-    c.ikt4 = cmul_i(kc.kt) * 0.25;
-    c.Cg = i4 * pk * em1;
-    c.CD = c.ik4 * pk * em3;
-    c.CS = i4 * pt * em1;
-    c.CDt = c.ikt4 * pt * em3;
-    return c;
 }
 
 // ------------------------------------------------------------------ far kernel -----------
@@ -606,7 +458,7 @@ __global__ void k_excitation(int N, int q, double h, double k, const double *__r
         }
     }
     E[i + jc * ld] = ev;
-    H[i + jc * ld] = hv;
+    if (H) H[i + jc * ld] = hv;
 }
 
 void launch_excitation(const GeomDev &g, const PointTable &pt, const double *xi,
