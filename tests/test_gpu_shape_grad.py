@@ -1,0 +1,169 @@
+"""Far field and shape gradient of the HIP path (GPU tests, through the C ABI).
+
+The loss is the backscatter functional of the differentiation workload: for each incident
+plane wave j, the sum of |F|^2 over 181 observation angles on the half circle facing the
+source (workloads.backscatter_angles).  Checks:
+  * the far field against the oracle's (stored in tests/golden/shapegrad128.npz): both sides
+    converge to the same discrete far field, so they agree to the assembly's quadrature
+    accuracy (1e-10 of the largest value);
+  * the gradient with respect to the 16 shape coefficients of that file against the oracle's
+    reference gradient (central differences of the dense solve, extrapolated): the HIP
+    gradient is the exact derivative of its own discretisation, which differs from the
+    oracle's by quadrature error only (bar 1e-7 of the largest component);
+  * translation invariance: the derivative with respect to zhat_0 vanishes;
+  * at the full size of the workload (N = 8192, 64 shape modes, 16 waves) against central
+    differences of the HIP loss itself with step 1e-6 on sampled coefficients;
+  * the torch.autograd op, mixed precision, and argument errors.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2203_13283_amd")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _gold():
+    return np.load(os.path.join(HERE, "golden", "shapegrad128.npz"))
+
+
+def _selection(m, n_obs):
+    """(m, m n_obs) mask: wave j uses the observation block j."""
+    sel = np.zeros((m, m * n_obs))
+    for j in range(m):
+        sel[j, j * n_obs:(j + 1) * n_obs] = 1.0
+    return torch.as_tensor(sel, dtype=torch.float64, device="cuda")
+
+
+def _forward(zhat, N, k, inc, obs_flat, **opt):
+    s = P.Solver(**opt)
+    s.assemble(zhat, N, k)
+    s.factor()
+    X = s.solve(s.plane_wave_rhs(inc))
+    return s, X, s.far_field(X, obs_flat)
+
+
+def _loss(F, sel):
+    return float(((F.abs() ** 2) * sel).sum())
+
+
+def _shape_grad(gz, mmax):
+    """chain d/d(Re, Im zhat) to d/d(s, t) with the linear map of workloads.shape_to_zhat"""
+    return W.shape_jacobian(mmax).T @ gz.reshape(-1)
+
+
+def test_far_field_matches_oracle():
+    d = _gold()
+    N, k, inc, obs = int(d["N"]), float(d["k"]), d["angles"], d["obs"]
+    m, n_obs = obs.shape
+    _, _, F = _forward(d["zhat"], N, k, inc, obs.ravel(), compress_tol=1e-12)
+    F = F.cpu().numpy()
+    Fd = np.stack([F[j, j * n_obs:(j + 1) * n_obs] for j in range(m)])
+    err = np.abs(Fd - d["F"]).max() / np.abs(d["F"]).max()
+    print(f"far field vs oracle: {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_gradient_matches_oracle_reference():
+    d = _gold()
+    N, k, inc, obs, mmax = int(d["N"]), float(d["k"]), d["angles"], d["obs"], int(d["mmax"])
+    m, n_obs = obs.shape
+    s, X, F = _forward(d["zhat"], N, k, inc, obs.ravel(), compress_tol=1e-12)
+    sel = _selection(m, n_obs)
+    L = _loss(F, sel)
+    assert abs(L - float(d["L"])) <= 1e-9 * float(d["L"])
+    gz = s.shape_gradient(inc, X, obs.ravel(), (2 * F * sel).contiguous())
+    g = _shape_grad(gz, mmax)
+    ref = d["grad"]
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print(f"gradient vs oracle reference: {err:.2e} (max |g| {np.abs(ref).max():.3e})")
+    assert err <= 1e-7
+    # translation: |F| only changes phase
+    M = (d["zhat"].size - 1) // 2
+    tr = np.abs(gz[M]).max() / np.abs(gz).max()
+    print(f"translation component: {tr:.2e}")
+    assert tr <= 1e-9
+
+
+def test_gradient_fullsize_against_central_differences():
+    pr = W.shape_problem()                 # N = 8192, 64 shape modes, 16 waves, 181 angles
+    N, k, inc, obs = pr["n_nodes"], pr["k"], pr["angles"], pr["obs"]
+    m, n_obs = obs.shape
+    mmax = pr["s"].size
+    sel = _selection(m, n_obs)
+    opt = dict(compress_tol=1e-10)
+    t0 = time.time()
+    s, X, F = _forward(pr["zhat"], N, k, inc, obs.ravel(), **opt)
+    t1 = time.time()
+    gz = s.shape_gradient(inc, X, obs.ravel(), (2 * F * sel).contiguous())
+    t2 = time.time()
+    print(f"N={N}: forward {t1 - t0:.2f} s, gradient {t2 - t1:.2f} s, rank {s.info()['rank']}")
+    g = _shape_grad(gz, mmax)
+    p0 = np.concatenate([pr["s"], pr["t"]])
+    del s, X, F
+    torch.cuda.empty_cache()
+    h = 1e-6
+    gmax = np.abs(g).max()
+    for i in (0, 5, 40, mmax + 2, mmax + 63):
+        vals = []
+        for sg in (1.0, -1.0):
+            p = p0.copy()
+            p[i] += sg * h
+            z = W.shape_to_zhat(p[:mmax], p[mmax:])
+            sv, Xv, Fv = _forward(z, N, k, inc, obs.ravel(), **opt)
+            vals.append(_loss(Fv, sel))
+            del sv, Xv, Fv
+        fd = (vals[0] - vals[1]) / (2 * h)
+        print(f"param {i}: adjoint {g[i]: .10e}  central difference {fd: .10e}")
+        assert abs(g[i] - fd) <= 2e-6 * gmax + 1e-6 * abs(fd)
+
+
+def test_autograd_op_and_mixed_precision():
+    d = _gold()
+    N, k, inc, obs = int(d["N"]), float(d["k"]), d["angles"], d["obs"]
+    m, n_obs = obs.shape
+    sel = _selection(m, n_obs)
+    zr = torch.tensor(np.stack([d["zhat"].real, d["zhat"].imag], -1), dtype=torch.float64,
+                      requires_grad=True)
+    F = P.far_field_of_shape(zr, N, k, inc, obs.ravel(), compress_tol=1e-12)
+    L = ((F.abs() ** 2) * sel).sum()
+    L.backward()
+    s, X, F2 = _forward(d["zhat"], N, k, inc, obs.ravel(), compress_tol=1e-12)
+    gz = s.shape_gradient(inc, X, obs.ravel(), (2 * F2 * sel).contiguous())
+    assert np.abs(zr.grad.numpy() - gz).max() <= 1e-12 * np.abs(gz).max()
+    # mixed precision: complex64 skeleton, FP64 refinement of the solve and the adjoint
+    sm, Xm, Fm = _forward(d["zhat"], N, k, inc, obs.ravel(), precision=P.CFIE_MIXED,
+                          compress_tol=1e-4, refine_tol=1e-11)
+    gm = sm.shape_gradient(inc, Xm, obs.ravel(), (2 * Fm * sel).contiguous())
+    err = np.abs(gm - gz).max() / np.abs(gz).max()
+    print(f"mixed-precision gradient vs FP64: {err:.2e}")
+    assert err <= 1e-8
+
+
+def test_shape_gradient_arguments():
+    d = _gold()
+    N, k, inc, obs = int(d["N"]), float(d["k"]), d["angles"], d["obs"]
+    s = P.Solver(compress_tol=1e-10)
+    s.assemble(d["zhat"], N, k)
+    B = s.plane_wave_rhs(inc)
+    dF = torch.zeros((len(inc), 5), dtype=torch.complex128, device="cuda")
+    with pytest.raises(P.CfieError) as e:
+        s.shape_gradient(inc, B, obs.ravel()[:5], dF)
+    assert e.value.status == 4                      # ESTATE before factor
+    s.factor()
+    X = s.solve(B)
+    with pytest.raises(ValueError):
+        s.shape_gradient(inc, X, obs.ravel()[:6], dF)
+    g = s.shape_gradient(inc, X, obs.ravel()[:5], dF)
+    assert np.all(g == 0.0)                         # zero cotangent, zero gradient
+    with pytest.raises(P.CfieError) as e:
+        s.far_field(X, [0.0, float("nan")])
+    assert e.value.status == 1
