@@ -34,7 +34,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="perturbed16384",
-                    help="perturbed16384 (the metric), ellipse4096, ellipse256, or batch64")
+                    help="perturbed16384 (the metric), ellipse4096, ellipse256, batch64 or "
+                         "shapegrad8192")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--eps", type=float, default=None,
                     help="compression tolerance (default 1e-5 fp64, 1e-3 mixed)")
@@ -211,6 +212,69 @@ def batch_main(a):
     print(json.dumps(out), flush=True)
 
 
+def shapegrad_main(a):
+    """--workload shapegrad8192: the shape-differentiation workload (r = 1 + sum_{m<=64}
+    s_m cos + t_m sin, s_m, t_m ~ N(0, (0.01/m)^2), seed 0, N = 8192, 10 nodes/wavelength,
+    16 plane waves, 181 backscatter observation angles each).  A step is the forward pass
+    (assemble, factor, right-hand sides, solve, far field) and the gradient of the loss
+    sum |F|^2 with respect to the 128 shape coefficients (cfie_shape_gradient).
+    value = gradient evaluations per second (forward + backward)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2203_13283_amd as P
+    pr = W.shape_problem()
+    N, k, inc, obs = pr["n_nodes"], pr["k"], pr["angles"], pr["obs"]
+    m, n_obs = obs.shape
+    mmax = pr["s"].size
+    eps = a.eps if a.eps is not None else 1e-10
+    sel = np.zeros((m, m * n_obs))
+    for j in range(m):
+        sel[j, j * n_obs:(j + 1) * n_obs] = 1.0
+    sel = torch.as_tensor(sel, device="cuda")
+    J = W.shape_jacobian(mmax)
+
+    def one():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = P.Solver(compress_tol=eps, block=256)
+        s.assemble(pr["zhat"], N, k)
+        s.factor()
+        X = s.solve(s.plane_wave_rhs(inc))
+        F = s.far_field(X, obs.ravel())
+        L = float(((F.abs() ** 2) * sel).sum())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gz = s.shape_gradient(inc, X, obs.ravel(), (2 * F * sel).contiguous())
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        info = s.info()
+        return dict(fwd=t1 - t0, bwd=t2 - t1, L=L, g=J.T @ gz.reshape(-1), rank=info["rank"],
+                    asm=info["t_assemble_ms"] / 1e3, fac=info["t_factor_ms"] / 1e3)
+
+    for _ in range(a.warmup):
+        one()
+    runs = [one() for _ in range(a.steps)]
+    tot = sorted(r["fwd"] + r["bwd"] for r in runs)[len(runs) // 2]
+    r = runs[-1]
+    out = {
+        "metric": "shape-gradient evaluations/s (far-field backscatter loss, 128 shape "
+                  "coefficients)",
+        "value": 1.0 / tot, "unit": "gradients/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * tot, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "shapegrad8192: r = 1 + sum_{m=1..64} s_m cos(m t) + t_m sin(m t),"
+                               " s_m, t_m ~ N(0, (0.01/m)^2) seed 0, 10 nodes/wavelength, "
+                               "16 plane waves x 181 backscatter angles",
+                   "N": N, "k": k, "nrhs": m, "n_obs": n_obs, "compress_tol": eps},
+        "phase_s": {"forward": sorted(x["fwd"] for x in runs)[len(runs) // 2],
+                    "gradient": sorted(x["bwd"] for x in runs)[len(runs) // 2],
+                    "assemble_dev": r["asm"], "factor_dev": r["fac"]},
+        "rank": r["rank"], "loss": r["L"], "grad_norm": float(np.linalg.norm(r["g"])),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -219,6 +283,9 @@ def main():
         sys.exit(2)
     if a.workload == "batch64":
         batch_main(a)
+        return
+    if a.workload == "shapegrad8192":
+        shapegrad_main(a)
         return
     import workloads as W
     w = W.get(a.workload)
