@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-baseline", action=argparse.BooleanOptionalAction, default=True)
     ap.add_argument("--profile", action=argparse.BooleanOptionalAction, default=True,
                     help="HIP-event timing of every hot launch inside the library")
+    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=True,
+                    help="GEMM tile autotuner (bitwise-neutral; on by default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, copy a MIB-mebibyte device buffer once (a kernel of "
                          "known HBM traffic, the reference for hardware byte counters)")
@@ -204,7 +206,7 @@ def batch_main(a):
                                "waves, 10 nodes/wavelength",
                    "problems": len(probs), "N_min": min(Ns), "N_max": max(Ns),
                    "nrhs_total": nrhs, "compress_tol": eps, "streams": 4,
-                   "precision": a.precision},
+                   "precision": a.precision, "gemm_autotune": bool(a.autotune)},
         "problems_per_s": len(probs) / med,
         "rel_residual_sampled": worst,
         "max_rank": max(r["rank"] for r in res),
@@ -281,6 +283,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this "
               "build (the solver has no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
+    if not a.autotune:
+        import paper_2203_13283_amd as P
+        P.set_gemm_autotune(False)
     if a.workload == "batch64":
         batch_main(a)
         return

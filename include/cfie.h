@@ -118,6 +118,16 @@ typedef struct {
     double prof_ms[5];
 } cfie_info;
 
+/* Process-wide switch of the complex GEMM tile autotuner: mode 1 (the default) lets the first
+ * product of each shape class whose 64 x 64 output grid cannot fill the device time the four
+ * tile shapes (64 x 64, 32 x 64, 64 x 32, 32 x 32) on the caller's stream and keep the
+ * fastest for the rest of the process; mode 0 always uses 64 x 64.  The tile shapes give
+ * bitwise identical results (same K order per output element, split along K fixed
+ * independently of the tile), so the switch changes speed only.  Returns the previous
+ * mode.  cfie_gemm_tuned_classes returns how many shape classes have been measured. */
+int cfie_set_gemm_autotune(int mode);
+int cfie_gemm_tuned_classes(void);
+
 /* Zero the accumulated launch profile of ctx. */
 cfie_status cfie_profile_reset(cfie_ctx *ctx);
 

@@ -27,11 +27,22 @@ from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW,
 
 __all__ = ["Solver", "solve_batch", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
            "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
-           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library"]
+           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library",
+           "set_gemm_autotune", "gemm_tuned_classes"]
 
 
 def load_library():
     return _lib.load()
+
+
+def set_gemm_autotune(enabled: bool) -> bool:
+    """Process-wide GEMM tile autotuner switch (cfie_set_gemm_autotune); returns the
+    previous setting.  The tile shapes give bitwise identical results."""
+    return bool(_lib.load().cfie_set_gemm_autotune(1 if enabled else 0))
+
+
+def gemm_tuned_classes() -> int:
+    return int(_lib.load().cfie_gemm_tuned_classes())
 
 
 def _torch():

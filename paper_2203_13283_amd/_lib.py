@@ -29,6 +29,7 @@ EXPORTED = [
     "cfie_plane_wave_rhs", "cfie_apply", "cfie_export_matrix", "cfie_query",
     "cfie_last_error", "cfie_status_string", "cfie_destroy", "cfie_profile_reset",
     "cfie_solve_batch", "cfie_solve_adjoint", "cfie_far_field", "cfie_shape_gradient",
+    "cfie_set_gemm_autotune", "cfie_gemm_tuned_classes",
 ]
 
 
@@ -79,6 +80,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime (loaded by file name); importing it first makes the
+    # library bind to that same runtime instead of loading a second one next to it, so that
+    # device pointers and streams from torch are valid in the library
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     lib.cfie_default_options.argtypes = [ctypes.POINTER(Options)]
@@ -117,6 +125,10 @@ def load(path: str = LIB_PATH):
     lib.cfie_far_field.restype = i32
     lib.cfie_shape_gradient.argtypes = [vp, dp, i64, vp, i64, dp, i64, vp, i64, dp]
     lib.cfie_shape_gradient.restype = i32
+    lib.cfie_set_gemm_autotune.argtypes = [ctypes.c_int]
+    lib.cfie_set_gemm_autotune.restype = ctypes.c_int
+    lib.cfie_gemm_tuned_classes.argtypes = []
+    lib.cfie_gemm_tuned_classes.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -1659,6 +1659,10 @@ cfie_status cfie_export_matrix(cfie_ctx *c, int which, void *dst, int64_t ld) {
     });
 }
 
+int cfie_set_gemm_autotune(int mode) { return set_gemm_autotune(mode); }
+
+int cfie_gemm_tuned_classes(void) { return gemm_tuned_classes(); }
+
 cfie_status cfie_profile_reset(cfie_ctx *c) {
     if (!c) return CFIE_EINVAL;
     for (int i = 0; i < PROF_KINDS; ++i) {

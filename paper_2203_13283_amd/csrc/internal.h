@@ -189,6 +189,10 @@ void launch_padded_diagonal(const FFTPlan &p, const zd *eig_over_N, zd *work, zd
 enum { GEMM_N = 0, GEMM_C = 1, GEMM_R = 2 };
 // release the split-K workspace of (device, stream)
 void splitk_release(int device, hipStream_t s);
+// process-wide switch of the GEMM tile autotuner (returns the previous mode) and the number
+// of shape classes measured so far
+int set_gemm_autotune(int mode);
+int gemm_tuned_classes();
 template <typename T>
 void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A, int64_t lda,
           const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s);

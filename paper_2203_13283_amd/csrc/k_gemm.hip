@@ -17,6 +17,8 @@
 // second kernel sums the slices in a fixed order (deterministic) and applies alpha, beta.
 #include "internal.h"
 
+#include <atomic>
+#include <condition_variable>
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -357,30 +359,142 @@ void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *
 }
 }  // namespace
 
+// ---------------------------------------------------------------- tile autotuner --------
+// Output tiles of 64 x 64, 32 x 64, 64 x 32 or 32 x 32 per workgroup.  Every variant runs the
+// same K loop for every output element (the same K-slices in the same order, the same MFMA
+// sequence per slice), so the variants give bitwise identical results and the choice only
+// changes speed: smaller tiles put more workgroups on the 256 CUs when the output is small.
+// The split along K is fixed beforehand by the 64 x 64 tile count, so it does not depend on
+// the variant either.  The first product of each shape class (op, precision, and the binary
+// orders of m, n, k and the split) whose 64 x 64 grid is too small to fill the device runs
+// every variant once into a scratch output, timed with HIP events on the caller's stream,
+// and the fastest is kept for the rest of the process; other threads that need the same
+// class meanwhile wait for that decision.
+namespace {
+template <typename T>
+using LaunchFn = void (*)(int64_t, int64_t, int64_t, int, cpx<T>, const cpx<T> *, int64_t,
+                          const cpx<T> *, int64_t, cpx<T>, cpx<T> *, int64_t, hipStream_t);
+constexpr int kVariants = 4;
+template <typename T, int OPA>
+LaunchFn<T> variant(int v) {
+    switch (v) {
+        case 1: return launch<T, OPA, 1, 2, 16, true, 2>;
+        case 2: return launch<T, OPA, 2, 1, 16, true, 2>;
+        case 3: return launch<T, OPA, 1, 1, 16, true, 2>;
+        default: return launch<T, OPA, 2, 2, 16, true, 2>;
+    }
+}
+template <typename T>
+LaunchFn<T> variant_op(int op, int v) {
+    return op == GEMM_C ? variant<T, 1>(v) : op == GEMM_R ? variant<T, 2>(v) : variant<T, 0>(v);
+}
+
+struct TuneKey {
+    int op, bytes, lm, ln, lk, S;
+    bool operator<(const TuneKey &o) const {
+        const int a[6] = {op, bytes, lm, ln, lk, S}, b[6] = {o.op, o.bytes, o.lm, o.ln, o.lk, o.S};
+        for (int i = 0; i < 6; ++i)
+            if (a[i] != b[i]) return a[i] < b[i];
+        return false;
+    }
+};
+std::mutex g_tune_mu;
+std::condition_variable g_tune_cv;
+std::map<TuneKey, int> g_tune;            // variant, or -1 while being measured
+std::atomic<int> g_tune_mode{1};
+std::atomic<int> g_tuned{0};
+
+int ilog2c(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+template <typename T>
+int tuned_variant(int op, int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha,
+                  const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, hipStream_t s) {
+    const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
+    if (g_tune_mode.load() == 0 || tiles * S >= 512) return 0;
+    if (8.0 * (double)m * (double)n * (double)k > 3.5e10) return 0;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const TuneKey key{op, (int)sizeof(T), ilog2c(m), ilog2c(n), ilog2c(k), S};
+    {
+        std::unique_lock<std::mutex> lock(g_tune_mu);
+        for (;;) {
+            auto it = g_tune.find(key);
+            if (it == g_tune.end()) {
+                g_tune[key] = -1;
+                break;
+            }
+            if (it->second >= 0) return it->second;
+            g_tune_cv.wait(lock);
+        }
+    }
+    // measure every variant once (after one warm-up launch) into a scratch output
+    int best = 0;
+    cpx<T> *Ct = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = hipMallocAsync((void **)&Ct, (size_t)m * n * sizeof(cpx<T>), s) == hipSuccess &&
+              hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    if (ok) {
+        float tbest = 1e30f;
+        variant_op<T>(op, 0)(m, n, k, S, alpha, A, lda, B, ldb, mk((T)0, (T)0), Ct, m, s);
+        for (int v = 0; v < kVariants && ok; ++v) {
+            ok = hipEventRecord(e0, s) == hipSuccess;
+            variant_op<T>(op, v)(m, n, k, S, alpha, A, lda, B, ldb, mk((T)0, (T)0), Ct, m, s);
+            ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.0f;
+            ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (ok && ms < tbest) {
+                tbest = ms;
+                best = v;
+            }
+        }
+    }
+    if (Ct) (void)hipFreeAsync(Ct, s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (!ok) {
+        (void)hipGetLastError();
+        best = 0;
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[key] = best;
+        ++g_tuned;
+    }
+    g_tune_cv.notify_all();
+    return best;
+}
+}  // namespace
+
+int set_gemm_autotune(int mode) { return g_tune_mode.exchange(mode ? 1 : 0); }
+int gemm_tuned_classes() { return g_tuned.load(); }
+
 template <typename T>
 void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A, int64_t lda,
           const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s) {
     if (m <= 0 || n <= 0) return;
-    ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
-                   8.0 * (double)m * (double)n * (double)std::max<int64_t>(k, 0), s);
-    // 64 x 64 tiles in the 3M form measured fastest on gfx950 for every shape of the
-    // solver (about 110% of the FP64 matrix-core peak counted as 8 m n k real flops, i.e.
-    // 83-86% of the pipe for the 6 m n k it executes); K is split when the output has too
-    // few tiles to fill 256 CUs
+    // K is split when the output has too few 64 x 64 tiles to fill 256 CUs
     const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
     int S = 1;
     if (tiles < 192 && k >= 4096) {
         S = (int)std::min<int64_t>((512 + tiles - 1) / tiles, k / 512);
         S = std::max(1, std::min(S, 64));
     }
-    // two workgroups (two wavefronts per SIMD) per CU: the register budget of 256 per lane
-    // that this imposes measured 15-20% faster than one wavefront with more registers
-    if (op == GEMM_C)
-        launch<T, 1, 2, 2, 16, true, 2>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
-    else if (op == GEMM_R)
-        launch<T, 2, 2, 2, 16, true, 2>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
-    else
-        launch<T, 0, 2, 2, 16, true, 2>(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    const int v = tuned_variant<T>(op, m, n, k, S, alpha, A, lda, B, ldb, s);
+    ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
+                   8.0 * (double)m * (double)n * (double)std::max<int64_t>(k, 0), s);
+    // 64 x 64 tiles in the 3M form measured fastest on gfx950 for every large shape of the
+    // solver (about 110% of the FP64 matrix-core peak counted as 8 m n k real flops, i.e.
+    // 83-86% of the pipe for the 6 m n k it executes); two workgroups (two wavefronts per
+    // SIMD) per CU: the register budget of 256 per lane that this imposes measured 15-20%
+    // faster than one wavefront with more registers
+    variant_op<T>(op, v)(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
 }
 
 template void gemm<double>(int, int64_t, int64_t, int64_t, zd, const zd *, int64_t,
