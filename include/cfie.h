@@ -90,7 +90,20 @@ typedef struct {
     int64_t fail_alloc_after; /* test hook: fail the (n+1)-th device allocation; -1 off */
     int32_t profile;      /* 1: time every GEMM / assembly / FFT launch with HIP events on
                              the context stream and accumulate work and time (cfie_info) */
+    int32_t remainder_form; /* how cfie_factor applies C - C_c (CFIE_REMAINDER_*)         */
 } cfie_options;
+
+/* cfie_options.remainder_form.  The sketch and V^T = Q^H (C - C_c) cost 64 N^2 r flops when
+ * C is applied factor by factor (four N x N GEMMs per product, eq. (6)), and 16 N^3 + 16 N^2 r
+ * when C - C_c is first formed as a dense N x N matrix (two N x N x N GEMMs) and then applied
+ * with one GEMM; the dense form wins for ranks above N/3 and needs 16 N^2 more bytes (8 N^2
+ * in mixed precision) during the factorisation. */
+enum {
+    CFIE_REMAINDER_AUTO = 0,     /* factor by factor; switch to the dense form once the sketch
+                                    has reached rank N/2 without meeting the tolerance       */
+    CFIE_REMAINDER_FACTORED = 1, /* always factor by factor                                 */
+    CFIE_REMAINDER_DENSE = 2     /* form C - C_c densely before the sketch                   */
+};
 
 typedef struct {
     int32_t n_nodes;
@@ -132,7 +145,8 @@ int cfie_gemm_tuned_classes(void);
 cfie_status cfie_profile_reset(cfie_ctx *ctx);
 
 /* Fill *opt with defaults: FP64, compress_tol 1e-10, block 128, max_rank 0, seed 1,
- * refine_tol 1e-8, max_refine 20, quad_far 5, quad_near 10, near_band 6, no injection. */
+ * refine_tol 1e-8, max_refine 20, quad_far 5, quad_near 10, near_band 6, no injection,
+ * no profiling, remainder_form CFIE_REMAINDER_AUTO. */
 void cfie_default_options(cfie_options *opt);
 
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for

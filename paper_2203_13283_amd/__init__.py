@@ -23,11 +23,13 @@ import numpy as np
 from . import _lib
 from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW, MAT_DK,
                    MAT_DKT, MAT_G, MAT_NK, MAT_SKT, OP_C, OP_C_ADJ, OP_CC, OP_CC_INV,
-                   OP_REMAINDER, OP_SKELETON)
+                   OP_REMAINDER, OP_SKELETON, REMAINDER_AUTO, REMAINDER_DENSE,
+                   REMAINDER_FACTORED)
 
 __all__ = ["Solver", "solve_batch", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
            "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
-           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library",
+           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library", "REMAINDER_AUTO", "REMAINDER_FACTORED",
+           "REMAINDER_DENSE",
            "set_gemm_autotune", "gemm_tuned_classes"]
 
 
@@ -61,7 +63,8 @@ class Solver:
                  block: int = 128, max_rank: int = 0, seed: int = 1,
                  refine_tol: float = 1e-8, max_refine: int = 20, quad_far: int = 5,
                  quad_near: int = 10, near_band: int = 6, fail_alloc_after: int = -1,
-                 profile: bool = False, device: int = 0, stream=None):
+                 profile: bool = False, remainder_form: int = 0, device: int = 0,
+                 stream=None):
         lib = _lib.load()
         torch = _torch()
         o = _lib.default_options()
@@ -77,6 +80,7 @@ class Solver:
         o.near_band = near_band
         o.fail_alloc_after = fail_alloc_after
         o.profile = 1 if profile else 0
+        o.remainder_form = remainder_form
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)

@@ -23,6 +23,7 @@ CFIE_ESINGULAR, CFIE_ENOCONV, CFIE_WNONCONVEX = 5, 6, 100
 CFIE_FP64, CFIE_MIXED = 0, 1
 MAT_G, MAT_DK, MAT_NK, MAT_DKT, MAT_SKT, MAT_CC_EIG, MAT_CIRCLE_ROW = range(7)
 OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON, OP_C_ADJ = range(6)
+REMAINDER_AUTO, REMAINDER_FACTORED, REMAINDER_DENSE = 0, 1, 2
 
 EXPORTED = [
     "cfie_default_options", "cfie_create", "cfie_assemble", "cfie_factor", "cfie_solve",
@@ -44,7 +45,8 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("refine_tol", ctypes.c_double),
                 ("max_refine", ctypes.c_int32), ("quad_far", ctypes.c_int32),
                 ("quad_near", ctypes.c_int32), ("near_band", ctypes.c_int32),
-                ("fail_alloc_after", ctypes.c_int64), ("profile", ctypes.c_int32)]
+                ("fail_alloc_after", ctypes.c_int64), ("profile", ctypes.c_int32),
+                ("remainder_form", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

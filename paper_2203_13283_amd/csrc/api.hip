@@ -60,6 +60,9 @@ void launch_swaps_reverse(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda
 void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
                     hipStream_t s);
 void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s);
+// A = a I (set) or A += a I on the diagonal (n x n)
+template <typename T>
+void launch_diag(int64_t n, cpx<T> a, bool set, cpx<T> *A, int64_t lda, hipStream_t s);
 void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out,
                       hipStream_t s);
 void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz, zd *M,
@@ -579,6 +582,32 @@ void lu_solve_adj(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
     c->check_launch();
 }
 
+// Rd = C - C_c as a dense N x N matrix (precision T):
+//   C = (G/2 + D^kt) M + S^kt G^-1 N^k,  M = G^-1 (G/2 - D^k) = I/2 - G^-1 D^k   (eq. (6))
+// two N x N x N GEMMs; C_c densely as its circulant applied to the identity
+template <typename T>
+void form_remainder_dense(cfie_ctx *c, cpx<T> *Rd) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    const int nt = (int)c->gcoef.size();
+    const double h = c->hg.L / N;
+    cpx<T> *M = c->alloc_n<cpx<T>>((size_t)N * N);
+    launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0,
+                      cz<T>(-1), Ops<T>::mat(c, 0), N, M, N, N, s);
+    launch_diag<T>(N, cz<T>(0.5), false, M, N, s);
+    launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), M, N, Rd, N, N, s);
+    gemm<T>(GEMM_N, N, N, N, cz<T>(1), Ops<T>::mat(c, 2), N, M, N, cz<T>(1), Rd, N, s);
+    launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0,
+                      cz<T>(1), Ops<T>::mat(c, 1), N, M, N, N, s);
+    gemm<T>(GEMM_N, N, N, N, cz<T>(1), Ops<T>::mat(c, 3), N, M, N, cz<T>(1), Rd, N, s);
+    launch_diag<T>(N, cz<T>(1), true, M, N, s);
+    circ_apply<T>(c, Ops<T>::dC(c), M, N, N);
+    axpby<T>(N, N, cz<T>(-1), M, N, cz<T>(1), Rd, N, s);
+    c->check_launch();
+    c->sync();
+    c->dfree(M);
+}
+
 template <typename T>
 cfie_status factor_impl(cfie_ctx *c) {
     const int N = c->N;
@@ -595,10 +624,20 @@ cfie_status factor_impl(cfie_ctx *c) {
     uint64_t blk = 0;
     std::vector<double> nrm(b);
     c->remainder_est = 0.0;
+    // C - C_c applied factor by factor, or as a dense matrix (formed up front, or once the
+    // rank has reached N/2 in the automatic mode)
+    cpx<T> *Rd = nullptr;
+    if (c->opt.remainder_form == CFIE_REMAINDER_DENSE) {
+        Rd = c->alloc_n<cpx<T>>((size_t)N * N);
+        form_remainder_dense<T>(c, Rd);
+    }
     while (ell < cap) {
         int bb = std::min(b, cap - ell);
         randn<T>(N, bb, c->opt.seed, blk++, Om, N, s);
-        apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z);
+        if (Rd)
+            gemm<T>(GEMM_N, N, bb, N, cz<T>(1), Rd, N, Om, N, cz<T>(0), Y, N, s);
+        else
+            apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z);
         if (ell > 0) {
             for (int pass = 0; pass < 2; ++pass) {
                 gemm<T>(GEMM_C, ell, bb, N, cz<T>(1), Q, N, Y, N, cz<T>(0), S, ell, s);
@@ -620,23 +659,38 @@ cfie_status factor_impl(cfie_ctx *c) {
         // remaining range with at least 16 columns of oversampling: the remainder left after
         // it exceeds tau only with negligible probability, so no further block is drawn
         if (bb >= 32 && kept <= bb - 16) break;
+        if (!Rd && c->opt.remainder_form == CFIE_REMAINDER_AUTO && 2 * ell >= N && ell < cap) {
+            Rd = c->alloc_n<cpx<T>>((size_t)N * N);
+            form_remainder_dense<T>(c, Rd);
+        }
     }
     c->rank = ell;
     if (ell == 0) {
+        if (Rd) {
+            c->sync();
+            c->dfree(Rd);
+        }
         c->state = 2;
         return CFIE_OK;
     }
     // V^T = Q^H (C - C_c) = ((C - C_c)^H Q)^H, stored as an ell x N matrix; Ut = C_c^{-1} Q
-    cpx<T> *RHQ = (cpx<T> *)c->alloc_n<cpx<T>>((size_t)N * ell);
-    for (int j = 0; j < ell; j += b) {
-        int bb = std::min(b, ell - j);
-        apply_RH<T>(c, Q + (size_t)j * N, N, RHQ + (size_t)j * N, N, bb, Tt, W1, W2, Z);
-    }
     c->P = c->alloc_n<cpx<T>>((size_t)N * ell);
     cpx<T> *P = (cpx<T> *)c->P;
-    conj_transpose<T>(true, N, ell, RHQ, N, P, ell, s);
-    c->sync();
-    c->dfree(RHQ);
+    if (Rd) {
+        gemm<T>(GEMM_C, ell, N, N, cz<T>(1), Q, N, Rd, N, cz<T>(0), P, ell, s);
+        c->sync();
+        c->dfree(Rd);
+        Rd = nullptr;
+    } else {
+        cpx<T> *RHQ = (cpx<T> *)c->alloc_n<cpx<T>>((size_t)N * ell);
+        for (int j = 0; j < ell; j += b) {
+            int bb = std::min(b, ell - j);
+            apply_RH<T>(c, Q + (size_t)j * N, N, RHQ + (size_t)j * N, N, bb, Tt, W1, W2, Z);
+        }
+        conj_transpose<T>(true, N, ell, RHQ, N, P, ell, s);
+        c->sync();
+        c->dfree(RHQ);
+    }
     c->Ut = c->alloc_n<cpx<T>>((size_t)N * ell);
     cpx<T> *Ut = (cpx<T> *)c->Ut;
     axpby<T>(N, ell, cz<T>(1), Q, N, cz<T>(0), Ut, N, s);
@@ -943,6 +997,7 @@ void cfie_default_options(cfie_options *o) {
     o->near_band = 6;
     o->fail_alloc_after = -1;
     o->profile = 0;
+    o->remainder_form = CFIE_REMAINDER_AUTO;
 }
 
 const char *cfie_status_string(cfie_status s) {
@@ -975,6 +1030,8 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, c
         return bad("quad_far must be one of 3, 4, 5, 6, 8");
     if (o.quad_near < 4 || o.quad_near > 16) return bad("quad_near must be in [4, 16]");
     if (o.near_band < 1 || o.near_band > 64) return bad("near_band must be in [1, 64]");
+    if (o.remainder_form < CFIE_REMAINDER_AUTO || o.remainder_form > CFIE_REMAINDER_DENSE)
+        return bad("remainder_form must be CFIE_REMAINDER_AUTO, _FACTORED or _DENSE");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         (void)hipGetLastError();

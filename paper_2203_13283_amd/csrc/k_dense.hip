@@ -98,6 +98,29 @@ template void launch_gmul<float>(int, double, zf, const zf *, int64_t, zf, const
                                  zf *, int64_t, int64_t, hipStream_t);
 
 // ------------------------------------------------------------------ elementwise ----------
+// A = a I (set) or A += a I (add), n x n
+template <typename T>
+__global__ void k_diag(int64_t n, cpx<T> a, int set, cpx<T> *A, int64_t lda) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (set) {
+        if (t >= n * n) return;
+        const int64_t i = t % n, j = t / n;
+        A[i + j * lda] = i == j ? a : mk((T)0, (T)0);
+    } else {
+        if (t >= n) return;
+        A[t + t * lda] = A[t + t * lda] + a;
+    }
+}
+template <typename T>
+void launch_diag(int64_t n, cpx<T> a, bool set, cpx<T> *A, int64_t lda, hipStream_t s) {
+    const int64_t cnt = set ? n * n : n;
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_diag<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, n, a,
+                       set ? 1 : 0, A, lda);
+}
+template void launch_diag<double>(int64_t, zd, bool, zd *, int64_t, hipStream_t);
+template void launch_diag<float>(int64_t, zf, bool, zf *, int64_t, hipStream_t);
+
 // Y = a X + b Y   (m rows, n cols)
 template <typename T>
 __global__ void k_axpby(int64_t m, int64_t n, cpx<T> a, const cpx<T> *X, int64_t ldx, cpx<T> b,

@@ -268,3 +268,26 @@ def test_skeleton_approximates_remainder(cfg1):
     tau = eps * info["cc_norm"]
     print(f"skeleton: rank {info['rank']} ||(R - UV^T) x|| / ||x|| = {ratio:.2e}, tau {tau:.2e}")
     assert ratio <= 10 * tau
+
+
+@pytest.mark.parametrize("form,prec,tol,bar", [
+    (P.REMAINDER_DENSE, P.CFIE_FP64, 1e-10, 1e-10),
+    (P.REMAINDER_AUTO, P.CFIE_FP64, 1e-13, 1e-10),
+    (P.REMAINDER_DENSE, P.CFIE_MIXED, 1e-4, 1e-6),
+])
+def test_dense_remainder_form(cfg1, form, prec, tol, bar):
+    """C - C_c formed densely (two N x N x N GEMMs) before the sketch, or once the rank passes
+    N/2 (automatic mode at a tolerance that needs almost full rank): same solution as the
+    oracle's dense LU to the FP64 (or mixed-precision) bar."""
+    w, prob = cfg1
+    s = P.Solver(precision=prec, compress_tol=tol, remainder_form=form, block=64,
+                 refine_tol=1e-9)
+    s.assemble(w.zhat, w.n_nodes, w.k).factor()
+    B = s.plane_wave_rhs(w.angles)
+    X = _np(s.solve(B)).T
+    ref = prob.solve(_np(B).T)
+    err = S.rel_err(X, ref)
+    print(f"form {form} prec {prec}: rank {s.info()['rank']} rel.err {err:.2e}")
+    assert err <= bar
+    if form == P.REMAINDER_AUTO:
+        assert 2 * s.info()["rank"] >= w.n_nodes
