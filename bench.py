@@ -34,8 +34,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="perturbed16384",
-                    help="perturbed16384 (the metric), ellipse4096, ellipse256, batch64 or "
-                         "shapegrad8192")
+                    help="perturbed16384 (the metric), ellipse4096, ellipse256, batch64, "
+                         "shapegrad8192 or serve16384")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--eps", type=float, default=None,
                     help="compression tolerance (default 1e-5 fp64, 1e-3 mixed)")
@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--cpu-baseline", action=argparse.BooleanOptionalAction, default=True)
     ap.add_argument("--profile", action=argparse.BooleanOptionalAction, default=True,
                     help="HIP-event timing of every hot launch inside the library")
+    ap.add_argument("--serve-m", type=int, default=8,
+                    help="right-hand sides per call of the serve16384 workload")
+    ap.add_argument("--serve-workload", default="perturbed16384",
+                    help="problem of the serve16384 workload (default: the metric's)")
     ap.add_argument("--remainder", choices=("auto", "factored", "dense"), default=None,
                     help="how the factorisation applies C - C_c (default: auto; dense for "
                          "shapegrad8192, whose remainder has full rank at 1e-10)")
@@ -217,6 +221,52 @@ def batch_main(a):
     print(json.dumps(out), flush=True)
 
 
+def serve_main(a):
+    """--workload serve16384: the metric's problem (perturbed16384) factored once, then many
+    small solves (--serve-m right-hand sides per call, 200 calls), as a serving loop would
+    issue them: direct cfie_solve against recorded solves (options.solve_graphs).
+    value = right-hand sides per second of the recorded solves."""
+    import torch
+    import workloads as W
+    import paper_2203_13283_amd as P
+    w = W.get(a.serve_workload)
+    m, calls = a.serve_m, 200
+    eps = a.eps if a.eps is not None else 1e-5
+    out_modes = {}
+    for graphs in (False, True):
+        s = P.Solver(compress_tol=eps, block=256, solve_graphs=graphs)
+        s.assemble(w.zhat, w.n_nodes, w.k)
+        s.factor()
+        B = s.plane_wave_rhs(w.angles[:m])
+        X = torch.empty_like(B)
+        for _ in range(5):
+            s.solve(B, out=X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            s.solve(B, out=X)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / calls
+        out_modes["graph" if graphs else "direct"] = dict(ms_per_call=1e3 * dt,
+                                                          rhs_per_s=m / dt)
+        rank = s.info()["rank"]
+        del s, B, X
+        torch.cuda.empty_cache()
+    g = out_modes["graph"]
+    out = {
+        "metric": "preconditioned-CFIE RHS solves/s in small batches (serving loop)",
+        "value": g["rhs_per_s"], "unit": "RHS/s", "n_gpus": 1, "steps": calls, "warmup": 5,
+        "ms_per_step": g["ms_per_call"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serve16384: {w.name}: {w.description}, factored once, {m} "
+                               "plane waves per call", "N": w.n_nodes, "nrhs_per_call": m, "calls": calls,
+                   "compress_tol": eps},
+        "rank": rank, "modes": out_modes,
+        "graph_speedup": out_modes["direct"]["ms_per_call"] / g["ms_per_call"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def shapegrad_main(a):
     """--workload shapegrad8192: the shape-differentiation workload (r = 1 + sum_{m<=64}
     s_m cos + t_m sin, s_m, t_m ~ N(0, (0.01/m)^2), seed 0, N = 8192, 10 nodes/wavelength,
@@ -296,6 +346,9 @@ def main():
         return
     if a.workload == "shapegrad8192":
         shapegrad_main(a)
+        return
+    if a.workload == "serve16384":
+        serve_main(a)
         return
     import workloads as W
     w = W.get(a.workload)

@@ -91,6 +91,11 @@ typedef struct {
     int32_t profile;      /* 1: time every GEMM / assembly / FFT launch with HIP events on
                              the context stream and accumulate work and time (cfie_info) */
     int32_t remainder_form; /* how cfie_factor applies C - C_c (CFIE_REMAINDER_*)         */
+    int32_t solve_graphs; /* 1: FP64 cfie_solve records its kernel sequence (C_c^-1 by FFT,
+                             the two Woodbury GEMMs) once per batch size nrhs <= 4096 as a HIP
+                             graph on buffers it owns, and replays it on later calls with
+                             that nrhs (B copied in, X copied out); bitwise identical to the
+                             direct path.  For many small solves with one factorisation.   */
 } cfie_options;
 
 /* cfie_options.remainder_form.  The sketch and V^T = Q^H (C - C_c) cost 64 N^2 r flops when
@@ -146,7 +151,7 @@ cfie_status cfie_profile_reset(cfie_ctx *ctx);
 
 /* Fill *opt with defaults: FP64, compress_tol 1e-10, block 128, max_rank 0, seed 1,
  * refine_tol 1e-8, max_refine 20, quad_far 5, quad_near 10, near_band 6, no injection,
- * no profiling, remainder_form CFIE_REMAINDER_AUTO. */
+ * no profiling, remainder_form CFIE_REMAINDER_AUTO, solve_graphs 0. */
 void cfie_default_options(cfie_options *opt);
 
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for

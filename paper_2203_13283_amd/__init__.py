@@ -63,8 +63,8 @@ class Solver:
                  block: int = 128, max_rank: int = 0, seed: int = 1,
                  refine_tol: float = 1e-8, max_refine: int = 20, quad_far: int = 5,
                  quad_near: int = 10, near_band: int = 6, fail_alloc_after: int = -1,
-                 profile: bool = False, remainder_form: int = 0, device: int = 0,
-                 stream=None):
+                 profile: bool = False, remainder_form: int = 0, solve_graphs: bool = False,
+                 device: int = 0, stream=None):
         lib = _lib.load()
         torch = _torch()
         o = _lib.default_options()
@@ -81,6 +81,7 @@ class Solver:
         o.fail_alloc_after = fail_alloc_after
         o.profile = 1 if profile else 0
         o.remainder_form = remainder_form
+        o.solve_graphs = 1 if solve_graphs else 0
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)

@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("max_refine", ctypes.c_int32), ("quad_far", ctypes.c_int32),
                 ("quad_near", ctypes.c_int32), ("near_band", ctypes.c_int32),
                 ("fail_alloc_after", ctypes.c_int64), ("profile", ctypes.c_int32),
-                ("remainder_form", ctypes.c_int32)]
+                ("remainder_form", ctypes.c_int32), ("solve_graphs", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -170,8 +170,20 @@ struct cfie_ctx {
          *w_z = nullptr, *w_s = nullptr, *w_rinvT = nullptr;
     zd *w_gram = nullptr, *w_rinv = nullptr, *w_y64 = nullptr, *w_pchm = nullptr;
     double *w_norm = nullptr;
+    // recorded FP64 solves (options.solve_graphs): per batch size, the graph and the buffers
+    // its kernels use
+    struct SolveGraph {
+        hipGraphExec_t exec = nullptr;
+        zd *X = nullptr, *Z = nullptr, *P = nullptr;
+        void *W = nullptr;
+        bool ok = false;
+    };
+    std::map<int64_t, SolveGraph> graphs;
 
     ~cfie_ctx() {
+        for (auto &kv : graphs)
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        graphs.clear();
         for (auto &r : prof.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : prof.pool) (void)hipEventDestroy(e);
         for (auto &kv : live) (void)hipFreeAsync(kv.first, stream);
@@ -274,7 +286,20 @@ template <typename F> cfie_status guarded(cfie_ctx *c, F &&f) {
     }
 }
 
+void free_graphs(cfie_ctx *c) {
+    if (!c->graphs.empty()) (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        c->dfree(kv.second.X);
+        c->dfree(kv.second.Z);
+        c->dfree(kv.second.P);
+        c->dfree(kv.second.W);
+    }
+    c->graphs.clear();
+}
+
 void free_factor(cfie_ctx *c) {
+    free_graphs(c);
     void *bufs[] = {c->Q, c->P, c->Wf, c->Ut, c->K, c->piv, c->info, c->Linv, c->Uinv, c->w_om,
                     c->w_y, c->w_t, c->w_w1, c->w_w2, c->w_z, c->w_s, c->w_rinvT, c->w_gram,
                     c->w_rinv, c->w_norm, c->w_y64, c->w_pchm};
@@ -369,11 +394,12 @@ template <typename T> cpx<T> cz(double a, double b = 0.0) { return mk((T)a, (T)b
 // FFT pass at the length N when N is a power of two, else a zero-padded linear convolution
 // of length M through a grow-only workspace
 template <typename T>
-void circ_apply(cfie_ctx *c, const cpx<T> *d, cpx<T> *X, int64_t ldx, int64_t m) {
+void circ_apply(cfie_ctx *c, const cpx<T> *d, cpx<T> *X, int64_t ldx, int64_t m,
+                cpx<T> *ws = nullptr) {
     if (c->fft.M == c->N) {
         launch_circ_apply<T>(c->fft, d, X, ldx, m, c->stream);
     } else {
-        cpx<T> *P = c->scratch<cpx<T>>(3, (size_t)c->fft.M * (size_t)m);
+        cpx<T> *P = ws ? ws : c->scratch<cpx<T>>(3, (size_t)c->fft.M * (size_t)m);
         launch_circ_apply_padded<T>(c->fft, d, X, ldx, m, P, c->stream);
     }
 }
@@ -777,10 +803,10 @@ cfie_status factor_impl(cfie_ctx *c) {
 // X <- C^{-1} X in precision T (X is N x m in T, ld N) by eq. (9):
 // X = C_c^{-1} X - U~ (K^{-1} V^T) C_c^{-1} X, with U~ = C_c^{-1} U; Z: rank x m scratch
 template <typename T>
-void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, cpx<T> *Z) {
+void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, cpx<T> *Z, cpx<T> *ws = nullptr) {
     const int N = c->N;
     hipStream_t s = c->stream;
-    circ_apply<T>(c, Ops<T>::dCinv(c), X, N, m);
+    circ_apply<T>(c, Ops<T>::dCinv(c), X, N, m, ws);
     const int r = c->rank;
     if (r == 0) return;
     const cpx<T> *Wf = (const cpx<T> *)c->Wf, *Ut = (const cpx<T> *)c->Ut;
@@ -899,10 +925,57 @@ cfie_status solve_adjoint(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t 
     return st;
 }
 
+// The recorded solve of a batch of m right-hand sides: C_c^-1 by FFT and the two Woodbury
+// GEMMs on the graph's own buffers (X, Z, the padding buffer of the circulant product when
+// N is not a power of two, the split-K partial products), recorded on the context stream
+// after one direct run on the same buffers.  Returns nullptr when recording fails (the
+// caller then solves directly).
+cfie_ctx::SolveGraph *solve_graph(cfie_ctx *c, int64_t m) {
+    auto it = c->graphs.find(m);
+    if (it != c->graphs.end()) return it->second.ok ? &it->second : nullptr;
+    cfie_ctx::SolveGraph &g = c->graphs[m];
+    const int N = c->N, r = c->rank;
+    hipStream_t s = c->stream;
+    g.X = c->alloc_n<zd>((size_t)N * m);
+    g.Z = c->alloc_n<zd>((size_t)std::max(r, 1) * m);
+    if (c->fft.M != N) g.P = c->alloc_n<zd>((size_t)c->fft.M * m);
+    const size_t wb = std::max(gemm_splitk_bytes(r, m, N, sizeof(zd)),
+                               gemm_splitk_bytes(N, m, r, sizeof(zd)));
+    if (wb) g.W = c->dalloc(wb);
+    c->sync();
+    Profiler *saved = g_prof;
+    g_prof = nullptr;
+    set_splitk_override(g.W, wb);
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        woodbury<double>(c, g.X, m, g.Z, g.P);
+        ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
+    }
+    set_splitk_override(nullptr, 0);
+    g_prof = saved;
+    if (ok) ok = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    g.ok = ok;
+    return ok ? &g : nullptr;
+}
+
 cfie_status solve_fp64(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx, int64_t nrhs) {
     const int N = c->N;
     hipStream_t s = c->stream;
     const int64_t chunk = 4096;
+    if (c->opt.solve_graphs && nrhs <= chunk) {
+        cfie_ctx::SolveGraph *g = solve_graph(c, nrhs);
+        if (g) {
+            axpby<double>(N, nrhs, cz<double>(1), B, ldb, cz<double>(0), g->X, N, s);
+            HIPCHK(hipGraphLaunch(g->exec, s));
+            axpby<double>(N, nrhs, cz<double>(1), g->X, N, cz<double>(0), X, ldx, s);
+            c->check_launch();
+            c->sync();
+            return CFIE_OK;
+        }
+    }
     int r = std::max(c->rank, 1);
     int64_t mc = std::min<int64_t>(nrhs, chunk);
     // operate in place in X when it is packed (ld = N), else through a packed workspace
@@ -998,6 +1071,7 @@ void cfie_default_options(cfie_options *o) {
     o->fail_alloc_after = -1;
     o->profile = 0;
     o->remainder_form = CFIE_REMAINDER_AUTO;
+    o->solve_graphs = 0;
 }
 
 const char *cfie_status_string(cfie_status s) {
@@ -1032,6 +1106,7 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, c
     if (o.near_band < 1 || o.near_band > 64) return bad("near_band must be in [1, 64]");
     if (o.remainder_form < CFIE_REMAINDER_AUTO || o.remainder_form > CFIE_REMAINDER_DENSE)
         return bad("remainder_form must be CFIE_REMAINDER_AUTO, _FACTORED or _DENSE");
+    if (o.solve_graphs != 0 && o.solve_graphs != 1) return bad("solve_graphs must be 0 or 1");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         (void)hipGetLastError();

@@ -301,7 +301,13 @@ namespace {
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_ws;
 
+// a caller-owned workspace used instead of the shared one (HIP graph capture: the recorded
+// kernels must keep pointing at memory that no later call frees)
+thread_local void *t_ws_override = nullptr;
+thread_local size_t t_ws_override_bytes = 0;
+
 void *splitk_ws(size_t need, hipStream_t s) {
+    if (t_ws_override && need <= t_ws_override_bytes) return t_ws_override;
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lock(g_ws_mu);
@@ -473,6 +479,31 @@ int tuned_variant(int op, int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha,
 }  // namespace
 
 int set_gemm_autotune(int mode) { return g_tune_mode.exchange(mode ? 1 : 0); }
+
+void set_splitk_override(void *p, size_t bytes) {
+    t_ws_override = p;
+    t_ws_override_bytes = p ? bytes : 0;
+}
+
+namespace {
+int splitk_factor(int64_t m, int64_t n, int64_t k) {
+    const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
+    int S = 1;
+    if (tiles < 192 && k >= 4096) {
+        S = (int)std::min<int64_t>((512 + tiles - 1) / tiles, k / 512);
+        S = std::max(1, std::min(S, 64));
+    }
+    return S;
+}
+}  // namespace
+
+size_t gemm_splitk_bytes(int64_t m, int64_t n, int64_t k, size_t elem) {
+    int S = splitk_factor(m, n, k);
+    if (S <= 1) return 0;
+    const int64_t kchunk = ((k + S - 1) / S + 15) / 16 * 16;
+    S = (int)((k + kchunk - 1) / kchunk);
+    return (size_t)S * (size_t)m * (size_t)n * elem;
+}
 int gemm_tuned_classes() { return g_tuned.load(); }
 
 template <typename T>
@@ -480,12 +511,7 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
           const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s) {
     if (m <= 0 || n <= 0) return;
     // K is split when the output has too few 64 x 64 tiles to fill 256 CUs
-    const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
-    int S = 1;
-    if (tiles < 192 && k >= 4096) {
-        S = (int)std::min<int64_t>((512 + tiles - 1) / tiles, k / 512);
-        S = std::max(1, std::min(S, 64));
-    }
+    const int S = splitk_factor(m, n, k);
     const int v = tuned_variant<T>(op, m, n, k, S, alpha, A, lda, B, ldb, s);
     ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
                    8.0 * (double)m * (double)n * (double)std::max<int64_t>(k, 0), s);
