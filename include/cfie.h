@@ -64,8 +64,9 @@ enum {
 };
 
 typedef struct {
-    int32_t n_nodes;      /* N >= 8 nodes = elements, uniform in arc length from t = 0;
-                             N <= 65536 for powers of two, else N <= 32768             */
+    int32_t n_nodes;      /* 8 <= N <= 32768 nodes = elements, uniform in arc length from
+                             t = 0 (the four dense matrices take 64 N^2 bytes: 69 GB at
+                             N = 32768)                                                */
     int32_t n_modes;      /* M >= 1: z(t) = sum_{m=-M..M} zhat[m+M] e^{imt}, CCW       */
     const double *zhat;   /* host, 2*(2M+1) doubles (re, im); read during the call only */
 } cfie_contour;

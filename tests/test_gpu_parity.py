@@ -163,7 +163,8 @@ def test_circle_remainder_vanishes():
     assert np.linalg.norm(X[:, 1] - jm) / np.linalg.norm(jm) < 2e-2
 
 
-@pytest.mark.parametrize("N", [8, 32, 512, 2048, 8192, 16384, 9, 100, 1000, 3000, 6000])
+@pytest.mark.parametrize("N", [8, 32, 512, 2048, 8192, 16384, 32768, 9, 100, 1000, 3000, 6000,
+                               20000, 32767])
 def test_circulant_fft_lengths(N):
     """C_c x and C_c^-1 x by the library's FFT path against numpy's FFT with the exported
     eigenvalues: odd and even powers of two, one pass (N <= 4096) and the four-step split
@@ -240,6 +241,9 @@ def test_state_machine_and_errors(cfg1):
     assert e.value.status == 1
     with pytest.raises(P.CfieError) as e:
         s.assemble(w.zhat, 64, -1.0)
+    assert e.value.status == 1
+    with pytest.raises(P.CfieError) as e:
+        s.assemble(w.zhat, 32769, 3.0)                    # above the size limit
     assert e.value.status == 1
     with pytest.raises(P.CfieError) as e:
         s.assemble(w.zhat[::-1].copy(), 64, 3.0)          # clockwise
