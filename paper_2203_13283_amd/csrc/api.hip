@@ -193,6 +193,10 @@ struct cfie_ctx {
     }
     bool stream_owned = false;
 
+    // allocations of the current call that are temporaries (TempScope): released when the
+    // call ends, also when it ends early by an error
+    std::vector<void *> *tmp_track = nullptr;
+
     void *dalloc(size_t bytes) {
         if (opt.fail_alloc_after >= 0 && n_alloc >= opt.fail_alloc_after)
             throw HipError{CFIE_ENOMEM, "injected allocation failure"};
@@ -207,6 +211,7 @@ struct cfie_ctx {
                                             " bytes failed"};
         }
         live[p] = bytes;
+        if (tmp_track) tmp_track->push_back(p);
         return p;
     }
     void dfree(void *p) {
@@ -225,7 +230,15 @@ struct cfie_ctx {
             dfree(ws[slot]);
             ws[slot] = nullptr;
             ws_bytes[slot] = 0;
-            ws[slot] = dalloc(need);
+            std::vector<void *> *keep = tmp_track;     // the workspaces outlive the call
+            tmp_track = nullptr;
+            try {
+                ws[slot] = dalloc(need);
+            } catch (...) {
+                tmp_track = keep;
+                throw;
+            }
+            tmp_track = keep;
             ws_bytes[slot] = need;
         }
         return (T *)ws[slot];
@@ -238,6 +251,19 @@ struct cfie_ctx {
 };
 
 namespace {
+
+// Every device allocation made while it lives is released when it ends (calls whose
+// allocations are all temporaries, so that an error part-way leaves nothing behind).
+struct TempScope {
+    cfie_ctx *c;
+    std::vector<void *> list;
+    std::vector<void *> *prev;
+    explicit TempScope(cfie_ctx *cc) : c(cc), prev(cc->tmp_track) { c->tmp_track = &list; }
+    ~TempScope() {
+        c->tmp_track = prev;
+        for (void *p : list) c->dfree(p);           // no-op for what the call freed itself
+    }
+};
 
 cfie_status fail(cfie_ctx *c, cfie_status s, const std::string &m) {
     if (c) c->err = m;
@@ -1306,6 +1332,8 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         p.r1 = N;
         p.ld = N;
         for (int i = 0; i < 4; ++i) p.out[i] = c->mat[i];
+        zd *band_ws = c->alloc_n<zd>(far_band_ws_elems(p));
+        p.ws = band_ws;
         launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
         launch_assemble_near(p, c->pn, c->xn.data(), c->wn.data(), c->d_mom, s);
         c->check_launch();
@@ -1318,6 +1346,7 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         pc.ld = 1;
         for (int i = 0; i < 4; ++i) pc.out[i] = c->crow + (size_t)i * N;
         launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), s);
+        c->dfree(band_ws);
         launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, s);
         setup_fft(c);
         // rows of symmetric circulants equal their first columns
@@ -1451,6 +1480,7 @@ cfie_status cfie_plane_wave_rhs(cfie_ctx *c, const double *angles, int64_t nrhs,
         if (!std::isfinite(angles[i])) return fail(c, CFIE_EINVAL, "non-finite angle");
     return guarded(c, [&]() -> cfie_status {
         HIPCHK(hipSetDevice(c->device));
+        TempScope temps(c);
         const int N = c->N;
         hipStream_t s = c->stream;
         zd *B = (zd *)Bv;
@@ -1494,6 +1524,7 @@ cfie_status cfie_far_field(cfie_ctx *c, const void *X, int64_t ldx, int64_t nrhs
         if (!std::isfinite(obs[i])) return fail(c, CFIE_EINVAL, "non-finite angle");
     return guarded(c, [&]() -> cfie_status {
         HIPCHK(hipSetDevice(c->device));
+        TempScope temps(c);
         const int N = c->N;
         hipStream_t s = c->stream;
         std::vector<double> ang(n_obs);
@@ -1532,6 +1563,7 @@ cfie_status cfie_shape_gradient(cfie_ctx *c, const double *inc, int64_t nrhs, co
     if (nrhs == 0 || n_obs == 0) return CFIE_OK;
     return guarded(c, [&]() -> cfie_status {
         HIPCHK(hipSetDevice(c->device));
+        TempScope temps(c);
         const int N = c->N;
         const int64_t m = nrhs;
         hipStream_t s = c->stream;
@@ -1690,6 +1722,7 @@ cfie_status cfie_apply(cfie_ctx *c, int op, const void *X, int64_t ldx, void *Y,
     if (X == Y) return fail(c, CFIE_EINVAL, "X and Y must not alias");
     return guarded(c, [&]() -> cfie_status {
         HIPCHK(hipSetDevice(c->device));
+        TempScope temps(c);
         const int N = c->N;
         hipStream_t s = c->stream;
         const zd *Xd = (const zd *)X;

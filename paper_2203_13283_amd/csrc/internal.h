@@ -109,7 +109,11 @@ struct AsmParams {
     int r0, r1;
     int64_t ld;
     zd *out[4];                      // Dk, Nk, Dkt, Skt
+    zd *ws = nullptr;                // far assembly: far_band_ws_elems(*this) complex128
 };
+// work space of launch_assemble_far (blocks of the small-argument element pairs near the
+// diagonal), in complex128 elements
+size_t far_band_ws_elems(const AsmParams &p);
 void launch_assemble_far(const AsmParams &p, const PointTable &far, const double *xi,
                          const double *w, hipStream_t s);
 // Near part: entries with cyclic |i - j| <= nb + 1; touching element pairs by product

@@ -118,15 +118,23 @@ __device__ __forceinline__ double far_kRmin(double k, double h, double dxr, doub
 constexpr double kFarFast = 200.0;    // k R above which the 8-term series is used
 
 // One wavefront: 63 output rows (lane l holds element i0 - 1 + l) and kFarCols node
-// columns, walking the element columns f.  Two passes over the same tiles:
-//   SLOW = false: element pairs whose k R >= kFarFast for every point pair (by far_kRmin)
-//                 with the 8-term large-argument series; writes every entry of the tile;
-//   SLOW = true : the remaining element pairs outside the near band (any argument, per
-//                 lane forms) added to the entries they touch.
-// Entry (i, j) is owned by one lane in each pass, so the sum is deterministic.
-template <int Q, bool SLOW>
-__global__ __launch_bounds__(256, SLOW ? 1 : 2) void k_far(int N, double h, PairConsts c,
-                                                           int nb, int r0, int r1, int64_t ld,
+// columns, walking the element columns f.  Three passes over the same tiles, by the lower
+// bound of k R over the element pair's point pairs (far_kRmin):
+//   MODE 0: k R >= kFarFast for every point pair: the 8-term large-argument series; writes
+//           every entry of the tile;
+//   MODE 1: kAsymMin <= k R < kFarFast: the 22-term series (one code path for the whole
+//           wavefront, no divergence between lanes); adds to the entries it touches;
+//   MODE 2: the remaining element pairs outside the near band (small arguments: ascending
+//           series or Miller's recurrence, per-lane forms) further than dband elements from
+//           the diagonal (none on a contour that does not fold back on itself); adds to the
+//           entries it touches.
+// Entry (i, j) is owned by one lane in each pass, so the sum is deterministic.  The small-
+// argument element pairs within dband of the diagonal go to k_far_band / k_far_band_add: a
+// long serial chain per wavefront there left most of the device idle.
+template <int Q, int MODE>
+__global__ __launch_bounds__(256, MODE == 2 ? 1 : 2) void k_far(int N, double h, PairConsts c,
+                                                           int nb, int dband, int r0, int r1,
+                                                           int64_t ld,
                                                            zd *o0, zd *o1, zd *o2, zd *o3,
                                                            const double *__restrict__ PX,
                                                            const double *__restrict__ PY,
@@ -164,7 +172,7 @@ __global__ __launch_bounds__(256, SLOW ? 1 : 2) void k_far(int N, double h, Pair
     zd acc0[4][2], acc1[4][2];
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc0[m][0] = acc0[m][1] = acc1[m][0] = acc1[m][1] = mk(0.0, 0.0);
-    bool used_prev = false;                           // SLOW: this lane added at column f - 1
+    bool used_prev = false;                           // MODE > 0: this lane added at f - 1
     for (int f = j0 - 1; f < jend; ++f) {
         int fe = (f % N + N) % N;
         int off = fe - e;
@@ -173,9 +181,18 @@ __global__ __launch_bounds__(256, SLOW ? 1 : 2) void k_far(int N, double h, Pair
         const double kRmin = far_kRmin(c.k, h, xref - PX[fe * Q + Q / 2],
                                        yref - PY[fe * Q + Q / 2]);
         const bool fast = kRmin >= kFarFast;
-        const bool use = on && (SLOW ? !fast : fast);
+        const bool mid = !fast && kRmin >= kAsymMin;
+        // MODE 2 leaves the element pairs within dband of the diagonal to k_far_band
+        const bool use = on && (MODE == 0 ? fast
+                                : MODE == 1 ? mid
+                                            : (!fast && !mid && min(off, N - off) > dband));
         if (__any(use)) {
-            if constexpr (SLOW) {
+            if constexpr (MODE == 1) {
+                auto K22 = [&](double R, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
+                    pair_kernels_asym<kSerMax>(c, R, nu, g0, g1, g2, g3);
+                };
+                far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K22);
+            } else if constexpr (MODE == 2) {
                 auto KG = [&](double R, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
                     pair_kernels(c, R, nu, g0, g1, g2, g3);
                 };
@@ -192,10 +209,10 @@ __global__ __launch_bounds__(256, SLOW ? 1 : 2) void k_far(int N, double h, Pair
             int dij = out_row - j;
             dij = ((dij % N) + N) % N;
             int dd = min(dij, N - dij);
-            // SLOW: the entry changes if any of its element pairs (e, f-1), (e, f),
+            // MODE > 0: the entry changes if any of its element pairs (e, f-1), (e, f),
             // (e+1, f-1), (e+1, f) was added in this pass
             const int mine = (use || used_prev) ? 1 : 0;
-            const bool touched = SLOW ? (mine | __shfl_down(mine, 1)) != 0 : true;
+            const bool touched = MODE != 0 ? (mine | __shfl_down(mine, 1)) != 0 : true;
             zd *outs[4] = {o0, o1, o2, o3};
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -205,7 +222,7 @@ __global__ __launch_bounds__(256, SLOW ? 1 : 2) void k_far(int N, double h, Pair
                 zd v = acc0[m][1] + mk(nx, ny);
                 if (row_ok && dd >= nb + 2 && touched) {
                     zd *dst = outs[m] + (int64_t)out_row + (int64_t)j * ld;
-                    if (SLOW) v = v + *dst;
+                    if (MODE != 0) v = v + *dst;
                     *dst = v;
                 }
             }
@@ -220,6 +237,130 @@ __global__ __launch_bounds__(256, SLOW ? 1 : 2) void k_far(int N, double h, Pair
     }
 }
 
+// Element pairs (e, f = e + d) with nb < |d| <= dband whose k R can be below kAsymMin (the
+// MODE 2 condition of k_far): one thread per element pair, lanes of a wavefront share the
+// offset d (similar arguments, coherent branches).  The 2x2 node block of each of the four
+// matrices goes to Bk[((m 4 + 2a + b) nd + didx) ne + eidx] (zero for the other pairs);
+// elements e = r0 - 1 + eidx, offsets d = didx - dl.
+template <int Q>
+__global__ __launch_bounds__(256) void k_far_band(int N, double h, PairConsts c, int nb, int dl,
+                                                  int dr, int r0, int ne,
+                                                  const double *__restrict__ PX,
+                                                  const double *__restrict__ PY,
+                                                  const double *__restrict__ PTX,
+                                                  const double *__restrict__ PTY,
+                                                  QuadConsts<Q> qc, zd *Bk) {
+    const int nd = dl + dr + 1;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)ne * nd) return;
+    const int eidx = (int)(tid % ne), didx = (int)(tid / ne);
+    const int d = didx - dl;
+    const int e = ((r0 - 1 + eidx) % N + N) % N;
+    const int f = ((e + d) % N + N) % N;
+    zd acc[4][2][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        acc[m][0][0] = acc[m][0][1] = acc[m][1][0] = acc[m][1][1] = mk(0.0, 0.0);
+    const double kRmin = far_kRmin(c.k, h, PX[e * Q + Q / 2] - PX[f * Q + Q / 2],
+                                   PY[e * Q + Q / 2] - PY[f * Q + Q / 2]);
+    const int ad = d < 0 ? -d : d;
+    if (ad > nb && kRmin < kAsymMin) {
+        const double k2 = c.k * c.k;
+        for (int g = 0; g < Q; ++g) {
+            const double xo = PX[e * Q + g], yo = PY[e * Q + g];
+            const double txo = PTX[e * Q + g], tyo = PTY[e * Q + g];
+            const double xg = qc.xi[g], wg = qc.w[g];
+            const double wa[2] = {h * wg * (1.0 - xg), h * wg * xg};
+            for (int hh = 0; hh < Q; ++hh) {
+                const double xs = PX[f * Q + hh], ys = PY[f * Q + hh];
+                const double txs = PTX[f * Q + hh], tys = PTY[f * Q + hh];
+                const double xh = qc.xi[hh], wh = qc.w[hh];
+                const double wb[2] = {h * wh * (1.0 - xh), h * wh * xh};
+                const double dx = xo - xs, dy = yo - ys;
+                const double R = sqrt(dx * dx + dy * dy);
+                const double nu = (dx * tys - dy * txs) / R;
+                const double nn = tyo * tys + txo * txs;
+                zd gk, Dk, St, Dt;
+                pair_kernels(c, R, nu, gk, Dk, St, Dt);
+                const double wgh = wg * wh;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const double w = wa[a] * wb[b];
+                        acc[0][a][b] = acc[0][a][b] + Dk * w;
+                        acc[2][a][b] = acc[2][a][b] + Dt * w;
+                        acc[3][a][b] = acc[3][a][b] + St * w;
+                        acc[1][a][b] = acc[1][a][b] + gk * ((a == b ? wgh : -wgh) - k2 * nn * w);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                Bk[((int64_t)(m * 4 + 2 * a + b) * nd + didx) * ne + eidx] = acc[m][a][b];
+}
+
+// entry (i, j), r0 <= i < r1, in the far region (cyclic |i - j| >= nb + 2) within dband + 1
+// of the diagonal: adds the blocks of its element pairs (i - a, j - b) that k_far_band holds
+template <int Q>
+__global__ __launch_bounds__(256) void k_far_band_add(int N, int nb, int dl, int dr, int r0,
+                                                      int r1, int ne, int64_t ld, zd *o0,
+                                                      zd *o1, zd *o2, zd *o3,
+                                                      const zd *__restrict__ Bk) {
+    const int nd = dl + dr + 1;
+    const int nrows = r1 - r0;
+    const int no = dl + dr + 3;                      // entry offsets -(dl+1) .. dr+1
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)nrows * no) return;
+    const int i = r0 + (int)(tid % nrows);
+    const int o = (int)(tid / nrows) - (dl + 1);
+    // one representative per entry: offsets in (-N/2, N/2]
+    if (2 * o <= -N || 2 * o > N) return;
+    const int ao = o < 0 ? -o : o;
+    if (min(ao, N - ao) < nb + 2) return;
+    const int j = ((i + o) % N + N) % N;
+    zd v[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    bool any = false;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            // element pair (e = i - a, f = j - b), offset o - b + a in (-N/2, N/2]
+            int d = o - b + a;
+            d = ((d % N) + N) % N;
+            if (2 * d > N) d -= N;
+            if (d < -dl || d > dr) continue;
+            const int eidx = i - a - (r0 - 1);
+            if (eidx < 0 || eidx >= ne) continue;
+            const int didx = d + dl;
+            any = true;
+            for (int m = 0; m < 4; ++m)
+                v[m] = v[m] + Bk[((int64_t)(m * 4 + 2 * a + b) * nd + didx) * ne + eidx];
+        }
+    if (!any) return;
+    zd *outs[4] = {o0, o1, o2, o3};
+    const int64_t idx = (int64_t)i + (int64_t)j * ld;
+    for (int m = 0; m < 4; ++m) outs[m][idx] = outs[m][idx] + v[m];
+}
+
+// half-widths (dl, dr) of the band of k_far_band: past it the chord between the elements'
+// reference points exceeds kAsymMin / k + 2h on a contour that does not fold back (arc
+// length and chord agree to second order), with a margin of a quarter and four elements
+int far_band_width(int N, double k, double h, int nb) {
+    const double w = 1.25 * kAsymMin / (k * h) + 4.0;
+    int D = nb + (int)std::ceil(w);
+    return D;
+}
+size_t far_band_ws_elems(const AsmParams &p) {
+    const int D = far_band_width(p.N, p.kc.k, p.h, p.nb);
+    const int dl = std::min(D, (p.N - 1) / 2), dr = std::min(D, p.N / 2);
+    const int ne = std::min(p.r1 - p.r0 + 1, p.N + 1);
+    return (size_t)16 * (size_t)(dl + dr + 1) * (size_t)ne;
+}
+
 void launch_assemble_far(const AsmParams &p, const PointTable &far, const double *xi,
                          const double *w, hipStream_t s) {
     PairConsts c = make_consts(p.kc);
@@ -232,16 +373,31 @@ void launch_assemble_far(const AsmParams &p, const PointTable &far, const double
     double far_pairs = (double)nrows * (double)(p.N - std::min(p.N, 2 * p.nb + 1)) *
                        (double)far.q * far.q;
     ProfScope prof(PROF_FAR, far_pairs, s);
+    const int D = far_band_width(p.N, p.kc.k, p.h, p.nb);
+    const int dl = std::min(D, (p.N - 1) / 2), dr = std::min(D, p.N / 2);
+    const int dband = std::min(D, p.N / 2);
+    const int ne = std::min(p.r1 - p.r0 + 1, p.N + 1);
+    const int64_t nbe = (int64_t)ne * (dl + dr + 1);
+    const int64_t nbadd = (int64_t)(p.r1 - p.r0) * (dl + dr + 3);
 #define CFIE_FAR_CASE(QQ)                                                                   \
     case QQ: {                                                                             \
         QuadConsts<QQ> qc;                                                                 \
         for (int i = 0; i < QQ; ++i) { qc.xi[i] = xi[i]; qc.w[i] = w[i]; }                 \
-        hipLaunchKernelGGL((k_far<QQ, false>), dim3(blocks), dim3(256), 0, s, p.N, p.h, c, \
-                           p.nb, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2], p.out[3],  \
-                           far.x, far.y, far.tx, far.ty, qc, n_row_tiles);                 \
-        hipLaunchKernelGGL((k_far<QQ, true>), dim3(blocks), dim3(256), 0, s, p.N, p.h, c,  \
-                           p.nb, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2], p.out[3],  \
-                           far.x, far.y, far.tx, far.ty, qc, n_row_tiles);                 \
+        hipLaunchKernelGGL((k_far<QQ, 0>), dim3(blocks), dim3(256), 0, s, p.N, p.h, c,     \
+                           p.nb, dband, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2],     \
+                           p.out[3], far.x, far.y, far.tx, far.ty, qc, n_row_tiles);       \
+        hipLaunchKernelGGL((k_far<QQ, 1>), dim3(blocks), dim3(256), 0, s, p.N, p.h, c,     \
+                           p.nb, dband, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2],     \
+                           p.out[3], far.x, far.y, far.tx, far.ty, qc, n_row_tiles);       \
+        hipLaunchKernelGGL((k_far<QQ, 2>), dim3(blocks), dim3(256), 0, s, p.N, p.h, c,     \
+                           p.nb, dband, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2],     \
+                           p.out[3], far.x, far.y, far.tx, far.ty, qc, n_row_tiles);       \
+        hipLaunchKernelGGL((k_far_band<QQ>), dim3((unsigned)((nbe + 255) / 256)), dim3(256), \
+                           0, s, p.N, p.h, c, p.nb, dl, dr, p.r0, ne, far.x, far.y, far.tx, \
+                           far.ty, qc, p.ws);                                              \
+        hipLaunchKernelGGL((k_far_band_add<QQ>), dim3((unsigned)((nbadd + 255) / 256)),    \
+                           dim3(256), 0, s, p.N, p.nb, dl, dr, p.r0, p.r1, ne, p.ld,        \
+                           p.out[0], p.out[1], p.out[2], p.out[3], (const zd *)p.ws);      \
         break;                                                                             \
     }
     switch (far.q) {
