@@ -57,6 +57,8 @@ void launch_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_
 template <typename T>
 void launch_swaps_reverse(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0,
                           int64_t c1, hipStream_t s);
+void launch_tri_inv_blocks(int n, int blk, const zd *A, int64_t lda, zd *Linv, zd *Uinv,
+                           hipStream_t s);
 void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
                     hipStream_t s);
 void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s);
@@ -788,12 +790,7 @@ cfie_status factor_impl(cfie_ctx *c) {
         }
         c->check_launch();
     }
-    for (int bi = 0; bi < nblk; ++bi) {
-        const int k0 = bi * kLUBlock, kb = std::min(kLUBlock, ell - k0);
-        zd *Kd = c->K + k0 + (size_t)k0 * cap;
-        launch_tri_inv(kb, Kd, cap, true, c->Linv + (size_t)bi * kLUBlock * kLUBlock, kLUBlock, s);
-        launch_tri_inv(kb, Kd, cap, false, c->Uinv + (size_t)bi * kLUBlock * kLUBlock, kLUBlock, s);
-    }
+    launch_tri_inv_blocks(ell, kLUBlock, c->K, cap, c->Linv, c->Uinv, s);
     c->check_launch();
     int info = 0;
     HIPCHK(hipMemcpyAsync(&info, c->info, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1635,11 +1632,11 @@ cfie_status cfie_shape_gradient(cfie_ctx *c, const double *inc, int64_t nrhs, co
         // backward kernels
         const int qf = c->pf.q, qn = c->pn.q;
         const int64_t npf = (int64_t)N * qf, npn = (int64_t)N * qn;
-        const int n_strips = (N + 127) / 128;
+        const int nbf = std::min(c->opt.near_band, N);
         double *adjf = c->alloc_n<double>(4 * npf), *adjn = c->alloc_n<double>(5 * npn);
-        double *part = c->alloc_n<double>((size_t)n_strips * 4 * npf);
-        const int n_eg = (N + 63) / 64;
-        double *sp_far = c->alloc_n<double>(2 * (size_t)n_eg * n_strips);
+        double *part = c->alloc_n<double>(grad_far_ws_doubles(N, qf, k, h, nbf));
+        const int n_far_pairs = grad_far_spart_pairs(N, k, h, nbf);
+        double *sp_far = c->alloc_n<double>(2 * (size_t)n_far_pairs);
         const int bn = (int)((npn + 127) / 128), be = (int)((npn + 255) / 256);
         double *sp_near = c->alloc_n<double>(2 * (size_t)bn);
         double *sp_exc = c->alloc_n<double>(2 * (size_t)be);
@@ -1653,6 +1650,7 @@ cfie_status cfie_shape_gradient(cfie_ctx *c, const double *inc, int64_t nrhs, co
         int n_waves = 0;
         launch_grad_far(N, h, kc, nb, Omc, N, c->pf, c->xf.data(), c->wf.data(), part, sp_far,
                         adjf, n_waves, s);
+        if (n_waves != n_far_pairs) return fail(c, CFIE_EHIP, "far backward: work split mismatch");
         launch_grad_near(N, h, kc, nb, Omc, N, c->pn, c->xn.data(), c->wn.data(), c->d_mom, adjn,
                          sp_near, s);
         launch_grad_exc(N, h, k, c->pn, c->d_xn, c->d_wn, d_inc, m, z2, N, mk(0.0, -k), true, v,

@@ -114,6 +114,8 @@ struct AsmParams {
 // work space of launch_assemble_far (blocks of the small-argument element pairs near the
 // diagonal), in complex128 elements
 size_t far_band_ws_elems(const AsmParams &p);
+// half-width in elements of the band of small-argument element pairs near the diagonal
+int far_band_width(int N, double k, double h, int nb);
 void launch_assemble_far(const AsmParams &p, const PointTable &far, const double *xi,
                          const double *w, hipStream_t s);
 // Near part: entries with cyclic |i - j| <= nb + 1; touching element pairs by product
@@ -129,12 +131,14 @@ void launch_excitation(const GeomDev &g, const PointTable &pt, const double *xi,
 // ------------------------------------------------------------------ shape derivative -----
 // Backward passes of the assembly (far and near element pairs), of the plane-wave vectors and
 // of the point evaluation; Om = loss weights of (Dk, Nk, Dkt, Skt), column-major, ld.
-// far: adj (4 x N q_far) = d loss / d(x, y, tx, ty) of the far table; part: n_strips x 4 x
-// N q_far work space (n_strips = ceil(N / 128)); spart: 2 per wave (d/dh, d/dbeta), n_waves
-// returned.
+// far: adj (4 x N q_far) = d loss / d(x, y, tx, ty) of the far table (written); ws:
+// grad_far_ws_doubles work space; spart: grad_far_spart_pairs pairs (d/dh, d/dbeta), their
+// number returned in n_pairs.
+size_t grad_far_ws_doubles(int N, int q, double k, double h, int nb);
+int grad_far_spart_pairs(int N, double k, double h, int nb);
 void launch_grad_far(int N, double h, const KernelConsts &kc, int nb, const zd *const Om[4],
                      int64_t ld, const PointTable &pt, const double *xi, const double *w,
-                     double *part, double *spart, double *adj, int &n_waves, hipStream_t s);
+                     double *ws, double *spart, double *adj, int &n_pairs, hipStream_t s);
 // near: adj (5 x N q_near, with curvature) written; spart: 2 per block; returns the blocks
 int launch_grad_near(int N, double h, const KernelConsts &kc, int nb, const zd *const Om[4],
                      int64_t ld, const PointTable &pt, const double *xi, const double *w,

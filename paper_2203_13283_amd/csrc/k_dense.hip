@@ -34,6 +34,52 @@ __global__ void k_ginv(int N, int ntap, int t0, const double *__restrict__ coef,
     out[i + c * ldo] = r;
 }
 
+// The same for the 61-tap band (N >= 61) with R consecutive outputs per thread sharing one
+// window of R + 60 inputs in registers (each input is read once per R outputs instead of 61
+// times); the taps of every output are summed in the same order as above.
+constexpr int kGinvTaps = 61;
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_ginv_win(int N, int t0, const double *__restrict__ coef,
+                                                  cpx<T> a, const cpx<T> *X, int64_t ldx,
+                                                  cpx<T> b, const cpx<T> *__restrict__ Y,
+                                                  int64_t ldy, cpx<T> *out, int64_t ldo,
+                                                  int64_t ncol) {
+    const int nchunk = (N + R - 1) / R;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)nchunk * ncol) return;
+    const int i0 = (int)(tid % nchunk) * R;
+    const int64_t c = tid / nchunk;
+    const cpx<T> *y = Y + c * ldy;
+    constexpr int W = kGinvTaps + R - 1;
+    cpx<T> win[W];
+    // win[j] = y[(i0 - t0 - (taps - 1) + j) mod N]
+    int idx = i0 - t0 - (kGinvTaps - 1);
+    idx %= N;
+    if (idx < 0) idx += N;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        win[j] = y[idx];
+        idx = idx + 1 == N ? 0 : idx + 1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = i0 + r;
+        if (i < N) {
+            T sr = 0, si = 0;
+#pragma unroll
+            for (int u = 0; u < kGinvTaps; ++u) {
+                const cpx<T> v = win[kGinvTaps - 1 + r - u];
+                const T w = (T)coef[u];
+                sr += w * v.x;
+                si += w * v.y;
+            }
+            cpx<T> res = b * mk(sr, si);
+            if (X) res = res + a * X[i + c * ldx];
+            out[i + c * ldo] = res;
+        }
+    }
+}
+
 // out = a X + b G Y, G = h circ(2/3; 1/6, 1/6)
 template <typename T>
 __global__ void k_gmul(int N, double h, cpx<T> a, const cpx<T> *X, int64_t ldx, cpx<T> b,
@@ -76,6 +122,13 @@ void launch_ginv_ex(int N, int ntap, int t0, const double *coef, cpx<T> a, const
                     int64_t ldo, int64_t ncol, hipStream_t s) {
     int64_t n = (int64_t)N * ncol;
     if (n <= 0) return;
+    if (ntap == kGinvTaps) {
+        constexpr int R = 8;
+        const int64_t nt = (int64_t)((N + R - 1) / R) * ncol;
+        hipLaunchKernelGGL((k_ginv_win<T, R>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
+                           s, N, t0, coef, a, X, ldx, b, Y, ldy, out, ldo, ncol);
+        return;
+    }
     hipLaunchKernelGGL(k_ginv<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, ntap,
                        t0, coef, a, X, ldx, b, Y, ldy, out, ldo, ncol);
 }
@@ -739,10 +792,8 @@ template void launch_swaps<double>(int, int, const int *, zd *, int64_t, int64_t
 // inverse of the nb x nb (nb <= 64) diagonal block at A: unit lower (lower = true) or upper.
 // The block is staged in LDS; one thread per column of the inverse (element (r, c) of the
 // inverse at X[c + 65 r], so that the threads of a step touch consecutive words).
-__global__ __launch_bounds__(64) void k_tri_inv(int nb, const zd *A, int64_t lda, bool lower,
-                                                zd *Inv, int ldi) {
-    __shared__ zd Ab[64 * 65];
-    __shared__ zd X[64 * 65];
+__device__ __forceinline__ void tri_inv_body(int nb, const zd *A, int64_t lda, bool lower,
+                                             zd *Inv, int ldi, zd *Ab, zd *X) {
     const int c = threadIdx.x;
     for (int q = 0; q < nb; ++q)
         if (c < nb) Ab[c + q * 65] = A[c + (int64_t)q * lda];
@@ -769,9 +820,34 @@ __global__ __launch_bounds__(64) void k_tri_inv(int nb, const zd *A, int64_t lda
     for (int q = 0; q < nb; ++q)
         if (c < nb) Inv[c + q * ldi] = X[q + c * 65];
 }
+__global__ __launch_bounds__(64) void k_tri_inv(int nb, const zd *A, int64_t lda, bool lower,
+                                                zd *Inv, int ldi) {
+    __shared__ zd Ab[64 * 65];
+    __shared__ zd X[64 * 65];
+    tri_inv_body(nb, A, lda, lower, Inv, ldi, Ab, X);
+}
+// all diagonal blocks of an n x n LU at once: workgroup (bi, 0) inverts the unit lower
+// triangle of block bi into Linv + bi blk^2, (bi, 1) the upper one into Uinv + bi blk^2
+__global__ __launch_bounds__(64) void k_tri_inv_blocks(int n, int blk, const zd *A,
+                                                       int64_t lda, zd *Linv, zd *Uinv) {
+    __shared__ zd Ab[64 * 65];
+    __shared__ zd X[64 * 65];
+    const int bi = blockIdx.x;
+    const bool lower = blockIdx.y == 0;
+    const int k0 = bi * blk, kb = min(blk, n - k0);
+    const zd *Ad = A + k0 + (int64_t)k0 * lda;
+    zd *Inv = (lower ? Linv : Uinv) + (size_t)bi * blk * blk;
+    tri_inv_body(kb, Ad, lda, lower, Inv, blk, Ab, X);
+}
 void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_tri_inv, dim3(1), dim3(64), 0, s, nb, A, lda, lower, Inv, ldi);
+}
+void launch_tri_inv_blocks(int n, int blk, const zd *A, int64_t lda, zd *Linv, zd *Uinv,
+                           hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_tri_inv_blocks, dim3((n + blk - 1) / blk, 2), dim3(64), 0, s, n, blk, A,
+                       lda, Linv, Uinv);
 }
 
 // identity added to the diagonal: A += I

@@ -52,10 +52,14 @@ struct QW {
 
 // ------------------------------------------------------------------ far pairs -------------
 // Omega: the four loss-weight matrices (Dk, Nk, Dkt, Skt), column-major with leading
-// dimension ld.  part: [strip][4][N Q] partial adjoints of (x, y, tx, ty); spart: per wave
-// (d/dh, d/dbeta).
-template <int Q>
-__global__ __launch_bounds__(256) void k_grad_far(int N, double h, PairConsts c, int nb, int SL,
+// dimension ld.  part: [strip][4][N Q] partial adjoints of (x, y, tx, ty) (MODE 0 writes,
+// MODE 1 and 2 add); spart: per wave (d/dh, d/dbeta).  The passes split the element pairs
+// as the forward assembly does, by the lower bound of k R (far_kRmin): MODE 0 the 8-term
+// large-argument series, MODE 1 the 22-term series, MODE 2 the small arguments beyond
+// dband elements from the diagonal (those within go to k_grad_far_band).
+template <int Q, int MODE>
+__global__ __launch_bounds__(256) void k_grad_far(int N, double h, PairConsts c, int nb,
+                                                  int dband, int SL,
                                                   const zd *__restrict__ O0,
                                                   const zd *__restrict__ O1,
                                                   const zd *__restrict__ O2,
@@ -89,10 +93,17 @@ __global__ __launch_bounds__(256) void k_grad_far(int N, double h, PairConsts c,
     const double k = c.k, h2 = h * h;
     const double rsafe = 1000.0 * c.invk;
     const zd *Om[4] = {O0, O1, O2, O3};
+    const double xref = own[(0 * Q + Q / 2) * 256], yref = own[(1 * Q + Q / 2) * 256];
     double hbar = 0.0, bbar = 0.0;
     for (int f = f0; f < f1; ++f) {
         const int fn = (f + 1) % N;
-        const bool on = valid && cdist(e, f, N) > nb;
+        const int cd = cdist(e, f, N);
+        const double kRmin = far_kRmin(c.k, h, xref - PX[f * Q + Q / 2],
+                                       yref - PY[f * Q + Q / 2]);
+        const bool fast = kRmin >= kFarFast;
+        const bool mid = !fast && kRmin >= kAsymMin;
+        const bool on = valid && cd > nb &&
+                        (MODE == 0 ? fast : MODE == 1 ? mid : (!fast && !mid && cd > dband));
         if (!__any(on)) continue;
         // loss weights of the 2x2 node blocks, far entries only:
         //   Omega_m[e + a, f + b]   (own element observes)
@@ -156,7 +167,9 @@ __global__ __launch_bounds__(256) void k_grad_far(int N, double h, PairConsts c,
                 const double nu2 = (dy * txo - dx * tyo) / R;
                 const double nn = txo * txs + tyo * tys;
                 zd g0, g1, t0, t1;
-                pair_kernels(c, R, 1.0, g0, g1, t0, t1);
+                if constexpr (MODE == 0) pair_kernels_asym<8>(c, R, 1.0, g0, g1, t0, t1);
+                else if constexpr (MODE == 1) pair_kernels_asym<kSerMax>(c, R, 1.0, g0, g1, t0, t1);
+                else pair_kernels(c, R, 1.0, g0, g1, t0, t1);
                 const double xg = qc.xi[g], wg = qc.w[g];
                 const double pg[2] = {1.0 - xg, xg};
                 const double ww = wg * wh, hw = h2 * ww;
@@ -187,8 +200,10 @@ __global__ __launch_bounds__(256) void k_grad_far(int N, double h, PairConsts c,
     if (valid) {
         const size_t np = (size_t)N * Q;
         for (int v = 0; v < 4; ++v)
-            for (int g = 0; g < Q; ++g)
-                part[((size_t)strip * 4 + v) * np + (size_t)e * Q + g] = adj[(v * Q + g) * 256];
+            for (int g = 0; g < Q; ++g) {
+                double *dst = part + ((size_t)strip * 4 + v) * np + (size_t)e * Q + g;
+                *dst = (MODE == 0 ? 0.0 : *dst) + adj[(v * Q + g) * 256];
+            }
     }
     hbar = wave_sum(hbar);
     bbar = wave_sum(bbar);
@@ -196,6 +211,133 @@ __global__ __launch_bounds__(256) void k_grad_far(int N, double h, PairConsts c,
         spart[2 * (size_t)wave] = hbar;
         spart[2 * (size_t)wave + 1] = bbar;
     }
+}
+
+// Ordered element pairs (e, f = e + d) with nb < |d| <= band and k R below kAsymMin (the
+// forward's k_far_band pairs): one thread per pair, lanes sharing the offset d.  The
+// derivatives of the pair's loss terms with respect to the observation element's points go
+// to ob[v][didx][e Q + g], those with respect to the source element's points to
+// sb[v][didx][e Q + hh] (zero for the other pairs); d = didx - dl.  spart: per block
+// (d/dh, d/dbeta).
+template <int Q>
+__global__ __launch_bounds__(256) void k_grad_far_band(int N, double h, PairConsts c, int nb,
+                                                       int dl, int dr,
+                                                       const zd *__restrict__ O0,
+                                                       const zd *__restrict__ O1,
+                                                       const zd *__restrict__ O2,
+                                                       const zd *__restrict__ O3, int64_t ld,
+                                                       const double *__restrict__ PX,
+                                                       const double *__restrict__ PY,
+                                                       const double *__restrict__ PTX,
+                                                       const double *__restrict__ PTY,
+                                                       QW<Q> qc, double *ob, double *sb,
+                                                       double *spart) {
+    const int nd = dl + dr + 1;
+    const size_t np = (size_t)N * Q;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double hbar = 0.0, bbar = 0.0;
+    if (tid < (int64_t)N * nd) {
+        const int e = (int)(tid % N), didx = (int)(tid / N);
+        const int d = didx - dl;
+        const int f = ((e + d) % N + N) % N;
+        const int ad = d < 0 ? -d : d;
+        double oa[Q][4], sa[Q][4];
+        for (int g = 0; g < Q; ++g)
+            for (int v = 0; v < 4; ++v) oa[g][v] = sa[g][v] = 0.0;
+        const double kRmin = far_kRmin(c.k, h, PX[e * Q + Q / 2] - PX[f * Q + Q / 2],
+                                       PY[e * Q + Q / 2] - PY[f * Q + Q / 2]);
+        if (ad > nb && kRmin < kAsymMin) {
+            const zd *Om[4] = {O0, O1, O2, O3};
+            const int ri[2] = {e, (e + 1) % N}, rf[2] = {f, (f + 1) % N};
+            zd o[4][2][2];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const bool far_entry = cdist(ri[a], rf[b], N) >= nb + 2;
+                    for (int m = 0; m < 4; ++m)
+                        o[m][a][b] = far_entry ? Om[m][(int64_t)ri[a] + (int64_t)rf[b] * ld]
+                                               : mk(0.0, 0.0);
+                }
+            const double k = c.k, h2 = h * h;
+            for (int g = 0; g < Q; ++g) {
+                const double xo = PX[e * Q + g], yo = PY[e * Q + g];
+                const double txo = PTX[e * Q + g], tyo = PTY[e * Q + g];
+                const double xg = qc.xi[g], wg = qc.w[g];
+                const double pg[2] = {1.0 - xg, xg};
+                for (int hh = 0; hh < Q; ++hh) {
+                    const double xs = PX[f * Q + hh], ys = PY[f * Q + hh];
+                    const double txs = PTX[f * Q + hh], tys = PTY[f * Q + hh];
+                    const double xh = qc.xi[hh], wh = qc.w[hh];
+                    const double ph[2] = {1.0 - xh, xh};
+                    const double dx = xo - xs, dy = yo - ys;
+                    const double R = sqrt(dx * dx + dy * dy);
+                    const double nu = (dx * tys - dy * txs) / R;
+                    const double nn = txo * txs + tyo * tys;
+                    zd g0, g1, t0, t1;
+                    pair_kernels(c, R, 1.0, g0, g1, t0, t1);
+                    const double ww = wg * wh, hw = h2 * ww;
+                    zd wm[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+                    zd wsg = mk(0.0, 0.0);
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b) {
+                            for (int m = 0; m < 4; ++m) wm[m] = wm[m] + o[m][a][b] * (pg[a] * ph[b]);
+                            wsg = wsg + o[1][a][b] * (a == b ? 1.0 : -1.0);
+                        }
+                    SmoothW W;
+                    W.wD = wm[0] * hw;
+                    W.wN2 = wm[1] * hw;
+                    W.wDt = wm[2] * hw;
+                    W.wS = wm[3] * hw;
+                    W.wN1 = wsg * ww;
+                    const PairD pd = smooth_pair_adjoint(k, c.kt, R, nu, nn, g0, g1, t0, t1, W);
+                    pair_geom_adjoint(dx, dy, R, nu, txo, tyo, txs, tys, pd, oa[g], sa[hh]);
+                    hbar += 2.0 * pd.vh2 / h;
+                    bbar += pd.beta;
+                }
+            }
+        }
+        for (int g = 0; g < Q; ++g)
+            for (int v = 0; v < 4; ++v) {
+                const size_t at = ((size_t)v * nd + didx) * np + (size_t)e * Q + g;
+                ob[at] = oa[g][v];
+                sb[at] = sa[g][v];
+            }
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = hbar;
+    red[1][threadIdx.x] = bbar;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        spart[2 * (size_t)blockIdx.x] = red[0][0];
+        spart[2 * (size_t)blockIdx.x + 1] = red[1][0];
+    }
+}
+
+// adj[v][x Q + g] += sum_d ob[v][d][x Q + g] + sum_d sb[v][d][(x - d) Q + g], in order of d
+template <int Q>
+__global__ void k_grad_band_sum(int N, int dl, int dr, const double *ob, const double *sb,
+                                double *adj) {
+    const int nd = dl + dr + 1;
+    const int64_t np = (int64_t)N * Q;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * np) return;
+    const int v = (int)(i / np);
+    const int64_t p = i % np;
+    const int x = (int)(p / Q), g = (int)(p % Q);
+    double acc = 0.0;
+    for (int didx = 0; didx < nd; ++didx) {
+        const int d = didx - dl;
+        const int e = ((x - d) % N + N) % N;
+        acc += ob[((int64_t)v * nd + didx) * np + p];
+        acc += sb[((int64_t)v * nd + didx) * np + (int64_t)e * Q + g];
+    }
+    adj[i] += acc;
 }
 
 // sum of the strip partials: adj[v][p] = sum_s part[s][v][p]
@@ -207,23 +349,64 @@ __global__ void k_sum_strips(int64_t np, int n_strips, const double *part, doubl
     adj[i] = acc;
 }
 
+// work space of launch_grad_far in doubles: strip partials, then the band kernel's two
+// partial arrays
+size_t grad_far_ws_doubles(int N, int q, double k, double h, int nb) {
+    const int n_strips = (N + 127) / 128;
+    const int D = far_band_width(N, k, h, nb);
+    const int dl = std::min(D, (N - 1) / 2), dr = std::min(D, N / 2);
+    return (size_t)n_strips * 4 * N * q + (size_t)2 * 4 * (dl + dr + 1) * N * q;
+}
+// number of (d/dh, d/dbeta) pairs launch_grad_far writes to spart
+int grad_far_spart_pairs(int N, double k, double h, int nb) {
+    const int n_eg = (N + 63) / 64, n_strips = (N + 127) / 128;
+    const int D = far_band_width(N, k, h, nb);
+    const int dl = std::min(D, (N - 1) / 2), dr = std::min(D, N / 2);
+    const int64_t nbt = (int64_t)N * (dl + dr + 1);
+    return 3 * n_eg * n_strips + (int)((nbt + 255) / 256);
+}
+
 void launch_grad_far(int N, double h, const KernelConsts &kc, int nb, const zd *const Om[4],
                      int64_t ld, const PointTable &pt, const double *xi, const double *w,
-                     double *part, double *spart, double *adj, int &n_waves, hipStream_t s) {
+                     double *ws, double *spart, double *adj, int &n_pairs, hipStream_t s) {
     PairConsts c = make_consts(kc);
     const int SL = 128;
     const int n_eg = (N + 63) / 64, n_strips = (N + SL - 1) / SL;
-    n_waves = n_eg * n_strips;
+    const int n_waves = n_eg * n_strips;
     const int blocks = (n_waves + 3) / 4;
+    const int D = far_band_width(N, kc.k, h, nb);
+    const int dl = std::min(D, (N - 1) / 2), dr = std::min(D, N / 2);
+    const int dband = std::min(D, N / 2);
+    const int64_t np = (int64_t)N * pt.q;
+    const int64_t nbt = (int64_t)N * (dl + dr + 1);
+    const int bband = (int)((nbt + 255) / 256);
+    n_pairs = 3 * n_waves + bband;
+    double *part = ws;
+    double *ob = ws + (size_t)n_strips * 4 * np;
+    double *sb = ob + (size_t)4 * (dl + dr + 1) * np;
     ProfScope prof(PROF_FAR, 2.0 * (double)N * N * pt.q * pt.q, s);
-#define CFIE_GFAR(QQ)                                                                         \
-    case QQ: {                                                                               \
-        QW<QQ> qc;                                                                           \
-        for (int i = 0; i < QQ; ++i) { qc.xi[i] = xi[i]; qc.w[i] = w[i]; }                   \
-        hipLaunchKernelGGL((k_grad_far<QQ>), dim3(blocks), dim3(256), 0, s, N, h, c, nb, SL,  \
-                           Om[0], Om[1], Om[2], Om[3], ld, pt.x, pt.y, pt.tx, pt.ty, qc, n_eg, \
-                           n_strips, part, spart);                                           \
-        break;                                                                               \
+#define CFIE_GFAR(QQ)                                                                        \
+    case QQ: {                                                                              \
+        QW<QQ> qc;                                                                          \
+        for (int i = 0; i < QQ; ++i) { qc.xi[i] = xi[i]; qc.w[i] = w[i]; }                  \
+        hipLaunchKernelGGL((k_grad_far<QQ, 0>), dim3(blocks), dim3(256), 0, s, N, h, c, nb,  \
+                           dband, SL, Om[0], Om[1], Om[2], Om[3], ld, pt.x, pt.y, pt.tx,     \
+                           pt.ty, qc, n_eg, n_strips, part, spart);                         \
+        hipLaunchKernelGGL((k_grad_far<QQ, 1>), dim3(blocks), dim3(256), 0, s, N, h, c, nb,  \
+                           dband, SL, Om[0], Om[1], Om[2], Om[3], ld, pt.x, pt.y, pt.tx,     \
+                           pt.ty, qc, n_eg, n_strips, part, spart + 2 * (size_t)n_waves);   \
+        hipLaunchKernelGGL((k_grad_far<QQ, 2>), dim3(blocks), dim3(256), 0, s, N, h, c, nb,  \
+                           dband, SL, Om[0], Om[1], Om[2], Om[3], ld, pt.x, pt.y, pt.tx,     \
+                           pt.ty, qc, n_eg, n_strips, part, spart + 4 * (size_t)n_waves);   \
+        hipLaunchKernelGGL((k_grad_far_band<QQ>), dim3(bband), dim3(256), 0, s, N, h, c, nb, \
+                           dl, dr, Om[0], Om[1], Om[2], Om[3], ld, pt.x, pt.y, pt.tx, pt.ty, \
+                           qc, ob, sb, spart + 6 * (size_t)n_waves);                        \
+        hipLaunchKernelGGL(k_sum_strips, dim3((unsigned)((4 * np + 255) / 256)), dim3(256),  \
+                           0, s, np, n_strips, part, adj);                                  \
+        hipLaunchKernelGGL((k_grad_band_sum<QQ>), dim3((unsigned)((4 * np + 255) / 256)),    \
+                           dim3(256), 0, s, N, dl, dr, (const double *)ob,                  \
+                           (const double *)sb, adj);                                        \
+        break;                                                                              \
     }
     switch (pt.q) {
         CFIE_GFAR(3)
@@ -234,9 +417,6 @@ void launch_grad_far(int N, double h, const KernelConsts &kc, int nb, const zd *
         default: break;
     }
 #undef CFIE_GFAR
-    const int64_t np = (int64_t)N * pt.q;
-    hipLaunchKernelGGL(k_sum_strips, dim3((unsigned)((4 * np + 255) / 256)), dim3(256), 0, s, np,
-                       n_strips, part, adj);
 }
 
 // ------------------------------------------------------------------ near pairs ------------

@@ -174,4 +174,13 @@ static inline PairConsts make_consts(const KernelConsts &kc) {
     return c;
 }
 
+// Lower bound of k R over the Gauss point pairs of two elements whose reference points
+// (Gauss point Q/2, within arc length h of every Gauss point of its element) are dxr, dyr
+// apart.  Rounded operations only, so that both far passes take the same decision.
+__device__ __forceinline__ double far_kRmin(double k, double h, double dxr, double dyr) {
+    return __dmul_rn(k, __dsub_rn(__dsqrt_rn(__dadd_rn(__dmul_rn(dxr, dxr), __dmul_rn(dyr, dyr))),
+                                  __dmul_rn(2.0, h)));
+}
+constexpr double kFarFast = 200.0;    // k R above which the 8-term series is used
+
 }  // namespace cfie
