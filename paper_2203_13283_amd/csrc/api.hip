@@ -67,6 +67,7 @@ template <typename T>
 void launch_diag(int64_t n, cpx<T> a, bool set, cpx<T> *A, int64_t lda, hipStream_t s);
 void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out,
                       hipStream_t s);
+size_t pchol_workspace_elems(int b);
 void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz, zd *M,
                   int *kout, hipStream_t s);
 template <typename T>
@@ -571,7 +572,7 @@ void alloc_factor(cfie_ctx *c) {
     c->w_rinvT = c->alloc_n<cpx<T>>((size_t)b * b);
     c->w_gram = c->alloc_n<zd>((size_t)b * b);
     c->w_rinv = c->alloc_n<zd>((size_t)b * b);
-    c->w_pchm = c->alloc_n<zd>((size_t)b * b);
+    c->w_pchm = c->alloc_n<zd>(pchol_workspace_elems(b));
     c->w_norm = c->alloc_n<double>((size_t)std::max(b, 64));
     c->info = c->alloc_n<int>(4);
     if (sizeof(T) != sizeof(double)) c->w_y64 = c->alloc_n<zd>(nb);

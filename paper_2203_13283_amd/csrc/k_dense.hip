@@ -545,34 +545,57 @@ __global__ void k_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, z
     }
     if (tid == 0) kout[0] = k;
 }
-// Panel-blocked form of the same factorisation (b <= 512, one workgroup of 1024 threads).
-// No rows or columns are moved: with p_j the j-th pivot (largest remaining Schur-complement
-// diagonal d), the pivot row is r^(j)_c = (W_j[p_j, c]) / sqrt(d_p) where W_j is W minus the
-// rank-one terms of the earlier pivots, and the columns of Z are built alongside by
+// Panel-blocked form of the same factorisation (b <= 512).  No rows or columns are moved:
+// with p_j the j-th pivot (largest remaining Schur-complement diagonal d), the pivot row is
+// r^(j)_c = (W_j[p_j, c]) / sqrt(d_p) where W_j is W minus the rank-one terms of the earlier
+// pivots, and the columns of Z are built alongside by
 // z_j = (e_p - sum_{i<j} z_i r^(i)_p) / sqrt(d_p) (Gram-Schmidt in the coefficients of Y), so
-// that Y z_j is the j-th orthonormal direction.  The earlier pivots' terms are applied to W
-// and to M = -sum z_i r^(i) in rank-NB updates at the end of each panel of NB pivots; within
-// a panel the pivot rows and z vectors of the panel are kept in LDS.  M: b x b workspace.
-constexpr int kPcholLds = 4096;                 // complex entries per panel store
-__global__ __launch_bounds__(1024) void k_pchol_panel(int b, zd *W, int ldw, double thr_abs,
-                                                      double thr_rel, zd *Z, int ldz, zd *M,
-                                                      int *kout) {
+// that Y z_j is the j-th orthonormal direction.  Pivots come in panels of NB: a single
+// wavefront finds the panel's pivots (no workgroup barriers on that sequential path; rows and
+// z vectors of the panel in LDS), and a grid-wide kernel then applies the panel's rank-NB
+// terms to W and to M = -sum z_i r^(i) (b x b).  The state between launches (d, taken, the
+// pivot count, the stop flag) lives in a small device workspace, so no host round trip is
+// needed between panels; panels after a stop return at once.
+constexpr int kPcholNB = 16;
+// pivots per panel: 16, or 8 above b = 256 (the panel's rows and z vectors stay in LDS)
+__host__ __device__ inline int pchol_nb(int b) { return b <= 256 ? kPcholNB : kPcholNB / 2; }
+struct PcholWs {
+    zd *Rg, *Zg;            // the current panel's pivot rows and z vectors (NB x b each)
+    double *d, *thr;        // remaining diagonal; threshold
+    int *taken, *st;        // st[0] pivots so far, st[1] pivots of the last panel, st[2] stop
+};
+__host__ __device__ inline size_t pchol_ws_bytes(int b) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    return up((size_t)2 * kPcholNB * b * sizeof(zd)) + up((size_t)(b + 1) * sizeof(double)) +
+           up((size_t)(b + 4) * sizeof(int));
+}
+__host__ __device__ inline PcholWs pchol_ws(void *base, int b) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    char *p = (char *)base;
+    PcholWs w;
+    w.Rg = (zd *)p;
+    w.Zg = w.Rg + (size_t)kPcholNB * b;
+    p += up((size_t)2 * kPcholNB * b * sizeof(zd));
+    w.d = (double *)p;
+    w.thr = w.d + b;
+    p += up((size_t)(b + 1) * sizeof(double));
+    w.taken = (int *)p;
+    w.st = w.taken + b;
+    return w;
+}
+
+// M = 0, d = diag(W), taken = 0, threshold from the largest diagonal, counters cleared
+__global__ __launch_bounds__(1024) void k_pchol_init(int b, const zd *W, int ldw, double thr_abs,
+                                                     double thr_rel, zd *M, void *wsb) {
     const int tid = threadIdx.x;
-    const int NB = b <= 256 ? 16 : 8;
-    __shared__ zd Rp[kPcholLds];                 // Rp[i * b + c]: pivot rows of the panel
-    __shared__ zd Zp[kPcholLds];                 // Zp[i * b + r]: z vectors of the panel
-    __shared__ double d[512];
-    __shared__ int taken[512];
+    PcholWs ws = pchol_ws(wsb, b);
     __shared__ double wv[16];
-    __shared__ int wi[16];
-    __shared__ double thr;
-    // M = 0, diagonal, threshold from the largest diagonal
     for (int t = tid; t < b * b; t += 1024) M[t] = mk(0.0, 0.0);
     double mx = 0.0;
     if (tid < b) {
-        d[tid] = W[tid + (int64_t)tid * ldw].x;
-        taken[tid] = 0;
-        mx = d[tid];
+        ws.d[tid] = W[tid + (int64_t)tid * ldw].x;
+        ws.taken[tid] = 0;
+        mx = ws.d[tid];
     }
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
     if ((tid & 63) == 0) wv[tid >> 6] = mx;
@@ -580,97 +603,164 @@ __global__ __launch_bounds__(1024) void k_pchol_panel(int b, zd *W, int ldw, dou
     if (tid == 0) {
         double m = 0.0;
         for (int w = 0; w < 16; ++w) m = fmax(m, wv[w]);
-        thr = fmax(thr_abs, thr_rel * m);
+        ws.thr[0] = fmax(thr_abs, thr_rel * m);
+        ws.st[0] = ws.st[1] = ws.st[2] = 0;
     }
-    __syncthreads();
-    int k = 0;
-    int j0 = 0;                                   // first pivot of the current panel
-    while (k < b) {
-        // ---- pivot: largest untaken d (ties: smallest index)
+}
+
+// the next panel's pivots, one wavefront (lane l handles columns / rows l, l + 64, ...)
+__global__ __launch_bounds__(64) void k_pchol_pivots(int b, const zd *W, int ldw, zd *Z, int ldz,
+                                                     const zd *M, void *wsb) {
+    constexpr int PER = 8;                       // b <= 512 = 64 x 8
+    const int lane = threadIdx.x;
+    PcholWs ws = pchol_ws(wsb, b);
+    if (ws.st[2] || ws.st[0] >= b) {
+        if (lane == 0) ws.st[1] = 0;
+        return;
+    }
+    __shared__ zd Rp[kPcholNB * 256];            // Rp[i * b + c], NB b <= 4096
+    __shared__ zd Zp[kPcholNB * 256];            // Zp[i * b + r]
+    const int NB = pchol_nb(b);
+    double dl[PER];
+    int tk[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = lane + 64 * q;
+        dl[q] = c < b ? ws.d[c] : -1.0;
+        tk[q] = c < b ? ws.taken[c] : 1;
+    }
+    const double thr = ws.thr[0];
+    int k = ws.st[0];
+    int jp = 0;
+    bool stop = false;
+    for (; jp < NB && k < b; ++jp) {
+        // pivot: largest untaken d (ties: smallest index)
         double bv = -1.0;
         int bi = 0x7fffffff;
-        if (tid < b && !taken[tid]) { bv = d[tid]; bi = tid; }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int c = lane + 64 * q;
+            if (c < b && !tk[q] && (dl[q] > bv || (dl[q] == bv && c < bi))) {
+                bv = dl[q];
+                bi = c;
+            }
+        }
         for (int o = 32; o > 0; o >>= 1) {
-            double ov = __shfl_xor(bv, o);
-            int oi = __shfl_xor(bi, o);
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
             if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
         }
-        if ((tid & 63) == 0) { wv[tid >> 6] = bv; wi[tid >> 6] = bi; }
-        __syncthreads();
-        bv = wv[0];
-        bi = wi[0];
-        for (int w = 1; w < 16; ++w)
-            if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
-        const bool stop = !(bv > thr);
+        if (!(bv > thr)) {
+            stop = true;
+            break;
+        }
         const int p = bi;
-        const int jp = k - j0;
-        if (!stop) {
-            const double sd = sqrt(bv), isd = 1.0 / sd;
-            if (tid < b) {
-                // pivot row, from column p of the (panel-start) updated W: W[p, c] = conj(W[c, p])
-                const int cc = tid;
-                zd r = mk(0.0, 0.0);
-                if (cc == p) {
-                    r = mk(sd, 0.0);
-                } else if (!taken[cc]) {
-                    r = conj(W[cc + (int64_t)p * ldw]);
-                    for (int i = 0; i < jp; ++i) r = r - conj(Rp[i * b + p]) * Rp[i * b + cc];
-                    r = r * isd;
-                }
-                // z_j: row = tid
-                const int rr = tid;
-                zd z = M[rr + (int64_t)p * b];
-                if (rr == p) z = z + mk(1.0, 0.0);
-                for (int i = 0; i < jp; ++i) z = z - Zp[i * b + rr] * Rp[i * b + p];
-                z = z * isd;
-                Zp[jp * b + rr] = z;
-                Z[rr + (int64_t)k * ldz] = z;
-                Rp[jp * b + cc] = r;
+        const double sd = sqrt(bv), isd = 1.0 / sd;
+        // the pivot's entries of the earlier rows of this panel, for every lane
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int cc = lane + 64 * q;
+            if (cc >= b) break;
+            // pivot row from column p of W at the panel start: W[p, c] = conj(W[c, p])
+            zd r = mk(0.0, 0.0);
+            if (cc == p) {
+                r = mk(sd, 0.0);
+            } else if (!tk[q]) {
+                r = conj(W[cc + (int64_t)p * ldw]);
+                for (int i = 0; i < jp; ++i) r = r - conj(Rp[i * b + p]) * Rp[i * b + cc];
+                r = r * isd;
             }
+            zd z = M[cc + (int64_t)p * b];
+            if (cc == p) z = z + mk(1.0, 0.0);
+            for (int i = 0; i < jp; ++i) z = z - Zp[i * b + cc] * Rp[i * b + p];
+            z = z * isd;
+            Zp[jp * b + cc] = z;
+            Z[cc + (int64_t)k * ldz] = z;
+            Rp[jp * b + cc] = r;
         }
         __syncthreads();
-        if (!stop && tid < b) {
-            if (tid == p) taken[p] = 1;
-            else if (!taken[tid]) d[tid] -= abs2(Rp[jp * b + tid]);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int c = lane + 64 * q;
+            if (c >= b) break;
+            if (c == p) tk[q] = 1;
+            else if (!tk[q]) dl[q] -= abs2(Rp[jp * b + c]);
         }
-        if (!stop) ++k;
-        // ---- end of panel: W -= Rp^H Rp and M -= Zp Rp over the whole b x b
-        const int np = k - j0;
-        if (np == NB || (stop && np > 0) || (k == b && np > 0)) {
-            __syncthreads();
-            if (!(stop || k == b)) {
-                for (int64_t t = tid; t < (int64_t)b * b; t += 1024) {
-                    const int rr = (int)(t % b), cc = (int)(t / b);
-                    zd w = W[rr + (int64_t)cc * ldw], m = M[t];
-                    for (int i = 0; i < np; ++i) {
-                        const zd rc = Rp[i * b + cc];
-                        w = w - conj(Rp[i * b + rr]) * rc;
-                        m = m - Zp[i * b + rr] * rc;
-                    }
-                    W[rr + (int64_t)cc * ldw] = w;
-                    M[t] = m;
-                }
-            }
-            j0 = k;
-            __syncthreads();
-        }
-        if (stop) break;
-        __syncthreads();
+        ++k;
     }
-    // unused columns of Z are zero
-    for (int64_t t = tid; t < (int64_t)b * (b - k); t += 1024)
-        Z[(t % b) + (int64_t)(k + t / b) * ldz] = mk(0.0, 0.0);
-    if (tid == 0) kout[0] = k;
+    // hand the panel to the update kernel and the state to the next panel
+    for (int t = lane; t < jp * b; t += 64) {
+        ws.Rg[t] = Rp[t];
+        ws.Zg[t] = Zp[t];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = lane + 64 * q;
+        if (c < b) {
+            ws.d[c] = dl[q];
+            ws.taken[c] = tk[q];
+        }
+    }
+    if (lane == 0) {
+        ws.st[0] = k;
+        ws.st[1] = jp;
+        ws.st[2] = stop ? 1 : 0;
+    }
+}
+
+// W -= Rp^H Rp and M -= Zp Rp over the whole b x b for the panel just found (nothing after
+// the last panel: no pivots follow)
+__global__ void k_pchol_update(int b, zd *W, int ldw, zd *M, const void *wsb) {
+    const PcholWs ws = pchol_ws((void *)wsb, b);
+    const int np = ws.st[1];
+    if (np == 0 || ws.st[2] || ws.st[0] >= b) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)b * b) return;
+    const int rr = (int)(t % b), cc = (int)(t / b);
+    zd w = W[rr + (int64_t)cc * ldw], m = M[t];
+    for (int i = 0; i < np; ++i) {
+        const zd rc = ws.Rg[i * b + cc];
+        w = w - conj(ws.Rg[i * b + rr]) * rc;
+        m = m - ws.Zg[i * b + rr] * rc;
+    }
+    W[rr + (int64_t)cc * ldw] = w;
+    M[t] = m;
+}
+
+// unused columns of Z are zero; kout = the number of pivots
+__global__ void k_pchol_finish(int b, zd *Z, int ldz, const void *wsb, int *kout) {
+    const PcholWs ws = pchol_ws((void *)wsb, b);
+    const int k = ws.st[0];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (int64_t)b * (b - k)) Z[(t % b) + (int64_t)(k + t / b) * ldz] = mk(0.0, 0.0);
+    if (t == 0) kout[0] = k;
+}
+
+size_t pchol_workspace_elems(int b) {
+    return (size_t)b * b + (pchol_ws_bytes(b) + sizeof(zd) - 1) / sizeof(zd);
 }
 
 void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, int ldz, zd *M,
                   int *kout, hipStream_t s) {
-    if (b <= 512 && M)
-        hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(1024), 0, s, b, W, ldw, thr_abs,
-                           thr_rel, Z, ldz, M, kout);
-    else
+    if (b <= 512 && M) {
+        void *ws = M + (size_t)b * b;
+        hipLaunchKernelGGL(k_pchol_init, dim3(1), dim3(1024), 0, s, b, (const zd *)W, ldw,
+                           thr_abs, thr_rel, M, ws);
+        const int npanel = (b + pchol_nb(b) - 1) / pchol_nb(b);
+        const unsigned ub = (unsigned)(((int64_t)b * b + 255) / 256);
+        for (int pnl = 0; pnl < npanel; ++pnl) {
+            hipLaunchKernelGGL(k_pchol_pivots, dim3(1), dim3(64), 0, s, b, (const zd *)W, ldw, Z,
+                               ldz, (const zd *)M, ws);
+            hipLaunchKernelGGL(k_pchol_update, dim3(ub), dim3(256), 0, s, b, W, ldw, M,
+                               (const void *)ws);
+        }
+        const unsigned fb = (unsigned)(((int64_t)b * b + 255) / 256);
+        hipLaunchKernelGGL(k_pchol_finish, dim3(fb), dim3(256), 0, s, b, Z, ldz,
+                           (const void *)ws, kout);
+    } else {
         hipLaunchKernelGGL(k_pchol, dim3(1), dim3(1024), 0, s, b, W, ldw, thr_abs, thr_rel, Z,
                            ldz, kout);
+    }
 }
 
 // M = (3 I - G) / 2 in precision T (one Newton-Schulz step towards the polar factor)
