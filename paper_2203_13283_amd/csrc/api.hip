@@ -1333,6 +1333,8 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         zd *band_ws = c->alloc_n<zd>(far_band_ws_elems(p));
         p.ws = band_ws;
         launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
+        zd *near_ws = c->alloc_n<zd>(near_ws_elems(p));
+        p.ws = near_ws;
         launch_assemble_near(p, c->pn, c->xn.data(), c->wn.data(), c->d_mom, s);
         c->check_launch();
         // first row of each matrix on the circle -> eigenvalues (Sec. V)
@@ -1343,9 +1345,12 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         pc.r1 = 1;
         pc.ld = 1;
         for (int i = 0; i < 4; ++i) pc.out[i] = c->crow + (size_t)i * N;
+        pc.ws = band_ws;
         launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), s);
         c->dfree(band_ws);
+        pc.ws = near_ws;
         launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, s);
+        c->dfree(near_ws);
         setup_fft(c);
         // rows of symmetric circulants equal their first columns
         launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, s);

@@ -119,7 +119,9 @@ int far_band_width(int N, double k, double h, int nb);
 void launch_assemble_far(const AsmParams &p, const PointTable &far, const double *xi,
                          const double *w, hipStream_t s);
 // Near part: entries with cyclic |i - j| <= nb + 1; touching element pairs by product
-// integration of the log singularity (moments), others by q_near Gauss-Legendre.
+// integration of the log singularity (moments), others by q_near Gauss-Legendre.  p.ws:
+// near_ws_elems(p) complex128 (blocks of the element pairs).
+size_t near_ws_elems(const AsmParams &p);
 void launch_assemble_near(const AsmParams &p, const PointTable &near, const double *xi,
                           const double *w, const double *moments, hipStream_t s);
 

@@ -413,52 +413,55 @@ struct NearConsts {
     double xi[kMaxQNear], w[kMaxQNear];
 };
 
-// contribution of element pair (e, f) (kind: -1 regular, 0 same, 1 f = e+1, 2 f = e-1) to
-// the entry with local hats (a, b); adds to acc[4] (Dk, Nk, Dkt, Skt)
-__device__ void near_pair(const NearConsts &nc, int q, int e, int f, int kind, int a, int b,
-                          const double *__restrict__ PX, const double *__restrict__ PY,
-                          const double *__restrict__ PTX, const double *__restrict__ PTY,
-                          const double *__restrict__ PCV, const double *__restrict__ mom,
-                          zd acc[4]) {
+// The 2x2 node blocks acc[m][a][b] (m: Dk, Nk, Dkt, Skt; a, b: hats of the observation and
+// source elements) of element pair (e, f) (kind: -1 regular, 0 same, 1 f = e+1,
+// 2 f = e-1), all four hat combinations from one evaluation of the kernels per point pair.
+__device__ void near_block(const NearConsts &nc, int q, int e, int f, int kind,
+                           const double *__restrict__ PX, const double *__restrict__ PY,
+                           const double *__restrict__ PTX, const double *__restrict__ PTY,
+                           const double *__restrict__ PCV, const double *__restrict__ mom,
+                           zd (&acc)[4][2][2]) {
     const PairConsts &c = nc.pc;
     const double h = nc.h;
     const double k = c.k;
     const double k2 = k * k;
-    const double sab = (a ? 1.0 : -1.0) * (b ? 1.0 : -1.0);
-    const double *Mab = mom + ((size_t)(kind < 0 ? 0 : kind) * 5 + (2 * a + b)) * q * q;
-    const double *M0 = mom + ((size_t)(kind < 0 ? 0 : kind) * 5 + 4) * q * q;
+    const double *Mk = mom + (size_t)(kind < 0 ? 0 : kind) * 5 * q * q;
     const double inv2pi = 1.0 / (2.0 * kPi);
     for (int g = 0; g < q; ++g) {
-        double xg = nc.xi[g];
-        double pa = a ? xg : 1.0 - xg;
-        double xo = PX[e * q + g], yo = PY[e * q + g];
-        double txo = PTX[e * q + g], tyo = PTY[e * q + g];
+        const double xg = nc.xi[g];
+        const double pa[2] = {1.0 - xg, xg};
+        const double xo = PX[e * q + g], yo = PY[e * q + g];
+        const double txo = PTX[e * q + g], tyo = PTY[e * q + g];
         for (int hh = 0; hh < q; ++hh) {
-            double xh = nc.xi[hh];
-            double pb = b ? xh : 1.0 - xh;
-            double wgt = nc.w[g] * nc.w[hh];
-            double xs = PX[f * q + hh], ys = PY[f * q + hh];
-            double txs = PTX[f * q + hh], tys = PTY[f * q + hh];
+            const double xh = nc.xi[hh];
+            const double pb[2] = {1.0 - xh, xh};
+            const double wgt = nc.w[g] * nc.w[hh];
+            const double xs = PX[f * q + hh], ys = PY[f * q + hh];
+            const double txs = PTX[f * q + hh], tys = PTY[f * q + hh];
             if (kind < 0) {
-                double dx = xo - xs, dy = yo - ys;
-                double R = sqrt(dx * dx + dy * dy);
-                double nu = (dx * tys - dy * txs) / R;
-                double nn = tyo * tys + txo * txs;
+                const double dx = xo - xs, dy = yo - ys;
+                const double R = sqrt(dx * dx + dy * dy);
+                const double nu = (dx * tys - dy * txs) / R;
+                const double nn = tyo * tys + txo * txs;
                 zd gk, Dk, St, Dt;
                 pair_kernels(c, R, nu, gk, Dk, St, Dt);
-                double hw = h * h * wgt * pa * pb;
-                acc[0] = acc[0] + Dk * hw;
-                acc[2] = acc[2] + Dt * hw;
-                acc[3] = acc[3] + St * hw;
-                acc[1] = acc[1] + gk * (wgt * sab - k2 * nn * hw);
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        const double hw = h * h * wgt * pa[a] * pb[b];
+                        const double sab = (a == b) ? 1.0 : -1.0;
+                        acc[0][a][b] = acc[0][a][b] + Dk * hw;
+                        acc[2][a][b] = acc[2][a][b] + Dt * hw;
+                        acc[3][a][b] = acc[3][a][b] + St * hw;
+                        acc[1][a][b] = acc[1][a][b] + gk * (wgt * sab - k2 * nn * hw);
+                    }
                 continue;
             }
-            double mab = Mab[g * q + hh], m0 = M0[g * q + hh];
+            const double m0 = Mk[(size_t)4 * q * q + g * q + hh];
             zd Ag, As, Ad, At, Bg, Bs, Bd, Bt;
             double nn;
             if (kind == 0 && g == hh) {
                 // coincident points: limits of the smooth parts as R -> 0
-                double kc_ = PCV[e * q + g];
+                const double kc_ = PCV[e * q + g];
                 Ag = mk(-inv2pi, 0.0);
                 As = Ag;
                 Ad = At = mk(0.0, 0.0);
@@ -467,17 +470,17 @@ __device__ void near_pair(const NearConsts &nc, int q, int e, int f, int kind, i
                 Bd = Bt = mk(-kc_ / (4.0 * kPi), 0.0);
                 nn = 1.0;
             } else {
-                double dx = xo - xs, dy = yo - ys;
-                double R = sqrt(dx * dx + dy * dy);
-                double nu = (dx * tys - dy * txs) / R;
+                const double dx = xo - xs, dy = yo - ys;
+                const double R = sqrt(dx * dx + dy * dy);
+                const double nu = (dx * tys - dy * txs) / R;
                 nn = tyo * tys + txo * txs;
                 double sig;
                 if (kind == 0) sig = h * fabs(xg - xh);
                 else if (kind == 1) sig = h * (1.0 - xg + xh);
                 else sig = h * (1.0 + xg - xh);
-                double lr = log(R / sig);
-                BesselSplit b1 = bessel_split(mk(k * R, 0.0));
-                BesselSplit b2 = bessel_split(c.kt * R);
+                const double lr = log(R / sig);
+                const BesselSplit b1 = bessel_split(mk(k * R, 0.0));
+                const BesselSplit b2 = bessel_split(c.kt * R);
                 // S^kappa: A = -J0/(2 pi), B = (i/4) J0 - (log(kappa/2) + lr) J0/(2 pi) - Yh0/4
                 Ag = b1.J0 * (-inv2pi);
                 As = b2.J0 * (-inv2pi);
@@ -488,7 +491,7 @@ __device__ void near_pair(const NearConsts &nc, int q, int e, int f, int kind, i
                 // D^kappa: A = -(kappa/(2 pi)) J1 nu,
                 // B = [(i kappa/4) J1 - (kappa/(2 pi))(log(kappa/2) + lr) J1 - (kappa/4) Yh1] nu
                 //     + nu / (2 pi R)
-                zd kk = mk(k, 0.0);
+                const zd kk = mk(k, 0.0);
                 Ad = kk * b1.J1 * (-inv2pi * nu);
                 At = c.kt * b2.J1 * (-inv2pi * nu);
                 Bd = (cmul_i(kk) * b1.J1 * 0.25 - kk * (nc.logk2 + mk(lr, 0.0)) * b1.J1 * inv2pi -
@@ -502,59 +505,94 @@ __device__ void near_pair(const NearConsts &nc, int q, int e, int f, int kind, i
             Bs = Bs + As * nc.logh;
             Bd = Bd + Ad * nc.logh;
             Bt = Bt + At * nc.logh;
-            double hw = h * h * wgt * pa * pb;
-            double hm = h * h * mab;
-            acc[0] = acc[0] + Bd * hw + Ad * hm;
-            acc[2] = acc[2] + Bt * hw + At * hm;
-            acc[3] = acc[3] + Bs * hw + As * hm;
-            acc[1] = acc[1] + Bg * (wgt * sab - k2 * nn * hw) + Ag * (sab * m0 - k2 * nn * hm);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const double mab = Mk[(size_t)(2 * a + b) * q * q + g * q + hh];
+                    const double hw = h * h * wgt * pa[a] * pb[b];
+                    const double hm = h * h * mab;
+                    const double sab = (a == b) ? 1.0 : -1.0;
+                    acc[0][a][b] = acc[0][a][b] + Bd * hw + Ad * hm;
+                    acc[2][a][b] = acc[2][a][b] + Bt * hw + At * hm;
+                    acc[3][a][b] = acc[3][a][b] + Bs * hw + As * hm;
+                    acc[1][a][b] = acc[1][a][b] + Bg * (wgt * sab - k2 * nn * hw) +
+                                   Ag * (sab * m0 - k2 * nn * hm);
+                }
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_near(int N, NearConsts nc, int q, int nb, int r0,
-                                              int r1, int64_t ld, zd *o0, zd *o1, zd *o2,
-                                              zd *o3, const double *__restrict__ PX,
-                                              const double *__restrict__ PY,
-                                              const double *__restrict__ PTX,
-                                              const double *__restrict__ PTY,
-                                              const double *__restrict__ PCV,
-                                              const double *__restrict__ mom) {
-    int nrows = r1 - r0;
-    int ndiag = 2 * nb + 3;
-    long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= (long)nrows * ndiag) return;
-    int i = r0 + (int)(tid % nrows);
-    int delta = (int)(tid / nrows) - (nb + 1);
-    // skip duplicate diagonals when the band wraps around a small mesh
+// One thread per element pair (e = r0 - 1 + eidx, f = e + d) with |d| <= nb + 2 (the pairs
+// that feed the near entries); lanes of a wavefront share d.  Blocks to
+// Bk[((m 4 + 2a + b) nd + didx) ne + eidx], d = didx - dl.
+__global__ __launch_bounds__(128) void k_near_pairs(int N, NearConsts nc, int q, int dl, int dr,
+                                                    int r0, int ne,
+                                                    const double *__restrict__ PX,
+                                                    const double *__restrict__ PY,
+                                                    const double *__restrict__ PTX,
+                                                    const double *__restrict__ PTY,
+                                                    const double *__restrict__ PCV,
+                                                    const double *__restrict__ mom, zd *Bk) {
+    const int nd = dl + dr + 1;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)ne * nd) return;
+    const int eidx = (int)(tid % ne), didx = (int)(tid / ne);
+    const int d = didx - dl;
+    const int e = ((r0 - 1 + eidx) % N + N) % N;
+    const int f = ((e + d) % N + N) % N;
+    const int off = ((f - e) % N + N) % N;
+    const int kind = off == 0 ? 0 : off == 1 ? 1 : off == N - 1 ? 2 : -1;
+    zd acc[4][2][2];
+    for (int m = 0; m < 4; ++m)
+        acc[m][0][0] = acc[m][0][1] = acc[m][1][0] = acc[m][1][1] = mk(0.0, 0.0);
+    near_block(nc, q, e, f, kind, PX, PY, PTX, PTY, PCV, mom, acc);
+    for (int m = 0; m < 4; ++m)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                Bk[((int64_t)(m * 4 + 2 * a + b) * nd + didx) * ne + eidx] = acc[m][a][b];
+}
+
+// Entry (i, j), r0 <= i < r1, cyclic |i - j| <= nb + 1: the sum of its four element pairs'
+// blocks, in the order (i-1, j-1), (i-1, j), (i, j-1), (i, j).
+__global__ __launch_bounds__(256) void k_near_write(int N, int nb, int dl, int dr, int r0, int r1,
+                                                    int ne, int64_t ld, zd *o0, zd *o1,
+                                                    zd *o2, zd *o3, const zd *__restrict__ Bk) {
+    const int nd = dl + dr + 1;
+    const int nrows = r1 - r0;
+    const int no = 2 * nb + 3;                        // offsets -(nb+1) .. nb+1
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)nrows * no) return;
+    const int i = r0 + (int)(tid % nrows);
+    const int o = (int)(tid / nrows) - (nb + 1);
+    // one representative per entry when the band wraps around a small mesh
     if (2 * (nb + 1) + 1 > N) {
-        int dd = ((delta % N) + N) % N;
-        // keep the representative delta in [-(N-1)/2, N/2]
-        int rep = dd > N / 2 ? dd - N : dd;
-        if (rep != delta) return;
+        int dd = ((o % N) + N) % N;
+        const int rep = 2 * dd > N ? dd - N : dd;
+        if (rep != o) return;
     }
-    int j = ((i + delta) % N + N) % N;
-    zd acc[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    const int j = ((i + o) % N + N) % N;
+    zd v[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
     for (int p = 0; p < 4; ++p) {
-        int a = (p >> 1) ? 0 : 1;                       // p = 0,1: element i-1 (a = 1)
-        int b = (p & 1) ? 0 : 1;                        // p = 0,2: element j-1 (b = 1)
-        int e = a ? i - 1 : i;
-        int f = b ? j - 1 : j;
-        e = (e + N) % N;
-        f = (f + N) % N;
-        int off = ((f - e) % N + N) % N;
-        int kind;
-        if (off == 0) kind = 0;
-        else if (off == 1) kind = 1;
-        else if (off == N - 1) kind = 2;
-        else kind = -1;
-        near_pair(nc, q, e, f, kind, a, b, PX, PY, PTX, PTY, PCV, mom, acc);
+        const int a = (p >> 1) ? 0 : 1, b = (p & 1) ? 0 : 1;
+        int d = o - b + a;
+        d = ((d % N) + N) % N;
+        if (2 * d > N) d -= N;
+        const int eidx = i - a - (r0 - 1);
+        const int didx = d + dl;
+        for (int m = 0; m < 4; ++m)
+            v[m] = v[m] + Bk[((int64_t)(m * 4 + 2 * a + b) * nd + didx) * ne + eidx];
     }
-    int64_t idx = (int64_t)i + (int64_t)j * ld;
-    o0[idx] = acc[0];
-    o1[idx] = acc[1];
-    o2[idx] = acc[2];
-    o3[idx] = acc[3];
+    const int64_t idx = (int64_t)i + (int64_t)j * ld;
+    o0[idx] = v[0];
+    o1[idx] = v[1];
+    o2[idx] = v[2];
+    o3[idx] = v[3];
+}
+
+size_t near_ws_elems(const AsmParams &p) {
+    const int D = p.nb + 2;
+    const int dl = std::min(D, (p.N - 1) / 2), dr = std::min(D, p.N / 2);
+    const int ne = std::min(p.r1 - p.r0 + 1, p.N + 1);
+    return (size_t)16 * (size_t)(dl + dr + 1) * (size_t)ne;
 }
 
 void launch_assemble_near(const AsmParams &p, const PointTable &near, const double *xi,
@@ -569,13 +607,18 @@ void launch_assemble_near(const AsmParams &p, const PointTable &near, const doub
         nc.xi[i] = xi[i];
         nc.w[i] = w[i];
     }
-    int nrows = p.r1 - p.r0;
-    long n = (long)nrows * (2 * p.nb + 3);
-    int bs = 64;
-    ProfScope prof(PROF_NEAR, 4.0 * n * near.q * near.q, s);
-    hipLaunchKernelGGL(k_near, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, p.N, nc,
-                       near.q, p.nb, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2], p.out[3],
-                       near.x, near.y, near.tx, near.ty, near.curv, moments);
+    const int D = p.nb + 2;
+    const int dl = std::min(D, (p.N - 1) / 2), dr = std::min(D, p.N / 2);
+    const int ne = std::min(p.r1 - p.r0 + 1, p.N + 1);
+    const int64_t npairs = (int64_t)ne * (dl + dr + 1);
+    const int64_t nent = (int64_t)(p.r1 - p.r0) * (2 * p.nb + 3);
+    ProfScope prof(PROF_NEAR, (double)npairs * near.q * near.q, s);
+    hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, s,
+                       p.N, nc, near.q, dl, dr, p.r0, ne, near.x, near.y, near.tx, near.ty,
+                       near.curv, moments, p.ws);
+    hipLaunchKernelGGL(k_near_write, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s, p.N,
+                       p.nb, dl, dr, p.r0, p.r1, ne, p.ld, p.out[0], p.out[1], p.out[2], p.out[3],
+                       (const zd *)p.ws);
 }
 
 // ------------------------------------------------------------------ excitation -----------
