@@ -51,6 +51,7 @@ void launch_chol_inv(int b, zd *W, int ldw, double shift, zd *Rinv, int ldr, int
                      hipStream_t s);
 void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info,
                      hipStream_t s);
+int lu_panel_width(int n);
 template <typename T>
 void launch_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0,
                   int64_t c1, hipStream_t s);
@@ -772,8 +773,9 @@ cfie_status factor_impl(cfie_ctx *c) {
     zd *tmp = c->alloc_n<zd>((size_t)kLUPanel * std::max(ell, 1));
     zd *Lp = c->alloc_n<zd>((size_t)kLUPanel * kLUPanel);
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
-    for (int k0 = 0; k0 < ell; k0 += kLUPanel) {
-        const int kb = std::min(kLUPanel, ell - k0);
+    const int pw = lu_panel_width(ell);          // <= kLUPanel
+    for (int k0 = 0; k0 < ell; k0 += pw) {
+        const int kb = std::min(pw, ell - k0);
         launch_lu_panel(ell, k0, kb, c->K, cap, c->piv, c->info, s);
         launch_swaps<double>(k0, k0 + kb, c->piv, c->K, cap, 0, k0, s);
         launch_swaps<double>(k0, k0 + kb, c->piv, c->K, cap, k0 + kb, ell, s);

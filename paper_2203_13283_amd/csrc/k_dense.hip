@@ -833,9 +833,123 @@ __global__ __launch_bounds__(1024) void k_lu_panel(int n, int k0, int nb, zd *A,
         __syncthreads();
     }
 }
+// The same panel factorisation with the panel held in registers (row r of the panel,
+// r = k0 + tid + 1024 q, in thread tid, q < RPT; panels of up to NBMAX columns, n - k0 <=
+// 1024 RPT; RPT NBMAX <= 16 keeps it within the 128 registers of a 1024-thread workgroup):
+// the panel is read and written once instead of once per column.  Used for the last
+// panels of an LU (at most 1024 rows left).  Per column: argmax
+// of |a|^2 over the rows (ties: smallest row), exchange of rows j and p through LDS, the
+// pivot row broadcast through LDS, and the scaling and rank-one update in registers, in the
+// same arithmetic order as k_lu_panel.
+template <int RPT, int NBMAX>
+__global__ __launch_bounds__(1024) void k_lu_panel_reg(int n, int k0, int nb, zd *A, int64_t lda,
+                                                       int *piv, int *info) {
+    const int tid = threadIdx.x;
+    __shared__ double wv[16];
+    __shared__ int wi[16];
+    __shared__ zd rowj[NBMAX], rowp[NBMAX];
+    zd a[RPT][NBMAX];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = k0 + tid + 1024 * q;
+#pragma unroll
+        for (int c = 0; c < NBMAX; ++c)
+            a[q][c] = (r < n && c < nb) ? A[r + (int64_t)(k0 + c) * lda] : mk(0.0, 0.0);
+    }
+    for (int jj = 0; jj < nb; ++jj) {
+        const int j = k0 + jj;
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = k0 + tid + 1024 * q;
+            if (r >= j && r < n) {
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c < NBMAX; ++c)
+                    if (c == jj) v = abs2(a[q][c]);
+                if (v > bv) { bv = v; bi = r; }
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if ((tid & 63) == 0) { wv[tid >> 6] = bv; wi[tid >> 6] = bi; }
+        __syncthreads();
+        bv = wv[0];
+        bi = wi[0];
+        for (int w = 1; w < 16; ++w)
+            if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
+        const int p = bi < n ? bi : j;
+        if (tid == 0) {
+            piv[j] = p;
+            if (!(bv > 0.0)) info[0] = 1;
+        }
+        // rows j and p to LDS, then swapped back into registers
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = k0 + tid + 1024 * q;
+            if (r == j)
+#pragma unroll
+                for (int c = 0; c < NBMAX; ++c) rowj[c] = a[q][c];
+            if (r == p)
+#pragma unroll
+                for (int c = 0; c < NBMAX; ++c) rowp[c] = a[q][c];
+        }
+        __syncthreads();
+        if (p != j) {
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int r = k0 + tid + 1024 * q;
+                if (r == j)
+#pragma unroll
+                    for (int c = 0; c < NBMAX; ++c) a[q][c] = rowp[c];
+                if (r == p)
+#pragma unroll
+                    for (int c = 0; c < NBMAX; ++c) a[q][c] = rowj[c];
+            }
+        }
+        // the pivot row after the swap is rowp (rowj when p == j: the same row)
+        const zd d = rowp[jj];
+        const zd dinv = (abs2(d) > 0.0) ? cinv(d) : mk(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = k0 + tid + 1024 * q;
+            if (r > j && r < n) {
+                zd l = mk(0.0, 0.0);
+#pragma unroll
+                for (int c = 0; c < NBMAX; ++c)
+                    if (c == jj) { l = a[q][c] * dinv; a[q][c] = l; }
+#pragma unroll
+                for (int c = 0; c < NBMAX; ++c)
+                    if (c > jj && c < nb) a[q][c] = a[q][c] - l * rowp[c];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = k0 + tid + 1024 * q;
+        if (r < n)
+#pragma unroll
+            for (int c = 0; c < NBMAX; ++c)
+                if (c < nb) A[r + (int64_t)(k0 + c) * lda] = a[q][c];
+    }
+}
+
+// panel width of the LU (16 columns: narrower panels with two or four rows per thread in
+// registers measured slower overall, by the extra panels and trailing updates)
+int lu_panel_width(int) { return 16; }
+
 void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, s, n, k0, nb, A, lda, piv, info);
+    if (nb <= 16 && n - k0 <= 1024)
+        hipLaunchKernelGGL((k_lu_panel_reg<1, 16>), dim3(1), dim3(1024), 0, s, n, k0, nb, A, lda,
+                           piv, info);
+    else
+        hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, s, n, k0, nb, A, lda, piv, info);
 }
 
 // apply the row swaps piv[k0 .. k1) to columns [c0, c1) of A (one thread per column)
