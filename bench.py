@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--compare", action=argparse.BooleanOptionalAction, default=True,
                     help="also run one step of the other precision and report it")
     ap.add_argument("--cpu-baseline", action=argparse.BooleanOptionalAction, default=True)
+    ap.add_argument("--tight", action=argparse.BooleanOptionalAction, default=True,
+                    help="also run one FP64 step at epsilon = 1e-10 (the FP64 parity level)")
     ap.add_argument("--profile", action=argparse.BooleanOptionalAction, default=True,
                     help="HIP-event timing of every hot launch inside the library")
     ap.add_argument("--serve-m", type=int, default=8,
@@ -438,11 +440,11 @@ def main():
         if dom.startswith("zgemm"):
             # the 3M complex product executes 6 m n k of the 8 m n k counted above
             out["roofline"]["mfma_pipe_frac"] = 0.75 * achieved / peak
+    del last, s, B, X
+    torch.cuda.empty_cache()
     if a.compare:
         other = P.CFIE_MIXED if prec == P.CFIE_FP64 else P.CFIE_FP64
         eps_o = 1e-3 if other == P.CFIE_MIXED else 1e-5
-        del last, s, B, X
-        torch.cuda.empty_cache()
         so, Bo, Xo, to = step(P, w, other, eps_o, False, form)
         io = so.info()
         res_o, err_o = accuracy(P, so, w, Bo, Xo)
@@ -452,6 +454,16 @@ def main():
                           "refine_sweeps": io["refine_sweeps"], "rel_residual": res_o,
                           "rel_err_vs_oracle": err_o}
         del so, Bo, Xo
+    if a.tight and prec == P.CFIE_FP64 and a.eps is None:
+        # the FP64 path at the parity level of 1e-10 (nearly full rank at this size)
+        torch.cuda.empty_cache()
+        st, Bt, Xt, tt = step(P, w, P.CFIE_FP64, 1e-10, False, form)
+        it = st.info()
+        res_t, err_t = accuracy(P, st, w, Bt, Xt)
+        out["fp64_tight"] = {"compress_tol": 1e-10, "value": nrhs / tt["solve_s"],
+                             "setup_s": tt["setup_s"], "rank": it["rank"],
+                             "rel_residual": res_t, "rel_err_vs_oracle": err_t}
+        del st, Bt, Xt
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
