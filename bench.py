@@ -427,6 +427,11 @@ def main():
             continue
         kern[name] = {"launches": n, "ms_total": ms / a.steps, "avg_launch_ms": ms / n,
                       "work_per_launch": work / n}
+        if name in PEAKS:
+            bound, peak, unit = PEAKS[name]
+            scale = 1e-12 if unit == "TFLOP/s" else 1e-9
+            ach = (work / n) * scale / (ms / n / 1e3)
+            kern[name].update({"bound": bound, "achieved": ach, "unit": unit, "frac": ach / peak})
     out["kernels"] = kern
     dom = max((k for k in kern if k in PEAKS), key=lambda k: kern[k]["ms_total"], default=None)
     if dom is not None:

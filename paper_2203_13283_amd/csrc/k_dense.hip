@@ -34,46 +34,72 @@ __global__ void k_ginv(int N, int ntap, int t0, const double *__restrict__ coef,
     out[i + c * ldo] = r;
 }
 
-// The same for the 61-tap band (N >= 61) with R consecutive outputs per thread sharing one
-// window of R + 60 inputs in registers (each input is read once per R outputs instead of 61
-// times); the taps of every output are summed in the same order as above.
+// The same for the 61-tap band (N >= 61).  A workgroup takes 2048 consecutive rows of one
+// column: the 2048 + 60 inputs they need enter LDS by coalesced loads (wrapping around the
+// column), each thread forms 8 consecutive outputs from its window of 68 inputs (read once
+// from LDS, one pad word per 8 so that the stride-8 windows of a wavefront hit distinct
+// banks), and the outputs return through LDS so that the stores are coalesced too.  The taps
+// of every output are summed in the same order as above.
 constexpr int kGinvTaps = 61;
-template <typename T, int R>
-__global__ __launch_bounds__(256) void k_ginv_win(int N, int t0, const double *__restrict__ coef,
+constexpr int kGinvSeg = 2048;
+__device__ __forceinline__ int pad8(int e) { return e + (e >> 3); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ginv_seg(int N, int t0, const double *__restrict__ coef,
                                                   cpx<T> a, const cpx<T> *X, int64_t ldx,
                                                   cpx<T> b, const cpx<T> *__restrict__ Y,
-                                                  int64_t ldy, cpx<T> *out, int64_t ldo,
-                                                  int64_t ncol) {
-    const int nchunk = (N + R - 1) / R;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= (int64_t)nchunk * ncol) return;
-    const int i0 = (int)(tid % nchunk) * R;
-    const int64_t c = tid / nchunk;
+                                                  int64_t ldy, cpx<T> *out, int64_t ldo) {
+    constexpr int R = 8;
+    constexpr int W = kGinvSeg + kGinvTaps - 1;
+    constexpr int PW = W + W / 8 + 1;
+    __shared__ T sre[PW], sim[PW];
+    const int t = threadIdx.x;
+    const int nseg = (N + kGinvSeg - 1) / kGinvSeg;
+    const int i0 = (int)(blockIdx.x % nseg) * kGinvSeg;
+    const int64_t c = blockIdx.x / nseg;
     const cpx<T> *y = Y + c * ldy;
-    constexpr int W = kGinvTaps + R - 1;
-    cpx<T> win[W];
-    // win[j] = y[(i0 - t0 - (taps - 1) + j) mod N]
-    int idx = i0 - t0 - (kGinvTaps - 1);
-    idx %= N;
-    if (idx < 0) idx += N;
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-        win[j] = y[idx];
-        idx = idx + 1 == N ? 0 : idx + 1;
+    // window element e holds y[(i0 - t0 - (taps - 1) + e) mod N]
+    const int first = i0 - t0 - (kGinvTaps - 1);
+    for (int e = t; e < W; e += 256) {
+        int idx = (first + e) % N;
+        if (idx < 0) idx += N;
+        const cpx<T> v = y[idx];
+        sre[pad8(e)] = v.x;
+        sim[pad8(e)] = v.y;
     }
+    __syncthreads();
+    // outputs o = 8 t + r use window elements 8 t + m, m = 0..67, with tap u = 60 + r - m;
+    // m runs downwards so that each output takes its taps in increasing u
+    T ar[R], ai[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ar[r] = ai[r] = (T)0;
+#pragma unroll
+    for (int m = R + kGinvTaps - 2; m >= 0; --m) {
+        const int p = 9 * t + m + (m >> 3);
+        const T vr = sre[p], vi = sim[p];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int u = kGinvTaps - 1 + r - m;
+            if (u >= 0 && u < kGinvTaps) {
+                const T w = (T)coef[u];
+                ar[r] += w * vr;
+                ai[r] += w * vi;
+            }
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = i0 + r;
-        if (i < N) {
-            T sr = 0, si = 0;
+        sre[pad8(R * t + r)] = ar[r];
+        sim[pad8(R * t + r)] = ai[r];
+    }
+    __syncthreads();
 #pragma unroll
-            for (int u = 0; u < kGinvTaps; ++u) {
-                const cpx<T> v = win[kGinvTaps - 1 + r - u];
-                const T w = (T)coef[u];
-                sr += w * v.x;
-                si += w * v.y;
-            }
-            cpx<T> res = b * mk(sr, si);
+    for (int q = 0; q < R; ++q) {
+        const int o = t + 256 * q;
+        const int i = i0 + o;
+        if (i < N) {
+            cpx<T> res = b * mk(sre[pad8(o)], sim[pad8(o)]);
             if (X) res = res + a * X[i + c * ldx];
             out[i + c * ldo] = res;
         }
@@ -123,10 +149,9 @@ void launch_ginv_ex(int N, int ntap, int t0, const double *coef, cpx<T> a, const
     int64_t n = (int64_t)N * ncol;
     if (n <= 0) return;
     if (ntap == kGinvTaps) {
-        constexpr int R = 8;
-        const int64_t nt = (int64_t)((N + R - 1) / R) * ncol;
-        hipLaunchKernelGGL((k_ginv_win<T, R>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
-                           s, N, t0, coef, a, X, ldx, b, Y, ldy, out, ldo, ncol);
+        const int64_t nwg = (int64_t)((N + kGinvSeg - 1) / kGinvSeg) * ncol;
+        hipLaunchKernelGGL(k_ginv_seg<T>, dim3((unsigned)nwg), dim3(256), 0, s, N, t0, coef, a,
+                           X, ldx, b, Y, ldy, out, ldo);
         return;
     }
     hipLaunchKernelGGL(k_ginv<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, ntap,

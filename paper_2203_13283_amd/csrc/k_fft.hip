@@ -9,7 +9,8 @@
 // order, so the middle kernel does FFT_N1 -> multiply -> inverse FFT_N1 while the chunk is
 // in LDS, and the inverse of step A restores natural order.  Three passes over memory for
 // N > 4096, one for N <= 4096.  Radix-4 Stockham stages in LDS (one radix-2 stage for odd
-// powers of two), twiddles from tables, all index arithmetic by shifts and masks.
+// powers of two), twiddles from tables, all index arithmetic by shifts and masks; N1 = 4096
+// has a middle kernel of its own (radix 16, mostly in registers).
 #include "internal.h"
 
 namespace cfie {
@@ -86,16 +87,16 @@ __device__ __forceinline__ void lds_fft(T *re, T *im, int lgn, const cpx<T> *__r
     for (; lgL < lgn; lgL += 2) lds_stage<T, 4>(re, im, lgn, lgL, tw, inverse);
 }
 
-// middle step: chunk k2 = blockIdx.x of column blockIdx.y
+// middle step: chunk k2 = blockIdx.x mod N2 of column blockIdx.x / N2
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_mid(int N1, const cpx<T> *__restrict__ tw1,
+__global__ __launch_bounds__(256) void k_fft_mid(int N1, int N2, const cpx<T> *__restrict__ tw1,
                                                  const cpx<T> *__restrict__ d, cpx<T> *x,
                                                  int64_t ldx) {
     extern __shared__ unsigned char smem_raw[];
     T *re = reinterpret_cast<T *>(smem_raw);
     T *im = re + N1;
-    const int k2 = blockIdx.x;
-    cpx<T> *col = x + (int64_t)blockIdx.y * ldx + (int64_t)k2 * N1;
+    const int k2 = (int)(blockIdx.x % N2);
+    cpx<T> *col = x + (int64_t)(blockIdx.x / N2) * ldx + (int64_t)k2 * N1;
     const cpx<T> *dc = d + (int64_t)k2 * N1;
     for (int i = threadIdx.x; i < N1; i += blockDim.x) {
         cpx<T> v = col[i];
@@ -113,6 +114,148 @@ __global__ __launch_bounds__(256) void k_fft_mid(int N1, const cpx<T> *__restric
     __syncthreads();
     lds_fft(re, im, lg, tw1, true);
     for (int i = threadIdx.x; i < N1; i += blockDim.x) col[i] = mk(re[i], im[i]);
+}
+
+// ---- middle step for N1 = 4096 = 16^3: three radix-16 Stockham stages each way ----------
+// Thread j (256 per workgroup) owns the 16 points j + 256 r of every stage's input.  A
+// radix-16 butterfly is two layers of 4-point DFTs with the sixteenth roots of unity between
+// them; the first stage (L = 1) needs no twiddles, and the last (L = 256) leaves point
+// j + 256 q in the thread that computed it, so the chunk enters from global memory straight
+// into registers, is multiplied by the diagonal and starts the inverse transform without an
+// exchange, and leaves from registers.  Four exchanges through LDS in all (35 KB for FP64,
+// so that four workgroups share a compute unit), with one pad element per 16 so that the
+// stride-16 writes of the first stage hit distinct banks.  The
+// twiddles w^{r k} of the second and third stages come from the table of
+// e^{-2 pi i m / 4096} (conjugated for the inverse).
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cpx<T> &x0, cpx<T> &x1, cpx<T> &x2, cpx<T> &x3) {
+    const cpx<T> s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3;
+    const cpx<T> jd = INV ? mk(-d13.y, d13.x) : mk(d13.y, -d13.x);     // +/- i d13
+    x0 = s02 + s13;
+    x1 = d02 + jd;
+    x2 = s02 - s13;
+    x3 = d02 - jd;
+}
+
+// 16-point DFT of a[0..15]; output q = q1 + 4 q0 is left in a[4 q1 + q0]
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cpx<T> (&a)[16]) {
+    // cos and sin of 2 pi e / 16, e = 0..9
+    constexpr double C1 = 0.92387953251128675613, S1 = 0.38268343236508977173;
+    constexpr double R2 = 0.70710678118654752440;
+    constexpr double cs[10][2] = {{1, 0},  {C1, S1},  {R2, R2},  {S1, C1},  {0, 1},
+                                  {-S1, C1}, {-R2, R2}, {-C1, S1}, {-1, 0}, {-C1, -S1}};
+#pragma unroll
+    for (int r0 = 0; r0 < 4; ++r0) dft4<T, INV>(a[r0], a[r0 + 4], a[r0 + 8], a[r0 + 12]);
+#pragma unroll
+    for (int r0 = 1; r0 < 4; ++r0) {
+#pragma unroll
+        for (int q1 = 1; q1 < 4; ++q1) {
+            const int e = r0 * q1;
+            const cpx<T> w = mk((T)cs[e][0], (T)(INV ? cs[e][1] : -cs[e][1]));
+            a[r0 + 4 * q1] = a[r0 + 4 * q1] * w;
+        }
+    }
+#pragma unroll
+    for (int q1 = 0; q1 < 4; ++q1)
+        dft4<T, INV>(a[4 * q1], a[4 * q1 + 1], a[4 * q1 + 2], a[4 * q1 + 3]);
+}
+
+__device__ __forceinline__ int pad16(int p) { return p + (p >> 4); }
+
+// write the 16 outputs of a butterfly to positions base + q L, then read the next stage's
+// inputs j + 256 r; real and imaginary parts pass one after the other through the same
+// 4096 + 256 words of LDS
+template <typename T>
+__device__ __forceinline__ void exchange16(T *buf, cpx<T> (&a)[16], int base, int L) {
+    const int j = threadIdx.x;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const cpx<T> v = a[4 * (q & 3) + (q >> 2)];
+            buf[pad16(base + q * L)] = part ? v.y : v.x;
+        }
+        __syncthreads();
+        T t[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) t[r] = buf[pad16(j + 256 * r)];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (part) a[r].y = t[r];
+            else a[r].x = t[r];
+        }
+    }
+}
+
+// multiply a[1..15] by the stage twiddles w^{r k} (conjugated for the inverse); the stage
+// with L = 16 has w = e^{-2 pi i / 256}, k = j mod 16, the stage with L = 256 has
+// w = e^{-2 pi i / 4096}, k = j.  w^k and w^{4k} come from the table, the other powers
+// from at most two products of table values (w^{(4a + b) k} = w^{4ak} w^{bk}), which keeps
+// 6 twiddles live instead of 15.
+template <typename T, bool INV>
+__device__ __forceinline__ void twiddle16(cpx<T> (&a)[16], const cpx<T> *__restrict__ tw1,
+                                          int L) {
+    const int j = threadIdx.x;
+    const int k = L == 16 ? (j & 15) : j;
+    const int sh = L == 16 ? 4 : 0;
+    cpx<T> w1 = tw1[k << sh], w4 = tw1[(4 * k) << sh];
+    if (INV) {
+        w1 = conj(w1);
+        w4 = conj(w4);
+    }
+    const cpx<T> w2 = w1 * w1, w3 = w2 * w1;
+    const cpx<T> w8 = w4 * w4, w12 = w8 * w4;
+    a[1] = a[1] * w1;
+    a[2] = a[2] * w2;
+    a[3] = a[3] * w3;
+    a[4] = a[4] * w4;
+    a[8] = a[8] * w8;
+    a[12] = a[12] * w12;
+#pragma unroll
+    for (int b = 1; b < 4; ++b) {
+        const cpx<T> wb = b == 1 ? w1 : (b == 2 ? w2 : w3);
+        a[4 + b] = a[4 + b] * (w4 * wb);
+        a[8 + b] = a[8 + b] * (w8 * wb);
+        a[12 + b] = a[12 + b] * (w12 * wb);
+    }
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void fft4096_regs(T *buf, cpx<T> (&a)[16],
+                                             const cpx<T> *__restrict__ tw1) {
+    const int j = threadIdx.x;
+    dft16<T, INV>(a);
+    exchange16<T>(buf, a, 16 * j, 1);
+    twiddle16<T, INV>(a, tw1, 16);
+    dft16<T, INV>(a);
+    exchange16<T>(buf, a, (j >> 4) * 256 + (j & 15), 16);
+    twiddle16<T, INV>(a, tw1, 256);
+    dft16<T, INV>(a);
+}
+
+// chunk k2 = blockIdx.x mod N2 of column blockIdx.x / N2; register budget for three
+// workgroups per compute unit in FP64 (four in FP32), which the 35 KB of LDS allow
+template <typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 3 : 4) void k_fft_mid4096(
+    int N2, const cpx<T> *__restrict__ tw1, const cpx<T> *__restrict__ d, cpx<T> *x,
+    int64_t ldx) {
+    __shared__ T buf[4096 + 4096 / 16];
+    const int j = threadIdx.x;
+    const int k2 = (int)(blockIdx.x % N2);
+    cpx<T> *col = x + (int64_t)(blockIdx.x / N2) * ldx + (int64_t)k2 * 4096;
+    const cpx<T> *dc = d + (int64_t)k2 * 4096;
+    cpx<T> a[16], b[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = col[j + 256 * r];
+    fft4096_regs<T, false>(buf, a, tw1);
+    // spectrum point j + 256 q times the diagonal: the inverse's first-stage inputs
+#pragma unroll
+    for (int q = 0; q < 16; ++q) b[q] = a[4 * (q & 3) + (q >> 2)] * dc[j + 256 * q];
+    fft4096_regs<T, true>(buf, b, tw1);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) col[j + 256 * q] = b[4 * (q & 3) + (q >> 2)];
 }
 
 // step A (forward or inverse) for one (n1, column) per thread; N1, N2 powers of two.
@@ -184,9 +327,14 @@ void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx
     // algorithmic work: bytes of one read and one write of the batch
     ProfScope prof(PROF_FFT, 2.0 * sizeof(cpx<T>) * (double)p.M * (double)nb, s);
     if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), x, ldx, nb, false, s);
-    size_t sh = 2 * sizeof(T) * (size_t)p.N1;
-    hipLaunchKernelGGL(k_fft_mid<T>, dim3(p.N2, (unsigned)nb), dim3(bs), sh, s, p.N1,
-                       tw1_of<T>(p), d, x, ldx);
+    if (p.N1 == 4096) {
+        hipLaunchKernelGGL(k_fft_mid4096<T>, dim3((unsigned)(p.N2 * nb)), dim3(256), 0, s,
+                           p.N2, tw1_of<T>(p), d, x, ldx);
+    } else {
+        size_t sh = 2 * sizeof(T) * (size_t)p.N1;
+        hipLaunchKernelGGL(k_fft_mid<T>, dim3((unsigned)(p.N2 * nb)), dim3(bs), sh, s, p.N1,
+                           p.N2, tw1_of<T>(p), d, x, ldx);
+    }
     if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), x, ldx, nb, true, s);
 }
 

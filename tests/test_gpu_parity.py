@@ -163,13 +163,13 @@ def test_circle_remainder_vanishes():
     assert np.linalg.norm(X[:, 1] - jm) / np.linalg.norm(jm) < 2e-2
 
 
-@pytest.mark.parametrize("N", [8, 32, 512, 2048, 8192, 16384, 32768, 9, 100, 1000, 3000, 6000,
+@pytest.mark.parametrize("N", [8, 32, 512, 2048, 4096, 8192, 16384, 32768, 9, 100, 1000, 3000, 6000,
                                20000, 32767])
 def test_circulant_fft_lengths(N):
     """C_c x and C_c^-1 x by the library's FFT path against numpy's FFT with the exported
-    eigenvalues: odd and even powers of two, one pass (N <= 4096) and the four-step split
-    (N1 = 4096, N2 = 2, 4); other lengths through the zero-padded convolution (transform
-    lengths 32 ... 16384)."""
+    eigenvalues: odd and even powers of two, one pass (N <= 4096, the radix-16 kernel at
+    4096) and the four-step split (N1 = 4096, N2 = 2, 4, 8); other lengths through the
+    zero-padded convolution (transform lengths 32 ... 65536)."""
     zh = W.ellipse_coeffs(1.0, 0.6)
     L = S.Contour(zh).L
     s = P.Solver(compress_tol=1e-10)
@@ -183,6 +183,28 @@ def test_circulant_fft_lengths(N):
         y = _np(s.apply(op, x))
         err = np.abs(y - ref).max() / np.abs(ref).max()
         assert err <= 1e-13, (op, err)
+
+
+@pytest.mark.parametrize("N", [61, 64, 100, 1000, 2047, 2048, 2049, 4157])
+def test_apply_C_matches_dense_product(N):
+    """C X by the library (eq. (6) applied factor by factor, G^-1 as the 61-tap band) against
+    the same product formed with numpy from the exported matrices and the exact inverse of
+    the exported G: isolates the banded G^-1 kernel, including columns shorter than the
+    band's 2048-row workgroup segments and segments that wrap around the column."""
+    zh = W.ellipse_coeffs(1.0, 0.6)
+    L = S.Contour(zh).L
+    s = P.Solver(compress_tol=1e-10)
+    s.assemble(zh, N, 2 * np.pi * N / (10 * L))
+    G, Dk, Nk, Dkt, Skt = (_np(s.export_matrix(w)) for w in
+                           (P.MAT_G, P.MAT_DK, P.MAT_NK, P.MAT_DKT, P.MAT_SKT))
+    C = G / 4 + (Dkt - Dk) / 2 - Dkt @ np.linalg.solve(G, Dk) + Skt @ np.linalg.solve(G, Nk)
+    g = torch.Generator(device="cuda").manual_seed(N)
+    x = torch.randn((3, N), dtype=torch.complex128, device="cuda", generator=g)
+    ref = (C @ _np(x).T).T
+    y = _np(s.apply(P.OP_C, x))
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"N={N}: C X vs dense numpy product {err:.2e}")
+    assert err <= 1e-12
 
 
 @pytest.mark.parametrize("N", [200, 333])
