@@ -113,6 +113,39 @@ def test_solve_in_place_and_ragged_batch(cfg1, cfg1_solver):
     assert S.rel_err(_np(X).T, x_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("prec,adjoint,m", [(P.CFIE_FP64, False, 4100),
+                                             (P.CFIE_MIXED, False, 2050),
+                                             (P.CFIE_FP64, True, 1030)])
+def test_solve_leading_dimensions_and_chunks(cfg1, prec, adjoint, m):
+    """The C ABI with leading dimensions larger than N (B and X padded rows of different
+    widths) and more right-hand sides than one internal chunk (4096 FP64, 2048 mixed, 1024
+    adjoint): bitwise equal to the packed solve, the padding left untouched, and sampled
+    columns on both sides of the chunk boundary against the oracle's dense LU."""
+    w, prob = cfg1
+    N = w.n_nodes
+    eps = 1e-10 if prec == P.CFIE_FP64 else 1e-3
+    s = P.Solver(precision=prec, compress_tol=eps, refine_tol=1e-9)
+    s.assemble(w.zhat, N, w.k).factor()
+    ang = 2 * np.pi * np.arange(m) / m
+    B = s.plane_wave_rhs(ang)
+    Xp = s.solve_adjoint(B) if adjoint else s.solve(B)
+    ldb, ldx = N + 7, N + 3
+    Bw = torch.zeros((m, ldb), dtype=torch.complex128, device="cuda")
+    Bw[:, :N] = B
+    Xw = torch.full((m, ldx), 7 + 7j, dtype=torch.complex128, device="cuda")
+    fn = s._lib.cfie_solve_adjoint if adjoint else s._lib.cfie_solve
+    s._check(fn(s._h, P._ptr(Bw), ldb, P._ptr(Xw), ldx, m), "strided solve")
+    assert torch.equal(Xw[:, :N], Xp)
+    assert bool((Xw[:, N:] == 7 + 7j).all())
+    chunk = {P.CFIE_FP64: 1024 if adjoint else 4096, P.CFIE_MIXED: 2048}[prec]
+    cols = [0, chunk - 1, chunk, m - 1]
+    Bn = prob.rhs(ang[cols])
+    ref = np.linalg.solve(prob.C.conj().T, _np(B[cols]).T) if adjoint else prob.solve(Bn)
+    err = S.rel_err(_np(Xp[cols]).T, ref)
+    print(f"precision {prec} adjoint {adjoint} m={m}: rel.err {err:.2e}")
+    assert err <= (1e-10 if prec == P.CFIE_FP64 else 1e-6)
+
+
 def test_adjoint_solve_matches_dense_lu(cfg1, cfg1_solver):
     """C^H x = g with the same factorisation (adjoint Woodbury, conjugate circulant
     eigenvalues, K^H from the LU of K) against a dense LU of the oracle's C^H; the adjoint
