@@ -313,6 +313,8 @@ template <typename F> cfie_status guarded(cfie_ctx *c, F &&f) {
         return e.st;
     } catch (const std::bad_alloc &) {
         return fail(c, CFIE_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(c, CFIE_EINVAL, std::string("internal: ") + e.what());
     }
 }
 

@@ -810,17 +810,23 @@ template void launch_polar_coef<float>(int, const zd *, int, zf *, int, hipStrea
 // Pivot search by wavefront shuffles and one exchange through LDS (ties: smallest row).
 __global__ __launch_bounds__(1024) void k_lu_panel(int n, int k0, int nb, zd *A, int64_t lda,
                                                    int *piv, int *info) {
+    // nb <= 16 columns, rows k0 .. n-1, one workgroup.  Per column j: argmax of |a|^2 over
+    // rows >= j (ties: smallest row), exchange of rows j and p inside the panel with the new
+    // row j kept in LDS, then one pass over the rows below j that scales column j and
+    // applies the rank-one update to the panel's later columns (all loads of a row issued
+    // together) while it finds the largest entry of column j + 1 for the next step.
     const int tid = threadIdx.x;
     __shared__ double wv[16];
     __shared__ int wi[16];
+    __shared__ zd rowj[16];
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int r = k0 + tid; r < n; r += 1024) {
+        const double v = abs2(A[r + (int64_t)k0 * lda]);
+        if (v > bv) { bv = v; bi = r; }
+    }
     for (int jj = 0; jj < nb; ++jj) {
         const int j = k0 + jj;
-        double bv = -1.0;
-        int bi = 0x7fffffff;
-        for (int r = j + tid; r < n; r += 1024) {
-            const double v = abs2(A[r + (int64_t)j * lda]);
-            if (v > bv) { bv = v; bi = r; }
-        }
         for (int o = 32; o > 0; o >>= 1) {
             const double ov = __shfl_xor(bv, o);
             const int oi = __shfl_xor(bi, o);
@@ -837,23 +843,35 @@ __global__ __launch_bounds__(1024) void k_lu_panel(int n, int k0, int nb, zd *A,
             piv[j] = p;
             if (!(bv > 0.0)) info[0] = 1;
         }
-        // swap rows j and p inside the panel (one thread per column)
-        if (p != j && tid < nb) {
-            const int c = k0 + tid;
-            zd t = A[j + (int64_t)c * lda];
-            A[j + (int64_t)c * lda] = A[p + (int64_t)c * lda];
-            A[p + (int64_t)c * lda] = t;
+        if (tid < nb) {
+            const int64_t c = (int64_t)(k0 + tid) * lda;
+            const zd aj = A[j + c], ap = A[p + c];
+            if (p != j) {
+                A[j + c] = ap;
+                A[p + c] = aj;
+            }
+            rowj[tid] = p != j ? ap : aj;
         }
         __syncthreads();
-        const zd d = A[j + (int64_t)j * lda];
+        const zd d = rowj[jj];
         const zd dinv = (abs2(d) > 0.0) ? cinv(d) : mk(0.0, 0.0);
-        // scale the column and apply the rank-one update to the rest of the panel, row by row
-        const int cols = k0 + nb - j - 1;
+        bv = -1.0;
+        bi = 0x7fffffff;
         for (int r = j + 1 + tid; r < n; r += 1024) {
             const zd l = A[r + (int64_t)j * lda] * dinv;
             A[r + (int64_t)j * lda] = l;
-            for (int c = j + 1; c < j + 1 + cols; ++c)
-                A[r + (int64_t)c * lda] = A[r + (int64_t)c * lda] - l * A[j + (int64_t)c * lda];
+#pragma unroll
+            for (int cc = 1; cc < 16; ++cc) {
+                if (cc > jj && cc < nb) {
+                    zd *ac = A + r + (int64_t)(k0 + cc) * lda;
+                    const zd v = *ac - l * rowj[cc];
+                    *ac = v;
+                    if (cc == jj + 1) {
+                        const double m2 = abs2(v);
+                        if (m2 > bv) { bv = m2; bi = r; }
+                    }
+                }
+            }
         }
         __syncthreads();
     }
@@ -970,7 +988,8 @@ int lu_panel_width(int) { return 16; }
 
 void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info,
                      hipStream_t s) {
-    if (nb <= 16 && n - k0 <= 1024)
+    if (nb < 1 || nb > 16) throw std::runtime_error("LU panel width must be in [1, 16]");
+    if (n - k0 <= 1024)
         hipLaunchKernelGGL((k_lu_panel_reg<1, 16>), dim3(1), dim3(1024), 0, s, n, k0, nb, A, lda,
                            piv, info);
     else
