@@ -98,6 +98,8 @@ namespace {
 
 constexpr int kLUBlock = 64;          // diagonal blocks inverted for the triangular solves
 constexpr int kLUPanel = 16;          // columns per LU panel
+constexpr int kLUSuper = 256;         // columns per LU superpanel (inner dimension of the
+                                      // trailing updates and of the triangular solves)
 
 struct HipError {
     cfie_status st;
@@ -581,68 +583,89 @@ void alloc_factor(cfie_ctx *c) {
     if (sizeof(T) != sizeof(double)) c->w_y64 = c->alloc_n<zd>(nb);
 }
 
-// solve K Z = Z in place with the LU factors (piv, L, U; diagonal block inverses)
+// Triangular solves with the LU factors of K (P K = L U) by blocks of kLUBlock rows (their
+// diagonal inverses Linv, Uinv) grouped into superblocks of kLUSuper rows: inside a
+// superblock each block's update reaches the superblock's other rows only, and one update of
+// inner dimension kLUSuper carries the superblock to the rest of the right-hand sides.
+namespace {
+struct LUSolveCtx {
+    cfie_ctx *c;
+    zd *Z;
+    int64_t ldz, m;
+    zd *tmp;
+    const zd *at(int64_t i, int64_t j) const { return c->K + i + j * (int64_t)c->cap; }
+    // Z[k0:k0+kb] <- op(Inv_block) Z[k0:k0+kb]
+    void diag(int op, const zd *inv, int k0, int kb) const {
+        gemm<double>(op, kb, m, kb, cz<double>(1), inv + (size_t)(k0 / kLUBlock) * kLUBlock *
+                     kLUBlock, kLUBlock, Z + k0, ldz, cz<double>(0), tmp, kb, c->stream);
+        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, c->stream);
+    }
+    // Z[r0:r0+nr] -= op(A) Z[k0:k0+kb], A given by its stored block
+    void update(int op, const zd *A, int r0, int nr, int k0, int kb) const {
+        if (nr <= 0) return;
+        gemm<double>(op, nr, m, kb, cz<double>(-1), A, c->cap, Z + k0, ldz, cz<double>(1),
+                     Z + r0, ldz, c->stream);
+    }
+};
+}  // namespace
+
+// solve K Z = Z in place: row swaps, L (unit lower) forward, U backward
 void lu_solve(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
     const int n = c->rank;
-    hipStream_t s = c->stream;
-    launch_swaps<double>(0, n, c->piv, Z, ldz, 0, m, s);
     const int nb = kLUBlock;
-    int nblk = (n + nb - 1) / nb;
-    for (int bi = 0; bi < nblk; ++bi) {
-        int k0 = bi * nb, kb = std::min(nb, n - k0);
-        gemm<double>(GEMM_N, kb, m, kb, cz<double>(1), c->Linv + (size_t)bi * nb * nb, nb,
-                     Z + k0, ldz, cz<double>(0), tmp, kb, s);
-        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
-        int rest = n - k0 - kb;
-        if (rest > 0)
-            gemm<double>(GEMM_N, rest, m, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * c->cap,
-                         c->cap, Z + k0, ldz, cz<double>(1), Z + k0 + kb, ldz, s);
+    const LUSolveCtx L{c, Z, ldz, m, tmp};
+    launch_swaps<double>(0, n, c->piv, Z, ldz, 0, m, c->stream);
+    for (int s0 = 0; s0 < n; s0 += kLUSuper) {
+        const int s1 = std::min(n, s0 + kLUSuper);
+        for (int k0 = s0; k0 < s1; k0 += nb) {
+            const int kb = std::min(nb, s1 - k0);
+            L.diag(GEMM_N, c->Linv, k0, kb);
+            L.update(GEMM_N, L.at(k0 + kb, k0), k0 + kb, s1 - k0 - kb, k0, kb);
+        }
+        L.update(GEMM_N, L.at(s1, s0), s1, n - s1, s0, s1 - s0);
     }
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-        int k0 = bi * nb, kb = std::min(nb, n - k0);
-        gemm<double>(GEMM_N, kb, m, kb, cz<double>(1), c->Uinv + (size_t)bi * nb * nb, nb,
-                     Z + k0, ldz, cz<double>(0), tmp, kb, s);
-        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
-        if (k0 > 0)
-            gemm<double>(GEMM_N, k0, m, kb, cz<double>(-1), c->K + (size_t)k0 * c->cap, c->cap,
-                         Z + k0, ldz, cz<double>(1), Z, ldz, s);
+    const int nsup = (n + kLUSuper - 1) / kLUSuper;
+    for (int si = nsup - 1; si >= 0; --si) {
+        const int s0 = si * kLUSuper, s1 = std::min(n, s0 + kLUSuper);
+        for (int k0 = s0 + ((s1 - s0 - 1) / nb) * nb; k0 >= s0; k0 -= nb) {
+            const int kb = std::min(nb, s1 - k0);
+            L.diag(GEMM_N, c->Uinv, k0, kb);
+            L.update(GEMM_N, L.at(s0, k0), s0, k0 - s0, k0, kb);
+        }
+        L.update(GEMM_N, L.at(0, s0), 0, s0, s0, s1 - s0);
     }
     c->check_launch();
 }
 
-// solve K^H Z = Z in place with the LU factors of K (P K = L U, so K^H = U^H L^H P):
-// forward substitution with U^H, backward with L^H, then the row swaps in reverse order
+// solve K^H Z = Z in place (K^H = U^H L^H P): U^H forward, L^H backward, then the row swaps
+// in reverse order
 void lu_solve_adj(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
     const int n = c->rank;
-    hipStream_t s = c->stream;
     const int nb = kLUBlock;
-    const int nblk = (n + nb - 1) / nb;
-    for (int bi = 0; bi < nblk; ++bi) {
-        int k0 = bi * nb, kb = std::min(nb, n - k0);
-        gemm<double>(GEMM_C, kb, m, kb, cz<double>(1), c->Uinv + (size_t)bi * nb * nb, nb,
-                     Z + k0, ldz, cz<double>(0), tmp, kb, s);
-        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
-        int rest = n - k0 - kb;
-        if (rest > 0)
-            gemm<double>(GEMM_C, rest, m, kb, cz<double>(-1), c->K + k0 + (size_t)(k0 + kb) * c->cap,
-                         c->cap, Z + k0, ldz, cz<double>(1), Z + k0 + kb, ldz, s);
+    const LUSolveCtx L{c, Z, ldz, m, tmp};
+    for (int s0 = 0; s0 < n; s0 += kLUSuper) {
+        const int s1 = std::min(n, s0 + kLUSuper);
+        for (int k0 = s0; k0 < s1; k0 += nb) {
+            const int kb = std::min(nb, s1 - k0);
+            L.diag(GEMM_C, c->Uinv, k0, kb);
+            L.update(GEMM_C, L.at(k0, k0 + kb), k0 + kb, s1 - k0 - kb, k0, kb);
+        }
+        L.update(GEMM_C, L.at(s0, s1), s1, n - s1, s0, s1 - s0);
     }
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-        int k0 = bi * nb, kb = std::min(nb, n - k0);
-        gemm<double>(GEMM_C, kb, m, kb, cz<double>(1), c->Linv + (size_t)bi * nb * nb, nb,
-                     Z + k0, ldz, cz<double>(0), tmp, kb, s);
-        axpby<double>(kb, m, cz<double>(1), tmp, kb, cz<double>(0), Z + k0, ldz, s);
-        if (k0 > 0)
-            gemm<double>(GEMM_C, k0, m, kb, cz<double>(-1), c->K + k0, c->cap, Z + k0, ldz,
-                         cz<double>(1), Z, ldz, s);
+    const int nsup = (n + kLUSuper - 1) / kLUSuper;
+    for (int si = nsup - 1; si >= 0; --si) {
+        const int s0 = si * kLUSuper, s1 = std::min(n, s0 + kLUSuper);
+        for (int k0 = s0 + ((s1 - s0 - 1) / nb) * nb; k0 >= s0; k0 -= nb) {
+            const int kb = std::min(nb, s1 - k0);
+            L.diag(GEMM_C, c->Linv, k0, kb);
+            L.update(GEMM_C, L.at(k0, s0), s0, k0 - s0, k0, kb);
+        }
+        L.update(GEMM_C, L.at(s0, 0), 0, s0, s0, s1 - s0);
     }
-    launch_swaps_reverse<double>(0, n, c->piv, Z, ldz, 0, m, s);
+    launch_swaps_reverse<double>(0, n, c->piv, Z, ldz, 0, m, c->stream);
     c->check_launch();
 }
 
-// Rd = C - C_c as a dense N x N matrix (precision T):
-//   C = (G/2 + D^kt) M + S^kt G^-1 N^k,  M = G^-1 (G/2 - D^k) = I/2 - G^-1 D^k   (eq. (6))
-// two N x N x N GEMMs; C_c densely as its circulant applied to the identity
 template <typename T>
 void form_remainder_dense(cfie_ctx *c, cpx<T> *Rd) {
     const int N = c->N;
@@ -766,32 +789,64 @@ cfie_status factor_impl(cfie_ctx *c) {
         c->dfree(K32);
     }
     launch_add_identity(ell, c->K, cap, s);
-    // blocked LU with partial pivoting: panels of kLUPanel columns, trailing updates by GEMM;
-    // then the inverses of the kLUBlock x kLUBlock diagonal blocks of L and U for the solves
+    // blocked LU with partial pivoting in two levels: superpanels of kLUSuper columns, each
+    // factored by panels of kLUPanel columns whose updates stay inside the superpanel; then
+    // the superpanel's row swaps on the other columns, its block row of U by forward
+    // substitution with the panels' unit-lower diagonal blocks, and one trailing update of
+    // inner dimension kLUSuper (instead of one of inner dimension kLUPanel per panel, which
+    // would re-read the whole trailing matrix per panel).  Then the inverses of the
+    // kLUBlock x kLUBlock diagonal blocks of L and U for the triangular solves.
     c->piv = c->alloc_n<int>(std::max(ell, 1));
     int nblk = (ell + kLUBlock - 1) / kLUBlock;
     c->Linv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
     c->Uinv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
     zd *tmp = c->alloc_n<zd>((size_t)kLUPanel * std::max(ell, 1));
-    zd *Lp = c->alloc_n<zd>((size_t)kLUPanel * kLUPanel);
+    constexpr int kPanels = kLUSuper / kLUPanel;
+    zd *Lp = c->alloc_n<zd>((size_t)kPanels * kLUPanel * kLUPanel);
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
-    const int pw = lu_panel_width(ell);          // <= kLUPanel
-    for (int k0 = 0; k0 < ell; k0 += pw) {
-        const int kb = std::min(pw, ell - k0);
-        launch_lu_panel(ell, k0, kb, c->K, cap, c->piv, c->info, s);
-        launch_swaps<double>(k0, k0 + kb, c->piv, c->K, cap, 0, k0, s);
-        launch_swaps<double>(k0, k0 + kb, c->piv, c->K, cap, k0 + kb, ell, s);
-        const int rest = ell - k0 - kb;
+    const int pw = lu_panel_width(ell);          // == kLUPanel
+    zd *K = c->K;
+    auto at = [&](int64_t i, int64_t j) { return K + i + j * (int64_t)cap; };
+    for (int S0 = 0; S0 < ell; S0 += kLUSuper) {
+        const int S1 = std::min(ell, S0 + kLUSuper);
+        for (int k0 = S0; k0 < S1; k0 += pw) {
+            const int kb = std::min(pw, S1 - k0);
+            zd *Lpi = Lp + (size_t)((k0 - S0) / pw) * kLUPanel * kLUPanel;
+            launch_lu_panel(ell, k0, kb, K, cap, c->piv, c->info, s);
+            launch_swaps<double>(k0, k0 + kb, c->piv, K, cap, S0, k0, s);
+            launch_swaps<double>(k0, k0 + kb, c->piv, K, cap, k0 + kb, S1, s);
+            launch_tri_inv(kb, at(k0, k0), cap, true, Lpi, kLUPanel, s);
+            const int restS = S1 - k0 - kb;
+            if (restS > 0) {
+                // U12 inside the superpanel, then its trailing update over all rows below
+                gemm<double>(GEMM_N, kb, restS, kb, cz<double>(1), Lpi, kLUPanel, at(k0, k0 + kb),
+                             cap, cz<double>(0), tmp, kb, s);
+                axpby<double>(kb, restS, cz<double>(1), tmp, kb, cz<double>(0), at(k0, k0 + kb),
+                              cap, s);
+                gemm<double>(GEMM_N, ell - k0 - kb, restS, kb, cz<double>(-1), at(k0 + kb, k0),
+                             cap, at(k0, k0 + kb), cap, cz<double>(1), at(k0 + kb, k0 + kb), cap,
+                             s);
+            }
+            c->check_launch();
+        }
+        const int rest = ell - S1;
+        launch_swaps<double>(S0, S1, c->piv, K, cap, 0, S0, s);
         if (rest > 0) {
-            zd *Kd = c->K + k0 + (size_t)k0 * cap;
-            launch_tri_inv(kb, Kd, cap, true, Lp, kLUPanel, s);
-            zd *U12 = c->K + k0 + (size_t)(k0 + kb) * cap;
-            gemm<double>(GEMM_N, kb, rest, kb, cz<double>(1), Lp, kLUPanel, U12, cap,
-                         cz<double>(0), tmp, kb, s);
-            axpby<double>(kb, rest, cz<double>(1), tmp, kb, cz<double>(0), U12, cap, s);
-            gemm<double>(GEMM_N, rest, rest, kb, cz<double>(-1), c->K + (k0 + kb) + (size_t)k0 * cap,
-                         cap, U12, cap, cz<double>(1), c->K + (k0 + kb) + (size_t)(k0 + kb) * cap,
-                         cap, s);
+            launch_swaps<double>(S0, S1, c->piv, K, cap, S1, ell, s);
+            // U12 = L11^-1 K[S0:S1, S1:ell] by the panels' diagonal inverses
+            for (int k0 = S0; k0 < S1; k0 += pw) {
+                const int kb = std::min(pw, S1 - k0);
+                const zd *Lpi = Lp + (size_t)((k0 - S0) / pw) * kLUPanel * kLUPanel;
+                gemm<double>(GEMM_N, kb, rest, kb, cz<double>(1), Lpi, kLUPanel, at(k0, S1), cap,
+                             cz<double>(0), tmp, kb, s);
+                axpby<double>(kb, rest, cz<double>(1), tmp, kb, cz<double>(0), at(k0, S1), cap, s);
+                const int below = S1 - k0 - kb;
+                if (below > 0)
+                    gemm<double>(GEMM_N, below, rest, kb, cz<double>(-1), at(k0 + kb, k0), cap,
+                                 at(k0, S1), cap, cz<double>(1), at(k0 + kb, S1), cap, s);
+            }
+            gemm<double>(GEMM_N, rest, rest, S1 - S0, cz<double>(-1), at(S1, S0), cap, at(S0, S1),
+                         cap, cz<double>(1), at(S1, S1), cap, s);
         }
         c->check_launch();
     }
