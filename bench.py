@@ -113,7 +113,7 @@ def cpu_baseline(w):
     import scipy.linalg as sla
     from oracle import assembly as A
     from oracle import system as S
-    # the GPU machine grants this job a share of 16 host cores
+    # at most 16 host threads: the host share that comes with one GPU
     cores = max(1, min(16, os.cpu_count() or 1))
     Ns = 2048
     ks = w.k * Ns / w.n_nodes
@@ -337,8 +337,8 @@ def shapegrad_main(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this "
-              "build (the solver has no multi-GPU path).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported (the solver "
+              "has no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
     if not a.autotune:
         import paper_2203_13283_amd as P

@@ -13,7 +13,7 @@ R = |r - r'| formed from O(1) coordinates carries an absolute error of about 1e-
 relative error of about 1e-16 / R, and the smallest R between Gauss points of one element
 shrinks like h ~ 1/N (about 1e-5 at N = 16384, so log R is uncertain to about 1e-11); and a
 double-layer entry near the diagonal is a few 1e-8 (its kernel (r - r').n' / R^2 is formed
-from O(1) numbers), so it is judged at the scale of G/2, not relative to itself.
+from O(1) numbers), so it is compared at the scale of G/2, not relative to itself.
 Right-hand sides 1e-11;
 FP64 solve rel.err <= 1e-10 at epsilon = 1e-10 (ellipse4096) and <= 1e-6 at the bench's
 epsilon = 1e-5 (perturbed16384); mixed precision <= 1e-6 after refinement.
