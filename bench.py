@@ -107,8 +107,8 @@ def cpu_baseline(w):
 
     Sample: the oracle's dense assembly at N_s = 2048 nodes of the same contour and the same
     nodes per wavelength, then its dense C, LU and triangular solves for 64 right-hand
-    sides (about 20 s of CPU work on 16 cores).  Scaling to N: assembly ~ N^2 (pairs of elements), form C + LU ~ N^3, solve ~ N^2
-    per right-hand side."""
+    sides (about 11 s of CPU work on 16 cores).  Scaling to N: assembly ~ N^2 (pairs of
+    elements), form C + LU ~ N^3, solve ~ N^2 per right-hand side."""
     import numpy as np
     import scipy.linalg as sla
     from oracle import assembly as A
