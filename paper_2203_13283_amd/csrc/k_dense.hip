@@ -681,6 +681,17 @@ __global__ __launch_bounds__(64) void k_pchol_pivots(int b, const zd *W, int ldw
         }
         const int p = bi;
         const double sd = sqrt(bv), isd = 1.0 / sd;
+        // column p of W (at the panel start) and of M for every lane, all loads issued before
+        // the stores to Z below (which the compiler could not otherwise move them past)
+        zd wp[PER], mp[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int cc = lane + 64 * q;
+            if (cc < b) {
+                wp[q] = W[cc + (int64_t)p * ldw];
+                mp[q] = M[cc + (int64_t)p * b];
+            }
+        }
         // the pivot's entries of the earlier rows of this panel, for every lane
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -691,11 +702,11 @@ __global__ __launch_bounds__(64) void k_pchol_pivots(int b, const zd *W, int ldw
             if (cc == p) {
                 r = mk(sd, 0.0);
             } else if (!tk[q]) {
-                r = conj(W[cc + (int64_t)p * ldw]);
+                r = conj(wp[q]);
                 for (int i = 0; i < jp; ++i) r = r - conj(Rp[i * b + p]) * Rp[i * b + cc];
                 r = r * isd;
             }
-            zd z = M[cc + (int64_t)p * b];
+            zd z = mp[q];
             if (cc == p) z = z + mk(1.0, 0.0);
             for (int i = 0; i < jp; ++i) z = z - Zp[i * b + cc] * Rp[i * b + p];
             z = z * isd;
