@@ -122,11 +122,11 @@ __global__ __launch_bounds__(256) void k_fft_mid(int N1, int N2, const cpx<T> *_
 // them; the first stage (L = 1) needs no twiddles, and the last (L = 256) leaves point
 // j + 256 q in the thread that computed it, so the chunk enters from global memory straight
 // into registers, is multiplied by the diagonal and starts the inverse transform without an
-// exchange, and leaves from registers.  Four exchanges through LDS in all (35 KB for FP64,
-// so that four workgroups share a compute unit), with one pad element per 16 so that the
-// stride-16 writes of the first stage hit distinct banks.  The
-// twiddles w^{r k} of the second and third stages come from the table of
-// e^{-2 pi i m / 4096} (conjugated for the inverse).
+// exchange, and leaves from registers.  Four exchanges through LDS in all, real and
+// imaginary parts in turn through 35 KB (FP64), with one pad element per 16 so that the
+// stride-16 writes of the first stage hit distinct banks.  The twiddles w^{r k} of the
+// second and third stages come from the table of e^{-2 pi i m / 4096} (conjugated for the
+// inverse).
 template <typename T, bool INV>
 __device__ __forceinline__ void dft4(cpx<T> &x0, cpx<T> &x1, cpx<T> &x2, cpx<T> &x3) {
     const cpx<T> s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3;
@@ -235,8 +235,8 @@ __device__ __forceinline__ void fft4096_regs(T *buf, cpx<T> (&a)[16],
     dft16<T, INV>(a);
 }
 
-// chunk k2 = blockIdx.x mod N2 of column blockIdx.x / N2; register budget for three
-// workgroups per compute unit in FP64 (four in FP32), which the 35 KB of LDS allow
+// chunk k2 = blockIdx.x mod N2 of column blockIdx.x / N2; registers budgeted for three
+// workgroups per compute unit in FP64 and four in FP32 (the LDS would allow four in FP64)
 template <typename T>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? 3 : 4) void k_fft_mid4096(
     int N2, const cpx<T> *__restrict__ tw1, const cpx<T> *__restrict__ d, cpx<T> *x,
