@@ -49,7 +49,8 @@ void launch_dft_direct_tw(int N, const zd *x, int64_t ldx, zd *y, int64_t ldy, i
                           const zd *twN, hipStream_t s);
 void launch_chol_inv(int b, zd *W, int ldw, double shift, zd *Rinv, int ldr, int *info,
                      hipStream_t s);
-void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info,
+size_t lu_panel_ws_ints();
+void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info, int *ws,
                      hipStream_t s);
 int lu_panel_width(int n);
 template <typename T>
@@ -803,6 +804,7 @@ cfie_status factor_impl(cfie_ctx *c) {
     zd *tmp = c->alloc_n<zd>((size_t)kLUPanel * std::max(ell, 1));
     constexpr int kPanels = kLUSuper / kLUPanel;
     zd *Lp = c->alloc_n<zd>((size_t)kPanels * kLUPanel * kLUPanel);
+    int *panel_ws = c->alloc_n<int>(lu_panel_ws_ints());
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
     const int pw = lu_panel_width(ell);          // == kLUPanel
     zd *K = c->K;
@@ -812,7 +814,7 @@ cfie_status factor_impl(cfie_ctx *c) {
         for (int k0 = S0; k0 < S1; k0 += pw) {
             const int kb = std::min(pw, S1 - k0);
             zd *Lpi = Lp + (size_t)((k0 - S0) / pw) * kLUPanel * kLUPanel;
-            launch_lu_panel(ell, k0, kb, K, cap, c->piv, c->info, s);
+            launch_lu_panel(ell, k0, kb, K, cap, c->piv, c->info, panel_ws, s);
             launch_swaps<double>(k0, k0 + kb, c->piv, K, cap, S0, k0, s);
             launch_swaps<double>(k0, k0 + kb, c->piv, K, cap, k0 + kb, S1, s);
             launch_tri_inv(kb, at(k0, k0), cap, true, Lpi, kLUPanel, s);
@@ -857,6 +859,7 @@ cfie_status factor_impl(cfie_ctx *c) {
     c->sync();
     c->dfree(tmp);
     c->dfree(Lp);
+    c->dfree(panel_ws);
     if (info) return fail(c, CFIE_ESINGULAR, "zero pivot in the capacitance matrix");
     // K^{-1} V^T (ell x N) by the complex128 LU factors, once per factorisation, so that a
     // solve is C_c^{-1} by FFT and two GEMMs

@@ -995,16 +995,219 @@ __global__ __launch_bounds__(1024) void k_lu_panel_reg(int n, int k0, int nb, zd
 
 // panel width of the LU (16 columns: narrower panels with two or four rows per thread in
 // registers measured slower overall, by the extra panels and trailing updates)
+// ---- tall panels (more than 1024 rows) by tournament pivoting: partial pivoting inside
+// chunks of 256 rows picks 16 candidate rows per chunk (many workgroups at once), partial
+// pivoting over all candidates picks the panel's pivots, and the panel is then the LU of
+// its top block after the row exchanges with L21 = A21 U11^-1.  This is the
+// communication-avoiding form of the panel factorisation (Grigori, Demmel and Xiang, 2011):
+// the pivots can differ from those of partial pivoting over the whole column, the
+// factorisation is P A = L U all the same, and no workgroup waits for another inside a
+// column step (a single workgroup over the whole panel is held to one compute unit's
+// bandwidth for every column).
+constexpr int kTsluChunk = 256;
+constexpr int kTsluMaxCand = 1024;           // chunks x 16 candidates held by one workgroup
+
+// the entry jj of a register array (unrolled selection, no dynamic register indexing)
+__device__ __forceinline__ zd pick16(const zd (&a)[16], int jj) {
+    // value selects (a select of addresses would keep the array in scratch memory)
+    double xr = 0.0, xi = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        xr = c == jj ? a[c].x : xr;
+        xi = c == jj ? a[c].y : xi;
+    }
+    return mk(xr, xi);
+}
+
+// partial pivoting over the rows held by the workgroup (one row per thread, values in a,
+// rows already chosen or absent have taken = true); the chosen row ids go to out[0..nb)
+// (-1 when no row is left).  NW wavefronts.
+template <int NW>
+__device__ __forceinline__ void tournament(zd (&a)[16], bool taken, int row, int nb,
+                                           int *out) {
+    const int tid = threadIdx.x;
+    __shared__ double wv[NW];
+    __shared__ int wi[NW];
+    __shared__ zd prow[16];
+    for (int jj = 0; jj < nb; ++jj) {
+        double bv = taken ? -1.0 : abs2(pick16(a, jj));
+        int bi = taken ? 0x7fffffff : row;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if ((tid & 63) == 0) { wv[tid >> 6] = bv; wi[tid >> 6] = bi; }
+        __syncthreads();
+        bv = wv[0];
+        bi = wi[0];
+        for (int w = 1; w < NW; ++w)
+            if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
+        if (tid == 0) out[jj] = bv < 0.0 ? -1 : bi;
+        if (bv >= 0.0 && !taken && row == bi) {
+            taken = true;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) prow[c] = a[c];
+        }
+        __syncthreads();
+        if (bv >= 0.0 && !taken) {
+            const zd d = prow[jj];
+            const zd dinv = (abs2(d) > 0.0) ? cinv(d) : mk(0.0, 0.0);
+            const zd l = pick16(a, jj) * dinv;
+#pragma unroll
+            for (int c = 1; c < 16; ++c)
+                if (c > jj && c < nb) a[c] = a[c] - l * prow[c];
+        }
+        __syncthreads();
+    }
+}
+
+// candidates of chunk blockIdx.x (rows k0 + 256 blockIdx.x + tid) -> cand[16 blockIdx.x ..]
+__global__ __launch_bounds__(256) void k_tslu_local(int n, int k0, int nb, const zd *A,
+                                                    int64_t lda, int *cand) {
+    const int row = k0 + blockIdx.x * kTsluChunk + threadIdx.x;
+    const bool valid = row < n;
+    zd a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        a[c] = (valid && c < nb) ? A[row + (int64_t)(k0 + c) * lda] : mk(0.0, 0.0);
+    __shared__ int out[16];
+    tournament<kTsluChunk / 64>(a, !valid, row, nb, out);
+    if (threadIdx.x < 16)
+        cand[blockIdx.x * 16 + threadIdx.x] = (int)threadIdx.x < nb ? out[threadIdx.x] : -1;
+}
+
+// the panel's pivots from all candidates, the row exchanges inside the panel (piv in the
+// sequential-exchange form of partial pivoting), and the unpivoted LU of the top block
+template <int NW>              // wavefronts: 64 NW >= max(candidates, 256)
+__global__ __launch_bounds__(64 * NW) void k_tslu_final(int n, int k0, int nb, zd *A,
+                                                        int64_t lda, const int *cand, int ncand,
+                                                        int *piv, int *info) {
+    const int tid = threadIdx.x;
+    const int row = tid < ncand ? cand[tid] : -1;
+    const bool valid = row >= 0;
+    zd a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        a[c] = (valid && c < nb) ? A[row + (int64_t)(k0 + c) * lda] : mk(0.0, 0.0);
+    __shared__ int P[16], pv[16];
+    tournament<NW>(a, !valid, row, nb, P);
+    if (tid == 0) {
+        // pivot jj is original row P[jj]; its current position after the earlier exchanges
+        // (rows displaced from the top block are tracked in a short list)
+        int orig[32], pos[32], nd = 0;                 // at most two new entries per pivot
+        for (int jj = 0; jj < nb; ++jj) {
+            const int j = k0 + jj, t = P[jj];
+            int q = t;
+            for (int d = 0; d < nd; ++d)
+                if (orig[d] == t) q = pos[d];
+            pv[jj] = q < 0 ? j : q;
+            piv[j] = pv[jj];
+            if (q < 0) {                                  // fewer candidates than columns
+                info[0] = 1;
+                continue;
+            }
+            if (q != j) {
+                int oj = j;                          // the original row now at position j
+                for (int d = 0; d < nd; ++d)
+                    if (pos[d] == j) oj = orig[d];
+                bool f1 = false, f2 = false;
+                for (int d = 0; d < nd; ++d) {
+                    if (orig[d] == oj) { pos[d] = q; f1 = true; }
+                    else if (orig[d] == t) { pos[d] = j; f2 = true; }
+                }
+                if (!f1) { orig[nd] = oj; pos[nd] = q; ++nd; }
+                if (!f2) { orig[nd] = t; pos[nd] = j; ++nd; }
+            }
+        }
+    }
+    __syncthreads();
+    // the exchanges, in order, on the panel's columns
+    for (int jj = 0; jj < nb; ++jj) {
+        const int j = k0 + jj, q = pv[jj];
+        if (q != j && tid < nb) {
+            const int64_t c = (int64_t)(k0 + tid) * lda;
+            const zd t = A[j + c];
+            A[j + c] = A[q + c];
+            A[q + c] = t;
+        }
+        __syncthreads();
+    }
+    // unpivoted LU of the nb x nb top block in LDS (thread (i, c) = (tid / 16, tid % 16))
+    __shared__ zd T[16][16];
+    const int i = tid >> 4, c = tid & 15;
+    if (tid < 256 && i < nb && c < nb) T[i][c] = A[k0 + i + (int64_t)(k0 + c) * lda];
+    __syncthreads();
+    for (int jj = 0; jj < nb; ++jj) {
+        if (tid < 256 && i > jj && i < nb && c == jj) {
+            const zd d = T[jj][jj];
+            T[i][jj] = T[i][jj] * ((abs2(d) > 0.0) ? cinv(d) : mk(0.0, 0.0));
+        }
+        __syncthreads();
+        if (tid < 256 && i > jj && i < nb && c > jj && c < nb) T[i][c] = T[i][c] - T[i][jj] * T[jj][c];
+        __syncthreads();
+    }
+    if (tid < 256 && i < nb && c < nb) {
+        if (i == c && !(abs2(T[i][i]) > 0.0)) info[0] = 1;
+        A[k0 + i + (int64_t)(k0 + c) * lda] = T[i][c];
+    }
+}
+
+// L21 = A21 U11^-1 for the rows below the top block, one row per thread
+__global__ __launch_bounds__(256) void k_tslu_l21(int n, int k0, int nb, zd *A, int64_t lda) {
+    __shared__ zd U[16][16];
+    const int tid = threadIdx.x;
+    {
+        const int i = tid >> 4, c = tid & 15;
+        if (i < nb && c < nb) U[i][c] = A[k0 + i + (int64_t)(k0 + c) * lda];
+    }
+    __syncthreads();
+    const int row = k0 + nb + blockIdx.x * 256 + tid;
+    if (row >= n) return;
+    zd a[16], l[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        a[c] = c < nb ? A[row + (int64_t)(k0 + c) * lda] : mk(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        zd x = a[c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) x = x - l[m] * U[m][c];
+        const zd d = U[c][c];
+        l[c] = (c < nb && abs2(d) > 0.0) ? x * cinv(d) : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        if (c < nb) A[row + (int64_t)(k0 + c) * lda] = l[c];
+}
+
+size_t lu_panel_ws_ints() { return kTsluMaxCand; }
+
 int lu_panel_width(int) { return 16; }
 
-void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info,
+void launch_lu_panel(int n, int k0, int nb, zd *A, int64_t lda, int *piv, int *info, int *ws,
                      hipStream_t s) {
     if (nb < 1 || nb > 16) throw std::runtime_error("LU panel width must be in [1, 16]");
-    if (n - k0 <= 1024)
+    const int rows = n - k0;
+    const int nchunk = (rows + kTsluChunk - 1) / kTsluChunk;
+    if (rows <= 1024) {
         hipLaunchKernelGGL((k_lu_panel_reg<1, 16>), dim3(1), dim3(1024), 0, s, n, k0, nb, A, lda,
                            piv, info);
-    else
+    } else if (ws && nchunk * 16 <= kTsluMaxCand) {
+        hipLaunchKernelGGL(k_tslu_local, dim3(nchunk), dim3(kTsluChunk), 0, s, n, k0, nb,
+                           (const zd *)A, lda, ws);
+        const int ncand = nchunk * 16;
+        auto final_kernel = ncand <= 256 ? k_tslu_final<4>
+                          : ncand <= 512 ? k_tslu_final<8> : k_tslu_final<16>;
+        const int nthr = ncand <= 256 ? 256 : ncand <= 512 ? 512 : 1024;
+        hipLaunchKernelGGL(final_kernel, dim3(1), dim3(nthr), 0, s, n, k0, nb, A, lda,
+                           (const int *)ws, ncand, piv, info);
+        const int below = rows - nb;
+        hipLaunchKernelGGL(k_tslu_l21, dim3((below + 255) / 256), dim3(256), 0, s, n, k0, nb, A,
+                           lda);
+    } else {
         hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, s, n, k0, nb, A, lda, piv, info);
+    }
 }
 
 // apply the row swaps piv[k0 .. k1) to columns [c0, c1) of A (one thread per column)
