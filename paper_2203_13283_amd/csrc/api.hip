@@ -1025,8 +1025,8 @@ cfie_ctx::SolveGraph *solve_graph(cfie_ctx *c, int64_t m) {
     g.X = c->alloc_n<zd>((size_t)N * m);
     g.Z = c->alloc_n<zd>((size_t)std::max(r, 1) * m);
     if (c->fft.M != N) g.P = c->alloc_n<zd>((size_t)c->fft.M * m);
-    const size_t wb = std::max(gemm_splitk_bytes(r, m, N, sizeof(zd)),
-                               gemm_splitk_bytes(N, m, r, sizeof(zd)));
+    const size_t wb = std::max(gemm_splitk_bytes(GEMM_N, r, m, N, sizeof(zd)),
+                               gemm_splitk_bytes(GEMM_N, N, m, r, sizeof(zd)));
     if (wb) g.W = c->dalloc(wb);
     c->sync();
     Profiler *saved = g_prof;

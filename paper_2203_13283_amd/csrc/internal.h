@@ -207,7 +207,7 @@ int gemm_tuned_classes();
 // split-K workspace of the calling thread's GEMMs taken from p (bytes) instead of the shared
 // per-stream one while p is set (graph capture); the bytes a GEMM's split needs (0: none)
 void set_splitk_override(void *p, size_t bytes);
-size_t gemm_splitk_bytes(int64_t m, int64_t n, int64_t k, size_t elem);
+size_t gemm_splitk_bytes(int op, int64_t m, int64_t n, int64_t k, size_t elem);
 template <typename T>
 void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A, int64_t lda,
           const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s);

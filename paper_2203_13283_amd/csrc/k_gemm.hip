@@ -295,6 +295,81 @@ __global__ void k_splitk_reduce(int64_t m, int64_t n, int S, const cpx<T> *__res
     *p = v;
 }
 
+// ---------------------------------------------------------------- skinny products -------
+// C = alpha A B + beta C when B has at most 16 columns (op(A) = A, the Woodbury solve of a few
+// right-hand sides): the product streams A once from HBM and does 8 n flops per element of A,
+// so it is bound by memory, and a 64 x 64 matrix-core tile would spend its time on columns
+// that do not exist.  A workgroup of 256 threads takes 256 rows of A (one per thread, the
+// loads of a wavefront contiguous) and a range of K; the range's rows of B pass through LDS in
+// tiles of 32 and every thread forms NB complex dot products in registers, k in increasing
+// order.  Ranges of K are summed by the split-K reduction in a fixed order.
+constexpr int kSkinnyMaxN = 16, kSkinnyRows = 256, kSkinnyKT = 32;
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256, 2) void k_zgemm_skinny(int64_t m, int n, int64_t k,
+                                                      int64_t kchunk, cpx<T> alpha,
+                                                      const cpx<T> *__restrict__ A, int64_t lda,
+                                                      const cpx<T> *__restrict__ B, int64_t ldb,
+                                                      cpx<T> beta, cpx<T> *C, int64_t ldc,
+                                                      cpx<T> *W) {
+    __shared__ cpx<T> Bs[kSkinnyKT][NB];
+    const int tid = threadIdx.x;
+    const int64_t nrb = (m + kSkinnyRows - 1) / kSkinnyRows;
+    const int64_t rb = blockIdx.x % nrb, z = blockIdx.x / nrb;
+    const int64_t row = rb * kSkinnyRows + tid;
+    const int64_t rowc = row < m ? row : m - 1;     // loads in bounds; the store is skipped
+    const int64_t kb = z * kchunk, ke = min(k, kb + kchunk);
+    cpx<T> acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = mk((T)0, (T)0);
+    for (int64_t k0 = kb; k0 < ke; k0 += kSkinnyKT) {
+        const int kt = (int)min((int64_t)kSkinnyKT, ke - k0);
+        __syncthreads();
+        for (int e = tid; e < kSkinnyKT * NB; e += 256) {
+            const int kk = e % kSkinnyKT, j = e / kSkinnyKT;
+            Bs[kk][j] = (kk < kt && j < n) ? B[k0 + kk + (int64_t)j * ldb] : mk((T)0, (T)0);
+        }
+        __syncthreads();
+        const cpx<T> *a0 = A + rowc + k0 * lda;
+        if (kt == kSkinnyKT) {
+            for (int k8 = 0; k8 < kSkinnyKT; k8 += 8) {
+                cpx<T> a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = a0[(int64_t)(k8 + u) * lda];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) acc[j] = acc[j] + a[u] * Bs[k8 + u][j];
+            }
+        } else {
+            for (int kk = 0; kk < kt; ++kk) {
+                const cpx<T> a = a0[(int64_t)kk * lda];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = acc[j] + a * Bs[kk][j];
+            }
+        }
+    }
+    if (row >= m) return;
+    // fully unrolled over the register array (a loop over it would move it to scratch)
+    if (W) {
+        cpx<T> *w = W + z * m * n + row;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j < n) w[(int64_t)j * m] = acc[j];
+    } else {
+        const bool beta_zero = (beta.x == (T)0 && beta.y == (T)0);
+        cpx<T> *c = C + row;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (j < n) {
+                cpx<T> v = alpha * acc[j];
+                if (!beta_zero) v = v + beta * c[(int64_t)j * ldc];
+                c[(int64_t)j * ldc] = v;
+            }
+        }
+    }
+}
+
 // grow-only device workspaces for split-K partial products, one per (device, stream) so that
 // contexts on different streams can run from different host threads
 namespace {
@@ -497,7 +572,59 @@ int splitk_factor(int64_t m, int64_t n, int64_t k) {
 }
 }  // namespace
 
-size_t gemm_splitk_bytes(int64_t m, int64_t n, int64_t k, size_t elem) {
+namespace {
+// the skinny product for op(A) = A, at most 16 columns, and enough rows and K to matter
+bool skinny(int op, int64_t m, int64_t n, int64_t k) {
+    return op == GEMM_N && n <= kSkinnyMaxN && m >= 1024 && k >= 1024;
+}
+// K split of the skinny product: about four workgroups per compute unit; K-ranges that are
+// whole tiles of 32 (all but the last)
+void skinny_split(int64_t m, int64_t k, int &S, int64_t &kchunk) {
+    const int64_t nrb = (m + kSkinnyRows - 1) / kSkinnyRows;
+    S = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + nrb - 1) / nrb, k / 256));
+    kchunk = ((k + S - 1) / S + kSkinnyKT - 1) / kSkinnyKT * kSkinnyKT;
+    S = (int)((k + kchunk - 1) / kchunk);
+}
+template <typename T, int NB>
+void launch_skinny_nb(int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A,
+                      int64_t lda, const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C,
+                      int64_t ldc, hipStream_t s) {
+    int S;
+    int64_t kchunk;
+    skinny_split(m, k, S, kchunk);
+    cpx<T> *W = nullptr;
+    if (S > 1) {
+        W = (cpx<T> *)splitk_ws((size_t)S * m * n * sizeof(cpx<T>), s);
+        if (!W) { S = 1; kchunk = k; }
+    }
+    const int64_t nrb = (m + kSkinnyRows - 1) / kSkinnyRows;
+    hipLaunchKernelGGL((k_zgemm_skinny<T, NB>), dim3((unsigned)(nrb * S)), dim3(kSkinnyRows), 0,
+                       s, m, (int)n, k, kchunk, alpha, A, lda, B, ldb, beta, C, ldc,
+                       S > 1 ? W : nullptr);
+    if (S > 1) {
+        const int64_t t = m * n;
+        hipLaunchKernelGGL(k_splitk_reduce<T>, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s,
+                           m, n, S, (const cpx<T> *)W, alpha, beta, C, ldc);
+    }
+}
+template <typename T>
+void launch_skinny(int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A, int64_t lda,
+                   const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc,
+                   hipStream_t s) {
+    if (n <= 4) launch_skinny_nb<T, 4>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    else if (n <= 8) launch_skinny_nb<T, 8>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    else launch_skinny_nb<T, 16>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);
+}
+}  // namespace
+
+size_t gemm_splitk_bytes(int op, int64_t m, int64_t n, int64_t k, size_t elem) {
+    if (m <= 0 || n <= 0) return 0;
+    if (skinny(op, m, n, k)) {
+        int S;
+        int64_t kchunk;
+        skinny_split(m, k, S, kchunk);
+        return S > 1 ? (size_t)S * (size_t)m * (size_t)n * elem : 0;
+    }
     int S = splitk_factor(m, n, k);
     if (S <= 1) return 0;
     const int64_t kchunk = ((k + S - 1) / S + 15) / 16 * 16;
@@ -510,6 +637,11 @@ template <typename T>
 void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A, int64_t lda,
           const cpx<T> *B, int64_t ldb, cpx<T> beta, cpx<T> *C, int64_t ldc, hipStream_t s) {
     if (m <= 0 || n <= 0) return;
+    if (skinny(op, m, n, k)) {
+        // bound by HBM, not counted with the matrix-core products
+        launch_skinny<T>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);
+        return;
+    }
     // K is split when the output has too few 64 x 64 tiles to fill 256 CUs
     const int S = splitk_factor(m, n, k);
     const int v = tuned_variant<T>(op, m, n, k, S, alpha, A, lda, B, ldb, s);

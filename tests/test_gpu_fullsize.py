@@ -98,3 +98,29 @@ def test_ellipse4096_against_oracle():
 
 def test_perturbed16384_against_oracle():
     _check_case("perturbed16384", 1e-5, 1e-6)
+
+
+def test_few_right_hand_sides_match_a_full_batch():
+    """Batches of at most 16 right-hand sides go through the memory-bound product (A streamed
+    once, no matrix-core tile); the same columns solved inside a batch of 64 (matrix-core
+    GEMMs) agree to rounding, FP64 and mixed precision, and against the oracle."""
+    w = W.get("ellipse4096")
+    g = _golden("ellipse4096")
+    ang64 = w.angles[:64]
+    for prec, eps, tol in ((P.CFIE_FP64, 1e-10, 1e-12), (P.CFIE_MIXED, 1e-3, 1e-7)):
+        s = P.Solver(precision=prec, compress_tol=eps, block=256, refine_tol=1e-10)
+        s.assemble(w.zhat, w.n_nodes, w.k).factor()
+        assert s.info()["rank"] >= 1024
+        X64 = s.solve(s.plane_wave_rhs(ang64)).cpu().numpy().T
+        for m in (1, 5, 16):
+            Xm = s.solve(s.plane_wave_rhs(ang64[:m])).cpu().numpy().T
+            d = _rel_err(Xm, X64[:, :m])
+            print(f"precision {prec}: {m} right-hand sides vs the batch of 64: {d:.2e}")
+            assert d <= tol
+        cols = g["cols_rhs"]
+        Xo = s.solve(s.plane_wave_rhs(w.angles[cols])).cpu().numpy().T
+        e = _rel_err(Xo, g["x"])
+        print(f"precision {prec}: {len(cols)} right-hand sides vs the oracle: {e:.2e}")
+        assert e <= (1e-10 if prec == P.CFIE_FP64 else 1e-8)
+        del s
+        torch.cuda.empty_cache()

@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2203_13283_amd")
 
 
-@pytest.mark.parametrize("N", [512, 600])
+@pytest.mark.parametrize("N", [512, 600, 2048])
 def test_graph_replays_equal_direct_solves(N):
     zh = W.ellipse_coeffs(1.0, 0.6)
     k = 2 * np.pi * N / (10 * 5.1054)
