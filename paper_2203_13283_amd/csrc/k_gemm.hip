@@ -301,9 +301,13 @@ __global__ void k_splitk_reduce(int64_t m, int64_t n, int S, const cpx<T> *__res
 // so it is bound by memory, and a 64 x 64 matrix-core tile would spend its time on columns
 // that do not exist.  A workgroup of 256 threads takes 256 rows of A (one per thread, the
 // loads of a wavefront contiguous) and a range of K; the range's rows of B pass through LDS in
-// tiles of 32 and every thread forms NB complex dot products in registers, k in increasing
-// order.  Ranges of K are summed by the split-K reduction in a fixed order.
-constexpr int kSkinnyMaxN = 16, kSkinnyRows = 256, kSkinnyKT = 32;
+// tiles and every thread forms NB complex dot products in registers, k in increasing order.
+// Ranges of K are summed by the split-K reduction in a fixed order.
+constexpr int kSkinnyMaxN = 16, kSkinnyRows = 256;
+
+// K-tiles of KT rows of B, loads of A issued LB at a time: 32 and 8 for up to 8 columns, 64
+// and 16 for up to 16 (measured at N = 16384)
+template <int NB> struct SkinnyTile { static constexpr int KT = NB <= 8 ? 32 : 64, LB = NB <= 8 ? 8 : 16; };
 
 template <typename T, int NB>
 __global__ __launch_bounds__(256, 2) void k_zgemm_skinny(int64_t m, int n, int64_t k,
@@ -312,6 +316,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_skinny(int64_t m, int n, int64
                                                       const cpx<T> *__restrict__ B, int64_t ldb,
                                                       cpx<T> beta, cpx<T> *C, int64_t ldc,
                                                       cpx<T> *W) {
+    constexpr int kSkinnyKT = SkinnyTile<NB>::KT, kSkinnyLB = SkinnyTile<NB>::LB;
     __shared__ cpx<T> Bs[kSkinnyKT][NB];
     const int tid = threadIdx.x;
     const int64_t nrb = (m + kSkinnyRows - 1) / kSkinnyRows;
@@ -332,12 +337,12 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_skinny(int64_t m, int n, int64
         __syncthreads();
         const cpx<T> *a0 = A + rowc + k0 * lda;
         if (kt == kSkinnyKT) {
-            for (int k8 = 0; k8 < kSkinnyKT; k8 += 8) {
-                cpx<T> a[8];
+            for (int k8 = 0; k8 < kSkinnyKT; k8 += kSkinnyLB) {
+                cpx<T> a[kSkinnyLB];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) a[u] = a0[(int64_t)(k8 + u) * lda];
+                for (int u = 0; u < kSkinnyLB; ++u) a[u] = a0[(int64_t)(k8 + u) * lda];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < kSkinnyLB; ++u)
 #pragma unroll
                     for (int j = 0; j < NB; ++j) acc[j] = acc[j] + a[u] * Bs[k8 + u][j];
             }
@@ -579,10 +584,11 @@ bool skinny(int op, int64_t m, int64_t n, int64_t k) {
 }
 // K split of the skinny product: about four workgroups per compute unit; K-ranges that are
 // whole tiles of 32 (all but the last)
-void skinny_split(int64_t m, int64_t k, int &S, int64_t &kchunk) {
+void skinny_split(int64_t m, int64_t n, int64_t k, int &S, int64_t &kchunk) {
+    const int kt = n <= 4 ? SkinnyTile<4>::KT : n <= 8 ? SkinnyTile<8>::KT : SkinnyTile<16>::KT;
     const int64_t nrb = (m + kSkinnyRows - 1) / kSkinnyRows;
     S = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + nrb - 1) / nrb, k / 256));
-    kchunk = ((k + S - 1) / S + kSkinnyKT - 1) / kSkinnyKT * kSkinnyKT;
+    kchunk = ((k + S - 1) / S + kt - 1) / kt * kt;
     S = (int)((k + kchunk - 1) / kchunk);
 }
 template <typename T, int NB>
@@ -591,7 +597,7 @@ void launch_skinny_nb(int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T
                       int64_t ldc, hipStream_t s) {
     int S;
     int64_t kchunk;
-    skinny_split(m, k, S, kchunk);
+    skinny_split(m, n, k, S, kchunk);
     cpx<T> *W = nullptr;
     if (S > 1) {
         W = (cpx<T> *)splitk_ws((size_t)S * m * n * sizeof(cpx<T>), s);
@@ -622,7 +628,7 @@ size_t gemm_splitk_bytes(int op, int64_t m, int64_t n, int64_t k, size_t elem) {
     if (skinny(op, m, n, k)) {
         int S;
         int64_t kchunk;
-        skinny_split(m, k, S, kchunk);
+        skinny_split(m, n, k, S, kchunk);
         return S > 1 ? (size_t)S * (size_t)m * (size_t)n * elem : 0;
     }
     int S = splitk_factor(m, n, k);
