@@ -313,6 +313,25 @@ def test_state_machine_and_errors(cfg1):
     assert e.value.status == 2
 
 
+def test_empty_batches(cfg1, cfg1_solver):
+    """Zero right-hand sides, zero observation directions: every entry point returns at once
+    with an empty result and leaves the context usable."""
+    w, prob = cfg1
+    s = cfg1_solver
+    s.factor()
+    N = w.n_nodes
+    E = torch.zeros((0, N), dtype=torch.complex128, device="cuda")
+    assert s.plane_wave_rhs([]).shape == (0, N)
+    assert s.solve(E).shape == (0, N)
+    assert s.solve_adjoint(E).shape == (0, N)
+    assert s.apply(P.OP_C, E).shape == (0, N)
+    assert s.far_field(E, [0.1, 0.2]).shape == (0, 2)
+    B = s.plane_wave_rhs(w.angles[:2])
+    X = s.solve(B)
+    assert s.far_field(X, []).shape == (2, 0)
+    assert S.rel_err(_np(X).T, prob.solve(prob.rhs(w.angles[:2]))) <= 1e-10
+
+
 def test_skeleton_approximates_remainder(cfg1):
     """U V^T approximates C - C_c to the compression tolerance (Sec. V eq. (7))."""
     w, _ = cfg1
