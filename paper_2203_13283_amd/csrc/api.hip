@@ -122,6 +122,9 @@ struct cfie_ctx {
     cfie_options opt;
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream for the equivalent circle's first row (assembled beside the contour's)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Profiler prof;
     int64_t prof_n[PROF_KINDS] = {0, 0, 0, 0, 0};
     double prof_work[PROF_KINDS] = {0, 0, 0, 0, 0};
@@ -196,6 +199,12 @@ struct cfie_ctx {
         for (auto &kv : live) (void)hipFreeAsync(kv.first, stream);
         live.clear();
         (void)hipStreamSynchronize(stream);
+        if (aux) {
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamDestroy(aux);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         if (stream_owned && stream) (void)hipStreamDestroy(stream);
     }
     bool stream_owned = false;
@@ -1398,14 +1407,9 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         p.r1 = N;
         p.ld = N;
         for (int i = 0; i < 4; ++i) p.out[i] = c->mat[i];
-        zd *band_ws = c->alloc_n<zd>(far_band_ws_elems(p));
-        p.ws = band_ws;
-        launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
-        zd *near_ws = c->alloc_n<zd>(near_ws_elems(p));
-        p.ws = near_ws;
-        launch_assemble_near(p, c->pn, c->xn.data(), c->wn.data(), c->d_mom, s);
-        c->check_launch();
-        // first row of each matrix on the circle -> eigenvalues (Sec. V)
+        // first row of each matrix on the circle -> eigenvalues (Sec. V).  A single row
+        // leaves most lanes of the assembly kernels idle and is bound by their latency, so it
+        // runs on a second stream beside the contour's assembly, with workspaces of its own
         c->crow = c->alloc_n<zd>((size_t)4 * N);
         c->mu = c->alloc_n<zd>((size_t)4 * N);
         AsmParams pc = p;
@@ -1413,15 +1417,47 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         pc.r1 = 1;
         pc.ld = 1;
         for (int i = 0; i < 4; ++i) pc.out[i] = c->crow + (size_t)i * N;
-        pc.ws = band_ws;
-        launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), s);
+        setup_fft(c);                 // twiddle tables, used by the circle row's DFT below
+        zd *band_ws_c = c->alloc_n<zd>(far_band_ws_elems(pc));
+        zd *near_ws_c = c->alloc_n<zd>(near_ws_elems(pc));
+        if (!c->aux) {
+            HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        }
+        // if anything below throws, the circle's kernels finish before its buffers can be
+        // freed and reused in the context stream's order
+        struct AuxJoin {
+            hipStream_t aux;
+            bool joined = false;
+            ~AuxJoin() {
+                if (!joined) (void)hipStreamSynchronize(aux);
+            }
+        } aux_join{c->aux};
+        HIPCHK(hipEventRecord(c->ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+        pc.ws = band_ws_c;
+        launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), c->aux);
+        pc.ws = near_ws_c;
+        launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, c->aux);
+        // rows of symmetric circulants equal their first columns: their DFTs are the
+        // eigenvalues of the four circulants
+        launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, c->aux);
+        HIPCHK(hipEventRecord(c->ev_join, c->aux));
+        // the contour's matrices
+        zd *band_ws = c->alloc_n<zd>(far_band_ws_elems(p));
+        p.ws = band_ws;
+        launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
+        zd *near_ws = c->alloc_n<zd>(near_ws_elems(p));
+        p.ws = near_ws;
+        launch_assemble_near(p, c->pn, c->xn.data(), c->wn.data(), c->d_mom, s);
+        c->check_launch();
+        HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
+        aux_join.joined = true;
         c->dfree(band_ws);
-        pc.ws = near_ws;
-        launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, s);
         c->dfree(near_ws);
-        setup_fft(c);
-        // rows of symmetric circulants equal their first columns
-        launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, s);
+        c->dfree(band_ws_c);
+        c->dfree(near_ws_c);
         c->cvals = c->alloc_n<zd>(N);
         const int M = c->fft.M;
         c->dC = c->alloc_n<zd>(M); c->dCH = c->alloc_n<zd>(M); c->dCinv = c->alloc_n<zd>(M);
