@@ -377,32 +377,60 @@ template void launch_circ_apply_padded<double>(const FFTPlan &, const zd *, zd *
 template void launch_circ_apply_padded<float>(const FFTPlan &, const zf *, zf *, int64_t,
                                               int64_t, zf *, hipStream_t);
 
-// DFT by direct summation: y_m = scale sum_p x_p w^{m p} with w = tw[1] (tw: the n-th roots
-// of unity, e^{-2 pi i j / n}), conjugated for inverse; the table index advances by m
-// modulo n without division
-__global__ void k_dft_direct(int n, const zd *__restrict__ x, int64_t ldx, zd *y, int64_t ldy,
-                             const zd *__restrict__ tw, bool inverse, double scale) {
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
-    int c = blockIdx.y;
-    if (m >= n) return;
-    const zd *xc = x + (int64_t)c * ldx;
-    zd acc = mk(0.0, 0.0);
-    int idx = 0;
-    for (int q = 0; q < n; ++q) {
-        zd w = tw[idx];
-        if (inverse) w.y = -w.y;
-        acc = acc + xc[q] * w;
-        idx += m;
-        if (idx >= n) idx -= n;
+// DFT by direct summation: y_m = scale sum_q x_q w^{m q} with w = tw[1] (tw: the n-th roots
+// of unity, e^{-2 pi i j / n}), conjugated for inverse.  One wavefront per output m (so that
+// a transform of a few thousand points still spreads over the whole device): lane l sums the
+// terms q = l, l + 64, ..., its table index advancing by 64 m modulo n without division, for
+// up to four columns at once (one table read serves them all); the 64 partial sums are
+// combined by a butterfly, the same order on every run.
+constexpr int kDftCols = 4;
+__global__ __launch_bounds__(256) void k_dft_direct(int n, int ncol, const zd *__restrict__ x,
+                                                    int64_t ldx, zd *y, int64_t ldy,
+                                                    const zd *__restrict__ tw, bool inverse,
+                                                    double scale) {
+    const int lane = threadIdx.x & 63;
+    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= n) return;                          // whole wavefronts only; no block barrier
+    const int step = (int)((64 * m) % n);
+    const int idx0 = (int)(((int64_t)lane * m) % n);
+    for (int c0 = 0; c0 < ncol; c0 += kDftCols) {
+        const int nc = min(kDftCols, ncol - c0);
+        zd acc[kDftCols];
+#pragma unroll
+        for (int c = 0; c < kDftCols; ++c) acc[c] = mk(0.0, 0.0);
+        int idx = idx0;
+        for (int q = lane; q < n; q += 64) {
+            zd w = tw[idx];
+            if (inverse) w.y = -w.y;
+#pragma unroll
+            for (int c = 0; c < kDftCols; ++c)
+                if (c < nc) acc[c] = acc[c] + x[q + (int64_t)(c0 + c) * ldx] * w;
+            idx += step;
+            if (idx >= n) idx -= n;
+        }
+#pragma unroll
+        for (int c = 0; c < kDftCols; ++c) {
+            double re = acc[c].x, im = acc[c].y;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                re += __shfl_xor(re, o, 64);
+                im += __shfl_xor(im, o, 64);
+            }
+            if (lane == 0 && c < nc) y[m + (int64_t)(c0 + c) * ldy] = mk(re * scale, im * scale);
+        }
     }
-    y[m + (int64_t)c * ldy] = acc * scale;
+}
+
+void launch_dft(int n, int ncol, const zd *x, int64_t ldx, zd *y, int64_t ldy, const zd *tw,
+                bool inverse, double scale, hipStream_t s) {
+    if (n <= 0 || ncol <= 0) return;
+    hipLaunchKernelGGL(k_dft_direct, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, ncol, x,
+                       ldx, y, ldy, tw, inverse, scale);
 }
 
 void launch_dft_direct_tw(int N, const zd *x, int64_t ldx, zd *y, int64_t ldy, int ncol,
                           const zd *twN, hipStream_t s) {
-    int bs = 256;
-    hipLaunchKernelGGL(k_dft_direct, dim3((N + bs - 1) / bs, ncol), dim3(bs), 0, s, N, x, ldx, y,
-                       ldy, twN, false, 1.0);
+    launch_dft(N, ncol, x, ldx, y, ldy, twN, false, 1.0, s);
 }
 
 // kappa of length N (first column) -> wrapped kernel of length M: [0, N) and [M - N + 1, M)
@@ -428,13 +456,10 @@ void launch_padded_diagonal(const FFTPlan &p, const zd *eig_over_N, zd *work, zd
     // work: 3 M entries (kappa, wrapped kernel, its transform)
     const int bs = 256;
     zd *kap = work, *wrp = work + p.M, *hat = work + 2 * (size_t)p.M;
-    hipLaunchKernelGGL(k_dft_direct, dim3((p.N + bs - 1) / bs, 1), dim3(bs), 0, s, p.N,
-                       eig_over_N, (int64_t)p.N, kap, (int64_t)p.N, (const zd *)p.twN, true, 1.0);
+    launch_dft(p.N, 1, eig_over_N, p.N, kap, p.N, (const zd *)p.twN, true, 1.0, s);
     hipLaunchKernelGGL(k_wrap, dim3((p.M + bs - 1) / bs), dim3(bs), 0, s, p.N, p.M,
                        (const zd *)kap, wrp);
-    hipLaunchKernelGGL(k_dft_direct, dim3((p.M + bs - 1) / bs, 1), dim3(bs), 0, s, p.M,
-                       (const zd *)wrp, (int64_t)p.M, hat, (int64_t)p.M, (const zd *)p.twM, false,
-                       1.0 / p.M);
+    launch_dft(p.M, 1, wrp, p.M, hat, p.M, (const zd *)p.twM, false, 1.0 / p.M, s);
     hipLaunchKernelGGL(k_diag_transpose, dim3((p.M + bs - 1) / bs), dim3(bs), 0, s, p.M, p.N1,
                        p.N2, (const zd *)hat, dT, fT);
 }
