@@ -55,6 +55,9 @@ def parse():
                          "shapegrad8192, whose remainder has full rank at 1e-10)")
     ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=True,
                     help="GEMM tile autotuner (bitwise-neutral; on by default)")
+    ap.add_argument("--grouped", action=argparse.BooleanOptionalAction, default=False,
+                    help="batch64: every problem's solve in one recorded launch "
+                         "(cfie_solve_batch_grouped) after all are factored")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, copy a MIB-mebibyte device buffer once (a kernel of "
                          "known HBM traffic, the reference for hardware byte counters)")
@@ -186,7 +189,8 @@ def batch_main(a):
     for _ in range(a.steps):
         t0 = time.perf_counter()
         sols, res = P.solve_batch(probs, precision=prec, compress_tol=eps, block=128,
-                                  refine_tol=1e-8, n_streams=4)
+                                  refine_tol=1e-8, n_streams=4, grouped=a.grouped,
+                                  sweeps=2)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     med = sorted(times)[len(times) // 2]
@@ -215,7 +219,8 @@ def batch_main(a):
                                "waves, 10 nodes/wavelength",
                    "problems": len(probs), "N_min": min(Ns), "N_max": max(Ns),
                    "nrhs_total": nrhs, "compress_tol": eps, "streams": 4,
-                   "precision": a.precision, "gemm_autotune": bool(a.autotune)},
+                   "precision": a.precision, "gemm_autotune": bool(a.autotune),
+                   "grouped_solve": bool(a.grouped)},
         "problems_per_s": len(probs) / med,
         "rel_residual_sampled": worst,
         "max_rank": max(r["rank"] for r in res),

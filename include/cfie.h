@@ -289,6 +289,39 @@ typedef struct {
 cfie_status cfie_solve_batch(const cfie_options *opt, int device, int n_streams,
                              cfie_batch_item *items, int64_t n_items);
 
+/* Step A6 (+ A7) of eq. (9) (Sec. V) for many factored problems in one recorded launch: the
+ * solves of the n contexts ctxs[i] (X_i = C_i^-1 B_i, nrhs[i] columns, device complex128
+ * N_i x nrhs[i] column-major with leading dimensions ldb[i], ldx[i] >= N_i; B == X allowed)
+ * are recorded as one HIP graph, one independent branch per context between a fork and a
+ * join (each branch with buffers of its own, allocated before recording and released before
+ * the call returns), and launched once on a stream the call creates.  An FP64 context's
+ * branch is its Woodbury solve (circulant inverse by FFT, the two products), bitwise equal to
+ * cfie_solve; a mixed-precision context's branch holds `sweeps` refinement sweeps (complex64
+ * Woodbury solve of the residual, FP64 residual against the assembled operator) -- the same
+ * arithmetic as cfie_solve, so equal to it when cfie_solve takes that many sweeps -- after
+ * which contexts above refine_tol continue sweeping directly, up to max_refine in all
+ * (cfie_query reports the sweeps and residual of each).  The members' own streams are
+ * synchronised before recording and the call returns when every solve has completed.
+ * Contexts must be distinct, factored and on one device; members with nrhs[i] == 0 are
+ * skipped.  Errors: EINVAL for n < 0, NULL arrays, a NULL or repeated context, contexts on
+ * different devices, sweeps < 1, nrhs[i] < 0 or > 4096, NULL B or X, leading dimension < N;
+ * ESTATE before cfie_factor (message on that context); ENOCONV if some mixed member
+ * did not reach refine_tol (its X holds the last iterate); EHIP/ENOMEM otherwise (message on
+ * ctxs[0] unless it names another context). */
+cfie_status cfie_solve_group(cfie_ctx *const *ctxs, int64_t n, const void *const *B_dev,
+                             const int64_t *ldb, void *const *X_dev, const int64_t *ldx,
+                             const int64_t *nrhs, int32_t sweeps);
+
+/* cfie_solve_batch with every solve in one recorded launch: each item is assembled, factored
+ * and given its plane-wave right-hand sides (in X_dev) as in cfie_solve_batch, its context
+ * kept; then the solves of all items run through cfie_solve_group (in place, `sweeps`
+ * recorded refinement sweeps for mixed precision) and the contexts are released.  All items'
+ * contexts are alive together, so device memory holds every problem's matrices at once.
+ * t_ms covers each item's path up to its right-hand sides.  Errors as for cfie_solve_batch,
+ * and EINVAL for sweeps < 1 or an item with nrhs > 4096. */
+cfie_status cfie_solve_batch_grouped(const cfie_options *opt, int device, int n_streams,
+                                     cfie_batch_item *items, int64_t n_items, int32_t sweeps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW,
                    OP_REMAINDER, OP_SKELETON, REMAINDER_AUTO, REMAINDER_DENSE,
                    REMAINDER_FACTORED)
 
-__all__ = ["Solver", "solve_batch", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
+__all__ = ["Solver", "solve_batch", "solve_group", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
            "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
            "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library", "REMAINDER_AUTO", "REMAINDER_FACTORED",
            "REMAINDER_DENSE",
@@ -295,15 +295,47 @@ def far_field_of_shape(zhat_ri, n_nodes: int, k: float, inc_angles, obs_angles, 
     return _FarFieldOfShape.get().apply(zhat_ri, n_nodes, k, inc_angles, obs_angles, options)
 
 
+def solve_group(solvers, rhs, sweeps: int = 2, out=None):
+    """X_i = C_i^-1 B_i for many factored solvers in one recorded launch (cfie_solve_group).
+
+    solvers: distinct factored Solver objects on one device; rhs: one (m_i, N_i) complex128
+    CUDA tensor per solver (m_i <= 4096); sweeps: refinement sweeps recorded for
+    mixed-precision solvers.  Returns the list of solutions (out, if given, in place)."""
+    torch = _torch()
+    lib = _lib.load()
+    n = len(solvers)
+    if len(rhs) != n or (out is not None and len(out) != n):
+        raise ValueError("one right-hand-side batch (and output) per solver")
+    outs = []
+    for i, (s, B) in enumerate(zip(solvers, rhs)):
+        Solver._check_batch(B, s.N, "B")
+        X = out[i] if out is not None else s._batch(B.shape[0])
+        Solver._check_batch(X, s.N, "X")
+        outs.append(X)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    hs = (vp * n)(*[s._h.value for s in solvers])
+    bs = (vp * n)(*[B.data_ptr() if B.numel() else None for B in rhs])
+    xs = (vp * n)(*[X.data_ptr() if X.numel() else None for X in outs])
+    lds = (i64 * n)(*[s.N for s in solvers])
+    ms = (i64 * n)(*[B.shape[0] for B in rhs])
+    st = lib.cfie_solve_group(hs, n, bs, lds, xs, lds, ms, int(sweeps))
+    if st != 0:
+        msg = lib.cfie_last_error(solvers[0]._h).decode() if n else ""
+        raise CfieError(st, "cfie_solve_group", msg)
+    return outs
+
+
 def solve_batch(problems, precision: int = CFIE_FP64, compress_tol: float = 1e-10,
                 block: int = 128, refine_tol: float = 1e-8, n_streams: int = 4,
-                device: int = 0, **options):
+                device: int = 0, grouped: bool = False, sweeps: int = 2, **options):
     """Solve independent problems concurrently (cfie_solve_batch).
 
     problems: sequence of dicts with keys zhat (Fourier coefficients of the contour), n_nodes,
     k and angles (plane-wave directions).  Returns (solutions, results): solutions[i] is a
     (len(angles), n_nodes) complex128 CUDA tensor, results[i] a dict with status, rank,
-    refine_residual and t_ms.  The whole path of every problem runs in the library."""
+    refine_residual and t_ms.  The whole path of every problem runs in the library.
+    grouped: the solves of all problems run in one recorded launch after every problem is
+    factored (cfie_solve_batch_grouped, `sweeps` recorded refinement sweeps)."""
     torch = _torch()
     lib = _lib.load()
     o = _lib.default_options()
@@ -334,11 +366,16 @@ def solve_batch(problems, precision: int = CFIE_FP64, compress_tol: float = 1e-1
         it.nrhs = ang.size
         it.X_dev = X.data_ptr() if ang.size else None
     torch.cuda.synchronize(device)
-    st = lib.cfie_solve_batch(ctypes.byref(o), device, n_streams, items, n)
+    if grouped:
+        st = lib.cfie_solve_batch_grouped(ctypes.byref(o), device, n_streams, items, n,
+                                          int(sweeps))
+    else:
+        st = lib.cfie_solve_batch(ctypes.byref(o), device, n_streams, items, n)
     results = [dict(status=items[i].status, rank=items[i].rank,
                     refine_residual=items[i].refine_residual, t_ms=items[i].t_ms)
                for i in range(n)]
     if st != 0:
         bad = [i for i in range(n) if results[i]["status"] not in (0, 100)]
-        raise CfieError(st, "cfie_solve_batch", f"items {bad} failed")
+        raise CfieError(st, "cfie_solve_batch" + ("_grouped" if grouped else ""),
+                        f"items {bad} failed")
     return sols, results

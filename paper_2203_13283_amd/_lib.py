@@ -30,7 +30,8 @@ EXPORTED = [
     "cfie_plane_wave_rhs", "cfie_apply", "cfie_export_matrix", "cfie_query",
     "cfie_last_error", "cfie_status_string", "cfie_destroy", "cfie_profile_reset",
     "cfie_solve_batch", "cfie_solve_adjoint", "cfie_far_field", "cfie_shape_gradient",
-    "cfie_set_gemm_autotune", "cfie_gemm_tuned_classes",
+    "cfie_set_gemm_autotune", "cfie_gemm_tuned_classes", "cfie_solve_group",
+    "cfie_solve_batch_grouped",
 ]
 
 
@@ -122,6 +123,13 @@ def load(path: str = LIB_PATH):
     lib.cfie_solve_batch.argtypes = [ctypes.POINTER(Options), ctypes.c_int, ctypes.c_int,
                                      ctypes.POINTER(BatchItem), i64]
     lib.cfie_solve_batch.restype = i32
+    lib.cfie_solve_batch_grouped.argtypes = [ctypes.POINTER(Options), ctypes.c_int,
+                                             ctypes.c_int, ctypes.POINTER(BatchItem), i64, i32]
+    lib.cfie_solve_batch_grouped.restype = i32
+    i64p = ctypes.POINTER(i64)
+    lib.cfie_solve_group.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(vp), i64p,
+                                     ctypes.POINTER(vp), i64p, i64p, i32]
+    lib.cfie_solve_group.restype = i32
     dp = ctypes.POINTER(ctypes.c_double)
     lib.cfie_far_field.argtypes = [vp, vp, i64, i64, dp, i64, vp, i64]
     lib.cfie_far_field.restype = i32

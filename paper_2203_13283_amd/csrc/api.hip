@@ -101,6 +101,7 @@ constexpr int kLUBlock = 64;          // diagonal blocks inverted for the triang
 constexpr int kLUPanel = 16;          // columns per LU panel
 constexpr int kLUSuper = 256;         // columns per LU superpanel (inner dimension of the
                                       // trailing updates and of the triangular solves)
+constexpr int64_t kGroupMaxRhs = 4096;  // right-hand sides per member of a group solve
 
 struct HipError {
     cfie_status st;
@@ -1151,6 +1152,212 @@ cfie_status solve_mixed(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ld
     return CFIE_OK;
 }
 
+// ------------------------------------------------------ recorded solves of many problems ---
+// One member of a group solve: a factored context, its right-hand sides and the buffers its
+// recorded work runs on (allocated before recording on the context's stream, released when
+// the call ends).  The split-K partial products of the member's products get a buffer of
+// their own, since the members' branches of the graph run concurrently.
+struct GroupMember {
+    cfie_ctx *c = nullptr;
+    const zd *B = nullptr;
+    int64_t ldb = 0;
+    zd *X = nullptr;
+    int64_t ldx = 0;
+    int64_t m = 0;
+    zd *Xw = nullptr, *Z = nullptr, *P = nullptr, *Rb = nullptr, *Tt = nullptr, *W1 = nullptr,
+       *W2 = nullptr;
+    zf *R32 = nullptr, *Z32 = nullptr, *P32 = nullptr;
+    double *b2 = nullptr, *r2 = nullptr, *mx = nullptr;
+    void *W = nullptr;
+    size_t wbytes = 0;
+    hipStream_t own = nullptr;           // the context's stream, restored after recording
+    hipStream_t branch = nullptr;        // the member's branch while recording
+    hipEvent_t done = nullptr;
+    double rel = 0.0;
+    int sweeps = 0;
+    bool mixed() const { return c->opt.precision == CFIE_MIXED; }
+
+    void alloc() {
+        const int N = c->N, r = std::max(c->rank, 1);
+        const bool padded = c->fft.M != N;
+        size_t wb = 0;
+        auto need = [&](int64_t a, int64_t b, int64_t k, size_t e) {
+            wb = std::max(wb, gemm_splitk_bytes(GEMM_N, a, b, k, e));
+        };
+        Xw = c->alloc_n<zd>((size_t)N * m);
+        if (!mixed()) {
+            Z = c->alloc_n<zd>((size_t)r * m);
+            if (padded) P = c->alloc_n<zd>((size_t)c->fft.M * m);
+            need(c->rank, m, N, sizeof(zd));
+            need(N, m, c->rank, sizeof(zd));
+        } else {
+            Z32 = c->alloc_n<zf>((size_t)r * m);
+            if (padded) P32 = c->alloc_n<zf>((size_t)c->fft.M * m);
+            Rb = c->alloc_n<zd>((size_t)N * m);
+            Tt = c->alloc_n<zd>((size_t)N * m);
+            W1 = c->alloc_n<zd>((size_t)N * m);
+            W2 = c->alloc_n<zd>((size_t)N * m);
+            R32 = c->alloc_n<zf>((size_t)N * m);
+            b2 = c->alloc_n<double>(m);
+            r2 = c->alloc_n<double>(m);
+            mx = c->alloc_n<double>(2);
+            need(c->rank, m, N, sizeof(zf));
+            need(N, m, c->rank, sizeof(zf));
+            need(N, m, N, sizeof(zd));
+        }
+        if (wb) W = c->dalloc(wb);
+        wbytes = wb;
+    }
+    void release() {
+        void *bufs[] = {Xw, Z, P, Rb, Tt, W1, W2, R32, Z32, P32, b2, r2, mx, W};
+        for (void *p : bufs) c->dfree(p);
+        Xw = Z = P = Rb = Tt = W1 = W2 = nullptr;
+        R32 = Z32 = P32 = nullptr;
+        b2 = r2 = mx = nullptr;
+        W = nullptr;
+    }
+    // one refinement sweep, the arithmetic of the mixed-precision cfie_solve: a complex64
+    // Woodbury solve of the residual, the correction added in FP64, the new residual
+    // B - C X against the FP64 operator and max_j |r_j| / |b_j| into mx
+    void sweep(bool first) {
+        const int N = c->N;
+        hipStream_t s = c->stream;
+        convert<float, double>(N, m, Rb, N, R32, N, s);
+        woodbury<float>(c, R32, m, Z32, P32);
+        convert<double, float>(N, m, R32, N, Tt, N, s);
+        axpby<double>(N, m, cz<double>(1), Tt, N, cz<double>(first ? 0 : 1), Xw, N, s);
+        apply_C<double>(c, Xw, N, Rb, N, m, Tt, W1, W2);
+        axpby<double>(N, m, cz<double>(1), B, ldb, cz<double>(-1), Rb, N, s);
+        colnorm2<double>(N, m, Rb, N, r2, s);
+        launch_ratio_max(m, r2, b2, mx, s);
+        ++sweeps;
+    }
+    // the member's recorded work: FP64 -- the Woodbury solve, X written; mixed -- the first
+    // `nsweep` sweeps (X is written after the convergence check, since B may alias it)
+    void record(int nsweep) {
+        const int N = c->N;
+        hipStream_t s = c->stream;
+        if (!mixed()) {
+            axpby<double>(N, m, cz<double>(1), B, ldb, cz<double>(0), Xw, N, s);
+            woodbury<double>(c, Xw, m, Z, P);
+            axpby<double>(N, m, cz<double>(1), Xw, N, cz<double>(0), X, ldx, s);
+        } else {
+            colnorm2<double>(N, m, B, ldb, b2, s);
+            axpby<double>(N, m, cz<double>(1), B, ldb, cz<double>(0), Rb, N, s);
+            for (int k = 0; k < nsweep; ++k) sweep(k == 0);
+        }
+        c->check_launch();
+    }
+};
+
+// Records the members' solves as one graph (a branch per member between a fork and a join
+// on the stream cs) and launches it once on cs; then finishes the mixed-precision members
+// whose residual is above refine_tol with further sweeps, directly on their own streams.
+cfie_status solve_group(std::vector<GroupMember> &gm, int nsweep, hipStream_t cs) {
+    hipEvent_t fork = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool capturing = false;
+    Profiler *saved_prof = g_prof;
+    g_prof = nullptr;
+    auto restore = [&]() {
+        if (capturing) {
+            hipGraph_t g2 = nullptr;
+            (void)hipStreamEndCapture(cs, &g2);
+            if (g2) (void)hipGraphDestroy(g2);
+            capturing = false;
+        }
+        set_splitk_override(nullptr, 0);
+        for (auto &g : gm) {
+            if (g.own || g.branch) g.c->stream = g.own;
+        }
+        (void)hipStreamSynchronize(cs);
+        for (auto &g : gm) {
+            if (g.branch) (void)hipStreamDestroy(g.branch);
+            if (g.done) (void)hipEventDestroy(g.done);
+            g.branch = nullptr;
+            g.done = nullptr;
+            (void)hipStreamSynchronize(g.c->stream);
+            g.release();
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (fork) (void)hipEventDestroy(fork);
+        exec = nullptr;
+        graph = nullptr;
+        fork = nullptr;
+        g_prof = saved_prof;
+        (void)hipGetLastError();
+    };
+    try {
+        for (auto &g : gm) {
+            g.own = g.c->stream;
+            g.alloc();
+            HIPCHK(hipStreamCreateWithFlags(&g.branch, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&g.done, hipEventDisableTiming));
+        }
+        // inputs produced on the members' streams and the buffers above are ready
+        for (auto &g : gm) g.c->sync();
+        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        capturing = true;
+        HIPCHK(hipEventRecord(fork, cs));
+        for (auto &g : gm) {
+            HIPCHK(hipStreamWaitEvent(g.branch, fork, 0));
+            g.c->stream = g.branch;
+            set_splitk_override(g.W, g.wbytes);
+            g.record(nsweep);
+            set_splitk_override(nullptr, 0);
+            g.c->stream = g.own;
+            HIPCHK(hipEventRecord(g.done, g.branch));
+            HIPCHK(hipStreamWaitEvent(cs, g.done, 0));
+        }
+        capturing = false;
+        HIPCHK(hipStreamEndCapture(cs, &graph));
+        if (!graph) throw HipError{CFIE_EHIP, "recording of the group solve failed"};
+        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIPCHK(hipGraphLaunch(exec, cs));
+        HIPCHK(hipStreamSynchronize(cs));
+        // mixed-precision members: convergence check, further sweeps where needed, X
+        cfie_status st = CFIE_OK;
+        for (auto &g : gm) {
+            if (!g.mixed()) continue;
+            cfie_ctx *c = g.c;
+            const int N = c->N;
+            HIPCHK(hipMemcpy(&g.rel, g.mx, sizeof(double), hipMemcpyDeviceToHost));
+            set_splitk_override(g.W, g.wbytes);
+            while (g.rel > c->opt.refine_tol && g.sweeps < std::max(1, c->opt.max_refine)) {
+                g.sweep(false);
+                HIPCHK(hipMemcpyAsync(&g.rel, g.mx, sizeof(double), hipMemcpyDeviceToHost,
+                                      c->stream));
+                c->sync();
+            }
+            axpby<double>(N, g.m, cz<double>(1), g.Xw, N, cz<double>(0), g.X, g.ldx, c->stream);
+            c->check_launch();
+            set_splitk_override(nullptr, 0);
+            c->refine_sweeps = g.sweeps;
+            c->refine_res = g.rel;
+            if (g.rel > c->opt.refine_tol) {
+                fail(c, CFIE_ENOCONV, "refinement did not reach refine_tol");
+                st = CFIE_ENOCONV;
+            }
+        }
+        restore();
+        return st;
+    } catch (const HipError &e) {
+        restore();
+        if (!gm.empty()) gm[0].c->err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        restore();
+        return CFIE_ENOMEM;
+    } catch (const std::exception &e) {
+        restore();
+        if (!gm.empty()) gm[0].c->err = std::string("internal: ") + e.what();
+        return CFIE_EINVAL;
+    }
+}
+
 }  // namespace
 
 // ============================================================================ C ABI ======
@@ -1294,6 +1501,170 @@ cfie_status cfie_solve_batch(const cfie_options *opt, int device, int n_streams,
     std::vector<std::thread> th;
     for (int t = 0; t < ns; ++t) th.emplace_back(worker, t);
     for (auto &x : th) x.join();
+    for (int t = 0; t < ns; ++t) {
+        (void)hipStreamSynchronize(streams[(size_t)t]);
+        splitk_release(device, streams[(size_t)t]);
+        (void)hipStreamDestroy(streams[(size_t)t]);
+    }
+    cfie_status worst = CFIE_OK;
+    for (int64_t i = 0; i < n_items; ++i)
+        if (items[i].status != CFIE_OK && items[i].status < 100 && worst == CFIE_OK)
+            worst = (cfie_status)items[i].status;
+    return worst;
+}
+
+cfie_status cfie_solve_group(cfie_ctx *const *ctxs, int64_t n, const void *const *B_dev,
+                             const int64_t *ldb, void *const *X_dev, const int64_t *ldx,
+                             const int64_t *nrhs, int32_t sweeps) {
+    if (n < 0) return CFIE_EINVAL;
+    if (n == 0) return CFIE_OK;
+    if (!ctxs || !B_dev || !ldb || !X_dev || !ldx || !nrhs) return CFIE_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!ctxs[i]) return CFIE_EINVAL;
+    cfie_ctx *c0 = ctxs[0];
+    if (sweeps < 1) return fail(c0, CFIE_EINVAL, "sweeps must be >= 1");
+    std::vector<GroupMember> gm;
+    std::vector<cfie_ctx *> seen;
+    for (int64_t i = 0; i < n; ++i) {
+        cfie_ctx *c = ctxs[i];
+        if (c->device != c0->device) return fail(c0, CFIE_EINVAL, "contexts on different devices");
+        if (std::find(seen.begin(), seen.end(), c) != seen.end())
+            return fail(c0, CFIE_EINVAL, "a context appears twice");
+        seen.push_back(c);
+        if (c->state < 2) return fail(c, CFIE_ESTATE, "cfie_solve_group before cfie_factor");
+        if (nrhs[i] < 0) return fail(c, CFIE_EINVAL, "nrhs must be >= 0");
+        if (nrhs[i] > kGroupMaxRhs) return fail(c, CFIE_EINVAL, "nrhs must be <= 4096");
+        if (nrhs[i] == 0) continue;
+        if (!B_dev[i] || !X_dev[i]) return fail(c, CFIE_EINVAL, "NULL B or X");
+        if (ldb[i] < c->N || ldx[i] < c->N) return fail(c, CFIE_EINVAL, "leading dimension < N");
+        GroupMember g;
+        g.c = c;
+        g.B = (const zd *)B_dev[i];
+        g.ldb = ldb[i];
+        g.X = (zd *)X_dev[i];
+        g.ldx = ldx[i];
+        g.m = nrhs[i];
+        gm.push_back(g);
+    }
+    if (gm.empty()) return CFIE_OK;
+    if (hipSetDevice(c0->device) != hipSuccess) return fail(c0, CFIE_EHIP, "hipSetDevice failed");
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c0, CFIE_EHIP, "stream creation failed");
+    }
+    cfie_status st = solve_group(gm, sweeps, cs);
+    (void)hipStreamSynchronize(cs);
+    splitk_release(c0->device, cs);
+    (void)hipStreamDestroy(cs);
+    return st;
+}
+
+cfie_status cfie_solve_batch_grouped(const cfie_options *opt, int device, int n_streams,
+                                     cfie_batch_item *items, int64_t n_items, int32_t sweeps) {
+    if (n_items < 0 || n_streams < 1 || n_streams > 16 || (n_items > 0 && !items) || sweeps < 1)
+        return CFIE_EINVAL;
+    if (n_items == 0) return CFIE_OK;
+    for (int64_t i = 0; i < n_items; ++i)
+        if (items[i].nrhs > kGroupMaxRhs) return CFIE_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return CFIE_EHIP;
+    std::vector<int64_t> order((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
+    auto work = [&](int64_t i) {
+        double nn = (double)items[i].contour.n_nodes;
+        return nn * nn + nn * (double)std::max<int64_t>(items[i].nrhs, 0);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return work(a) > work(b); });
+    for (int64_t i = 0; i < n_items; ++i) {
+        items[i].status = CFIE_EINVAL;
+        items[i].rank = 0;
+        items[i].refine_residual = 0.0;
+        items[i].t_ms = 0.0;
+    }
+    const int ns = (int)std::min<int64_t>(n_streams, n_items);
+    std::vector<hipStream_t> streams((size_t)ns, nullptr);
+    for (int t = 0; t < ns; ++t) {
+        if (hipStreamCreateWithFlags(&streams[(size_t)t], hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int u = 0; u < t; ++u) (void)hipStreamDestroy(streams[(size_t)u]);
+            return CFIE_EHIP;
+        }
+    }
+    // every problem up to its right-hand sides (in X_dev), contexts kept for the group solve
+    std::vector<cfie_ctx *> ctx((size_t)n_items, nullptr);
+    std::atomic<int64_t> next{0};
+    auto worker = [&](int t) {
+        (void)hipSetDevice(device);
+        for (;;) {
+            const int64_t q = next.fetch_add(1);
+            if (q >= n_items) break;
+            const int64_t i = order[(size_t)q];
+            cfie_batch_item &it = items[i];
+            auto t0 = std::chrono::steady_clock::now();
+            cfie_ctx *c = nullptr;
+            cfie_status st = cfie_create(opt, device, streams[(size_t)t], &c);
+            if (st == CFIE_OK) {
+                st = cfie_assemble(c, &it.contour, it.k);
+                if (st == CFIE_OK || st >= 100) {
+                    cfie_status sf = cfie_factor(c);
+                    if (sf != CFIE_OK) st = sf;
+                }
+                if ((st == CFIE_OK || st >= 100) && it.nrhs > 0) {
+                    cfie_status sr = cfie_plane_wave_rhs(c, it.angles_host, it.nrhs, it.X_dev,
+                                                         it.contour.n_nodes);
+                    if (sr != CFIE_OK) st = sr;
+                }
+                if (st == CFIE_OK || st >= 100) {
+                    ctx[(size_t)i] = c;
+                } else {
+                    cfie_destroy(c);
+                }
+            }
+            it.status = st;
+            it.t_ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t0).count();
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 0; t < ns; ++t) th.emplace_back(worker, t);
+    for (auto &x : th) x.join();
+    // all solves in one recorded launch, in place
+    std::vector<cfie_ctx *> gc;
+    std::vector<const void *> gb;
+    std::vector<void *> gx;
+    std::vector<int64_t> gl, gn;
+    std::vector<int64_t> gi;
+    for (int64_t i = 0; i < n_items; ++i) {
+        if (!ctx[(size_t)i] || items[i].nrhs <= 0) continue;
+        gc.push_back(ctx[(size_t)i]);
+        gb.push_back(items[i].X_dev);
+        gx.push_back(items[i].X_dev);
+        gl.push_back(items[i].contour.n_nodes);
+        gn.push_back(items[i].nrhs);
+        gi.push_back(i);
+    }
+    cfie_status sg = cfie_solve_group(gc.data(), (int64_t)gc.size(), gb.data(), gl.data(),
+                                      gx.data(), gl.data(), gn.data(), sweeps);
+    for (size_t j = 0; j < gi.size(); ++j) {
+        cfie_batch_item &it = items[gi[j]];
+        cfie_ctx *c = gc[j];
+        if (sg != CFIE_OK && sg != CFIE_ENOCONV) {
+            it.status = sg;
+        } else if (c->opt.precision == CFIE_MIXED && !(c->refine_res <= c->opt.refine_tol)) {
+            it.status = CFIE_ENOCONV;
+        }
+    }
+    for (int64_t i = 0; i < n_items; ++i) {
+        cfie_ctx *c = ctx[(size_t)i];
+        if (!c) continue;
+        cfie_info inf;
+        if (cfie_query(c, &inf) == CFIE_OK) {
+            items[i].rank = inf.rank;
+            items[i].refine_residual = inf.refine_residual;
+        }
+        cfie_destroy(c);
+    }
     for (int t = 0; t < ns; ++t) {
         (void)hipStreamSynchronize(streams[(size_t)t]);
         splitk_release(device, streams[(size_t)t]);

@@ -1,0 +1,144 @@
+"""Solves of many factored problems in one recorded launch (cfie_solve_group and
+cfie_solve_batch_grouped; GPU tests through the C ABI).
+
+The recorded branch of a context runs the same kernels on the same shapes as cfie_solve, so
+an FP64 member must equal cfie_solve on the same context value for value, and a
+mixed-precision member must equal it too when the recorded sweeps plus the direct ones after
+the convergence check make the same sequence of sweeps as cfie_solve (which stops at the
+first sweep below refine_tol).  Sizes that are and are not powers of two (zero-padded
+circulant products), right-hand-side counts that take the small-batch product and the tiled
+one, in place and out of place, empty members, and the argument errors."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import system as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2203_13283_amd")
+
+
+@pytest.fixture(scope="module")
+def problems():
+    return W.batch_problems(count=4, seed=11, n_range=(200, 1100), rhs_range=(5, 40))
+
+
+def _factored(pr, **opt):
+    s = P.Solver(**opt)
+    s.assemble(pr["zhat"], pr["n_nodes"], pr["k"]).factor()
+    return s
+
+
+def _rel(a, b):
+    return float(((a - b).abs().pow(2).sum(1).sqrt() / b.abs().pow(2).sum(1).sqrt()).max())
+
+
+def test_group_fp64_equals_solve(problems):
+    opt = dict(compress_tol=1e-10, block=64)
+    solvers = [_factored(pr, **opt) for pr in problems]
+    rhs = [s.plane_wave_rhs(pr["angles"]) for s, pr in zip(solvers, problems)]
+    alone = [s.solve(B) for s, B in zip(solvers, rhs)]
+    outs = P.solve_group(solvers, rhs)
+    for pr, X, Xa, s in zip(problems, outs, alone, solvers):
+        print(f"N={pr['n_nodes']:4d} m={pr['angles'].size:3d} rank {s.info()['rank']}")
+        assert torch.equal(X, Xa)
+    # in place, twice in a row (fresh recording each call), the second with fewer columns
+    work = [B.clone() for B in rhs]
+    P.solve_group(solvers, work, out=work)
+    for X, Xa in zip(work, alone):
+        assert torch.equal(X, Xa)
+    half = [B[: max(1, B.shape[0] // 2)].contiguous() for B in rhs]
+    outs2 = P.solve_group(solvers, half)
+    for X, Xa in zip(outs2, alone):
+        assert torch.equal(X, Xa[: X.shape[0]])
+
+
+def test_group_against_oracle(problems):
+    pr = min(problems, key=lambda p: p["n_nodes"])
+    s = _factored(pr, compress_tol=1e-10, block=64)
+    (X,) = P.solve_group([s], [s.plane_wave_rhs(pr["angles"])])
+    prob = S.Problem(pr["zhat"], pr["n_nodes"], pr["k"])
+    err = S.rel_err(X.cpu().numpy().T, prob.solve(prob.rhs(pr["angles"])))
+    print(f"N={pr['n_nodes']}: rel.err vs oracle {err:.2e}")
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("recorded", [1, "same"])
+def test_group_mixed_equals_solve(problems, recorded):
+    opt = dict(precision=P.CFIE_MIXED, compress_tol=1e-3, refine_tol=1e-8, block=64)
+    solvers = [_factored(pr, **opt) for pr in problems[:3]]
+    rhs = [s.plane_wave_rhs(pr["angles"]) for s, pr in zip(solvers, problems)]
+    alone, sweeps = [], []
+    for s, B in zip(solvers, rhs):
+        alone.append(s.solve(B))
+        sweeps.append(s.info()["refine_sweeps"])
+    # one recorded sweep (the rest direct), or as many as the slowest member needs (members
+    # that need fewer then take extra sweeps: compared by residual, not by value)
+    k = 1 if recorded == 1 else max(sweeps)
+    outs = P.solve_group(solvers, rhs, sweeps=k)
+    for s, X, Xa, n in zip(solvers, outs, alone, sweeps):
+        inf = s.info()
+        print(f"N={s.N}: sweeps alone {n}, group {inf['refine_sweeps']}, "
+              f"residual {inf['refine_residual']:.1e}")
+        assert inf["refine_residual"] <= 1e-8
+        if k <= n:
+            assert inf["refine_sweeps"] == n
+            assert torch.equal(X, Xa)
+        else:
+            assert inf["refine_sweeps"] == k
+            assert _rel(X, Xa) <= 1e-6
+
+
+def test_group_empty_members_and_mixed_kinds(problems):
+    a = _factored(problems[0], compress_tol=1e-10, block=64)
+    b = _factored(problems[1], precision=P.CFIE_MIXED, compress_tol=1e-3, block=64)
+    Ba = a.plane_wave_rhs(problems[0]["angles"])
+    Bb = b.plane_wave_rhs(problems[1]["angles"])
+    empty = torch.empty((0, a.N), dtype=torch.complex128, device="cuda")
+    xa = a.solve(Ba)
+    xb = b.solve(Bb)
+    outs = P.solve_group([a, b], [Ba, Bb], sweeps=1)
+    assert torch.equal(outs[0], xa) and torch.equal(outs[1], xb)
+    outs = P.solve_group([a], [empty])
+    assert outs[0].shape == (0, a.N)
+    assert P.solve_group([], []) == []
+
+
+def test_group_argument_errors(problems):
+    pr = problems[0]
+    s = _factored(pr, compress_tol=1e-10, block=64)
+    B = s.plane_wave_rhs(pr["angles"])
+    with pytest.raises(P.CfieError, match="status 1"):
+        P.solve_group([s, s], [B, B])                  # the same context twice
+    with pytest.raises(P.CfieError, match="status 1"):
+        P.solve_group([s], [B], sweeps=0)
+    big = torch.zeros((4097, s.N), dtype=torch.complex128, device="cuda")
+    with pytest.raises(P.CfieError, match="status 1"):
+        P.solve_group([s], [big])
+    u = P.Solver(compress_tol=1e-10)
+    u.assemble(pr["zhat"], pr["n_nodes"], pr["k"])    # not factored
+    with pytest.raises(P.CfieError, match="status 4"):
+        P.solve_group([s, u], [B, B])
+    # the failed calls left the factored context usable
+    (X,) = P.solve_group([s], [B])
+    assert torch.equal(X, s.solve(B))
+
+
+def test_batch_grouped_equals_batch():
+    probs = W.batch_problems(count=6, seed=5, n_range=(128, 900), rhs_range=(3, 24))
+    opt = dict(compress_tol=1e-10, block=64)
+    ref, _ = P.solve_batch(probs, n_streams=3, **opt)
+    sols, res = P.solve_batch(probs, n_streams=3, grouped=True, **opt)
+    for pr, X, Xr, r in zip(probs, sols, ref, res):
+        assert r["status"] == 0
+        assert torch.equal(X, Xr)
+    mopt = dict(precision=P.CFIE_MIXED, compress_tol=1e-3, refine_tol=1e-8, block=64)
+    mref, mres = P.solve_batch(probs, n_streams=3, **mopt)
+    sols, res = P.solve_batch(probs, n_streams=3, grouped=True, sweeps=1, **mopt)
+    for X, Xr, r, rr in zip(sols, mref, res, mres):
+        assert r["status"] == 0 and r["refine_residual"] <= 1e-8
+        assert torch.equal(X, Xr) and r["refine_residual"] == rr["refine_residual"]
+    with pytest.raises(P.CfieError):
+        P.solve_batch(probs[:1], grouped=True, sweeps=0)
