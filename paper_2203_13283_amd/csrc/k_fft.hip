@@ -399,6 +399,7 @@ __global__ __launch_bounds__(256) void k_dft_direct(int n, int ncol, const zd *_
 #pragma unroll
         for (int c = 0; c < kDftCols; ++c) acc[c] = mk(0.0, 0.0);
         int idx = idx0;
+#pragma unroll 4
         for (int q = lane; q < n; q += 64) {
             zd w = tw[idx];
             if (inverse) w.y = -w.y;
