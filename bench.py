@@ -447,9 +447,6 @@ def main():
         out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
                            "unit": unit, "frac": achieved / peak,
                            "traffic": measured_traffic(dom, d["launches"] // a.steps)}
-        if dom.startswith("zgemm"):
-            # the 3M complex product executes 6 m n k of the 8 m n k counted above
-            out["roofline"]["mfma_pipe_frac"] = 0.75 * achieved / peak
     del last, s, B, X
     torch.cuda.empty_cache()
     if a.compare:

@@ -468,16 +468,18 @@ template <> struct Ops<float> {
 
 // Y = C X, C = (G/2 + Dkt) G^{-1} (G/2 - Dk) + Skt G^{-1} Nk   (eq. (6))
 // temps: T, W1, W2 (N x m each)
+// (x_real: X has zero imaginary parts, so its products with D^k and N^k are two real ones)
 template <typename T>
 void apply_C(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
-             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2) {
+             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, bool x_real = false) {
     const int N = c->N;
     const double h = c->hg.L / N;
     hipStream_t s = c->stream;
     const int nt = (int)c->gcoef.size();
-    gemm<T>(GEMM_N, N, m, N, cz<T>(1), Ops<T>::mat(c, 0), N, X, ldx, cz<T>(0), Tt, N, s);
+    const int opx = x_real ? GEMM_NREAL : GEMM_N;
+    gemm<T>(opx, N, m, N, cz<T>(1), Ops<T>::mat(c, 0), N, X, ldx, cz<T>(0), Tt, N, s);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0.5), X, ldx, cz<T>(-1), Tt, N, W1, N, m, s);
-    gemm<T>(GEMM_N, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, X, ldx, cz<T>(0), Tt, N, s);
+    gemm<T>(opx, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, X, ldx, cz<T>(0), Tt, N, s);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(1),
                       Tt, N, W2, N, m, s);
     launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), W1, N, Y, ldy, m, s);
@@ -489,9 +491,9 @@ void apply_C(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, 
 // Y = (C - C_c) X ; temps T, W1, W2, Z
 template <typename T>
 void apply_R(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
-             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z) {
+             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z, bool x_real = false) {
     const int N = c->N;
-    apply_C<T>(c, X, ldx, Y, ldy, m, Tt, W1, W2);
+    apply_C<T>(c, X, ldx, Y, ldy, m, Tt, W1, W2, x_real);
     axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, c->stream);
     circ_apply<T>(c, Ops<T>::dC(c), Z, N, m);
     axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, c->stream);
@@ -725,11 +727,11 @@ cfie_status factor_impl(cfie_ctx *c) {
     }
     while (ell < cap) {
         int bb = std::min(b, cap - ell);
-        randn<T>(N, bb, c->opt.seed, blk++, Om, N, s);
+        randn<T>(N, bb, c->opt.seed, blk++, Om, N, s);    // real Gaussian block
         if (Rd)
-            gemm<T>(GEMM_N, N, bb, N, cz<T>(1), Rd, N, Om, N, cz<T>(0), Y, N, s);
+            gemm<T>(GEMM_NREAL, N, bb, N, cz<T>(1), Rd, N, Om, N, cz<T>(0), Y, N, s);
         else
-            apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z);
+            apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z, true);
         if (ell > 0) {
             // block Gram-Schmidt against Q.  After one pass the kept directions deviate from
             // orthogonality to Q by about the unit roundoff times ||Y|| / tau (they are kept

@@ -196,8 +196,10 @@ void launch_padded_diagonal(const FFTPlan &p, const zd *eig_over_N, zd *work, zd
                             hipStream_t s);
 
 // complex GEMM: C = alpha * op(A) * B + beta * C, op(A) = A (GEMM_N), A^H (GEMM_C) or the
-// elementwise conjugate of A (GEMM_R)
-enum { GEMM_N = 0, GEMM_C = 1, GEMM_R = 2 };
+// elementwise conjugate of A (GEMM_R); GEMM_NREAL: op(A) = A and B real-valued (stored
+// complex, its imaginary parts taken as zero and not read), two real products instead of
+// the three of the 3M form
+enum { GEMM_N = 0, GEMM_C = 1, GEMM_R = 2, GEMM_NREAL = 3 };
 // release the split-K workspace of (device, stream)
 void splitk_release(int device, hipStream_t s);
 // process-wide switch of the GEMM tile autotuner (returns the previous mode) and the number

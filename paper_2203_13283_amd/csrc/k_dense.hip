@@ -282,7 +282,11 @@ template void conj_transpose<float>(bool, int64_t, int64_t, const zf *, int64_t,
 
 // ------------------------------------------------------------------ Gaussian sketch ------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter = (element index lo/hi,
-// stream, 0), key = seed.  Two 32-bit outputs make one uniform pair -> Box-Muller.
+// stream, 0), key = seed.  Its four 32-bit outputs make one pair of 53-bit uniforms ->
+// Box-Muller -> one real standard normal per element.  The test matrix of the sketch is
+// real: the range of a complex matrix is sampled as well by real Gaussian columns, and the
+// products with the assembled complex matrices then need two real products instead of the
+// three of the 3M form (GEMM_NREAL).
 __device__ __forceinline__ void philox_round(uint32_t &c0, uint32_t &c1, uint32_t &c2,
                                              uint32_t &c3, uint32_t k0, uint32_t k1) {
     const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
@@ -312,10 +316,8 @@ __global__ void k_randn(int64_t m, int64_t n, uint64_t seed, uint64_t stream, cp
     // 53-bit uniforms in (0, 1]
     double u1 = ((double)(((uint64_t)ctr[0] << 21) ^ (ctr[1] >> 11)) + 1.0) * (1.0 / 9007199254740993.0);
     double u2 = ((double)(((uint64_t)ctr[2] << 21) ^ (ctr[3] >> 11)) + 0.5) * (1.0 / 9007199254740992.0);
-    double r = sqrt(-log(u1));                        // |z|^2 ~ Exp(1): E|z|^2 = 1
-    double sn, cs;
-    sincospi(2.0 * u2, &sn, &cs);
-    X[i + c * ldx] = mk((T)(r * cs), (T)(r * sn));
+    double r = sqrt(-2.0 * log(u1));
+    X[i + c * ldx] = mk((T)(r * cospi(2.0 * u2)), (T)0);
 }
 template <typename T>
 void randn(int64_t m, int64_t n, uint64_t seed, uint64_t stream, cpx<T> *X, int64_t ldx,

@@ -58,6 +58,8 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
                                                cpx<T> beta, cpx<T> *C, int64_t ldc,
                                                cpx<T> *W) {
     constexpr bool CONJA = OPA == 1;
+    constexpr bool BREAL = OPA == 3;          // op(A) = A, B real (its imaginary parts unread)
+    constexpr bool P3 = G3 && !BREAL;         // the third product of the 3M form
     constexpr int BM = 32 * TI, BN = 32 * TJ;
     // LDS tiles split into real and imaginary parts.  The layout follows the order in which
     // the global loads arrive so that the stores are free of bank conflicts: A is [k][i]
@@ -101,15 +103,16 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
     const int64_t kbeg = zslice * kchunk;
     const int64_t kend = min(kdim, kbeg + kchunk);
 
-    // 4M: accr, acci are the real and imaginary parts; 3M: accr = P1, acci = P2, acc3 = P3
-    acc_t accr[TI][TJ], acci[TI][TJ], acc3[G3 ? TI : 1][G3 ? TJ : 1];
+    // 4M and real B: accr, acci are the real and imaginary parts; 3M: accr = P1, acci = P2,
+    // acc3 = P3
+    acc_t accr[TI][TJ], acci[TI][TJ], acc3[P3 ? TI : 1][P3 ? TJ : 1];
 #pragma unroll
     for (int a = 0; a < TI; ++a)
 #pragma unroll
         for (int b = 0; b < TJ; ++b) {
             accr[a][b] = acc_t{0, 0, 0, 0};
             acci[a][b] = acc_t{0, 0, 0, 0};
-            if constexpr (G3) acc3[a][b] = acc_t{0, 0, 0, 0};
+            if constexpr (P3) acc3[a][b] = acc_t{0, 0, 0, 0};
         }
 
     constexpr int NA = BM * BKT / 256;
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
             int e = tid + 256 * r;
             int kk = e % BKT, j = e / BKT;
             Bs[0][bidx(kk, j)] = rb[r].x;
-            Bs[1][bidx(kk, j)] = rb[r].y;
+            if constexpr (!BREAL) Bs[1][bidx(kk, j)] = rb[r].y;
         }
     };
     auto mma_slice = [&]() {
@@ -184,9 +187,18 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
 #pragma unroll
             for (int b = 0; b < TJ; ++b) {
                 br[b] = Bs[0][bidx(kk, wcol + b * 16 + (lane & 15))];
-                bi[b] = Bs[1][bidx(kk, wcol + b * 16 + (lane & 15))];
+                bi[b] = BREAL ? (T)0 : Bs[1][bidx(kk, wcol + b * 16 + (lane & 15))];
             }
-            if constexpr (G3) {
+            if constexpr (BREAL) {
+                // a complex matrix times a real one: two real products
+#pragma unroll
+                for (int a = 0; a < TI; ++a)
+#pragma unroll
+                    for (int b = 0; b < TJ; ++b) {
+                        accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
+                        acci[a][b] = mfma(ai[a], br[b], acci[a][b]);
+                    }
+            } else if constexpr (G3) {
                 // conj(A) (op A^H and op conj(A)): P3 takes Ar - Ai and the signs of P2 flip
                 // in the epilogue, so no operand is negated
                 T sb[TJ];
@@ -261,7 +273,7 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
                 int64_t gi = row0 + wrow + a * 16 + acc_row<T>(lane, r);
                 if (gi < m && gj < n) {
                     cpx<T> v;
-                    if constexpr (G3) {
+                    if constexpr (P3) {
                         T p1 = accr[a][b][r], p2 = acci[a][b][r], p3 = acc3[a][b][r];
                         v = OPA != 0 ? mk(p1 + p2, p3 - p1 + p2) : mk(p1 - p2, p3 - p1 - p2);
                     } else {
@@ -472,7 +484,10 @@ LaunchFn<T> variant(int v) {
 }
 template <typename T>
 LaunchFn<T> variant_op(int op, int v) {
-    return op == GEMM_C ? variant<T, 1>(v) : op == GEMM_R ? variant<T, 2>(v) : variant<T, 0>(v);
+    return op == GEMM_C       ? variant<T, 1>(v)
+           : op == GEMM_R     ? variant<T, 2>(v)
+           : op == GEMM_NREAL ? variant<T, 3>(v)
+                              : variant<T, 0>(v);
 }
 
 struct TuneKey {
@@ -651,8 +666,11 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
     // K is split when the output has too few 64 x 64 tiles to fill 256 CUs
     const int S = splitk_factor(m, n, k);
     const int v = tuned_variant<T>(op, m, n, k, S, alpha, A, lda, B, ldb, s);
+    // algorithmic work: 8 m n k real flops for a complex product, 4 m n k with a real B
     ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
-                   8.0 * (double)m * (double)n * (double)std::max<int64_t>(k, 0), s);
+                   (op == GEMM_NREAL ? 4.0 : 8.0) * (double)m * (double)n *
+                       (double)std::max<int64_t>(k, 0),
+                   s);
     // 64 x 64 tiles in the 3M form measured fastest on gfx950 for every large shape of the
     // solver (about 110% of the FP64 matrix-core peak counted as 8 m n k real flops, i.e.
     // 83-86% of the pipe for the 6 m n k it executes); two workgroups (two wavefronts per
