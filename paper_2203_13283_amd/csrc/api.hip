@@ -718,6 +718,7 @@ cfie_status factor_impl(cfie_ctx *c) {
     uint64_t blk = 0;
     std::vector<double> nrm(b);
     c->remainder_est = 0.0;
+    double y_first = 0.0;     // largest column norm of the first (unprojected) block
     // C - C_c applied factor by factor, or as a dense matrix (formed up front, or once the
     // rank has reached N/2 in the automatic mode)
     cpx<T> *Rd = nullptr;
@@ -735,10 +736,17 @@ cfie_status factor_impl(cfie_ctx *c) {
         if (ell > 0) {
             // block Gram-Schmidt against Q.  After one pass the kept directions deviate from
             // orthogonality to Q by about the unit roundoff times ||Y|| / tau (they are kept
-            // only above tau), i.e. u ||C - C_c|| / (epsilon ||C_c||): in FP64 with epsilon >=
-            // 1e-7 about 1e-9, which adds less than a hundredth of tau to the skeleton's
-            // error, so one pass suffices; FP32 data or a tighter epsilon repeat the pass
-            const int passes = (sizeof(T) == sizeof(double) && c->opt.compress_tol >= 1e-7) ? 1 : 2;
+            // only above tau), and the skeleton Q Q^H (C - C_c) then errs by that times
+            // ||C - C_c||: relative to ||C_c||, u y^2 / (tau ||C_c||) with y the largest
+            // column of the unprojected first block (a Gaussian column measures ||C - C_c||
+            // from above).  One pass in FP64 when this is below a hundredth of epsilon (the
+            // metric's near-circle: y / ||C_c|| of order 1, epsilon = 1e-5), two otherwise
+            // (FP32 data, tight epsilon, or contours far from their circle)
+            const double u = std::ldexp(1.0, -53);
+            const bool one = sizeof(T) == sizeof(double) && tau > 0.0 &&
+                             u * y_first * y_first / (tau * c->cc_norm) <=
+                                 0.01 * c->opt.compress_tol;
+            const int passes = one ? 1 : 2;
             for (int pass = 0; pass < passes; ++pass) {
                 gemm<T>(GEMM_C, ell, bb, N, cz<T>(1), Q, N, Y, N, cz<T>(0), S, ell, s);
                 gemm<T>(GEMM_N, N, bb, ell, cz<T>(-1), Q, N, S, ell, cz<T>(1), Y, N, s);
@@ -750,6 +758,7 @@ cfie_status factor_impl(cfie_ctx *c) {
         double mx = 0.0;
         for (int i = 0; i < bb; ++i) mx = std::max(mx, nrm[i]);
         c->remainder_est = std::sqrt(mx);
+        if (ell == 0) y_first = c->remainder_est;
         if (c->remainder_est <= tau) break;
         int kept = orthonormalise<T>(c, Y, bb, tau);
         if (kept == 0) break;
