@@ -52,3 +52,41 @@ def test_create_rejects_bad_options_before_touching_a_device():
     assert lib.cfie_factor(None) == _lib.CFIE_EINVAL
     assert lib.cfie_solve(None, None, 0, None, 0, 0) == _lib.CFIE_EINVAL
     lib.cfie_destroy(None)
+
+
+def test_group_solve_argument_checks_before_touching_a_device():
+    import ctypes
+    from paper_2203_13283_amd import _lib
+    lib = _lib.load()
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    assert lib.cfie_solve_group(None, 0, None, None, None, None, None, 1) == _lib.CFIE_OK
+    assert lib.cfie_solve_group(None, -1, None, None, None, None, None, 1) == _lib.CFIE_EINVAL
+    assert lib.cfie_solve_group(None, 2, None, None, None, None, None, 1) == _lib.CFIE_EINVAL
+    hs = (vp * 1)(None)
+    bs = (vp * 1)(None)
+    ls = (i64 * 1)(8)
+    assert lib.cfie_solve_group(hs, 1, bs, ls, bs, ls, ls, 1) == _lib.CFIE_EINVAL   # NULL ctx
+    assert lib.cfie_solve_batch_grouped(None, 0, 1, None, 0, 1) == _lib.CFIE_OK
+    assert lib.cfie_solve_batch_grouped(None, 0, 1, None, 0, 0) == _lib.CFIE_EINVAL
+    assert lib.cfie_solve_batch_grouped(None, 0, 0, None, 0, 1) == _lib.CFIE_EINVAL
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/cfie.h compiles as ISO C99 with every warning on (a C caller's view)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "use.c"
+    src.write_text('#include "cfie.h"\n'
+                   "int main(void) {\n"
+                   "    cfie_options o;\n"
+                   "    cfie_default_options(&o);\n"
+                   "    return (int)cfie_solve_group((cfie_ctx *const *)0, 0, 0, 0, 0, 0, 0, 1);\n"
+                   "}\n")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-fsyntax-only", "-I", os.path.join(root, "include"), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
