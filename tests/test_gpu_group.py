@@ -142,3 +142,21 @@ def test_batch_grouped_equals_batch():
         assert torch.equal(X, Xr) and r["refine_residual"] == rr["refine_residual"]
     with pytest.raises(P.CfieError):
         P.solve_batch(probs[:1], grouped=True, sweeps=0)
+
+
+def test_group_small_batches_take_the_skinny_product():
+    """At most 16 right-hand sides with rank and N above 1024: both Woodbury products take the
+    small-batch kernel with its K split, whose partial products live in the branch's own
+    buffer inside the recording."""
+    N = 1500
+    zhat = W.ellipse_coeffs(1.0, 0.5)
+    k = 2 * np.pi * N / (10 * 4.844224110273837)          # 10 nodes per wavelength
+    s = P.Solver(compress_tol=1e-10, block=128)
+    s.assemble(zhat, N, k).factor()
+    rank = s.info()["rank"]
+    print(f"N={N} rank {rank}")
+    B = s.plane_wave_rhs(np.linspace(0.0, 2 * np.pi, 8, endpoint=False))
+    Xa = s.solve(B)
+    (X,) = P.solve_group([s], [B])
+    assert torch.equal(X, Xa)
+    assert rank >= 1024
