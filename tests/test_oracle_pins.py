@@ -4,7 +4,6 @@ Each test checks the oracle against something that is not the oracle: closed for
 exact identities, an independent brute-force integration, or the analytic PEC-cylinder
 solution.
 """
-import math
 
 import numpy as np
 import pytest
@@ -253,10 +252,3 @@ def test_circle_solution_converges_to_mie_series():
     assert errs[-1] < 1e-2
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0, errs
-
-
-def test_ktilde_formula():
-    k, L = 20.0, 2 * math.pi * 0.5
-    kt = S.ktilde(k, L)
-    assert kt.real == k
-    assert abs(kt.imag - 0.4 * k ** (1 / 3) * 0.5 ** (-2 / 3)) <= 1e-15 * kt.imag
