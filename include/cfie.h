@@ -76,9 +76,8 @@ typedef struct {
                              complex128 capacitance LU, FP64 iterative refinement)      */
     double compress_tol;  /* epsilon, tau = epsilon * ||C_c||_2 (||C_c||_2 = max |c_m|):
                              sketch blocks are added until a block's projected columns all
-                             have norm <= tau, or a block keeps at most block - 16
-                             directions of norm > tau (the remaining range has then been
-                             sampled with 16 or more columns of oversampling)            */
+                             have norm <= tau, or a block keeps at most block - oversample
+                             directions of norm > tau (see oversample)                  */
     int32_t block;        /* columns added to the sketch per adaptive step (b)         */
     int32_t max_rank;     /* cap on the skeleton rank; 0 = N                            */
     uint64_t seed;        /* seed of the Gaussian sketch (Philox4x32-10 counter stream) */
@@ -97,6 +96,11 @@ typedef struct {
                              graph on buffers it owns, and replays it on later calls with
                              that nrhs (B copied in, X copied out); bitwise identical to the
                              direct path.  For many small solves with one factorisation.   */
+    int32_t oversample;   /* p >= 0: the sketch stops after a block of b >= 2p Gaussian
+                             columns that keeps at most b - p directions above tau (the
+                             remaining range has then been sampled with p or more columns of
+                             oversampling); 0 turns the rule off, so blocks are drawn until
+                             one has no column above tau                                 */
 } cfie_options;
 
 /* cfie_options.remainder_form.  The sketch and V^T = Q^H (C - C_c) cost 64 N^2 r flops when
@@ -130,11 +134,16 @@ typedef struct {
     int32_t convex;           /* 1 if curvature >= 0 everywhere sampled                */
     /* launch profile (options.profile = 1), accumulated since cfie_create or the last
      * reset; index: 0 complex128 GEMM, 1 complex64 GEMM, 2 far-pair assembly, 3 near-pair
-     * assembly, 4 circulant FFT apply.  work: flops (GEMM, 8 m n k), Gauss point pairs
-     * (assembly), bytes of one read and one write of the batch (FFT). */
+     * assembly, 4 circulant FFT apply.  work: real flops executed (GEMM: 6 m n k for a
+     * complex product in the 3M form, 4 m n k for a complex times a real matrix), Gauss point
+     * pairs (assembly), bytes of one read and one write of the batch (FFT). */
     int64_t prof_launches[5];
     double prof_work[5];
     double prof_ms[5];
+    /* device time of the phases of the last cfie_factor: 0 range finder (sketch blocks and
+     * their orthonormalisation), 1 V^T = Q^H (C - C_c) and U~ = C_c^-1 Q, 2 the capacitance
+     * matrix K = I + V^T U~ and its LU, 3 K^-1 V^T; a phase not reached is 0 */
+    double t_factor_phase_ms[4];
 } cfie_info;
 
 /* Process-wide switch of the complex GEMM tile autotuner: mode 1 (the default) lets the first
@@ -152,7 +161,7 @@ cfie_status cfie_profile_reset(cfie_ctx *ctx);
 
 /* Fill *opt with defaults: FP64, compress_tol 1e-10, block 128, max_rank 0, seed 1,
  * refine_tol 1e-8, max_refine 20, quad_far 5, quad_near 10, near_band 6, no injection,
- * no profiling, remainder_form CFIE_REMAINDER_AUTO, solve_graphs 0. */
+ * no profiling, remainder_form CFIE_REMAINDER_AUTO, solve_graphs 0, oversample 16. */
 void cfie_default_options(cfie_options *opt);
 
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for
@@ -300,12 +309,13 @@ cfie_status cfie_solve_batch(const cfie_options *opt, int device, int n_streams,
  * Woodbury solve of the residual, FP64 residual against the assembled operator) -- the same
  * arithmetic as cfie_solve, so equal to it when cfie_solve takes that many sweeps -- after
  * which contexts above refine_tol continue sweeping directly, up to max_refine in all
- * (cfie_query reports the sweeps and residual of each).  The members' own streams are
+ * (a member records min(sweeps, max_refine) sweeps; cfie_query reports the sweeps and
+ * residual of each).  The members' own streams are
  * synchronised before recording and the call returns when every solve has completed.
  * Contexts must be distinct, factored and on one device; members with nrhs[i] == 0 are
  * skipped.  Errors: EINVAL for n < 0, NULL arrays, a NULL or repeated context, contexts on
- * different devices, sweeps < 1, nrhs[i] < 0 or > 4096, NULL B or X, leading dimension < N;
- * ESTATE before cfie_factor (message on that context); ENOCONV if some mixed member
+ * different devices, sweeps < 1 or > 64, nrhs[i] < 0 or > 4096, NULL B or X, leading
+ * dimension < N; ESTATE before cfie_factor (message on that context); ENOCONV if some mixed member
  * did not reach refine_tol (its X holds the last iterate); EHIP/ENOMEM otherwise (message on
  * ctxs[0] unless it names another context). */
 cfie_status cfie_solve_group(cfie_ctx *const *ctxs, int64_t n, const void *const *B_dev,
@@ -318,7 +328,7 @@ cfie_status cfie_solve_group(cfie_ctx *const *ctxs, int64_t n, const void *const
  * recorded refinement sweeps for mixed precision) and the contexts are released.  All items'
  * contexts are alive together, so device memory holds every problem's matrices at once.
  * t_ms covers each item's path up to its right-hand sides.  Errors as for cfie_solve_batch,
- * and EINVAL for sweeps < 1 or an item with nrhs > 4096. */
+ * and EINVAL for sweeps < 1 or > 64 or an item with nrhs > 4096. */
 cfie_status cfie_solve_batch_grouped(const cfie_options *opt, int device, int n_streams,
                                      cfie_batch_item *items, int64_t n_items, int32_t sweeps);
 

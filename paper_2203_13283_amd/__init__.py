@@ -64,7 +64,7 @@ class Solver:
                  refine_tol: float = 1e-8, max_refine: int = 20, quad_far: int = 5,
                  quad_near: int = 10, near_band: int = 6, fail_alloc_after: int = -1,
                  profile: bool = False, remainder_form: int = 0, solve_graphs: bool = False,
-                 device: int = 0, stream=None):
+                 oversample: int = 16, device: int = 0, stream=None):
         lib = _lib.load()
         torch = _torch()
         o = _lib.default_options()
@@ -82,6 +82,7 @@ class Solver:
         o.profile = 1 if profile else 0
         o.remainder_form = remainder_form
         o.solve_graphs = 1 if solve_graphs else 0
+        o.oversample = oversample
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -236,7 +237,7 @@ class Solver:
         out = {}
         for f, _ in i._fields_:
             v = getattr(i, f)
-            out[f] = list(v) if f.startswith("prof_") else v
+            out[f] = list(v) if f.startswith("prof_") or f == "t_factor_phase_ms" else v
         return out
 
     def profile(self) -> dict:

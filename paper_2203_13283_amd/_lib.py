@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
                 ("max_refine", ctypes.c_int32), ("quad_far", ctypes.c_int32),
                 ("quad_near", ctypes.c_int32), ("near_band", ctypes.c_int32),
                 ("fail_alloc_after", ctypes.c_int64), ("profile", ctypes.c_int32),
-                ("remainder_form", ctypes.c_int32), ("solve_graphs", ctypes.c_int32)]
+                ("remainder_form", ctypes.c_int32), ("solve_graphs", ctypes.c_int32),
+                ("oversample", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -60,7 +61,8 @@ class Info(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double), ("refine_sweeps", ctypes.c_int32),
                 ("refine_residual", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("convex", ctypes.c_int32), ("prof_launches", ctypes.c_int64 * 5),
-                ("prof_work", ctypes.c_double * 5), ("prof_ms", ctypes.c_double * 5)]
+                ("prof_work", ctypes.c_double * 5), ("prof_ms", ctypes.c_double * 5),
+                ("t_factor_phase_ms", ctypes.c_double * 4)]
 
 PROF_NAMES = ("zgemm_f64", "zgemm_f32", "assemble_far", "assemble_near", "circ_fft")
 

@@ -102,6 +102,7 @@ constexpr int kLUPanel = 16;          // columns per LU panel
 constexpr int kLUSuper = 256;         // columns per LU superpanel (inner dimension of the
                                       // trailing updates and of the triangular solves)
 constexpr int64_t kGroupMaxRhs = 4096;  // right-hand sides per member of a group solve
+constexpr int32_t kGroupMaxSweeps = 64; // refinement sweeps recorded per mixed member
 
 struct HipError {
     cfie_status st;
@@ -144,6 +145,14 @@ struct cfie_ctx {
     int rank = 0;
     double remainder_est = 0.0;
     float t_asm = 0, t_fac = 0, t_sol = 0;
+    // phase marks of the last cfie_factor (range finder, projection, capacitance LU,
+    // K^-1 V^T) and their durations
+    hipEvent_t fmk[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int fmk_n = 0;
+    float t_fphase[4] = {0, 0, 0, 0};
+    void fac_mark() {
+        if (fmk_n < 5 && fmk[fmk_n]) HIPCHK(hipEventRecord(fmk[fmk_n++], stream));
+    }
     int refine_sweeps = 0;
     double refine_res = 0.0;
 
@@ -204,6 +213,8 @@ struct cfie_ctx {
             (void)hipStreamSynchronize(aux);
             (void)hipStreamDestroy(aux);
         }
+        for (auto e : fmk)
+            if (e) (void)hipEventDestroy(e);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (stream_owned && stream) (void)hipStreamDestroy(stream);
@@ -764,16 +775,20 @@ cfie_status factor_impl(cfie_ctx *c) {
         if (kept == 0) break;
         axpby<T>(N, kept, cz<T>(1), Y, N, cz<T>(0), Q + (size_t)ell * N, N, s);
         ell += kept;
-        // a Gaussian block that kept at most bb - 16 directions above tau has sampled the
-        // remaining range with at least 16 columns of oversampling: the remainder left after
-        // it exceeds tau only with negligible probability, so no further block is drawn
-        if (bb >= 32 && kept <= bb - 16) break;
+        // a Gaussian block that kept at most bb - p directions above tau has sampled the
+        // remaining range with at least p columns of oversampling: the remainder left after
+        // it exceeds tau only with a probability that falls geometrically with p (Halko,
+        // Martinsson and Tropp's bound for a Gaussian test matrix), so no further block is
+        // drawn
+        const int p = c->opt.oversample;
+        if (p > 0 && bb >= 2 * p && kept <= bb - p) break;
         if (!Rd && c->opt.remainder_form == CFIE_REMAINDER_AUTO && 2 * ell >= N && ell < cap) {
             Rd = c->alloc_n<cpx<T>>((size_t)N * N);
             form_remainder_dense<T>(c, Rd);
         }
     }
     c->rank = ell;
+    c->fac_mark();                                     // end of the range finder
     if (ell == 0) {
         if (Rd) {
             c->sync();
@@ -804,6 +819,7 @@ cfie_status factor_impl(cfie_ctx *c) {
     cpx<T> *Ut = (cpx<T> *)c->Ut;
     axpby<T>(N, ell, cz<T>(1), Q, N, cz<T>(0), Ut, N, s);
     circ_apply<T>(c, Ops<T>::dCinv(c), Ut, N, ell);
+    c->fac_mark();                                     // end of V^T and U~
     // K = I + P^H Ut  (Woodbury capacitance, eq. (9)), always complex128
     c->K = c->alloc_n<zd>((size_t)cap * cap);
     if (sizeof(T) == sizeof(double)) {
@@ -881,6 +897,7 @@ cfie_status factor_impl(cfie_ctx *c) {
     }
     launch_tri_inv_blocks(ell, kLUBlock, c->K, cap, c->Linv, c->Uinv, s);
     c->check_launch();
+    c->fac_mark();                                     // end of K and its LU
     int info = 0;
     HIPCHK(hipMemcpyAsync(&info, c->info, sizeof(int), hipMemcpyDeviceToHost, s));
     c->sync();
@@ -906,6 +923,7 @@ cfie_status factor_impl(cfie_ctx *c) {
         c->sync();
         c->dfree(tmpN);
     }
+    c->fac_mark();                                     // end of K^-1 V^T
     // the FP64 solve's rank x m workspace, sized with the factorisation for batches of up to
     // 1024 right-hand sides (larger batches grow it on first use)
     if (sizeof(T) == sizeof(double)) (void)c->scratch<zd>(1, (size_t)ell * 1024);
@@ -1255,7 +1273,9 @@ struct GroupMember {
         } else {
             colnorm2<double>(N, m, B, ldb, b2, s);
             axpby<double>(N, m, cz<double>(1), B, ldb, cz<double>(0), Rb, N, s);
-            for (int k = 0; k < nsweep; ++k) sweep(k == 0);
+            // at most max_refine sweeps in all, as for cfie_solve
+            const int ns = std::min(nsweep, std::max(1, c->opt.max_refine));
+            for (int k = 0; k < ns; ++k) sweep(k == 0);
         }
         c->check_launch();
     }
@@ -1391,6 +1411,7 @@ void cfie_default_options(cfie_options *o) {
     o->profile = 0;
     o->remainder_form = CFIE_REMAINDER_AUTO;
     o->solve_graphs = 0;
+    o->oversample = 16;
 }
 
 const char *cfie_status_string(cfie_status s) {
@@ -1426,6 +1447,7 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, c
     if (o.remainder_form < CFIE_REMAINDER_AUTO || o.remainder_form > CFIE_REMAINDER_DENSE)
         return bad("remainder_form must be CFIE_REMAINDER_AUTO, _FACTORED or _DENSE");
     if (o.solve_graphs != 0 && o.solve_graphs != 1) return bad("solve_graphs must be 0 or 1");
+    if (o.oversample < 0 || o.oversample > 256) return bad("oversample must be in [0, 256]");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         (void)hipGetLastError();
@@ -1533,7 +1555,8 @@ cfie_status cfie_solve_group(cfie_ctx *const *ctxs, int64_t n, const void *const
     for (int64_t i = 0; i < n; ++i)
         if (!ctxs[i]) return CFIE_EINVAL;
     cfie_ctx *c0 = ctxs[0];
-    if (sweeps < 1) return fail(c0, CFIE_EINVAL, "sweeps must be >= 1");
+    if (sweeps < 1 || sweeps > kGroupMaxSweeps)
+        return fail(c0, CFIE_EINVAL, "sweeps must be in [1, 64]");
     std::vector<GroupMember> gm;
     std::vector<cfie_ctx *> seen;
     for (int64_t i = 0; i < n; ++i) {
@@ -1573,7 +1596,8 @@ cfie_status cfie_solve_group(cfie_ctx *const *ctxs, int64_t n, const void *const
 
 cfie_status cfie_solve_batch_grouped(const cfie_options *opt, int device, int n_streams,
                                      cfie_batch_item *items, int64_t n_items, int32_t sweeps) {
-    if (n_items < 0 || n_streams < 1 || n_streams > 16 || (n_items > 0 && !items) || sweeps < 1)
+    if (n_items < 0 || n_streams < 1 || n_streams > 16 || (n_items > 0 && !items) || sweeps < 1 ||
+        sweeps > kGroupMaxSweeps)
         return CFIE_EINVAL;
     if (n_items == 0) return CFIE_OK;
     for (int64_t i = 0; i < n_items; ++i)
@@ -1903,12 +1927,19 @@ cfie_status cfie_factor(cfie_ctx *c) {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
+        for (auto &e : c->fmk)
+            if (!e) HIPCHK(hipEventCreate(&e));
+        c->fmk_n = 0;
+        for (auto &t : c->t_fphase) t = 0.0f;
         HIPCHK(hipEventRecord(e0, c->stream));
+        c->fac_mark();
         c->state = 1;
         cfie_status st = c->opt.precision == CFIE_MIXED ? factor_impl<float>(c) : factor_impl<double>(c);
         HIPCHK(hipEventRecord(e1, c->stream));
         c->sync();
         HIPCHK(hipEventElapsedTime(&c->t_fac, e0, e1));
+        for (int i = 0; i + 1 < c->fmk_n; ++i)
+            HIPCHK(hipEventElapsedTime(&c->t_fphase[i], c->fmk[i], c->fmk[i + 1]));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         return st;
@@ -2343,6 +2374,7 @@ cfie_status cfie_query(const cfie_ctx *c, cfie_info *o) {
     o->t_assemble_ms = c->t_asm;
     o->t_factor_ms = c->t_fac;
     o->t_solve_ms = c->t_sol;
+    for (int i = 0; i < 4; ++i) o->t_factor_phase_ms[i] = c->t_fphase[i];
     o->refine_sweeps = c->refine_sweeps;
     o->refine_residual = c->refine_res;
     o->precision = c->opt.precision;

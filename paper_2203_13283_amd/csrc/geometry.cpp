@@ -6,6 +6,7 @@
 // polynomial; its arc-length density |z'(t)| is expanded in a Fourier series (sampled on a
 // fine grid and transformed), which gives s(t) in closed form for the device-side Newton
 // inversion t(s).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -37,6 +38,51 @@ bool seg_intersect(zd a, zd b, zd c, zd d) {
     if (den == 0.0) return false;
     double t = cross(ca, s) / den, u = cross(ca, r) / den;
     return t > 0.0 && t < 1.0 && u > 0.0 && u < 1.0;
+}
+
+// Whether two edges of the closed polygon p that do not share a vertex cross.  The edges are
+// put into the cells of a uniform grid that their bounding boxes overlap (cells about two
+// mean edge lengths wide, at most about 4 cells per edge), and only edges sharing a cell are
+// tested against each other: linear work for a smooth curve instead of all pairs.
+bool polygon_self_intersects(const std::vector<zd> &p) {
+    const int64_t Q = (int64_t)p.size();
+    if (Q < 4) return false;
+    double x0 = p[0].x, x1 = p[0].x, y0 = p[0].y, y1 = p[0].y, len = 0.0;
+    for (int64_t j = 0; j < Q; ++j) {
+        x0 = std::fmin(x0, p[j].x);
+        x1 = std::fmax(x1, p[j].x);
+        y0 = std::fmin(y0, p[j].y);
+        y1 = std::fmax(y1, p[j].y);
+        len += cabs(p[(j + 1) % Q] - p[j]);
+    }
+    double cell = std::fmax(2.0 * len / (double)Q, 1e-300);
+    while (((x1 - x0) / cell + 1.0) * ((y1 - y0) / cell + 1.0) > 4.0 * (double)Q) cell *= 2.0;
+    const int64_t gx = (int64_t)((x1 - x0) / cell) + 1;
+    std::vector<std::pair<int64_t, int64_t>> ce;      // (cell, edge)
+    ce.reserve((size_t)Q * 4);
+    for (int64_t e = 0; e < Q; ++e) {
+        const zd a = p[e], b = p[(e + 1) % Q];
+        const int64_t i0 = (int64_t)((std::fmin(a.x, b.x) - x0) / cell);
+        const int64_t i1 = (int64_t)((std::fmax(a.x, b.x) - x0) / cell);
+        const int64_t j0 = (int64_t)((std::fmin(a.y, b.y) - y0) / cell);
+        const int64_t j1 = (int64_t)((std::fmax(a.y, b.y) - y0) / cell);
+        for (int64_t j = j0; j <= j1; ++j)
+            for (int64_t i = i0; i <= i1; ++i) ce.emplace_back(j * gx + i, e);
+    }
+    std::sort(ce.begin(), ce.end());
+    for (size_t lo = 0; lo < ce.size();) {
+        size_t hi = lo;
+        while (hi < ce.size() && ce[hi].first == ce[lo].first) ++hi;
+        for (size_t u = lo; u < hi; ++u)
+            for (size_t v = u + 1; v < hi; ++v) {
+                const int64_t a = ce[u].second, b = ce[v].second;
+                const int64_t d = b > a ? b - a : a - b;
+                if (d <= 1 || d == Q - 1) continue;          // edges sharing a vertex
+                if (seg_intersect(p[a], p[(a + 1) % Q], p[b], p[(b + 1) % Q])) return true;
+            }
+        lo = hi;
+    }
+    return false;
 }
 
 }  // namespace
@@ -88,7 +134,6 @@ std::string build_geometry(const cfie_contour &c, HostGeometry &g) {
     int P = 4096;
     while (P < 64 * (2 * g.M + 1)) P *= 2;
     std::vector<double> speed(P), curv(P);
-    std::vector<zd> pos(P);
     double area = 0.0;
     double min_speed = 1e300;
     for (int j = 0; j < P; ++j) {
@@ -100,23 +145,27 @@ std::string build_geometry(const cfie_contour &c, HostGeometry &g) {
         speed[j] = sp;
         min_speed = std::fmin(min_speed, sp);
         curv[j] = (d1.x * d2.y - d1.y * d2.x) / (sp * sp * sp);
-        pos[j] = z;
         area += 0.5 * (z.x * d1.y - z.y * d1.x);
     }
     area *= 2.0 * kPi / P;
     if (!(min_speed > 0.0)) return "contour has a zero tangent (not a regular curve)";
     if (!(area > 0.0)) return "contour must be counter-clockwise (positive signed area)";
-    // self-intersection on a 1024-point polygon
+    // self-intersection of the polygon through 16 N points of the curve (at least 1024)
     {
-        const int Q = 1024;
+        const int Q = std::max(1024, 16 * c.n_nodes);
         std::vector<zd> poly(Q);
-        for (int j = 0; j < Q; ++j) poly[j] = pos[(long)j * P / Q];
-        for (int a = 0; a < Q; ++a)
-            for (int b = a + 2; b < Q; ++b) {
-                if (a == 0 && b == Q - 1) continue;
-                if (seg_intersect(poly[a], poly[(a + 1) % Q], poly[b], poly[(b + 1) % Q]))
-                    return "contour intersects itself";
+        for (int j = 0; j < Q; ++j) {
+            // z(t) = sum_m zhat_m w^m, w = e^{it}, by Horner in w and in 1/w = conj(w)
+            const double t = 2.0 * kPi * j / Q;
+            const zd w = mk(std::cos(t), std::sin(t)), wc = mk(w.x, -w.y);
+            zd hi = mk(0.0, 0.0), lo = mk(0.0, 0.0);
+            for (int m = g.M; m >= 1; --m) {
+                hi = hi * w + g.zhat[g.M + m];
+                lo = lo * wc + g.zhat[g.M - m];
             }
+            poly[j] = g.zhat[g.M] + hi * w + lo * wc;
+        }
+        if (polygon_self_intersects(poly)) return "contour intersects itself";
     }
     // Fourier coefficients of the speed by direct summation with exact root indices
     std::vector<zd> roots(P);

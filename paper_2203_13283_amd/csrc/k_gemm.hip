@@ -666,16 +666,17 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
     // K is split when the output has too few 64 x 64 tiles to fill 256 CUs
     const int S = splitk_factor(m, n, k);
     const int v = tuned_variant<T>(op, m, n, k, S, alpha, A, lda, B, ldb, s);
-    // algorithmic work: 8 m n k real flops for a complex product, 4 m n k with a real B
+    // work: the real flops the kernel executes -- 6 m n k for a complex product in the 3M
+    // form (three real products), 4 m n k with a real B (two real products).  The classical
+    // complex product counts 8 m n k; the 3M form reaches the same result with 3/4 of it.
     ProfScope prof(sizeof(T) == sizeof(double) ? PROF_GEMM64 : PROF_GEMM32,
-                   (op == GEMM_NREAL ? 4.0 : 8.0) * (double)m * (double)n *
+                   (op == GEMM_NREAL ? 4.0 : 6.0) * (double)m * (double)n *
                        (double)std::max<int64_t>(k, 0),
                    s);
     // 64 x 64 tiles in the 3M form measured fastest on gfx950 for every large shape of the
-    // solver (about 110% of the FP64 matrix-core peak counted as 8 m n k real flops, i.e.
-    // 83-86% of the pipe for the 6 m n k it executes); two workgroups (two wavefronts per
-    // SIMD) per CU: the register budget of 256 per lane that this imposes measured 15-20%
-    // faster than one wavefront with more registers
+    // solver; two workgroups (two wavefronts per SIMD) per CU: the register budget of 256
+    // per lane that this imposes measured 15-20% faster than one wavefront with more
+    // registers
     variant_op<T>(op, v)(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
 }
 
