@@ -15,8 +15,13 @@ modes 1..8, four incident waves, 181 observation angles each), its far fields an
 reference gradient with respect to the 16 shape coefficients (central differences with two
 Richardson extrapolations of the oracle's dense solve).
 
+fig5_ellipse: the sweep of Sec. VI (Fig. 5) on the 2:1 ellipse at N = 256 ... 2048 (dense-LU
+solutions for 16 plane waves, singular values of C - C_c, ||C_c||_2), and shapegrad_dir<N>:
+the full shape workload's loss and its derivative along one seeded direction of the 128
+shape coefficients.
+
 Run:  python tests/golden/make_golden.py ellipse4096 perturbed16384 spectra512 shapegrad128
-      [--workers 8]
+      fig5 shapegrad_dir2048 [--workers 8]
 (about 2 minutes for ellipse4096 and 40 minutes for perturbed16384 on 8 cores; the
 larger one needs about 40 GB of host memory).
 """
@@ -114,6 +119,61 @@ def make_shapegrad(N: int, workers: int, mmax: int = 8, n_inc: int = 4, fd_step:
     print(f"shapegrad{N}: written", flush=True)
 
 
+def make_fig5(Ns, workers: int, n_rhs: int = 16):
+    """The sweep of Sec. VI (Fig. 5): the 2:1 ellipse with semi-axes 2 and 1 at 10 nodes per
+    wavelength for each N of Ns.  Stores, per N, k, the dense-LU solutions of eq. (5) for
+    n_rhs plane waves at 2 pi j / n_rhs, the singular values of C - C_c (dense SVD) and
+    ||C_c||_2 = max |c_m| (the DFT of the dense circle C_c's first column)."""
+    import math
+    zh = W.ellipse_coeffs(2.0, 1.0)
+    L = S.Contour(zh).L
+    out = dict(Ns=np.asarray(Ns), L=L, n_rhs=n_rhs)
+    for N in Ns:
+        t0 = time.time()
+        k = 2 * math.pi * N / (10 * L)
+        pr = S.Problem(zh, N, k, workers=workers)
+        ang = W.plane_wave_angles(n_rhs)
+        b = pr.rhs(ang)
+        x = pr.solve(b)
+        sR = np.linalg.svd(pr.C - pr.Cc, compute_uv=False)
+        out[f"k_{N}"] = k
+        out[f"x_{N}"] = x
+        out[f"sR_{N}"] = sR
+        out[f"cc_max_{N}"] = float(np.abs(np.fft.fft(pr.Cc[:, 0])).max())
+        print(f"fig5: N={N} in {time.time() - t0:.0f} s", flush=True)
+        del pr
+    np.savez_compressed(os.path.join(HERE, "fig5_ellipse.npz"), **out)
+    print("fig5_ellipse: written", flush=True)
+
+
+def make_shapegrad_direction(N: int, workers: int, mmax: int = 64, n_inc: int = 16,
+                             fd_step: float = 1e-3, seed: int = 7):
+    """The shape-differentiation workload's loss (16 waves, 181 backscatter angles each) at N
+    nodes with all 128 shape coefficients, and its derivative along one seeded unit direction
+    of the coefficients by central differences with two Richardson extrapolations of the
+    oracle's dense solve (six solves)."""
+    from oracle import gradient as G
+    pr = W.shape_problem(N=N, mmax=mmax, n_inc=n_inc)
+    p0 = np.concatenate([pr["s"], pr["t"]])
+    d = np.random.default_rng(seed).normal(size=p0.size)
+    d /= np.linalg.norm(d)
+
+    def loss_along(u):
+        p = p0 + u[0] * d
+        return G.backscatter_loss(W.shape_to_zhat(p[:mmax], p[mmax:]), N, pr["k"],
+                                  pr["angles"], pr["obs"], workers=workers)[0]
+
+    t0 = time.time()
+    L0, F = G.backscatter_loss(pr["zhat"], N, pr["k"], pr["angles"], pr["obs"],
+                               workers=workers)
+    dL = float(G.richardson_gradient(loss_along, np.zeros(1), fd_step)[0])
+    print(f"shapegrad_dir{N}: loss {L0:.6e}, dL/du {dL:.9e} in {time.time() - t0:.0f} s",
+          flush=True)
+    np.savez_compressed(os.path.join(HERE, f"shapegrad_dir{N}.npz"), N=N, mmax=mmax,
+                        k=pr["k"], direction=d, L=L0, F=F, dL=dL, fd_step=fd_step)
+    print(f"shapegrad_dir{N}: written", flush=True)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("names", nargs="+")
@@ -122,6 +182,10 @@ if __name__ == "__main__":
     for n in a.names:
         if n.startswith("spectra"):
             make_spectra(int(n[len("spectra"):]), a.workers)
+        elif n == "fig5":
+            make_fig5([256, 512, 1024, 2048], a.workers)
+        elif n.startswith("shapegrad_dir"):
+            make_shapegrad_direction(int(n[len("shapegrad_dir"):]), a.workers)
         elif n.startswith("shapegrad"):
             make_shapegrad(int(n[len("shapegrad"):]), a.workers)
         else:

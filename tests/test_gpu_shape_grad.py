@@ -13,6 +13,8 @@ source (workloads.backscatter_angles).  Checks:
   * translation invariance: the derivative with respect to zhat_0 vanishes;
   * at the full size of the workload (N = 8192, 64 shape modes, 16 waves) against central
     differences of the HIP loss itself with step 1e-6 on sampled coefficients;
+  * the full workload at N = 2048 (k R up to about 400) projected on a seeded direction
+    against the oracle's extrapolated directional difference;
   * the torch.autograd op, mixed precision, and argument errors.
 """
 import os
@@ -124,6 +126,37 @@ def test_gradient_fullsize_against_central_differences():
         fd = (vals[0] - vals[1]) / (2 * h)
         print(f"param {i}: adjoint {g[i]: .10e}  central difference {fd: .10e}")
         assert abs(g[i] - fd) <= 2e-6 * gmax + 1e-6 * abs(fd)
+
+
+def test_gradient_direction_at_N2048_against_oracle():
+    """The full shape workload (128 coefficients, 16 waves x 181 backscatter angles) at
+    N = 2048, where k R reaches about 400, so the backward far kernel's large-argument pass
+    (k R >= 200) carries most element pairs: the HIP gradient projected on the stored seeded
+    direction against the oracle's extrapolated directional difference of its dense solve
+    (tests/golden/shapegrad_dir2048.npz).  Both are derivatives of discretisations that differ
+    by quadrature error only (the loss agrees to 1e-9); bar 1e-6 of the directional
+    derivative."""
+    path = os.path.join(HERE, "golden", "shapegrad_dir2048.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (tests/golden/make_golden.py shapegrad_dir2048)")
+    d = np.load(path)
+    N, mmax = int(d["N"]), int(d["mmax"])
+    pr = W.shape_problem(N=N, mmax=mmax)
+    assert abs(pr["k"] - float(d["k"])) <= 1e-12 * pr["k"]
+    inc, obs = pr["angles"], pr["obs"]
+    m, n_obs = obs.shape
+    sel = _selection(m, n_obs)
+    s, X, F = _forward(pr["zhat"], N, pr["k"], inc, obs.ravel(), compress_tol=1e-12)
+    L = _loss(F, sel)
+    print(f"N={N}: loss {L:.12e} oracle {float(d['L']):.12e} rank {s.info()['rank']}")
+    assert abs(L - float(d["L"])) <= 1e-9 * float(d["L"])
+    gz = s.shape_gradient(inc, X, obs.ravel(), (2 * F * sel).contiguous())
+    g = _shape_grad(gz, mmax)
+    proj = float(g @ d["direction"])
+    ref = float(d["dL"])
+    print(f"directional derivative: adjoint {proj:.12e} oracle {ref:.12e} "
+          f"rel {abs(proj - ref) / abs(ref):.2e}")
+    assert abs(proj - ref) <= 1e-6 * abs(ref)
 
 
 def test_autograd_op_and_mixed_precision():
