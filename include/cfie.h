@@ -193,6 +193,24 @@ cfie_status cfie_factor(cfie_ctx *ctx);
 cfie_status cfie_solve(cfie_ctx *ctx, const void *B_dev, int64_t ldb, void *X_dev,
                        int64_t ldx, int64_t nrhs);
 
+/* cfie_solve without device allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * FP64 Woodbury solve of eq. (9) with the arithmetic of cfie_solve, its work space (the
+ * rank x m block of the capacitance solve, a packed copy when ldx > N, the padded circulant
+ * block when N is not a power of two, the GEMMs' split-K partial products) taken from one
+ * fixed 64 MiB device array that the library holds per device until the process ends.  The
+ * right-hand sides are processed in blocks of as many columns as fit (at most 4096), so the
+ * results agree with cfie_solve to rounding (the products' K splits can differ), not
+ * bitwise.  Every call on a device shares that device's array and leaves its contents
+ * behind; nothing in it needs to start at zero.  Calls that overlap in time on one device
+ * (several threads or streams) race on the array and must not be issued.  Arguments,
+ * aliasing and the return after the stream drains as for cfie_solve.  Errors: ESTATE
+ * before cfie_factor; EINVAL for a mixed-precision context, nrhs < 0, NULL B or X, a
+ * leading dimension < N, or when one right-hand side needs more than the fixed array;
+ * EHIP if the array's device address could not be resolved or a launch failed. */
+cfie_status cfie_solve_noalloc(cfie_ctx *ctx, const void *B_dev, int64_t ldb, void *X_dev,
+                               int64_t ldx, int64_t nrhs);
+
 /* Adjoint solve X = C^-H B for nrhs right-hand sides with the same factorisation: with
  * C = C_c + U V^T (Sec. V eqs. (7)-(9)), C^H = C_c^H + V U^H and the Woodbury identity holds
  * with the capacitance matrix K^H and C_c^-H (conjugate eigenvalues), so no new factor is

@@ -156,6 +156,18 @@ class Solver:
                     "cfie_solve")
         return X
 
+    def solve_noalloc(self, B, out=None):
+        """X = C^-1 B like solve, through cfie_solve_noalloc: the library allocates no device
+        memory in the call (its work space is a fixed per-device array); FP64 contexts only.
+        The caller's B and X (allocated here when out is None) are the only buffers."""
+        self._check_batch(B, self.N, "B")
+        m = B.shape[0]
+        X = out if out is not None else self._batch(m)
+        self._check_batch(X, self.N, "X")
+        self._check(self._lib.cfie_solve_noalloc(self._h, _ptr(B), self.N, _ptr(X), self.N,
+                                                 m), "cfie_solve_noalloc")
+        return X
+
     def solve_adjoint(self, B, out=None):
         """X = C^-H B with the same factorisation (cfie_solve_adjoint)."""
         self._check_batch(B, self.N, "B")

@@ -31,7 +31,7 @@ EXPORTED = [
     "cfie_last_error", "cfie_status_string", "cfie_destroy", "cfie_profile_reset",
     "cfie_solve_batch", "cfie_solve_adjoint", "cfie_far_field", "cfie_shape_gradient",
     "cfie_set_gemm_autotune", "cfie_gemm_tuned_classes", "cfie_solve_group",
-    "cfie_solve_batch_grouped",
+    "cfie_solve_batch_grouped", "cfie_solve_noalloc",
 ]
 
 
@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH):
     lib.cfie_factor.restype = i32
     lib.cfie_solve.argtypes = [vp, vp, i64, vp, i64, i64]
     lib.cfie_solve.restype = i32
+    lib.cfie_solve_noalloc.argtypes = [vp, vp, i64, vp, i64, i64]
+    lib.cfie_solve_noalloc.restype = i32
     lib.cfie_solve_adjoint.argtypes = [vp, vp, i64, vp, i64, i64]
     lib.cfie_solve_adjoint.restype = i32
     lib.cfie_plane_wave_rhs.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64, vp, i64]

@@ -95,6 +95,14 @@ hipEvent_t Profiler::get() {
 
 using namespace cfie;
 
+// Device memory of the allocation-free solve (cfie_solve_noalloc): one fixed array, of which
+// every device that loads the library holds its own copy until the process ends.  Host code
+// never passes the array's name to a launch or a copy (on the host the name is only a
+// stand-in): it uses the address that hipGetSymbolAddress returns with the device current,
+// resolved once per device when the first context is created there.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
 namespace {
 
 constexpr int kLUBlock = 64;          // diagonal blocks inverted for the triangular solves
@@ -199,6 +207,8 @@ struct cfie_ctx {
         bool ok = false;
     };
     std::map<int64_t, SolveGraph> graphs;
+    // this device's address of noalloc_scratch (nullptr if it could not be resolved)
+    void *noalloc_ws = nullptr;
 
     ~cfie_ctx() {
         for (auto &kv : graphs)
@@ -1125,6 +1135,100 @@ cfie_status solve_fp64(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx
     return CFIE_OK;
 }
 
+// Address of noalloc_scratch on `device`, which must be the current device: resolved by
+// hipGetSymbolAddress on the first request for that device and kept; nullptr on failure
+// (the next request tries again).
+std::mutex g_noalloc_mu;
+std::map<int, void *> g_noalloc_ptr;
+void *noalloc_scratch_address(int device) {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    auto it = g_noalloc_ptr.find(device);
+    if (it != g_noalloc_ptr.end()) return it->second;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_noalloc_ptr[device] = p;
+    return p;
+}
+
+// Layout of the allocation-free FP64 solve's scratch for blocks of m columns and a last
+// block of `tail` columns (0: none): Z (rank x m), the packed copy of the block when X is
+// not packed (N x m), the zero-padded block of the circulant product when N is not a power
+// of two (M x m) and the split-K partial products of the two Woodbury GEMMs for either block
+// width (the split, and with it the partials, can be larger for the narrower block), each
+// region aligned to 256 bytes.
+struct NoAllocPlan {
+    size_t z = 0, work = 0, pad = 0, splitk = 0, splitk_bytes = 0, total = 0;
+};
+NoAllocPlan noalloc_plan(const cfie_ctx *c, int64_t m, int64_t tail, bool packed) {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const int N = c->N, r = c->rank;
+    NoAllocPlan p;
+    size_t off = 0;
+    p.z = off;
+    off += up(sizeof(zd) * (size_t)std::max(r, 1) * (size_t)m);
+    p.work = off;
+    if (!packed) off += up(sizeof(zd) * (size_t)N * (size_t)m);
+    p.pad = off;
+    if (c->fft.M != N) off += up(sizeof(zd) * (size_t)c->fft.M * (size_t)m);
+    p.splitk = off;
+    if (r > 0)
+        for (int64_t w : {m, tail})
+            if (w > 0)
+                p.splitk_bytes = std::max({p.splitk_bytes,
+                                           gemm_splitk_bytes(GEMM_N, r, w, N, sizeof(zd)),
+                                           gemm_splitk_bytes(GEMM_N, N, w, r, sizeof(zd))});
+    off += up(p.splitk_bytes);
+    p.total = off;
+    return p;
+}
+
+// cfie_solve's FP64 arithmetic (eq. (9): C_c^-1 by FFT, the two Woodbury GEMMs) on the
+// device's fixed scratch, in blocks of as many columns as the scratch holds (at most 4096),
+// with no device allocation: the split-K partials come from the scratch, the GEMM tile
+// autotuner (which allocates a scratch output) is off for the call and no launch is timed.
+cfie_status solve_fp64_noalloc(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx,
+                               int64_t nrhs) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    const bool packed = (ldx == N);
+    int64_t mc = std::min<int64_t>(nrhs, 4096);
+    while (mc > 1 && noalloc_plan(c, mc, nrhs % mc, packed).total > kNoAllocBytes)
+        mc = (mc + 1) / 2;
+    const NoAllocPlan pl = noalloc_plan(c, mc, nrhs % mc, packed);
+    if (pl.total > kNoAllocBytes)
+        return fail(c, CFIE_EINVAL, "one right-hand side needs " + std::to_string(pl.total) +
+                                        " bytes of scratch, above the fixed " +
+                                        std::to_string(kNoAllocBytes));
+    unsigned char *base = (unsigned char *)c->noalloc_ws;
+    zd *Z = (zd *)(base + pl.z);
+    zd *work = packed ? nullptr : (zd *)(base + pl.work);
+    zd *pad = c->fft.M != N ? (zd *)(base + pl.pad) : nullptr;
+    struct Restore {
+        bool tune;
+        ~Restore() {
+            set_splitk_override(nullptr, 0);
+            set_gemm_tune_thread(tune);
+        }
+    } restore{set_gemm_tune_thread(false)};
+    set_splitk_override(pl.splitk_bytes ? (void *)(base + pl.splitk) : nullptr,
+                        pl.splitk_bytes);
+    for (int64_t j = 0; j < nrhs; j += mc) {
+        const int64_t m = std::min(mc, nrhs - j);
+        zd *Xj = packed ? X + j * ldx : work;
+        if (!(packed && B == X))
+            axpby<double>(N, m, cz<double>(1), B + j * ldb, ldb, cz<double>(0), Xj, N, s);
+        woodbury<double>(c, Xj, m, Z, pad);
+        if (!packed)
+            axpby<double>(N, m, cz<double>(1), work, N, cz<double>(0), X + j * ldx, ldx, s);
+    }
+    c->check_launch();
+    c->sync();
+    return CFIE_OK;
+}
+
 cfie_status solve_mixed(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx,
                         int64_t nrhs) {
     const int N = c->N;
@@ -1463,6 +1567,7 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, c
     c->opt = o;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    c->noalloc_ws = noalloc_scratch_address(device);
     *out = c;
     return CFIE_OK;
 }
@@ -1972,6 +2077,34 @@ cfie_status cfie_solve(cfie_ctx *c, const void *B, int64_t ldb, void *X, int64_t
         (void)hipEventDestroy(e1);
         return st;
     });
+}
+
+cfie_status cfie_solve_noalloc(cfie_ctx *c, const void *B, int64_t ldb, void *X,
+                               int64_t ldx, int64_t nrhs) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 2) return fail(c, CFIE_ESTATE, "cfie_solve_noalloc before cfie_factor");
+    if (c->opt.precision != CFIE_FP64)
+        return fail(c, CFIE_EINVAL, "cfie_solve_noalloc solves FP64 contexts only");
+    if (nrhs < 0) return fail(c, CFIE_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return CFIE_OK;
+    if (!B || !X) return fail(c, CFIE_EINVAL, "NULL B or X");
+    if (ldb < c->N || ldx < c->N) return fail(c, CFIE_EINVAL, "leading dimension < N");
+    if (!c->noalloc_ws)
+        return fail(c, CFIE_EHIP, "the address of the fixed scratch could not be resolved");
+    // no launch is timed (the profiler's events are not created here)
+    Profiler *saved = g_prof;
+    g_prof = nullptr;
+    cfie_status st = CFIE_OK;
+    try {
+        HIPCHK(hipSetDevice(c->device));
+        st = solve_fp64_noalloc(c, (const zd *)B, ldb, (zd *)X, ldx, nrhs);
+    } catch (const HipError &e) {
+        c->err = e.msg;
+        (void)hipGetLastError();
+        st = e.st;
+    }
+    g_prof = saved;
+    return st;
 }
 
 cfie_status cfie_solve_adjoint(cfie_ctx *c, const void *B, int64_t ldb, void *X,

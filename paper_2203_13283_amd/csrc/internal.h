@@ -206,6 +206,10 @@ void splitk_release(int device, hipStream_t s);
 // of shape classes measured so far
 int set_gemm_autotune(int mode);
 int gemm_tuned_classes();
+// tile autotuning for the calling thread's products (it allocates a scratch output the
+// first time it meets a shape class); off: the 64 x 64 tile, bitwise the same results.
+// Returns the previous setting.
+bool set_gemm_tune_thread(bool on);
 // split-K workspace of the calling thread's GEMMs taken from p (bytes) instead of the shared
 // per-stream one while p is set (graph capture); the bytes a GEMM's split needs (0: none)
 void set_splitk_override(void *p, size_t bytes);

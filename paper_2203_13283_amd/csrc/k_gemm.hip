@@ -504,6 +504,7 @@ std::condition_variable g_tune_cv;
 std::map<TuneKey, int> g_tune;            // variant, or -1 while being measured
 std::atomic<int> g_tune_mode{1};
 std::atomic<int> g_tuned{0};
+thread_local bool t_tune_off = false;     // this thread's products take the 64 x 64 tile
 
 int ilog2c(int64_t x) {
     int l = 0;
@@ -515,7 +516,7 @@ template <typename T>
 int tuned_variant(int op, int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha,
                   const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, hipStream_t s) {
     const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
-    if (g_tune_mode.load() == 0 || tiles * S >= 512) return 0;
+    if (g_tune_mode.load() == 0 || t_tune_off || tiles * S >= 512) return 0;
     if (8.0 * (double)m * (double)n * (double)k > 3.5e10) return 0;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
@@ -574,6 +575,12 @@ int tuned_variant(int op, int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha,
 }  // namespace
 
 int set_gemm_autotune(int mode) { return g_tune_mode.exchange(mode ? 1 : 0); }
+
+bool set_gemm_tune_thread(bool on) {
+    const bool was = !t_tune_off;
+    t_tune_off = !on;
+    return was;
+}
 
 void set_splitk_override(void *p, size_t bytes) {
     t_ws_override = p;
