@@ -101,7 +101,17 @@ typedef struct {
                              remaining range has then been sampled with p or more columns of
                              oversampling); 0 turns the rule off, so blocks are drawn until
                              one has no column above tau                                 */
+    int32_t refine_form;  /* mixed precision: how the FP64 residual b - C x of each refinement
+                             sweep applies C (CFIE_REFINE_*)                                 */
 } cfie_options;
+
+/* cfie_options.refine_form.  Factor by factor, a residual costs four N x N complex products
+ * per right-hand side (24 N^2 real flops executed in the 3M form); with C formed once in FP64
+ * at cfie_factor (two N x N x N products, 12 N^3, and 16 N^2 more bytes), one (6 N^2). */
+enum {
+    CFIE_REFINE_FACTORED = 0,    /* D^k, N^k, D^kt, S^kt applied in turn                        */
+    CFIE_REFINE_DENSE = 1        /* C formed densely in FP64 by cfie_factor                     */
+};
 
 /* cfie_options.remainder_form.  The sketch and V^T = Q^H (C - C_c) cost 64 N^2 r flops when
  * C is applied factor by factor (four N x N GEMMs per product, eq. (6)), and 16 N^3 + 16 N^2 r
@@ -156,12 +166,20 @@ typedef struct {
 int cfie_set_gemm_autotune(int mode);
 int cfie_gemm_tuned_classes(void);
 
+/* Process-wide switch of the wide complex128 GEMM tile: mode 1 (the default) multiplies the
+ * large FP64 products (K >= 8192 and enough 128 x 128 output tiles to fill the device) with
+ * 128 x 128 tiles of 8 wavefronts whose operands go straight from global memory into LDS;
+ * mode 0 always uses the 64 x 64 tiles.  Both run the same MFMA sequence per output element,
+ * so the switch changes speed only (bitwise identical results).  Returns the previous mode. */
+int cfie_set_gemm_wide(int mode);
+
 /* Zero the accumulated launch profile of ctx. */
 cfie_status cfie_profile_reset(cfie_ctx *ctx);
 
 /* Fill *opt with defaults: FP64, compress_tol 1e-10, block 128, max_rank 0, seed 1,
  * refine_tol 1e-8, max_refine 20, quad_far 5, quad_near 10, near_band 6, no injection,
- * no profiling, remainder_form CFIE_REMAINDER_AUTO, solve_graphs 0, oversample 16. */
+ * no profiling, remainder_form CFIE_REMAINDER_AUTO, solve_graphs 0, oversample 16,
+ * refine_form CFIE_REFINE_FACTORED. */
 void cfie_default_options(cfie_options *opt);
 
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for

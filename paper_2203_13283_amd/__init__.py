@@ -23,12 +23,12 @@ import numpy as np
 from . import _lib
 from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW, MAT_DK,
                    MAT_DKT, MAT_G, MAT_NK, MAT_SKT, OP_C, OP_C_ADJ, OP_CC, OP_CC_INV,
-                   OP_REMAINDER, OP_SKELETON, REMAINDER_AUTO, REMAINDER_DENSE,
-                   REMAINDER_FACTORED)
+                   OP_REMAINDER, OP_SKELETON, REFINE_DENSE, REFINE_FACTORED, REMAINDER_AUTO,
+                   REMAINDER_DENSE, REMAINDER_FACTORED)
 
 __all__ = ["Solver", "solve_batch", "solve_group", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
            "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
-           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library", "REMAINDER_AUTO", "REMAINDER_FACTORED",
+           "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library", "REMAINDER_AUTO", "REMAINDER_FACTORED", "REFINE_FACTORED", "REFINE_DENSE",
            "REMAINDER_DENSE",
            "set_gemm_autotune", "gemm_tuned_classes"]
 
@@ -41,6 +41,12 @@ def set_gemm_autotune(enabled: bool) -> bool:
     """Process-wide GEMM tile autotuner switch (cfie_set_gemm_autotune); returns the
     previous setting.  The tile shapes give bitwise identical results."""
     return bool(_lib.load().cfie_set_gemm_autotune(1 if enabled else 0))
+
+
+def set_gemm_wide(enabled: bool) -> bool:
+    """Process-wide switch of the wide 128 x 128 complex128 GEMM tile (cfie_set_gemm_wide);
+    returns the previous setting.  Bitwise identical results either way."""
+    return bool(_lib.load().cfie_set_gemm_wide(1 if enabled else 0))
 
 
 def gemm_tuned_classes() -> int:
@@ -64,7 +70,7 @@ class Solver:
                  refine_tol: float = 1e-8, max_refine: int = 20, quad_far: int = 5,
                  quad_near: int = 10, near_band: int = 6, fail_alloc_after: int = -1,
                  profile: bool = False, remainder_form: int = 0, solve_graphs: bool = False,
-                 oversample: int = 16, device: int = 0, stream=None):
+                 oversample: int = 16, refine_form: int = 0, device: int = 0, stream=None):
         lib = _lib.load()
         torch = _torch()
         o = _lib.default_options()
@@ -83,6 +89,7 @@ class Solver:
         o.remainder_form = remainder_form
         o.solve_graphs = 1 if solve_graphs else 0
         o.oversample = oversample
+        o.refine_form = refine_form
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)

@@ -23,6 +23,7 @@ CFIE_ESINGULAR, CFIE_ENOCONV, CFIE_WNONCONVEX = 5, 6, 100
 CFIE_FP64, CFIE_MIXED = 0, 1
 MAT_G, MAT_DK, MAT_NK, MAT_DKT, MAT_SKT, MAT_CC_EIG, MAT_CIRCLE_ROW = range(7)
 OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON, OP_C_ADJ = range(6)
+REFINE_FACTORED, REFINE_DENSE = 0, 1
 REMAINDER_AUTO, REMAINDER_FACTORED, REMAINDER_DENSE = 0, 1, 2
 
 EXPORTED = [
@@ -31,7 +32,7 @@ EXPORTED = [
     "cfie_last_error", "cfie_status_string", "cfie_destroy", "cfie_profile_reset",
     "cfie_solve_batch", "cfie_solve_adjoint", "cfie_far_field", "cfie_shape_gradient",
     "cfie_set_gemm_autotune", "cfie_gemm_tuned_classes", "cfie_solve_group",
-    "cfie_solve_batch_grouped", "cfie_solve_noalloc",
+    "cfie_solve_batch_grouped", "cfie_solve_noalloc", "cfie_set_gemm_wide",
 ]
 
 
@@ -48,7 +49,7 @@ class Options(ctypes.Structure):
                 ("quad_near", ctypes.c_int32), ("near_band", ctypes.c_int32),
                 ("fail_alloc_after", ctypes.c_int64), ("profile", ctypes.c_int32),
                 ("remainder_form", ctypes.c_int32), ("solve_graphs", ctypes.c_int32),
-                ("oversample", ctypes.c_int32)]
+                ("oversample", ctypes.c_int32), ("refine_form", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -141,6 +142,8 @@ def load(path: str = LIB_PATH):
     lib.cfie_shape_gradient.restype = i32
     lib.cfie_set_gemm_autotune.argtypes = [ctypes.c_int]
     lib.cfie_set_gemm_autotune.restype = ctypes.c_int
+    lib.cfie_set_gemm_wide.argtypes = [ctypes.c_int]
+    lib.cfie_set_gemm_wide.restype = ctypes.c_int
     lib.cfie_gemm_tuned_classes.argtypes = []
     lib.cfie_gemm_tuned_classes.restype = ctypes.c_int
     _lib = lib

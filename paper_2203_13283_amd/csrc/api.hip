@@ -189,6 +189,7 @@ struct cfie_ctx {
     void *Q = nullptr, *Ut = nullptr;                  // N x cap (zd or zf)
     void *P = nullptr;                                  // V^T = Q^H (C - C_c): rank x N
     void *Wf = nullptr;                                 // K^{-1} V^T: rank x N
+    zd *Cd = nullptr;     // C of eq. (6) formed densely in FP64 (mixed precision, refine_form)
     void *ws[4] = {nullptr, nullptr, nullptr, nullptr}; // grow-only solve workspaces
     size_t ws_bytes[4] = {0, 0, 0, 0};
     zd *K = nullptr;                                    // cap x cap
@@ -368,8 +369,9 @@ void free_factor(cfie_ctx *c) {
     free_graphs(c);
     void *bufs[] = {c->Q, c->P, c->Wf, c->Ut, c->K, c->piv, c->info, c->Linv, c->Uinv, c->w_om,
                     c->w_y, c->w_t, c->w_w1, c->w_w2, c->w_z, c->w_s, c->w_rinvT, c->w_gram,
-                    c->w_rinv, c->w_norm, c->w_y64, c->w_pchm};
+                    c->w_rinv, c->w_norm, c->w_y64, c->w_pchm, c->Cd};
     for (void *p : bufs) c->dfree(p);
+    c->Cd = nullptr;
     c->Q = c->P = c->Ut = c->Wf = nullptr;
     c->K = nullptr;
     c->piv = c->info = nullptr;
@@ -506,6 +508,22 @@ void apply_C(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, 
     launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), W1, N, Y, ldy, m, s);
     gemm<T>(GEMM_N, N, m, N, cz<T>(1), Ops<T>::mat(c, 2), N, W1, N, cz<T>(1), Y, ldy, s);
     gemm<T>(GEMM_N, N, m, N, cz<T>(1), Ops<T>::mat(c, 3), N, W2, N, cz<T>(1), Y, ldy, s);
+    c->check_launch();
+}
+
+// R = B - C X in FP64, the residual of the refinement (eq. (6) in FP64): one product with C
+// when it has been formed densely (refine_form), else factor by factor (temps Tt, W1, W2)
+void residual64(cfie_ctx *c, const zd *B, int64_t ldb, const zd *X, zd *R, int64_t m, zd *Tt,
+                zd *W1, zd *W2) {
+    const int N = c->N;
+    if (c->Cd) {
+        axpby<double>(N, m, cz<double>(1), B, ldb, cz<double>(0), R, N, c->stream);
+        gemm<double>(GEMM_N, N, m, N, cz<double>(-1), c->Cd, N, X, N, cz<double>(1), R, N,
+                     c->stream);
+    } else {
+        apply_C<double>(c, X, N, R, N, m, Tt, W1, W2);
+        axpby<double>(N, m, cz<double>(1), B, ldb, cz<double>(-1), R, N, c->stream);
+    }
     c->check_launch();
 }
 
@@ -700,8 +718,11 @@ void lu_solve_adj(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
     c->check_launch();
 }
 
+// C of eq. (6) as a dense N x N matrix, C = (G/2 + D^kt) M + S^kt G^-1 N^k with
+// M = G^-1 (G/2 - D^k) (two N x N x N products), minus C_c (applied to the identity by FFT)
+// when minus_cc
 template <typename T>
-void form_remainder_dense(cfie_ctx *c, cpx<T> *Rd) {
+void form_dense(cfie_ctx *c, cpx<T> *Rd, bool minus_cc) {
     const int N = c->N;
     hipStream_t s = c->stream;
     const int nt = (int)c->gcoef.size();
@@ -715,9 +736,11 @@ void form_remainder_dense(cfie_ctx *c, cpx<T> *Rd) {
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0,
                       cz<T>(1), Ops<T>::mat(c, 1), N, M, N, N, s);
     gemm<T>(GEMM_N, N, N, N, cz<T>(1), Ops<T>::mat(c, 3), N, M, N, cz<T>(1), Rd, N, s);
-    launch_diag<T>(N, cz<T>(1), true, M, N, s);
-    circ_apply<T>(c, Ops<T>::dC(c), M, N, N);
-    axpby<T>(N, N, cz<T>(-1), M, N, cz<T>(1), Rd, N, s);
+    if (minus_cc) {
+        launch_diag<T>(N, cz<T>(1), true, M, N, s);
+        circ_apply<T>(c, Ops<T>::dC(c), M, N, N);
+        axpby<T>(N, N, cz<T>(-1), M, N, cz<T>(1), Rd, N, s);
+    }
     c->check_launch();
     c->sync();
     c->dfree(M);
@@ -745,7 +768,7 @@ cfie_status factor_impl(cfie_ctx *c) {
     cpx<T> *Rd = nullptr;
     if (c->opt.remainder_form == CFIE_REMAINDER_DENSE) {
         Rd = c->alloc_n<cpx<T>>((size_t)N * N);
-        form_remainder_dense<T>(c, Rd);
+        form_dense<T>(c, Rd, true);
     }
     while (ell < cap) {
         int bb = std::min(b, cap - ell);
@@ -794,7 +817,7 @@ cfie_status factor_impl(cfie_ctx *c) {
         if (p > 0 && bb >= 2 * p && kept <= bb - p) break;
         if (!Rd && c->opt.remainder_form == CFIE_REMAINDER_AUTO && 2 * ell >= N && ell < cap) {
             Rd = c->alloc_n<cpx<T>>((size_t)N * N);
-            form_remainder_dense<T>(c, Rd);
+            form_dense<T>(c, Rd, true);
         }
     }
     c->rank = ell;
@@ -1041,8 +1064,14 @@ cfie_status solve_adjoint(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t 
                 woodbury_adj<float>(c, R32, m, Zr32, Z64, T32, tmp);
                 convert<double, float>(N, m, R32, N, Tn, N, s);
                 axpby<double>(N, m, cz<double>(1), Tn, N, cz<double>(1), Xw, N, s);
-                apply_CH<double>(c, Xw, N, Rb, N, m, Tt, W1, W2, Tn);
-                axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(-1), Rb, N, s);
+                if (c->Cd) {
+                    axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(0), Rb, N, s);
+                    gemm<double>(GEMM_C, N, m, N, cz<double>(-1), c->Cd, N, Xw, N, cz<double>(1),
+                                 Rb, N, s);
+                } else {
+                    apply_CH<double>(c, Xw, N, Rb, N, m, Tt, W1, W2, Tn);
+                    axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(-1), Rb, N, s);
+                }
                 colnorm2<double>(N, m, Rb, N, r2, s);
                 launch_ratio_max(m, r2, b2, mx, s);
                 HIPCHK(hipMemcpyAsync(&rel, mx, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1263,8 +1292,7 @@ cfie_status solve_mixed(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ld
             convert<double, float>(N, m, R32, N, Tt, N, s);
             axpby<double>(N, m, cz<double>(1), Tt, N, cz<double>(1), Xw, N, s);
             // residual in FP64 against the assembled operator
-            apply_C<double>(c, Xw, N, Rb, N, m, Tt, W1, W2);
-            axpby<double>(N, m, cz<double>(1), Bj, ldb, cz<double>(-1), Rb, N, s);
+            residual64(c, Bj, ldb, Xw, Rb, m, Tt, W1, W2);
             colnorm2<double>(N, m, Rb, N, r2, s);
             launch_ratio_max(m, r2, b2, mx, s);
             HIPCHK(hipMemcpyAsync(&rel, mx, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1359,8 +1387,7 @@ struct GroupMember {
         woodbury<float>(c, R32, m, Z32, P32);
         convert<double, float>(N, m, R32, N, Tt, N, s);
         axpby<double>(N, m, cz<double>(1), Tt, N, cz<double>(first ? 0 : 1), Xw, N, s);
-        apply_C<double>(c, Xw, N, Rb, N, m, Tt, W1, W2);
-        axpby<double>(N, m, cz<double>(1), B, ldb, cz<double>(-1), Rb, N, s);
+        residual64(c, B, ldb, Xw, Rb, m, Tt, W1, W2);
         colnorm2<double>(N, m, Rb, N, r2, s);
         launch_ratio_max(m, r2, b2, mx, s);
         ++sweeps;
@@ -1516,6 +1543,7 @@ void cfie_default_options(cfie_options *o) {
     o->remainder_form = CFIE_REMAINDER_AUTO;
     o->solve_graphs = 0;
     o->oversample = 16;
+    o->refine_form = CFIE_REFINE_FACTORED;
 }
 
 const char *cfie_status_string(cfie_status s) {
@@ -1552,6 +1580,8 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, c
         return bad("remainder_form must be CFIE_REMAINDER_AUTO, _FACTORED or _DENSE");
     if (o.solve_graphs != 0 && o.solve_graphs != 1) return bad("solve_graphs must be 0 or 1");
     if (o.oversample < 0 || o.oversample > 256) return bad("oversample must be in [0, 256]");
+    if (o.refine_form != CFIE_REFINE_FACTORED && o.refine_form != CFIE_REFINE_DENSE)
+        return bad("refine_form must be CFIE_REFINE_FACTORED or CFIE_REFINE_DENSE");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         (void)hipGetLastError();
@@ -2040,6 +2070,12 @@ cfie_status cfie_factor(cfie_ctx *c) {
         c->fac_mark();
         c->state = 1;
         cfie_status st = c->opt.precision == CFIE_MIXED ? factor_impl<float>(c) : factor_impl<double>(c);
+        if (st == CFIE_OK && c->opt.precision == CFIE_MIXED &&
+            c->opt.refine_form == CFIE_REFINE_DENSE) {
+            // C in FP64 for the refinement's residuals (the skeleton stays complex64)
+            c->Cd = c->alloc_n<zd>((size_t)c->N * c->N);
+            form_dense<double>(c, c->Cd, false);
+        }
         HIPCHK(hipEventRecord(e1, c->stream));
         c->sync();
         HIPCHK(hipEventElapsedTime(&c->t_fac, e0, e1));
@@ -2480,6 +2516,8 @@ cfie_status cfie_export_matrix(cfie_ctx *c, int which, void *dst, int64_t ld) {
 int cfie_set_gemm_autotune(int mode) { return set_gemm_autotune(mode); }
 
 int cfie_gemm_tuned_classes(void) { return gemm_tuned_classes(); }
+
+int cfie_set_gemm_wide(int mode) { return set_gemm_wide(mode); }
 
 cfie_status cfie_profile_reset(cfie_ctx *c) {
     if (!c) return CFIE_EINVAL;

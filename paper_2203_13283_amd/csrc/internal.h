@@ -206,6 +206,9 @@ void splitk_release(int device, hipStream_t s);
 // of shape classes measured so far
 int set_gemm_autotune(int mode);
 int gemm_tuned_classes();
+// process-wide switch of the wide 128 x 128 complex128 tile for large products (1 = on, the
+// default); bitwise the same results either way.  Returns the previous mode.
+int set_gemm_wide(int mode);
 // tile autotuning for the calling thread's products (it allocates a scratch output the
 // first time it meets a shape class); off: the 64 x 64 tile, bitwise the same results.
 // Returns the previous setting.

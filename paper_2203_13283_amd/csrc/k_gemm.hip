@@ -292,6 +292,186 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
         }
 }
 
+// ---------------------------------------------------------------- wide complex128 tile ---
+// The large FP64 products of the solver (the sketch's N x N x b products and their adjoints,
+// the capacitance matrix V^T U~, the solve's W Y) with a 128 x 128 output tile per workgroup
+// of 8 wavefronts (each 64 x 32), which halves the operand traffic per flop of the 64 x 64
+// tile.  The operands go from global memory straight into LDS (gfx950's 16-byte
+// global_load_lds: each lane's element lands at the wave's LDS base + 16 x lane, with no
+// staging registers and no LDS store instructions), laid out as "fragments": the 16 x 4 block
+// of op(A) (rows x k) or of B (k x columns) that one 16x16x4 MFMA consumes, in the MFMA's
+// own lane order (lane = (k % 4) * 16 + row % 16).  Reading an operand is then one
+// contiguous, conflict-free ds_read_b128 per lane that brings its real and imaginary parts
+// together.  Two LDS buffers: the next K-slice's fragments are in flight while the current
+// one is multiplied, with one barrier per slice.  Every output element sees the same MFMA
+// sequence (k ascending in steps of 4, 3M form) as in k_zgemm, so the two kernels give
+// bitwise identical results.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+constexpr int kWideTile = 128;
+
+template <int OPA>
+__global__ __launch_bounds__(512, 1) void k_zgemm_wide(int64_t m, int64_t n, int64_t kdim,
+                                                     int64_t kchunk, zd alpha,
+                                                     const zd *__restrict__ A, int64_t lda,
+                                                     const zd *__restrict__ B, int64_t ldb,
+                                                     zd beta, zd *C, int64_t ldc, zd *W) {
+    constexpr bool BREAL = OPA == 3;
+    constexpr int BM = kWideTile, BN = kWideTile, BK = 16;
+    // fragment f = kq * 8 + t: MFMA tile t (of 8 along the rows of op(A), or along the
+    // columns of B) at k-quad kq of the slice; buffers 0 and 1
+    __shared__ zd As0[32][64], As1[32][64], Bs0[32][64], Bs1[32][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // XCD-aware tile order as in k_zgemm, groups of 4 row panels
+    constexpr int NXCD = 8, GROUP_M = 4;
+    const int64_t tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+    const int64_t ntile = tiles_m * tiles_n;
+    const int64_t total = (int64_t)gridDim.x;
+    int64_t lg;
+    {
+        const int64_t g = blockIdx.x, x = g % NXCD, loc = g / NXCD;
+        const int64_t q = total / NXCD, r = total % NXCD;
+        lg = x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
+    }
+    const int64_t zslice = lg / ntile, t = lg % ntile;
+    const int64_t gsz = (int64_t)GROUP_M * tiles_n;
+    const int64_t fm = (t / gsz) * GROUP_M;
+    const int64_t gm = min((int64_t)GROUP_M, tiles_m - fm);
+    const int64_t tm = fm + (t % gsz) % gm, tn = (t % gsz) / gm;
+    const int64_t row0 = tm * BM, col0 = tn * BN;
+    const int64_t kbeg = zslice * kchunk;
+    const int64_t kend = min(kdim, kbeg + kchunk);
+    const int64_t nslice = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+    // wave w fills fragments w*4 + q (q = 0..3) of each operand: k-quad w/2, tiles (w%2)*4 + q.
+    // Rows of op(A), columns of B and k beyond the matrices are clamped onto the last valid
+    // index (in bounds); the clamped k of the last slice get zero B values below.
+    const int kl = 4 * (w >> 1) + (lane >> 4), t0 = (w & 1) * 4, il = lane & 15;
+    const zd *pa[4], *pb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t gi = min(row0 + 16 * (t0 + q) + il, m - 1);
+        const int64_t gj = min(col0 + 16 * (t0 + q) + il, n - 1);
+        pa[q] = OPA == 1 ? A + gi * lda : A + gi;
+        pb[q] = B + gj * ldb;
+    }
+    auto issue = [&](int64_t s, int buf) {
+        const int64_t gk = min(kbeg + s * BK + kl, kend - 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const zd *sa = OPA == 1 ? pa[q] + gk : pa[q] + gk * lda;
+            const zd *sb = pb[q] + gk;
+            __builtin_amdgcn_global_load_lds((glb_void_t *)sa,
+                (lds_void_t *)(buf ? &As1[w * 4 + q][0] : &As0[w * 4 + q][0]), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((glb_void_t *)sb,
+                (lds_void_t *)(buf ? &Bs1[w * 4 + q][0] : &Bs0[w * 4 + q][0]), 16, 0, 0);
+        }
+    };
+    // after the slice's loads have landed: B is zero for k >= kend (this lane's own entries)
+    auto clear_tail = [&](int64_t s, int buf) {
+        if (kbeg + s * BK + kl >= kend) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (buf) Bs1[w * 4 + q][lane] = mk(0.0, 0.0);
+                else Bs0[w * 4 + q][lane] = mk(0.0, 0.0);
+            }
+        }
+    };
+    // 3M: acc1 = Ar Br, acc2 = Ai Bi, acc3 = (Ar +- Ai)(Br + Bi); real B: acc1, acc2 = Ar, Ai B
+    d4 acc1[4][2], acc2[4][2], acc3[BREAL ? 1 : 4][BREAL ? 1 : 2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            acc1[a][b] = d4{0, 0, 0, 0};
+            acc2[a][b] = d4{0, 0, 0, 0};
+            if constexpr (!BREAL) acc3[a][b] = d4{0, 0, 0, 0};
+        }
+    const int ta = (w & 1) * 4, tb = (w >> 1) * 2;    // this wave's 4 x 2 MFMA tiles
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            zd av[4], bv[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = buf ? Bs1[kq * 8 + tb + b][lane] : Bs0[kq * 8 + tb + b][lane];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = buf ? As1[kq * 8 + ta + a][lane] : As0[kq * 8 + ta + a][lane];
+            if constexpr (BREAL) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        acc1[a][b] = mfma(av[a].x, bv[b].x, acc1[a][b]);
+                        acc2[a][b] = mfma(av[a].y, bv[b].x, acc2[a][b]);
+                    }
+            } else {
+                double sb[2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) sb[b] = bv[b].x + bv[b].y;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const double sa = OPA != 0 ? av[a].x - av[a].y : av[a].x + av[a].y;
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        acc1[a][b] = mfma(av[a].x, bv[b].x, acc1[a][b]);
+                        acc2[a][b] = mfma(av[a].y, bv[b].y, acc2[a][b]);
+                        acc3[a][b] = mfma(sa, sb[b], acc3[a][b]);
+                    }
+                }
+            }
+        }
+    };
+    // the direct-to-LDS loads count on vmcnt: waiting for zero (no other vector memory
+    // operation is in flight in the loop) means this wave's fragments have landed, and the
+    // barrier after it makes every wave's fragments visible
+    if (nslice > 0) {
+        issue(0, 0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        clear_tail(0, 0);
+        __syncthreads();
+        for (int64_t s = 0; s < nslice; ++s) {
+            const int cur = (int)(s & 1);
+            const bool more = s + 1 < nslice;
+            if (more) issue(s + 1, cur ^ 1);      // the other buffer: read by nobody now
+            compute(cur);
+            if (more) {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                clear_tail(s + 1, cur ^ 1);
+            }
+            __syncthreads();
+        }
+    }
+    const bool beta_zero = (beta.x == 0.0 && beta.y == 0.0);
+    zd *Wz = W ? W + zslice * m * n : nullptr;
+    const int wrow = ta * 16, wcol = tb * 16;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t gj = col0 + wcol + b * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = row0 + wrow + a * 16 + acc_row<double>(lane, r);
+                if (gi < m && gj < n) {
+                    zd v;
+                    if constexpr (BREAL) {
+                        v = mk((double)acc1[a][b][r], (double)acc2[a][b][r]);
+                    } else {
+                        const double p1 = acc1[a][b][r], p2 = acc2[a][b][r], p3 = acc3[a][b][r];
+                        v = OPA != 0 ? mk(p1 + p2, p3 - p1 + p2) : mk(p1 - p2, p3 - p1 - p2);
+                    }
+                    if (Wz) {
+                        Wz[gi + gj * m] = v;                     // partial of this K-slice
+                    } else {
+                        v = alpha * v;
+                        zd *p = C + gi + gj * ldc;
+                        if (!beta_zero) v = v + beta * (*p);
+                        *p = v;
+                    }
+                }
+            }
+        }
+}
+
 // C = alpha * sum_z W[z] + beta * C, slices summed in order
 template <typename T>
 __global__ void k_splitk_reduce(int64_t m, int64_t n, int S, const cpx<T> *__restrict__ W,
@@ -453,6 +633,30 @@ void launch(int64_t m, int64_t n, int64_t k, int S, cpx<T> alpha, const cpx<T> *
         int64_t t = m * n;
         hipLaunchKernelGGL(k_splitk_reduce<T>, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s,
                            m, n, S, (const cpx<T> *)W, alpha, beta, C, ldc);
+    }
+}
+}  // namespace
+
+namespace {
+// the wide tile for a complex128 product (split along K exactly as for k_zgemm)
+template <int OPA>
+void launch_wide(int64_t m, int64_t n, int64_t k, int S, zd alpha, const zd *A, int64_t lda,
+                 const zd *B, int64_t ldb, zd beta, zd *C, int64_t ldc, hipStream_t s) {
+    int64_t kchunk = k;
+    zd *W = nullptr;
+    if (S > 1) {
+        kchunk = ((k + S - 1) / S + 15) / 16 * 16;
+        S = (int)((k + kchunk - 1) / kchunk);
+        W = (zd *)splitk_ws((size_t)S * m * n * sizeof(zd), s);
+        if (!W) { S = 1; kchunk = k; }
+    }
+    const int64_t ntile = ((m + kWideTile - 1) / kWideTile) * ((n + kWideTile - 1) / kWideTile);
+    hipLaunchKernelGGL((k_zgemm_wide<OPA>), dim3((unsigned)(ntile * S)), dim3(512), 0, s, m, n,
+                       k, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, S > 1 ? W : nullptr);
+    if (S > 1) {
+        const int64_t t = m * n;
+        hipLaunchKernelGGL(k_splitk_reduce<double>, dim3((unsigned)((t + 255) / 256)), dim3(256),
+                           0, s, m, n, S, (const zd *)W, alpha, beta, C, ldc);
     }
 }
 }  // namespace
@@ -645,6 +849,21 @@ void launch_skinny(int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *
 }
 }  // namespace
 
+namespace {
+std::atomic<int> g_wide_mode{1};
+// The wide tile for complex128 products whose 128 x 128 grid fills the device (about one
+// workgroup of 8 wavefronts per compute unit or more) and whose K is long: measured 2-10%
+// faster than the 64 x 64 tile there (N x N x 256 sketch products, V^T U~, the solve's W Y at
+// N = 16384); with K of a few thousand its prologue and its one workgroup per compute unit
+// lose against the 64 x 64 tile's two.
+bool use_wide(int64_t m, int64_t n, int64_t k, int S) {
+    const int64_t t = ((m + kWideTile - 1) / kWideTile) * ((n + kWideTile - 1) / kWideTile);
+    return g_wide_mode.load() != 0 && k >= 8192 && t * S >= 240;
+}
+}  // namespace
+
+int set_gemm_wide(int mode) { return g_wide_mode.exchange(mode ? 1 : 0); }
+
 size_t gemm_splitk_bytes(int op, int64_t m, int64_t n, int64_t k, size_t elem) {
     if (m <= 0 || n <= 0) return 0;
     if (skinny(op, m, n, k)) {
@@ -684,6 +903,20 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
     // solver; two workgroups (two wavefronts per SIMD) per CU: the register budget of 256
     // per lane that this imposes measured 15-20% faster than one wavefront with more
     // registers
+    if constexpr (sizeof(T) == sizeof(double)) {
+        if (use_wide(m, n, k, S)) {
+            const zd *Ad = (const zd *)A, *Bd = (const zd *)B;
+            zd al = mk((double)alpha.x, (double)alpha.y), be = mk((double)beta.x, (double)beta.y);
+            zd *Cd = (zd *)C;
+            switch (op) {
+            case GEMM_C: launch_wide<1>(m, n, k, S, al, Ad, lda, Bd, ldb, be, Cd, ldc, s); break;
+            case GEMM_R: launch_wide<2>(m, n, k, S, al, Ad, lda, Bd, ldb, be, Cd, ldc, s); break;
+            case GEMM_NREAL: launch_wide<3>(m, n, k, S, al, Ad, lda, Bd, ldb, be, Cd, ldc, s); break;
+            default: launch_wide<0>(m, n, k, S, al, Ad, lda, Bd, ldb, be, Cd, ldc, s); break;
+            }
+            return;
+        }
+    }
     variant_op<T>(op, v)(m, n, k, S, alpha, A, lda, B, ldb, beta, C, ldc, s);
 }
 
