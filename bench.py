@@ -44,6 +44,9 @@ def parse():
                     help="perturbed16384 (the metric), ellipse4096, ellipse256, batch64, "
                          "shapegrad8192 or serve16384")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--refine", choices=("factored", "dense"), default="dense",
+                    help="mixed precision: residuals factor by factor or with C formed densely "
+                         "in FP64 at factor time")
     ap.add_argument("--eps", type=float, default=None,
                     help="compression tolerance (default 1e-5 fp64, 1e-3 mixed)")
     ap.add_argument("--compare", action=argparse.BooleanOptionalAction, default=True,
@@ -71,10 +74,10 @@ def parse():
     return ap.parse_args()
 
 
-def step(P, w, prec, eps, profile, form=0):
+def step(P, w, prec, eps, profile, form=0, refine=0):
     import torch
     s = P.Solver(precision=prec, compress_tol=eps, block=256, refine_tol=1e-8,
-                 profile=profile, remainder_form=form)
+                 profile=profile, remainder_form=form, refine_form=refine)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.assemble(w.zhat, w.n_nodes, w.k)
@@ -440,8 +443,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     cold = None
+    refine = P.REFINE_DENSE if a.refine == "dense" else P.REFINE_FACTORED
     for _ in range(a.warmup):
-        s, B, X, _t = step(P, w, prec, eps, False, form)
+        s, B, X, _t = step(P, w, prec, eps, False, form, refine)
         cold = _t["setup_s"] if cold is None else cold
         del s, B, X
     torch.cuda.synchronize()
@@ -452,7 +456,7 @@ def main():
     for _ in range(a.steps):
         if last is not None:
             del last
-        s, B, X, t = step(P, w, prec, eps, a.profile, form)
+        s, B, X, t = step(P, w, prec, eps, a.profile, form, refine)
         cold = t["setup_s"] if cold is None else cold
         times.append(t)
         for name, (n, work, ms) in s.profile().items():
@@ -532,15 +536,25 @@ def main():
     if a.compare:
         other = P.CFIE_MIXED if prec == P.CFIE_FP64 else P.CFIE_FP64
         eps_o = 1e-3 if other == P.CFIE_MIXED else 1e-5
-        so, Bo, Xo, to = step(P, w, other, eps_o, False, form)
-        io = so.info()
-        res_o, err_o = accuracy(P, so, w, Bo, Xo)
-        out["compare"] = {"precision": "mixed" if other == P.CFIE_MIXED else "fp64",
-                          "compress_tol": eps_o, "value": nrhs / to["solve_s"],
-                          "setup_s": to["setup_s"], "rank": io["rank"],
-                          "refine_sweeps": io["refine_sweeps"], "rel_residual": res_o,
-                          "rel_err_vs_oracle": err_o}
-        del so, Bo, Xo
+        # mixed precision: the refinement's residual factor by factor and with C formed
+        # densely in FP64 at factor time
+        forms = (P.REFINE_FACTORED, P.REFINE_DENSE) if other == P.CFIE_MIXED else (0,)
+        legs = []
+        for rf in forms:
+            torch.cuda.empty_cache()
+            so, Bo, Xo, to = step(P, w, other, eps_o, False, form, rf)
+            io = so.info()
+            res_o, err_o = accuracy(P, so, w, Bo, Xo)
+            legs.append({"precision": "mixed" if other == P.CFIE_MIXED else "fp64",
+                         "compress_tol": eps_o, "value": nrhs / to["solve_s"],
+                         "setup_s": to["setup_s"], "rank": io["rank"],
+                         "refine_form": "dense" if rf == P.REFINE_DENSE else "factored",
+                         "refine_sweeps": io["refine_sweeps"], "rel_residual": res_o,
+                         "rel_err_vs_oracle": err_o})
+            del so, Bo, Xo
+        out["compare"] = legs[-1]
+        if len(legs) > 1:
+            out["compare_refine_factored"] = legs[0]
     if a.tight and prec == P.CFIE_FP64 and a.eps is None:
         # the FP64 path at the parity level of 1e-10 (nearly full rank at this size)
         torch.cuda.empty_cache()

@@ -83,13 +83,18 @@ def _check_case(name, eps_fp64, tol_fp64):
     assert e64 <= tol_fp64
     del s
     torch.cuda.empty_cache()
-    sm = P.Solver(precision=P.CFIE_MIXED, compress_tol=1e-3, block=256, refine_tol=1e-8)
-    sm.assemble(w.zhat, w.n_nodes, w.k).factor()
-    Xm = sm.solve(sm.plane_wave_rhs(ang)).cpu().numpy().T
-    em = _rel_err(Xm, g["x"])
-    im = sm.info()
-    print(f"{name}: mixed rank {im['rank']} sweeps {im['refine_sweeps']} rel.err {em:.2e}")
-    assert em <= 1e-6
+    for form in (P.REFINE_FACTORED, P.REFINE_DENSE):
+        sm = P.Solver(precision=P.CFIE_MIXED, compress_tol=1e-3, block=256, refine_tol=1e-8,
+                      refine_form=form)
+        sm.assemble(w.zhat, w.n_nodes, w.k).factor()
+        Xm = sm.solve(sm.plane_wave_rhs(ang)).cpu().numpy().T
+        em = _rel_err(Xm, g["x"])
+        im = sm.info()
+        print(f"{name}: mixed (refine form {form}) rank {im['rank']} sweeps "
+              f"{im['refine_sweeps']} rel.err {em:.2e}")
+        assert em <= 1e-6
+        del sm
+        torch.cuda.empty_cache()
 
 
 def test_ellipse4096_against_oracle():

@@ -258,19 +258,28 @@ def test_solve_non_power_of_two(N):
         assert err <= tol
 
 
-def test_mixed_precision_refinement(cfg1):
+@pytest.mark.parametrize("form", [0, 1])
+def test_mixed_precision_refinement(cfg1, form):
+    """Mixed precision with FP64 refinement, the residual applied factor by factor (form 0)
+    or with C formed densely in FP64 (form 1): both against the oracle, and the adjoint solve
+    against the oracle's C^H."""
     w, prob = cfg1
-    s = P.Solver(precision=P.CFIE_MIXED, compress_tol=1e-3, refine_tol=1e-8)
+    s = P.Solver(precision=P.CFIE_MIXED, compress_tol=1e-3, refine_tol=1e-8, refine_form=form)
     s.assemble(w.zhat, w.n_nodes, w.k).factor()
     B = s.plane_wave_rhs(w.angles)
     X = s.solve(B)
     info = s.info()
     x_ref = prob.solve(prob.rhs(w.angles))
     err = S.rel_err(_np(X).T, x_ref)
-    print(f"mixed: rank {info['rank']} sweeps {info['refine_sweeps']} "
+    print(f"mixed (refine form {form}): rank {info['rank']} sweeps {info['refine_sweeps']} "
           f"residual {info['refine_residual']:.2e} rel.err {err:.2e}")
     assert info["refine_residual"] <= 1e-8
     assert err <= 1e-6
+    Xa = s.solve_adjoint(B)
+    xa_ref = np.linalg.solve(prob.C.conj().T, _np(B).T)
+    erra = S.rel_err(_np(Xa).T, xa_ref)
+    print(f"mixed adjoint (refine form {form}): rel.err {erra:.2e}")
+    assert erra <= 1e-6
 
 
 def test_smallest_mesh():
