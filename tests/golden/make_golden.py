@@ -147,11 +147,17 @@ def make_fig5(Ns, workers: int, n_rhs: int = 16):
 
 
 def make_shapegrad_direction(N: int, workers: int, mmax: int = 64, n_inc: int = 16,
-                             fd_step: float = 1e-3, seed: int = 7):
+                             fd_step: float = 2e-5, seed: int = 7):
     """The shape-differentiation workload's loss (16 waves, 181 backscatter angles each) at N
     nodes with all 128 shape coefficients, and its derivative along one seeded unit direction
     of the coefficients by central differences with two Richardson extrapolations of the
-    oracle's dense solve (six solves)."""
+    oracle's dense solve (six solves).
+
+    Step: a unit step along the direction moves the contour by up to about ten units of
+    length (the sum of the direction's 128 components), so the loss's phases (k about 200 at
+    N = 2048) vary on steps of about 1/(10 k) = 5e-4; h = 2e-5 keeps the extrapolation's
+    O(h^6) remainder below 1e-9 relative, and the loss's rounding (about 1e-14 relative)
+    gives about 1e-8 after the differences.  (h = 1e-3 left a 7e-6 remainder.)"""
     from oracle import gradient as G
     pr = W.shape_problem(N=N, mmax=mmax, n_inc=n_inc)
     p0 = np.concatenate([pr["s"], pr["t"]])

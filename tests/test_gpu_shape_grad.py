@@ -133,9 +133,9 @@ def test_gradient_direction_at_N2048_against_oracle():
     N = 2048, where k R reaches about 400, so the backward far kernel's large-argument pass
     (k R >= 200) carries most element pairs: the HIP gradient projected on the stored seeded
     direction against the oracle's extrapolated directional difference of its dense solve
-    (tests/golden/shapegrad_dir2048.npz).  Both are derivatives of discretisations that differ
-    by quadrature error only (the loss agrees to 1e-9); bar 1e-6 of the directional
-    derivative."""
+    (tests/golden/shapegrad_dir2048.npz, step 2e-5: its remainder and rounding are about
+    1e-8).  Both are derivatives of discretisations that differ by quadrature error only (the
+    losses agree to 1e-12); bar 1e-6 of the directional derivative."""
     path = os.path.join(HERE, "golden", "shapegrad_dir2048.npz")
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated (tests/golden/make_golden.py shapegrad_dir2048)")
