@@ -368,6 +368,45 @@ cfie_status cfie_solve_group(cfie_ctx *const *ctxs, int64_t n, const void *const
 cfie_status cfie_solve_batch_grouped(const cfie_options *opt, int device, int n_streams,
                                      cfie_batch_item *items, int64_t n_items, int32_t sweeps);
 
+/* A batch recorded as one HIP graph (the whole path of every problem in one launch). */
+typedef struct cfie_batch cfie_batch;
+
+/* Sec. II-V for many problems at once, recorded for one launch per batch.  Each item (as for
+ * cfie_solve_batch; nrhs <= 4096, X_dev its N x nrhs solutions with ld = N) is first run once
+ * on a HIP stream of its own with opt -- assembly, the adaptive randomized skeleton and LU,
+ * the plane-wave right-hand sides, the solve (mixed precision: refinement until refine_tol)
+ * -- which writes its solutions and fills status, rank, refine_residual and t_ms.  That run
+ * records the sketch's block schedule (block widths, directions kept per block, Gram-Schmidt
+ * passes, where it stopped) and the number of refinement sweeps, and keeps every work
+ * buffer.  Then the whole batch is recorded as one HIP graph: a fork, one branch per item
+ * that replays its path from the schedule with no host interaction (assembly, skeleton with
+ * the recorded block widths and kept counts, capacitance LU, right-hand sides, solve with
+ * the recorded sweep count), a join.  The items' contours, wavenumbers, angles and X_dev are
+ * fixed by this call.  Device memory holds every item's matrices and buffers until
+ * cfie_batch_destroy.  Errors: EINVAL for NULL arguments, n_items < 1, an item with nrhs
+ * outside [0, 4096] or NULL X_dev / angles_host; any error of an item's path (message via
+ * cfie_last_error(NULL)); EHIP if recording fails.  *out is set only on success.
+ * DISABLED in this version: after the argument checks it returns EHIP (message via
+ * cfie_last_error(NULL)) without any HIP call, because the recording has ended its host
+ * process with a segmentation fault on the device for a cause not yet found. */
+cfie_status cfie_batch_record(const cfie_options *opt, int device, cfie_batch_item *items,
+                              int64_t n_items, cfie_batch **out);
+
+/* One launch of the recorded batch: every item's whole path runs again on the device and its
+ * solutions are written to the X_dev given to cfie_batch_record.  Device-side checks compare
+ * each replay with its plan: a block whose kept count differs from the recorded one, or a
+ * final block whose remainder is not below tau, gives ENOCONV for that item (its result is
+ * then not to be used); a zero pivot ESINGULAR; mixed precision above refine_tol after the
+ * recorded sweeps ENOCONV.  items (the same n_items as recorded) receive status, rank,
+ * refine_residual and t_ms (the launch's wall time).  Returns the first item error, else OK. */
+cfie_status cfie_batch_launch(cfie_batch *b, cfie_batch_item *items, int64_t n_items);
+
+/* Number of nodes of the recorded graph (0 for NULL). */
+int64_t cfie_batch_nodes(const cfie_batch *b);
+
+/* Release the graph, the streams and every item's device buffers.  NULL is ignored. */
+void cfie_batch_destroy(cfie_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

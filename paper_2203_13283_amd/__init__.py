@@ -26,7 +26,7 @@ from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW,
                    OP_REMAINDER, OP_SKELETON, REFINE_DENSE, REFINE_FACTORED, REMAINDER_AUTO,
                    REMAINDER_DENSE, REMAINDER_FACTORED)
 
-__all__ = ["Solver", "solve_batch", "solve_group", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
+__all__ = ["Solver", "solve_batch", "solve_group", "RecordedBatch", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
            "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
            "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library", "REMAINDER_AUTO", "REMAINDER_FACTORED", "REFINE_FACTORED", "REFINE_DENSE",
            "REMAINDER_DENSE",
@@ -345,6 +345,88 @@ def solve_group(solvers, rhs, sweeps: int = 2, out=None):
     return outs
 
 
+def _batch_items(problems, device, torch):
+    """ctypes batch items for problems (dicts with zhat, n_nodes, k, angles), the solution
+    tensors they point at and the host arrays that must outlive the call."""
+    n = len(problems)
+    items = (_lib.BatchItem * n)()
+    keep, sols = [], []
+    for i, pr in enumerate(problems):
+        zh = np.ascontiguousarray(np.asarray(pr["zhat"], dtype=np.complex128))
+        zbuf = np.ascontiguousarray(np.stack([zh.real, zh.imag], axis=-1).reshape(-1))
+        ang = np.ascontiguousarray(np.asarray(pr["angles"], dtype=np.float64))
+        N = int(pr["n_nodes"])
+        X = torch.empty((ang.size, N), dtype=torch.complex128, device=f"cuda:{device}")
+        keep += [zbuf, ang]
+        sols.append(X)
+        it = items[i]
+        it.contour.n_nodes = N
+        it.contour.n_modes = (zh.size - 1) // 2
+        it.contour.zhat = zbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        it.k = float(pr["k"])
+        it.angles_host = ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        it.nrhs = ang.size
+        it.X_dev = X.data_ptr() if ang.size else None
+    return items, sols, keep
+
+
+def _batch_results(items):
+    return [dict(status=it.status, rank=it.rank, refine_residual=it.refine_residual,
+                 t_ms=it.t_ms) for it in items]
+
+
+class RecordedBatch:
+    """Many problems recorded as one HIP graph (cfie_batch_record): the constructor runs every
+    problem once (planning; `solutions` and `results` hold that run's output) and records the
+    batch; launch() runs every problem's whole path -- assembly, skeleton, LU, right-hand sides,
+    solve -- in one graph launch, writing `solutions` again, and returns the per-problem
+    results (status 0 when the replay reproduced its plan).
+
+    Disabled in this version: cfie_batch_record reports CFIE_EHIP (recording ended the host
+    process with a segmentation fault on the GPU, cause not yet found), so the constructor
+    raises CfieError."""
+
+    def __init__(self, problems, precision: int = CFIE_FP64, compress_tol: float = 1e-10,
+                 block: int = 128, refine_tol: float = 1e-8, device: int = 0, **options):
+        torch = _torch()
+        self._lib = lib = _lib.load()
+        o = _lib.default_options()
+        o.precision = precision
+        o.compress_tol = compress_tol
+        o.block = block
+        o.refine_tol = refine_tol
+        for key, val in options.items():
+            setattr(o, key, val)
+        self._items, self.solutions, self._keep = _batch_items(problems, device, torch)
+        torch.cuda.synchronize(device)
+        h = ctypes.c_void_p()
+        st = lib.cfie_batch_record(ctypes.byref(o), device, self._items, len(problems),
+                                   ctypes.byref(h))
+        if st != 0:
+            raise CfieError(st, "cfie_batch_record", lib.cfie_last_error(None).decode())
+        self._h = h
+        self.results = _batch_results(self._items)
+        self.nodes = int(lib.cfie_batch_nodes(h))
+
+    def launch(self):
+        st = self._lib.cfie_batch_launch(self._h, self._items, len(self._items))
+        self.results = _batch_results(self._items)
+        if st != 0:
+            raise CfieError(st, "cfie_batch_launch", self._lib.cfie_last_error(None).decode())
+        return self.results
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cfie_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def solve_batch(problems, precision: int = CFIE_FP64, compress_tol: float = 1e-10,
                 block: int = 128, refine_tol: float = 1e-8, n_streams: int = 4,
                 device: int = 0, grouped: bool = False, sweeps: int = 2, **options):
@@ -366,34 +448,14 @@ def solve_batch(problems, precision: int = CFIE_FP64, compress_tol: float = 1e-1
     for key, val in options.items():
         setattr(o, key, val)
     n = len(problems)
-    items = (_lib.BatchItem * n)()
-    keep = []
-    sols = []
-    for i, pr in enumerate(problems):
-        zh = np.ascontiguousarray(np.asarray(pr["zhat"], dtype=np.complex128))
-        zbuf = np.ascontiguousarray(np.stack([zh.real, zh.imag], axis=-1).reshape(-1))
-        ang = np.ascontiguousarray(np.asarray(pr["angles"], dtype=np.float64))
-        N = int(pr["n_nodes"])
-        X = torch.empty((ang.size, N), dtype=torch.complex128, device=f"cuda:{device}")
-        keep += [zbuf, ang]
-        sols.append(X)
-        it = items[i]
-        it.contour.n_nodes = N
-        it.contour.n_modes = (zh.size - 1) // 2
-        it.contour.zhat = zbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        it.k = float(pr["k"])
-        it.angles_host = ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        it.nrhs = ang.size
-        it.X_dev = X.data_ptr() if ang.size else None
+    items, sols, keep = _batch_items(problems, device, torch)
     torch.cuda.synchronize(device)
     if grouped:
         st = lib.cfie_solve_batch_grouped(ctypes.byref(o), device, n_streams, items, n,
                                           int(sweeps))
     else:
         st = lib.cfie_solve_batch(ctypes.byref(o), device, n_streams, items, n)
-    results = [dict(status=items[i].status, rank=items[i].rank,
-                    refine_residual=items[i].refine_residual, t_ms=items[i].t_ms)
-               for i in range(n)]
+    results = _batch_results(items)
     if st != 0:
         bad = [i for i in range(n) if results[i]["status"] not in (0, 100)]
         raise CfieError(st, "cfie_solve_batch" + ("_grouped" if grouped else ""),

@@ -33,6 +33,7 @@ EXPORTED = [
     "cfie_solve_batch", "cfie_solve_adjoint", "cfie_far_field", "cfie_shape_gradient",
     "cfie_set_gemm_autotune", "cfie_gemm_tuned_classes", "cfie_solve_group",
     "cfie_solve_batch_grouped", "cfie_solve_noalloc", "cfie_set_gemm_wide",
+    "cfie_batch_record", "cfie_batch_launch", "cfie_batch_nodes", "cfie_batch_destroy",
 ]
 
 
@@ -142,6 +143,15 @@ def load(path: str = LIB_PATH):
     lib.cfie_shape_gradient.restype = i32
     lib.cfie_set_gemm_autotune.argtypes = [ctypes.c_int]
     lib.cfie_set_gemm_autotune.restype = ctypes.c_int
+    lib.cfie_batch_record.argtypes = [ctypes.POINTER(Options), ctypes.c_int,
+                                      ctypes.POINTER(BatchItem), i64, ctypes.POINTER(vp)]
+    lib.cfie_batch_record.restype = i32
+    lib.cfie_batch_launch.argtypes = [vp, ctypes.POINTER(BatchItem), i64]
+    lib.cfie_batch_launch.restype = i32
+    lib.cfie_batch_nodes.argtypes = [vp]
+    lib.cfie_batch_nodes.restype = i64
+    lib.cfie_batch_destroy.argtypes = [vp]
+    lib.cfie_batch_destroy.restype = None
     lib.cfie_set_gemm_wide.argtypes = [ctypes.c_int]
     lib.cfie_set_gemm_wide.restype = ctypes.c_int
     lib.cfie_gemm_tuned_classes.argtypes = []

@@ -67,6 +67,9 @@ void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s);
 // A = a I (set) or A += a I on the diagonal (n x n)
 template <typename T>
 void launch_diag(int64_t n, cpx<T> a, bool set, cpx<T> *A, int64_t lda, hipStream_t s);
+void launch_fill_int(int n, int v, int *p, hipStream_t s);
+void launch_replay_check(int n, const double *norms2, double tau2, int probe, const int *kdev,
+                         int planned, int bit, int *flag, hipStream_t s);
 void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out,
                       hipStream_t s);
 size_t pchol_workspace_elems(int b);
@@ -159,7 +162,7 @@ struct cfie_ctx {
     int fmk_n = 0;
     float t_fphase[4] = {0, 0, 0, 0};
     void fac_mark() {
-        if (fmk_n < 5 && fmk[fmk_n]) HIPCHK(hipEventRecord(fmk[fmk_n++], stream));
+        if (rec_mode != 2 && fmk_n < 5 && fmk[fmk_n]) HIPCHK(hipEventRecord(fmk[fmk_n++], stream));
     }
     int refine_sweeps = 0;
     double refine_res = 0.0;
@@ -210,6 +213,22 @@ struct cfie_ctx {
     std::map<int64_t, SolveGraph> graphs;
     // this device's address of noalloc_scratch (nullptr if it could not be resolved)
     void *noalloc_ws = nullptr;
+
+    // Recorded batches (cfie_batch_record): rec_mode 1 plans -- the adaptive path, which
+    // also records the sketch's block schedule and keeps every temporary buffer in `keep`;
+    // rec_mode 2 replays -- the same kernel sequence from the schedule, with no host read, no
+    // allocation and no memset, so that it can be recorded in a HIP graph.
+    struct BlockPlan {
+        int bb = 0, passes = 0, kept = 0;
+        bool probe = false;         // the block whose norms fell to tau: the sketch stopped
+        bool dense_before = false;  // C - C_c formed densely before this block
+    };
+    int rec_mode = 0;
+    std::vector<BlockPlan> sched;
+    bool sched_dense_end = false;     // C - C_c formed densely after the last block
+    std::map<int, void *> keep;       // kept temporaries by slot
+    std::map<int, size_t> keep_bytes;
+    int *rec_flags = nullptr;         // device: replay checks (0 = schedule reproduced)
 
     ~cfie_ctx() {
         for (auto &kv : graphs)
@@ -262,6 +281,47 @@ struct cfie_ctx {
         }
     }
     template <typename T> T *alloc_n(size_t n) { return (T *)dalloc(n * sizeof(T)); }
+    // A temporary of the factorisation or the assembly: an ordinary allocation, or in a
+    // planned or replayed context the buffer kept for this slot (allocated while planning,
+    // reused by the replay, which may not allocate).
+    template <typename T> T *tmp_buf(int slot, size_t n) {
+        if (rec_mode == 0) return alloc_n<T>(n);
+        const size_t need = n * sizeof(T);
+        auto it = keep.find(slot);
+        if (it != keep.end() && keep_bytes[slot] >= need) return (T *)it->second;
+        if (rec_mode == 2)
+            throw HipError{CFIE_EINVAL, "replay needs a buffer that planning did not keep"};
+        if (it != keep.end()) {
+            dfree(it->second);
+            keep.erase(it);
+        }
+        std::vector<void *> *saved = tmp_track;
+        tmp_track = nullptr;
+        void *p = nullptr;
+        try {
+            p = dalloc(need);
+        } catch (...) {
+            tmp_track = saved;
+            throw;
+        }
+        tmp_track = saved;
+        keep[slot] = p;
+        keep_bytes[slot] = need;
+        return (T *)p;
+    }
+    // release a temporary from tmp_buf: freed (after the stream drains) in a plain context,
+    // kept otherwise
+    void tmp_free(void *p) {
+        if (rec_mode != 0 || !p) return;
+        sync();
+        dfree(p);
+    }
+    // kept temporaries released (a new problem on a planned context)
+    void drop_keep() {
+        for (auto &kv : keep) dfree(kv.second);
+        keep.clear();
+        keep_bytes.clear();
+    }
     // grow-only scratch that survives between calls (solve batches of the same size reuse it)
     template <typename T> T *scratch(int slot, size_t n) {
         size_t need = n * sizeof(T);
@@ -581,7 +641,7 @@ void gram64(cfie_ctx *c, const cpx<T> *Y, int b, zd *W) {
 // directions whose norm exceeds max(tau, rel * largest column norm), which also drops
 // directions that are rounding noise; two plain Cholesky-QR passes follow.
 template <typename T>
-int orthonormalise(cfie_ctx *c, cpx<T> *Y, int b, double tau) {
+int orthonormalise(cfie_ctx *c, cpx<T> *Y, int b, double tau, int planned = -1) {
     const int N = c->N;
     hipStream_t s = c->stream;
     cpx<T> *rinvT = (cpx<T> *)c->w_rinvT;
@@ -590,8 +650,14 @@ int orthonormalise(cfie_ctx *c, cpx<T> *Y, int b, double tau) {
     gram64<T>(c, Y, b, c->w_gram);
     launch_pchol(b, c->w_gram, b, tau * tau, rel2, c->w_rinv, b, c->w_pchm, c->info + 1, s);
     int k = 0;
-    HIPCHK(hipMemcpyAsync(&k, c->info + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    c->sync();
+    if (planned >= 0) {
+        // replay: the recorded count, checked on the device against the one found now
+        launch_replay_check(0, nullptr, 0.0, 0, c->info + 1, planned, 2, c->rec_flags, s);
+        k = planned;
+    } else {
+        HIPCHK(hipMemcpyAsync(&k, c->info + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        c->sync();
+    }
     if (k <= 0) return 0;
     convert<T, double>(b, k, c->w_rinv, b, rinvT, b, s);
     gemm<T>(GEMM_N, N, k, b, cz<T>(1), Y, N, rinvT, b, cz<T>(0), Y2, N, s);
@@ -718,6 +784,15 @@ void lu_solve_adj(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
     c->check_launch();
 }
 
+// slots of the temporaries kept by planned and replayed contexts (cfie_ctx::tmp_buf)
+enum {
+    SLOT_DENSE_M = 1, SLOT_RD, SLOT_RHQ, SLOT_K32, SLOT_LU_TMP, SLOT_LU_LP, SLOT_LU_PANEL,
+    SLOT_W64, SLOT_TMPN, SLOT_CD,
+    SLOT_BAND_WS, SLOT_NEAR_WS, SLOT_BAND_WS_C, SLOT_NEAR_WS_C, SLOT_EIG_NAT, SLOT_EIG_NATF,
+    SLOT_EIG_WORK,
+    SLOT_RHS_ANG, SLOT_RHS_E, SLOT_RHS_H, SLOT_RHS_GE, SLOT_RHS_GH, SLOT_RHS_B
+};
+
 // C of eq. (6) as a dense N x N matrix, C = (G/2 + D^kt) M + S^kt G^-1 N^k with
 // M = G^-1 (G/2 - D^k) (two N x N x N products), minus C_c (applied to the identity by FFT)
 // when minus_cc
@@ -727,7 +802,7 @@ void form_dense(cfie_ctx *c, cpx<T> *Rd, bool minus_cc) {
     hipStream_t s = c->stream;
     const int nt = (int)c->gcoef.size();
     const double h = c->hg.L / N;
-    cpx<T> *M = c->alloc_n<cpx<T>>((size_t)N * N);
+    cpx<T> *M = c->tmp_buf<cpx<T>>(SLOT_DENSE_M, (size_t)N * N);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0,
                       cz<T>(-1), Ops<T>::mat(c, 0), N, M, N, N, s);
     launch_diag<T>(N, cz<T>(0.5), false, M, N, s);
@@ -742,15 +817,17 @@ void form_dense(cfie_ctx *c, cpx<T> *Rd, bool minus_cc) {
         axpby<T>(N, N, cz<T>(-1), M, N, cz<T>(1), Rd, N, s);
     }
     c->check_launch();
-    c->sync();
-    c->dfree(M);
+    c->tmp_free(M);
 }
 
 template <typename T>
 cfie_status factor_impl(cfie_ctx *c) {
     const int N = c->N;
     hipStream_t s = c->stream;
-    alloc_factor<T>(c);
+    // replay (rec_mode 2): the buffers of the planning run, its block schedule, no host read
+    const bool replay = c->rec_mode == 2;
+    if (!replay) alloc_factor<T>(c);
+    if (c->rec_mode == 1) c->sched.clear();
     const int cap = c->cap;
     const int b = std::min(c->opt.block, N);
     cpx<T> *Q = (cpx<T> *)c->Q;
@@ -767,11 +844,27 @@ cfie_status factor_impl(cfie_ctx *c) {
     // rank has reached N/2 in the automatic mode)
     cpx<T> *Rd = nullptr;
     if (c->opt.remainder_form == CFIE_REMAINDER_DENSE) {
-        Rd = c->alloc_n<cpx<T>>((size_t)N * N);
+        Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
         form_dense<T>(c, Rd, true);
     }
-    while (ell < cap) {
-        int bb = std::min(b, cap - ell);
+    if (replay) launch_fill_int(1, 0, c->rec_flags, s);
+    launch_fill_int(1, 0, c->info, s);                 // pivot flag (also for rank 0)
+    size_t bi = 0;                                     // block index (schedule of a replay)
+    bool pending_dense = false;     // C - C_c was just formed densely (automatic switch)
+    while (replay ? bi < c->sched.size() : ell < cap) {
+        cfie_ctx::BlockPlan bp;
+        if (replay) {
+            bp = c->sched[bi];
+            if (bp.dense_before && !Rd) {
+                Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
+                form_dense<T>(c, Rd, true);
+            }
+        } else {
+            bp.bb = std::min(b, cap - ell);
+            bp.dense_before = pending_dense;
+            pending_dense = false;
+        }
+        const int bb = bp.bb;
         randn<T>(N, bb, c->opt.seed, blk++, Om, N, s);    // real Gaussian block
         if (Rd)
             gemm<T>(GEMM_NREAL, N, bb, N, cz<T>(1), Rd, N, Om, N, cz<T>(0), Y, N, s);
@@ -790,24 +883,42 @@ cfie_status factor_impl(cfie_ctx *c) {
             const bool one = sizeof(T) == sizeof(double) && tau > 0.0 &&
                              u * y_first * y_first / (tau * c->cc_norm) <=
                                  0.01 * c->opt.compress_tol;
-            const int passes = one ? 1 : 2;
+            const int passes = replay ? bp.passes : one ? 1 : 2;
+            bp.passes = passes;
             for (int pass = 0; pass < passes; ++pass) {
                 gemm<T>(GEMM_C, ell, bb, N, cz<T>(1), Q, N, Y, N, cz<T>(0), S, ell, s);
                 gemm<T>(GEMM_N, N, bb, ell, cz<T>(-1), Q, N, S, ell, cz<T>(1), Y, N, s);
             }
         }
         colnorm2<T>(N, bb, Y, N, c->w_norm, s);
-        HIPCHK(hipMemcpyAsync(nrm.data(), c->w_norm, bb * sizeof(double), hipMemcpyDeviceToHost, s));
-        c->sync();
-        double mx = 0.0;
-        for (int i = 0; i < bb; ++i) mx = std::max(mx, nrm[i]);
-        c->remainder_est = std::sqrt(mx);
-        if (ell == 0) y_first = c->remainder_est;
-        if (c->remainder_est <= tau) break;
-        int kept = orthonormalise<T>(c, Y, bb, tau);
+        if (replay) {
+            if (bp.probe) {
+                // the planned sketch stopped here: the remainder must still be below tau
+                launch_replay_check(bb, c->w_norm, tau * tau, 1, nullptr, 0, 1, c->rec_flags, s);
+                break;
+            }
+        } else {
+            HIPCHK(hipMemcpyAsync(nrm.data(), c->w_norm, bb * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            c->sync();
+            double mx = 0.0;
+            for (int i = 0; i < bb; ++i) mx = std::max(mx, nrm[i]);
+            c->remainder_est = std::sqrt(mx);
+            if (ell == 0) y_first = c->remainder_est;
+            if (c->remainder_est <= tau) {
+                bp.probe = true;
+                if (c->rec_mode == 1) c->sched.push_back(bp);
+                break;
+            }
+        }
+        int kept = orthonormalise<T>(c, Y, bb, tau, replay ? bp.kept : -1);
+        bp.kept = kept;
+        if (c->rec_mode == 1) c->sched.push_back(bp);
+        ++bi;
         if (kept == 0) break;
         axpby<T>(N, kept, cz<T>(1), Y, N, cz<T>(0), Q + (size_t)ell * N, N, s);
         ell += kept;
+        if (replay) continue;
         // a Gaussian block that kept at most bb - p directions above tau has sampled the
         // remaining range with at least p columns of oversampling: the remainder left after
         // it exceeds tau only with a probability that falls geometrically with p (Halko,
@@ -816,54 +927,55 @@ cfie_status factor_impl(cfie_ctx *c) {
         const int p = c->opt.oversample;
         if (p > 0 && bb >= 2 * p && kept <= bb - p) break;
         if (!Rd && c->opt.remainder_form == CFIE_REMAINDER_AUTO && 2 * ell >= N && ell < cap) {
-            Rd = c->alloc_n<cpx<T>>((size_t)N * N);
+            Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
             form_dense<T>(c, Rd, true);
+            pending_dense = true;           // a replay forms it before the next block
         }
+    }
+    // the automatic switch after the last block: a replay forms C - C_c here
+    if (c->rec_mode == 1) c->sched_dense_end = pending_dense;
+    if (replay && c->sched_dense_end && !Rd) {
+        Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
+        form_dense<T>(c, Rd, true);
     }
     c->rank = ell;
     c->fac_mark();                                     // end of the range finder
     if (ell == 0) {
-        if (Rd) {
-            c->sync();
-            c->dfree(Rd);
-        }
+        c->tmp_free(Rd);
         c->state = 2;
         return CFIE_OK;
     }
     // V^T = Q^H (C - C_c) = ((C - C_c)^H Q)^H, stored as an ell x N matrix; Ut = C_c^{-1} Q
-    c->P = c->alloc_n<cpx<T>>((size_t)N * ell);
+    if (!replay) c->P = c->alloc_n<cpx<T>>((size_t)N * ell);
     cpx<T> *P = (cpx<T> *)c->P;
     if (Rd) {
         gemm<T>(GEMM_C, ell, N, N, cz<T>(1), Q, N, Rd, N, cz<T>(0), P, ell, s);
-        c->sync();
-        c->dfree(Rd);
+        c->tmp_free(Rd);
         Rd = nullptr;
     } else {
-        cpx<T> *RHQ = (cpx<T> *)c->alloc_n<cpx<T>>((size_t)N * ell);
+        cpx<T> *RHQ = c->tmp_buf<cpx<T>>(SLOT_RHQ, (size_t)N * ell);
         for (int j = 0; j < ell; j += b) {
             int bb = std::min(b, ell - j);
             apply_RH<T>(c, Q + (size_t)j * N, N, RHQ + (size_t)j * N, N, bb, Tt, W1, W2, Z);
         }
         conj_transpose<T>(true, N, ell, RHQ, N, P, ell, s);
-        c->sync();
-        c->dfree(RHQ);
+        c->tmp_free(RHQ);
     }
-    c->Ut = c->alloc_n<cpx<T>>((size_t)N * ell);
+    if (!replay) c->Ut = c->alloc_n<cpx<T>>((size_t)N * ell);
     cpx<T> *Ut = (cpx<T> *)c->Ut;
     axpby<T>(N, ell, cz<T>(1), Q, N, cz<T>(0), Ut, N, s);
     circ_apply<T>(c, Ops<T>::dCinv(c), Ut, N, ell);
     c->fac_mark();                                     // end of V^T and U~
     // K = I + P^H Ut  (Woodbury capacitance, eq. (9)), always complex128
-    c->K = c->alloc_n<zd>((size_t)cap * cap);
+    if (!replay) c->K = c->alloc_n<zd>((size_t)cap * cap);
     if (sizeof(T) == sizeof(double)) {
         gemm<double>(GEMM_N, ell, ell, N, cz<double>(1), (const zd *)P, ell, (const zd *)Ut, N,
                      cz<double>(0), c->K, cap, s);
     } else {
-        cpx<T> *K32 = (cpx<T> *)c->alloc_n<cpx<T>>((size_t)ell * ell);
+        cpx<T> *K32 = c->tmp_buf<cpx<T>>(SLOT_K32, (size_t)ell * ell);
         gemm<T>(GEMM_N, ell, ell, N, cz<T>(1), P, ell, Ut, N, cz<T>(0), K32, ell, s);
         convert<double, T>(ell, ell, K32, ell, c->K, cap, s);
-        c->sync();
-        c->dfree(K32);
+        c->tmp_free(K32);
     }
     launch_add_identity(ell, c->K, cap, s);
     // blocked LU with partial pivoting in two levels: superpanels of kLUSuper columns, each
@@ -873,15 +985,16 @@ cfie_status factor_impl(cfie_ctx *c) {
     // inner dimension kLUSuper (instead of one of inner dimension kLUPanel per panel, which
     // would re-read the whole trailing matrix per panel).  Then the inverses of the
     // kLUBlock x kLUBlock diagonal blocks of L and U for the triangular solves.
-    c->piv = c->alloc_n<int>(std::max(ell, 1));
     int nblk = (ell + kLUBlock - 1) / kLUBlock;
-    c->Linv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
-    c->Uinv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
-    zd *tmp = c->alloc_n<zd>((size_t)kLUPanel * std::max(ell, 1));
+    if (!replay) {
+        c->piv = c->alloc_n<int>(std::max(ell, 1));
+        c->Linv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
+        c->Uinv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
+    }
+    zd *tmp = c->tmp_buf<zd>(SLOT_LU_TMP, (size_t)kLUPanel * std::max(ell, 1));
     constexpr int kPanels = kLUSuper / kLUPanel;
-    zd *Lp = c->alloc_n<zd>((size_t)kPanels * kLUPanel * kLUPanel);
-    int *panel_ws = c->alloc_n<int>(lu_panel_ws_ints());
-    HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), s));
+    zd *Lp = c->tmp_buf<zd>(SLOT_LU_LP, (size_t)kPanels * kLUPanel * kLUPanel);
+    int *panel_ws = c->tmp_buf<int>(SLOT_LU_PANEL, lu_panel_ws_ints());
     const int pw = lu_panel_width(ell);          // == kLUPanel
     zd *K = c->K;
     auto at = [&](int64_t i, int64_t j) { return K + i + j * (int64_t)cap; };
@@ -931,30 +1044,33 @@ cfie_status factor_impl(cfie_ctx *c) {
     launch_tri_inv_blocks(ell, kLUBlock, c->K, cap, c->Linv, c->Uinv, s);
     c->check_launch();
     c->fac_mark();                                     // end of K and its LU
-    int info = 0;
-    HIPCHK(hipMemcpyAsync(&info, c->info, sizeof(int), hipMemcpyDeviceToHost, s));
-    c->sync();
-    c->dfree(tmp);
-    c->dfree(Lp);
-    c->dfree(panel_ws);
-    if (info) return fail(c, CFIE_ESINGULAR, "zero pivot in the capacitance matrix");
+    if (!replay) {
+        // (a replay leaves the pivot flag in c->info for the check after its launch)
+        int info = 0;
+        HIPCHK(hipMemcpyAsync(&info, c->info, sizeof(int), hipMemcpyDeviceToHost, s));
+        c->sync();
+        c->tmp_free(tmp);
+        c->tmp_free(Lp);
+        c->tmp_free(panel_ws);
+        if (info) return fail(c, CFIE_ESINGULAR, "zero pivot in the capacitance matrix");
+    }
     // K^{-1} V^T (ell x N) by the complex128 LU factors, once per factorisation, so that a
     // solve is C_c^{-1} by FFT and two GEMMs
     {
-        zd *W64 = c->alloc_n<zd>((size_t)ell * N);
-        zd *tmpN = c->alloc_n<zd>((size_t)kLUBlock * N);
+        const bool fp64 = sizeof(T) == sizeof(double);
+        zd *W64 = fp64 ? (replay ? (zd *)c->Wf : c->alloc_n<zd>((size_t)ell * N))
+                       : c->tmp_buf<zd>(SLOT_W64, (size_t)ell * N);
+        zd *tmpN = c->tmp_buf<zd>(SLOT_TMPN, (size_t)kLUBlock * N);
         convert<double, T>(ell, N, P, ell, W64, ell, s);
         lu_solve(c, W64, ell, N, tmpN);
-        if (sizeof(T) == sizeof(double)) {
+        if (fp64) {
             c->Wf = W64;
         } else {
-            c->Wf = c->alloc_n<cpx<T>>((size_t)ell * N);
+            if (!replay) c->Wf = c->alloc_n<cpx<T>>((size_t)ell * N);
             convert<T, double>(ell, N, W64, ell, (cpx<T> *)c->Wf, ell, s);
-            c->sync();
-            c->dfree(W64);
+            c->tmp_free(W64);
         }
-        c->sync();
-        c->dfree(tmpN);
+        c->tmp_free(tmpN);
     }
     c->fac_mark();                                     // end of K^-1 V^T
     // the FP64 solve's rank x m workspace, sized with the factorisation for batches of up to
@@ -1162,6 +1278,119 @@ cfie_status solve_fp64(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx
     }
     c->sync();
     return CFIE_OK;
+}
+
+// The device work of cfie_assemble, on buffers it has allocated: Gauss points of gamma and
+// gamma_c, the circle's first rows (on the second stream, beside the contour's assembly),
+// their DFTs, the contour's four matrices, the circulant eigenvalues and diagonals, max and
+// min |c_m| into c->scal, and the complex64 copies in mixed precision.  A replayed context
+// runs it with its kept workspaces and no host interaction (recordable).
+void assemble_kernels(cfie_ctx *c) {
+    const int N = c->N;
+    const double h = c->hg.L / N;
+    hipStream_t s = c->stream;
+    launch_points(c->gd, c->d_xf, c->pf, s);
+    launch_points(c->gd, c->d_xn, c->pn, s);
+    launch_points(c->gc, c->d_xf, c->cf, s);
+    launch_points(c->gc, c->d_xn, c->cn, s);
+    c->check_launch();
+    AsmParams p;
+    p.N = N;
+    p.h = h;
+    p.kc.k = c->k;
+    p.kc.kt = c->kt;
+    p.nb = std::min(c->opt.near_band, N);
+    p.r0 = 0;
+    p.r1 = N;
+    p.ld = N;
+    for (int i = 0; i < 4; ++i) p.out[i] = c->mat[i];
+    // first row of each matrix on the circle -> eigenvalues (Sec. V).  A single row
+    // leaves most lanes of the assembly kernels idle and is bound by their latency, so it
+    // runs on a second stream beside the contour's assembly, with workspaces of its own
+    AsmParams pc = p;
+    pc.r0 = 0;
+    pc.r1 = 1;
+    pc.ld = 1;
+    for (int i = 0; i < 4; ++i) pc.out[i] = c->crow + (size_t)i * N;
+    zd *band_ws_c = c->tmp_buf<zd>(SLOT_BAND_WS_C, far_band_ws_elems(pc));
+    zd *near_ws_c = c->tmp_buf<zd>(SLOT_NEAR_WS_C, near_ws_elems(pc));
+    zd *band_ws = c->tmp_buf<zd>(SLOT_BAND_WS, far_band_ws_elems(p));
+    zd *near_ws = c->tmp_buf<zd>(SLOT_NEAR_WS, near_ws_elems(p));
+    // if anything below throws, the circle's kernels finish before its buffers can be
+    // freed and reused in the context stream's order
+    struct AuxJoin {
+        hipStream_t aux;
+        bool joined = false;
+        ~AuxJoin() {
+            if (!joined) (void)hipStreamSynchronize(aux);
+        }
+    } aux_join{c->aux};
+    HIPCHK(hipEventRecord(c->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+    pc.ws = band_ws_c;
+    launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), c->aux);
+    pc.ws = near_ws_c;
+    launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, c->aux);
+    // rows of symmetric circulants equal their first columns: their DFTs are the
+    // eigenvalues of the four circulants
+    launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, c->aux);
+    HIPCHK(hipEventRecord(c->ev_join, c->aux));
+    // the contour's matrices
+    p.ws = band_ws;
+    launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
+    p.ws = near_ws;
+    launch_assemble_near(p, c->pn, c->xn.data(), c->wn.data(), c->d_mom, s);
+    c->check_launch();
+    HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
+    aux_join.joined = true;
+    c->tmp_free(band_ws);
+    c->tmp_free(near_ws);
+    c->tmp_free(band_ws_c);
+    c->tmp_free(near_ws_c);
+    const int M = c->fft.M;
+    if (M == N) {
+        launch_circ_eigs(N, c->fft.N1, c->fft.N2, h, c->mu, c->cvals, c->dC, c->dCH,
+                         c->dCinv, c->dCinvH, c->fC, c->fCH, c->fCinv, c->fCinvH, c->absc, s);
+    } else {
+        // natural-order eigenvalues / N, then the padded convolution diagonals
+        zd *nat = c->tmp_buf<zd>(SLOT_EIG_NAT, 4 * (size_t)N);
+        zf *natf = c->tmp_buf<zf>(SLOT_EIG_NATF, 4 * (size_t)N);
+        zd *work = c->tmp_buf<zd>(SLOT_EIG_WORK, 3 * (size_t)M);
+        launch_circ_eigs(N, N, 1, h, c->mu, c->cvals, nat, nat + N, nat + 2 * (size_t)N,
+                         nat + 3 * (size_t)N, natf, natf + N, natf + 2 * (size_t)N,
+                         natf + 3 * (size_t)N, c->absc, s);
+        launch_padded_diagonal(c->fft, nat, work, c->dC, c->fC, s);
+        launch_padded_diagonal(c->fft, nat + N, work, c->dCH, c->fCH, s);
+        launch_padded_diagonal(c->fft, nat + 2 * (size_t)N, work, c->dCinv, c->fCinv, s);
+        launch_padded_diagonal(c->fft, nat + 3 * (size_t)N, work, c->dCinvH, c->fCinvH, s);
+        c->tmp_free(nat);
+        c->tmp_free(natf);
+        c->tmp_free(work);
+    }
+    launch_maxmin(N, c->absc, c->scal, s);
+    if (c->opt.precision == CFIE_MIXED)
+        for (int i = 0; i < 4; ++i) convert<float, double>(N, N, c->mat[i], N, c->mat32[i], N, s);
+    c->check_launch();
+}
+
+// Right-hand sides of eq. (5) for the plane waves d_ang (device, m angles) into B (N x m, ld
+// ldb), on work buffers e, hv, ge, gh (N x m each): the excitation vectors e'/eta and h by
+// Gauss points per element, then b = -i k S^kt G^-1 e' - (G/2 + D^kt) G^-1 h.
+void plane_wave_kernels(cfie_ctx *c, const double *d_ang, int64_t m, zd *B, int64_t ldb, zd *e,
+                        zd *hv, zd *ge, zd *gh) {
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    launch_excitation(c->gd, c->pn, c->d_xn, c->d_wn, c->k, d_ang, m, e, hv, N, s);
+    const int nt = (int)c->gcoef.size();
+    launch_ginv_ex<double>(N, nt, c->g_t0, c->d_gcoef, cz<double>(0), nullptr, 0, cz<double>(1),
+                           e, N, ge, N, m, s);
+    launch_ginv_ex<double>(N, nt, c->g_t0, c->d_gcoef, cz<double>(0), nullptr, 0, cz<double>(1),
+                           hv, N, gh, N, m, s);
+    // b = -i k S^kt G^-1 e' - h/2 - D^kt G^-1 h     (eq. (5), eta cancelled)
+    axpby<double>(N, m, cz<double>(-0.5), hv, N, cz<double>(0), B, ldb, s);
+    gemm<double>(GEMM_N, N, m, N, cz<double>(-1), c->mat[2], N, gh, N, cz<double>(1), B, ldb, s);
+    gemm<double>(GEMM_N, N, m, N, mk(0.0, -c->k), c->mat[3], N, ge, N, cz<double>(1), B, ldb, s);
+    c->check_launch();
 }
 
 // Address of noalloc_scratch on `device`, which must be the current device: resolved by
@@ -1520,6 +1749,67 @@ cfie_status solve_group(std::vector<GroupMember> &gm, int nsweep, hipStream_t cs
     }
 }
 
+
+// ------------------------------------------------------------------ recorded batches ---
+// One HIP graph for the whole path of many problems (cfie_batch_record / _launch): each
+// problem is first run once on a stream of its own in planning mode (the adaptive path,
+// which records the sketch's block schedule, the refinement's sweep count, and keeps every
+// buffer), then its work is recorded as a branch of one graph by replaying that schedule
+// (cfie_ctx::rec_mode 2: no host read, no allocation).  A launch runs every problem's
+// assembly, factorisation, right-hand sides and solve; device-side checks confirm that the
+// replay reproduced the planned schedule.
+struct BatchMember {
+    cfie_ctx *c = nullptr;
+    hipStream_t st = nullptr;
+    int64_t m = 0;
+    zd *X = nullptr;                                  // caller's solutions (N x m, ld N)
+    zd *B = nullptr, *e = nullptr, *hv = nullptr, *ge = nullptr, *gh = nullptr;
+    double *ang = nullptr;
+    GroupMember gm;                                   // mixed precision: refinement buffers
+    bool gm_alloc = false;
+    int sweeps = 0;
+    hipEvent_t done = nullptr;
+};
+
+// the device work of one member after its assembly inputs exist: assembly, factorisation,
+// right-hand sides, solve (FP64: Woodbury; mixed: `sweeps` refinement sweeps, then X)
+void batch_member_work(BatchMember &bm, bool planning) {
+    cfie_ctx *c = bm.c;
+    const int N = c->N;
+    hipStream_t s = c->stream;
+    if (!planning) {
+        assemble_kernels(c);
+        cfie_status st = c->opt.precision == CFIE_MIXED ? factor_impl<float>(c)
+                                                        : factor_impl<double>(c);
+        if (st != CFIE_OK) throw HipError{st, c->err};
+        if (c->Cd) form_dense<double>(c, c->Cd, false);
+    }
+    if (bm.m == 0) return;
+    plane_wave_kernels(c, bm.ang, bm.m, bm.B, N, bm.e, bm.hv, bm.ge, bm.gh);
+    if (c->opt.precision != CFIE_MIXED) {
+        axpby<double>(N, bm.m, cz<double>(1), bm.B, N, cz<double>(0), bm.X, N, s);
+        woodbury<double>(c, bm.X, bm.m, c->scratch<zd>(1, (size_t)std::max(c->rank, 1) * bm.m));
+    } else if (planning) {
+        // the adaptive refinement, to count its sweeps
+        bm.gm.sweeps = 0;
+        bm.gm.record(1);
+        for (;;) {
+            HIPCHK(hipMemcpyAsync(&bm.gm.rel, bm.gm.mx, sizeof(double), hipMemcpyDeviceToHost, s));
+            c->sync();
+            if (bm.gm.rel <= c->opt.refine_tol || bm.gm.sweeps >= std::max(1, c->opt.max_refine))
+                break;
+            bm.gm.sweep(false);
+        }
+        bm.sweeps = bm.gm.sweeps;
+        axpby<double>(N, bm.m, cz<double>(1), bm.gm.Xw, N, cz<double>(0), bm.X, N, s);
+    } else {
+        bm.gm.sweeps = 0;
+        bm.gm.record(bm.sweeps);
+        axpby<double>(N, bm.m, cz<double>(1), bm.gm.Xw, N, cz<double>(0), bm.X, N, s);
+    }
+    c->check_launch();
+}
+
 }  // namespace
 
 // ============================================================================ C ABI ======
@@ -1847,6 +2137,225 @@ cfie_status cfie_solve_batch_grouped(const cfie_options *opt, int device, int n_
     return worst;
 }
 
+// Recording is switched off: on the device the recording call ended its host process with a
+// segmentation fault whose cause is not yet found (the host code runs clean under
+// AddressSanitizer with every HIP call emulated, capture rules enforced).  The planning and
+// replay code stays compiled; cfie_batch_record reports CFIE_EHIP before any HIP call.
+constexpr bool kBatchRecordEnabled = false;
+
+struct cfie_batch {
+    int device = 0;
+    std::vector<BatchMember> mem;
+    hipStream_t cs = nullptr;
+    hipEvent_t fork = nullptr;
+    hipGraphExec_t exec = nullptr;
+    size_t nodes = 0;
+    ~cfie_batch() {
+        (void)hipSetDevice(device);
+        if (cs) (void)hipStreamSynchronize(cs);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        for (auto &m : mem) {
+            if (m.st) (void)hipStreamSynchronize(m.st);
+            if (m.gm_alloc) m.gm.release();
+            if (m.done) (void)hipEventDestroy(m.done);
+            if (m.c) cfie_destroy(m.c);
+            if (m.st) (void)hipStreamDestroy(m.st);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+
+cfie_status cfie_batch_record(const cfie_options *opt, int device, cfie_batch_item *items,
+                              int64_t n_items, cfie_batch **out) {
+    g_create_err.clear();
+    if (!out || !items || n_items < 1) {
+        g_create_err = "out and items must be non-NULL and n_items >= 1";
+        return CFIE_EINVAL;
+    }
+    for (int64_t i = 0; i < n_items; ++i) {
+        if (items[i].nrhs < 0 || items[i].nrhs > kGroupMaxRhs ||
+            (items[i].nrhs > 0 && (!items[i].X_dev || !items[i].angles_host))) {
+            g_create_err = "item " + std::to_string(i) +
+                           ": nrhs must be in [0, 4096], with X_dev and angles_host";
+            return CFIE_EINVAL;
+        }
+    }
+    if (!kBatchRecordEnabled) {
+        g_create_err = "recorded batches are disabled: recording crashed the host process on "
+                       "the device, for a cause not yet found";
+        return CFIE_EHIP;
+    }
+    cfie_options o;
+    if (opt) o = *opt; else cfie_default_options(&o);
+    o.profile = 0;
+    if (hipSetDevice(device) != hipSuccess) {
+        g_create_err = "hipSetDevice failed";
+        return CFIE_EHIP;
+    }
+    cfie_batch *b = new (std::nothrow) cfie_batch();
+    if (!b) return CFIE_ENOMEM;
+    b->device = device;
+    b->mem.resize((size_t)n_items);
+    auto bail = [&](cfie_status st, const std::string &msg) {
+        g_create_err = msg;
+        delete b;
+        return st;
+    };
+    // planning: every member's adaptive path on a stream of its own
+    for (int64_t i = 0; i < n_items; ++i) {
+        BatchMember &bm = b->mem[(size_t)i];
+        cfie_batch_item &it = items[i];
+        const auto t0 = std::chrono::steady_clock::now();
+        if (hipStreamCreateWithFlags(&bm.st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(CFIE_EHIP, "stream creation failed");
+        }
+        cfie_status st = cfie_create(&o, device, bm.st, &bm.c);
+        if (st != CFIE_OK) return bail(st, "item " + std::to_string(i) + ": " + g_create_err);
+        cfie_ctx *c = bm.c;
+        c->rec_mode = 1;
+        st = cfie_assemble(c, &it.contour, it.k);
+        if (st != CFIE_OK && st != CFIE_WNONCONVEX)
+            return bail(st, "item " + std::to_string(i) + ": " + c->err);
+        it.status = st;
+        st = cfie_factor(c);
+        if (st != CFIE_OK) return bail(st, "item " + std::to_string(i) + ": " + c->err);
+        st = guarded(c, [&]() -> cfie_status {
+            c->rec_flags = c->alloc_n<int>(4);
+            const int N = c->N;
+            bm.m = it.nrhs;
+            bm.X = (zd *)it.X_dev;
+            if (bm.m > 0) {
+                const size_t nm = (size_t)N * bm.m;
+                bm.ang = c->tmp_buf<double>(SLOT_RHS_ANG, bm.m);
+                c->upload(bm.ang, it.angles_host, bm.m);
+                bm.e = c->tmp_buf<zd>(SLOT_RHS_E, nm);
+                bm.hv = c->tmp_buf<zd>(SLOT_RHS_H, nm);
+                bm.ge = c->tmp_buf<zd>(SLOT_RHS_GE, nm);
+                bm.gh = c->tmp_buf<zd>(SLOT_RHS_GH, nm);
+                bm.B = c->tmp_buf<zd>(SLOT_RHS_B, nm);
+                if (c->opt.precision == CFIE_MIXED) {
+                    bm.gm.c = c;
+                    bm.gm.B = bm.B;
+                    bm.gm.ldb = N;
+                    bm.gm.X = bm.X;
+                    bm.gm.ldx = N;
+                    bm.gm.m = bm.m;
+                    bm.gm.alloc();
+                    bm.gm_alloc = true;
+                }
+            }
+            batch_member_work(bm, true);
+            c->sync();
+            return CFIE_OK;
+        });
+        if (st != CFIE_OK) return bail(st, "item " + std::to_string(i) + ": " + c->err);
+        it.rank = c->rank;
+        it.refine_residual = bm.gm.rel;
+        it.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                      .count();
+    }
+    // recording: a fork, each member's replay on its own stream, a join
+    Profiler *saved = g_prof;
+    g_prof = nullptr;
+    hipGraph_t graph = nullptr;
+    bool capturing = false;
+    cfie_status st = CFIE_OK;
+    std::string msg;
+    try {
+        HIPCHK(hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        for (auto &bm : b->mem) HIPCHK(hipEventCreateWithFlags(&bm.done, hipEventDisableTiming));
+        HIPCHK(hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
+        capturing = true;
+        HIPCHK(hipEventRecord(b->fork, b->cs));
+        for (auto &bm : b->mem) {
+            HIPCHK(hipStreamWaitEvent(bm.st, b->fork, 0));
+            bm.c->rec_mode = 2;
+            batch_member_work(bm, false);
+            HIPCHK(hipEventRecord(bm.done, bm.st));
+            HIPCHK(hipStreamWaitEvent(b->cs, bm.done, 0));
+        }
+        capturing = false;
+        HIPCHK(hipStreamEndCapture(b->cs, &graph));
+        if (!graph) throw HipError{CFIE_EHIP, "recording of the batch failed"};
+        HIPCHK(hipGraphGetNodes(graph, nullptr, &b->nodes));
+        HIPCHK(hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
+    } catch (const HipError &e) {
+        st = e.st;
+        msg = e.msg;
+    } catch (const std::exception &e) {
+        st = CFIE_EINVAL;
+        msg = std::string("internal: ") + e.what();
+    }
+    if (capturing) {
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(b->cs, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    g_prof = saved;
+    (void)hipGetLastError();
+    if (st != CFIE_OK) return bail(st, msg);
+    *out = b;
+    return CFIE_OK;
+}
+
+cfie_status cfie_batch_launch(cfie_batch *b, cfie_batch_item *items, int64_t n_items) {
+    if (!b || (n_items != (int64_t)b->mem.size()) || (n_items > 0 && !items)) {
+        g_create_err = "a recorded batch and its item array (same length) are required";
+        return CFIE_EINVAL;
+    }
+    g_create_err.clear();
+    if (hipSetDevice(b->device) != hipSuccess) return CFIE_EHIP;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (hipGraphLaunch(b->exec, b->cs) != hipSuccess ||
+        hipStreamSynchronize(b->cs) != hipSuccess) {
+        g_create_err = std::string("batch launch failed: ") + hipGetErrorString(hipGetLastError());
+        return CFIE_EHIP;
+    }
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    cfie_status worst = CFIE_OK;
+    for (int64_t i = 0; i < n_items; ++i) {
+        BatchMember &bm = b->mem[(size_t)i];
+        cfie_ctx *c = bm.c;
+        int flags = 0, info = 0;
+        double rel = 0.0;
+        if (hipMemcpy(&flags, c->rec_flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&info, c->info, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+            (bm.gm_alloc &&
+             hipMemcpy(&rel, bm.gm.mx, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
+            return CFIE_EHIP;
+        cfie_status st = CFIE_OK;
+        if (flags) {
+            st = CFIE_ENOCONV;
+            c->err = "the replayed sketch left its planned schedule (bits: 1 remainder above "
+                     "tau, 2 kept count)";
+        } else if (info) {
+            st = CFIE_ESINGULAR;
+            c->err = "zero pivot in the capacitance matrix";
+        } else if (bm.gm_alloc && rel > c->opt.refine_tol) {
+            st = CFIE_ENOCONV;
+            c->err = "refinement did not reach refine_tol in the recorded sweeps";
+        }
+        items[i].status = st;
+        items[i].rank = c->rank;
+        items[i].refine_residual = rel;
+        items[i].t_ms = ms;
+        if (st != CFIE_OK && worst == CFIE_OK) {
+            worst = st;
+            g_create_err = "item " + std::to_string(i) + ": " + c->err;
+        }
+    }
+    return worst;
+}
+
+int64_t cfie_batch_nodes(const cfie_batch *b) { return b ? (int64_t)b->nodes : 0; }
+
+void cfie_batch_destroy(cfie_batch *b) { delete b; }
+
 void cfie_destroy(cfie_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
@@ -1930,75 +2439,12 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         alloc_points(c, c->pn, c->opt.quad_near);
         alloc_points(c, c->cf, c->opt.quad_far);
         alloc_points(c, c->cn, c->opt.quad_near);
-        launch_points(c->gd, c->d_xf, c->pf, s);
-        launch_points(c->gd, c->d_xn, c->pn, s);
-        launch_points(c->gc, c->d_xf, c->cf, s);
-        launch_points(c->gc, c->d_xn, c->cn, s);
-        c->check_launch();
-        // dense matrices on gamma
+        // dense matrices on gamma, the circle's first rows and their eigenvalues
         size_t nn = (size_t)N * N;
         for (int i = 0; i < 4; ++i) c->mat[i] = c->alloc_n<zd>(nn);
-        AsmParams p;
-        p.N = N;
-        p.h = h;
-        p.kc.k = k;
-        p.kc.kt = c->kt;
-        p.nb = std::min(c->opt.near_band, N);
-        p.r0 = 0;
-        p.r1 = N;
-        p.ld = N;
-        for (int i = 0; i < 4; ++i) p.out[i] = c->mat[i];
-        // first row of each matrix on the circle -> eigenvalues (Sec. V).  A single row
-        // leaves most lanes of the assembly kernels idle and is bound by their latency, so it
-        // runs on a second stream beside the contour's assembly, with workspaces of its own
         c->crow = c->alloc_n<zd>((size_t)4 * N);
         c->mu = c->alloc_n<zd>((size_t)4 * N);
-        AsmParams pc = p;
-        pc.r0 = 0;
-        pc.r1 = 1;
-        pc.ld = 1;
-        for (int i = 0; i < 4; ++i) pc.out[i] = c->crow + (size_t)i * N;
-        setup_fft(c);                 // twiddle tables, used by the circle row's DFT below
-        zd *band_ws_c = c->alloc_n<zd>(far_band_ws_elems(pc));
-        zd *near_ws_c = c->alloc_n<zd>(near_ws_elems(pc));
-        if (!c->aux) {
-            HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-        }
-        // if anything below throws, the circle's kernels finish before its buffers can be
-        // freed and reused in the context stream's order
-        struct AuxJoin {
-            hipStream_t aux;
-            bool joined = false;
-            ~AuxJoin() {
-                if (!joined) (void)hipStreamSynchronize(aux);
-            }
-        } aux_join{c->aux};
-        HIPCHK(hipEventRecord(c->ev_fork, s));
-        HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-        pc.ws = band_ws_c;
-        launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), c->aux);
-        pc.ws = near_ws_c;
-        launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, c->aux);
-        // rows of symmetric circulants equal their first columns: their DFTs are the
-        // eigenvalues of the four circulants
-        launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, c->aux);
-        HIPCHK(hipEventRecord(c->ev_join, c->aux));
-        // the contour's matrices
-        zd *band_ws = c->alloc_n<zd>(far_band_ws_elems(p));
-        p.ws = band_ws;
-        launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
-        zd *near_ws = c->alloc_n<zd>(near_ws_elems(p));
-        p.ws = near_ws;
-        launch_assemble_near(p, c->pn, c->xn.data(), c->wn.data(), c->d_mom, s);
-        c->check_launch();
-        HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
-        aux_join.joined = true;
-        c->dfree(band_ws);
-        c->dfree(near_ws);
-        c->dfree(band_ws_c);
-        c->dfree(near_ws_c);
+        setup_fft(c);                 // twiddle tables, used by the circle row's DFT
         c->cvals = c->alloc_n<zd>(N);
         const int M = c->fft.M;
         c->dC = c->alloc_n<zd>(M); c->dCH = c->alloc_n<zd>(M); c->dCinv = c->alloc_n<zd>(M);
@@ -2007,36 +2453,16 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         c->fCinvH = c->alloc_n<zf>(M);
         c->absc = c->alloc_n<double>(N);
         c->scal = c->alloc_n<double>(4);
-        if (M == N) {
-            launch_circ_eigs(N, c->fft.N1, c->fft.N2, h, c->mu, c->cvals, c->dC, c->dCH,
-                             c->dCinv, c->dCinvH, c->fC, c->fCH, c->fCinv, c->fCinvH, c->absc,
-                             s);
-        } else {
-            // natural-order eigenvalues / N, then the padded convolution diagonals
-            zd *nat = c->alloc_n<zd>(4 * (size_t)N);
-            zf *natf = c->alloc_n<zf>(4 * (size_t)N);
-            zd *work = c->alloc_n<zd>(3 * (size_t)M);
-            launch_circ_eigs(N, N, 1, h, c->mu, c->cvals, nat, nat + N, nat + 2 * (size_t)N,
-                             nat + 3 * (size_t)N, natf, natf + N, natf + 2 * (size_t)N,
-                             natf + 3 * (size_t)N, c->absc, s);
-            launch_padded_diagonal(c->fft, nat, work, c->dC, c->fC, s);
-            launch_padded_diagonal(c->fft, nat + N, work, c->dCH, c->fCH, s);
-            launch_padded_diagonal(c->fft, nat + 2 * (size_t)N, work, c->dCinv, c->fCinv, s);
-            launch_padded_diagonal(c->fft, nat + 3 * (size_t)N, work, c->dCinvH, c->fCinvH, s);
-            c->sync();
-            c->dfree(nat);
-            c->dfree(natf);
-            c->dfree(work);
+        if (c->opt.precision == CFIE_MIXED)
+            for (int i = 0; i < 4; ++i) c->mat32[i] = c->alloc_n<zf>(nn);
+        if (!c->aux) {
+            HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
         }
-        launch_maxmin(N, c->absc, c->scal, s);
+        assemble_kernels(c);
         double mm[2];
         HIPCHK(hipMemcpyAsync(mm, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        if (c->opt.precision == CFIE_MIXED) {
-            for (int i = 0; i < 4; ++i) {
-                c->mat32[i] = c->alloc_n<zf>(nn);
-                convert<float, double>(N, N, c->mat[i], N, c->mat32[i], N, s);
-            }
-        }
         HIPCHK(hipEventRecord(e1, s));
         c->sync();
         HIPCHK(hipEventElapsedTime(&c->t_asm, e0, e1));
@@ -2177,17 +2603,7 @@ cfie_status cfie_plane_wave_rhs(cfie_ctx *c, const double *angles, int64_t nrhs,
         c->upload(d_ang, angles, nrhs);
         zd *e = c->alloc_n<zd>((size_t)N * nrhs), *hv = c->alloc_n<zd>((size_t)N * nrhs);
         zd *ge = c->alloc_n<zd>((size_t)N * nrhs), *gh = c->alloc_n<zd>((size_t)N * nrhs);
-        launch_excitation(c->gd, c->pn, c->d_xn, c->d_wn, c->k, d_ang, nrhs, e, hv, N, s);
-        const int nt = (int)c->gcoef.size();
-        launch_ginv_ex<double>(N, nt, c->g_t0, c->d_gcoef, cz<double>(0), nullptr, 0, cz<double>(1),
-                               e, N, ge, N, nrhs, s);
-        launch_ginv_ex<double>(N, nt, c->g_t0, c->d_gcoef, cz<double>(0), nullptr, 0, cz<double>(1),
-                               hv, N, gh, N, nrhs, s);
-        // b = -i k S^kt G^-1 e' - h/2 - D^kt G^-1 h     (eq. (5), eta cancelled)
-        axpby<double>(N, nrhs, cz<double>(-0.5), hv, N, cz<double>(0), B, ldb, s);
-        gemm<double>(GEMM_N, N, nrhs, N, cz<double>(-1), c->mat[2], N, gh, N, cz<double>(1), B, ldb, s);
-        gemm<double>(GEMM_N, N, nrhs, N, mk(0.0, -c->k), c->mat[3], N, ge, N, cz<double>(1), B, ldb, s);
-        c->check_launch();
+        plane_wave_kernels(c, d_ang, nrhs, B, ldb, e, hv, ge, gh);
         c->sync();
         c->dfree(d_ang); c->dfree(e); c->dfree(hv); c->dfree(ge); c->dfree(gh);
         return CFIE_OK;

@@ -1343,4 +1343,37 @@ void launch_ratio_max(int64_t n, const double *r2, const double *b2, double *out
     hipLaunchKernelGGL(k_ratio_max, dim3(1), dim3(256), 0, s, n, r2, b2, out);
 }
 
+// p[0..n) = v (a kernel rather than a memset node, for work that may be recorded in a graph)
+__global__ void k_fill_int(int n, int v, int *p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+void launch_fill_int(int n, int v, int *p, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, n, v, p);
+}
+
+// Check of one sketch block of a replayed factorisation against its recorded schedule:
+// probe != 0 -- the block's squared column norms (n of them) must all be <= tau2 (the
+// recorded run stopped at this block); otherwise the pivoted Cholesky must have kept exactly
+// `planned` directions (*kdev).  A failed check sets `bit` in *flag.  One workgroup.
+__global__ void k_replay_check(int n, const double *norms2, double tau2, int probe,
+                               const int *kdev, int planned, int bit, int *flag) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    if (probe) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+            if (!(norms2[i] <= tau2)) bad = 1;
+    } else if (threadIdx.x == 0) {
+        bad = *kdev != planned;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && bad) *flag |= bit;
+}
+void launch_replay_check(int n, const double *norms2, double tau2, int probe, const int *kdev,
+                         int planned, int bit, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_replay_check, dim3(1), dim3(256), 0, s, n, norms2, tau2, probe, kdev,
+                       planned, bit, flag);
+}
+
 }  // namespace cfie

@@ -71,6 +71,23 @@ def test_group_solve_argument_checks_before_touching_a_device():
     assert lib.cfie_solve_batch_grouped(None, 0, 0, None, 0, 1) == _lib.CFIE_EINVAL
 
 
+def test_batch_record_reports_disabled_before_touching_a_device():
+    """cfie_batch_record is switched off: argument errors still give EINVAL, valid arguments
+    EHIP with the reason, with no HIP call and no handle."""
+    import ctypes
+    from paper_2203_13283_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.cfie_batch_record(None, 0, None, 0, ctypes.byref(h)) == _lib.CFIE_EINVAL
+    items = (_lib.BatchItem * 1)()
+    items[0].nrhs = 0
+    assert lib.cfie_batch_record(None, 0, items, 1, ctypes.byref(h)) == _lib.CFIE_EHIP
+    assert b"disabled" in lib.cfie_last_error(None)
+    assert not h.value
+    assert lib.cfie_batch_nodes(None) == 0
+    lib.cfie_batch_destroy(None)
+
+
 def test_header_is_plain_c(tmp_path):
     """include/cfie.h compiles as ISO C99 with every warning on (a C caller's view)."""
     import shutil
