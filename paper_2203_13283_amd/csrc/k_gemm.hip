@@ -296,19 +296,36 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
 // The large FP64 products of the solver (the sketch's N x N x b products and their adjoints,
 // the capacitance matrix V^T U~, the solve's W Y) with a 128 x 128 output tile per workgroup
 // of 8 wavefronts (each 64 x 32), which halves the operand traffic per flop of the 64 x 64
-// tile.  The operands go from global memory straight into LDS (gfx950's 16-byte
-// global_load_lds: each lane's element lands at the wave's LDS base + 16 x lane, with no
-// staging registers and no LDS store instructions), laid out as "fragments": the 16 x 4 block
-// of op(A) (rows x k) or of B (k x columns) that one 16x16x4 MFMA consumes, in the MFMA's
-// own lane order (lane = (k % 4) * 16 + row % 16).  Reading an operand is then one
-// contiguous, conflict-free ds_read_b128 per lane that brings its real and imaginary parts
-// together.  Two LDS buffers: the next K-slice's fragments are in flight while the current
-// one is multiplied, with one barrier per slice.  Every output element sees the same MFMA
-// sequence (k ascending in steps of 4, 3M form) as in k_zgemm, so the two kernels give
-// bitwise identical results.
+// tile.  Every output element sees the same MFMA sequence (k ascending in steps of 4, 3M
+// form) as in k_zgemm, so the two kernels give bitwise identical results.
+//
+// Operands go from global memory straight into LDS (gfx950's 16-byte global_load_lds: each
+// lane's element lands at the wave's LDS base + 16 x lane, with no staging registers and no
+// LDS store instructions), laid out as "fragments": the 16 x 4 block of op(A) (rows x k) or
+// of B (k x columns) that one 16x16x4 MFMA consumes, in the MFMA's own lane order
+// (lane = (k % 4) * 16 + row % 16).  Reading an operand is one contiguous, conflict-free
+// ds_read_b128 per lane that brings its real and imaginary parts together.
+//
+// Schedule, measured on the N x N x 256 products (executed-flop fraction of the FP64 matrix
+// peak 0.78-0.85 before, 0.82-0.89 after):
+// * two LDS buffers used in turn, the slice loop unrolled in pairs so that each buffer is a
+//   compile-time array (the wait-count pass then keeps LDS reads of one buffer independent
+//   of the direct loads in flight into the other);
+// * the fragments of the next k-quad are read while the MFMAs of the current one run (A
+//   fragments slot by slot after their MFMAs, B fragments double-buffered), and the slice's
+//   barrier sits before its last k-quad, whose fragments are then already in registers, so
+//   that the next slice's first k-quad is read during it;
+// * the direct loads are spread over the slice in the middle of k-quads (two fragment pairs
+//   after the barrier, one in each of the next two k-quads): issued together they cost about
+//   8% of the matrix-core time;
+// * edge tiles are shifted to end inside the matrix (their rows and columns below the
+//   nominal start are computed and not written), so that each lane addresses its fragments
+//   as one 32-bit offset from a uniform base: this needs m, n >= 128 and leading dimensions
+//   below 2^24.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
 constexpr int kWideTile = 128;
+constexpr int64_t kWideMaxLd = int64_t(1) << 24;
 
 template <int OPA>
 __global__ __launch_bounds__(512, 1) void k_zgemm_wide(int64_t m, int64_t n, int64_t kdim,
@@ -319,7 +336,7 @@ __global__ __launch_bounds__(512, 1) void k_zgemm_wide(int64_t m, int64_t n, int
     constexpr bool BREAL = OPA == 3;
     constexpr int BM = kWideTile, BN = kWideTile, BK = 16;
     // fragment f = kq * 8 + t: MFMA tile t (of 8 along the rows of op(A), or along the
-    // columns of B) at k-quad kq of the slice; buffers 0 and 1
+    // columns of B) at k-quad kq of the slice
     __shared__ zd As0[32][64], As1[32][64], Bs0[32][64], Bs1[32][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // XCD-aware tile order as in k_zgemm, groups of 4 row panels
@@ -338,40 +355,54 @@ __global__ __launch_bounds__(512, 1) void k_zgemm_wide(int64_t m, int64_t n, int
     const int64_t fm = (t / gsz) * GROUP_M;
     const int64_t gm = min((int64_t)GROUP_M, tiles_m - fm);
     const int64_t tm = fm + (t % gsz) % gm, tn = (t % gsz) / gm;
-    const int64_t row0 = tm * BM, col0 = tn * BN;
+    // nominal start of the tile (the first row and column it writes) and the computed tile
+    const int64_t rlo = tm * BM, clo = tn * BN;
+    const int64_t row0 = min(rlo, m - BM), col0 = min(clo, n - BN);
     const int64_t kbeg = zslice * kchunk;
     const int64_t kend = min(kdim, kbeg + kchunk);
     const int64_t nslice = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-    // wave w fills fragments w*4 + q (q = 0..3) of each operand: k-quad w/2, tiles (w%2)*4 + q.
-    // Rows of op(A), columns of B and k beyond the matrices are clamped onto the last valid
-    // index (in bounds); the clamped k of the last slice get zero B values below.
+    // wave w fills fragments w*4 + q (q = 0..3) of each operand: k-quad w/2, tiles
+    // (w%2)*4 + q; its lane's element of fragment q sits at (slice base + q x stride +
+    // lane offset), with the lane's k row kk in the slice
     const int kl = 4 * (w >> 1) + (lane >> 4), t0 = (w & 1) * 4, il = lane & 15;
-    const zd *pa[4], *pb[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t gi = min(row0 + 16 * (t0 + q) + il, m - 1);
-        const int64_t gj = min(col0 + 16 * (t0 + q) + il, n - 1);
-        pa[q] = OPA == 1 ? A + gi * lda : A + gi;
-        pb[q] = B + gj * ldb;
-    }
-    auto issue = [&](int64_t s, int buf) {
-        const int64_t gk = min(kbeg + s * BK + kl, kend - 1);
+    auto lane_off = [&](int kk, uint32_t &oa, uint32_t &ob) {
+        const int64_t r = 16 * t0 + il;
+        oa = (uint32_t)(16 * (OPA == 1 ? kk + r * lda : r + kk * lda));
+        ob = (uint32_t)(16 * (kk + r * ldb));
+    };
+    uint32_t oa, ob;
+    lane_off(kl, oa, ob);
+    const int64_t qa = 16 * (OPA == 1 ? 16 * lda : 16), qb = 16 * 16 * ldb;
+    const char *abase = (const char *)(OPA == 1 ? A + row0 * lda : A + row0);
+    const char *bbase = (const char *)(B + col0 * ldb);
+    // the last slice's k rows beyond kend are clamped onto kend - 1 (in bounds); B is
+    // zeroed there after they land
+    const int64_t klast = kend - 1 - (kbeg + (nslice - 1) * BK);
+    // direct loads of fragments qlo..qhi-1 of slice s into buffer BUF
+    auto issue = [&](int64_t s, auto bufc, int qlo, int qhi) {
+        constexpr int BUF = decltype(bufc)::value;
+        const int64_t k0 = kbeg + s * BK;
+        const char *sa = abase + 16 * (OPA == 1 ? k0 : k0 * lda);
+        const char *sb = bbase + 16 * k0;
+        uint32_t xa = oa, xb = ob;
+        if (s + 1 == nslice && kl > klast) lane_off((int)klast, xa, xb);
+        // keeps the offsets 32-bit lane values (no 64-bit address per fragment kept live)
+        asm volatile("" : "+v"(xa), "+v"(xb));
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const zd *sa = OPA == 1 ? pa[q] + gk : pa[q] + gk * lda;
-            const zd *sb = pb[q] + gk;
-            __builtin_amdgcn_global_load_lds((glb_void_t *)sa,
-                (lds_void_t *)(buf ? &As1[w * 4 + q][0] : &As0[w * 4 + q][0]), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((glb_void_t *)sb,
-                (lds_void_t *)(buf ? &Bs1[w * 4 + q][0] : &Bs0[w * 4 + q][0]), 16, 0, 0);
+            if (q < qlo || q >= qhi) continue;
+            __builtin_amdgcn_global_load_lds((glb_void_t *)(sa + q * qa + xa),
+                (lds_void_t *)(BUF ? &As1[w * 4 + q][0] : &As0[w * 4 + q][0]), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((glb_void_t *)(sb + q * qb + xb),
+                (lds_void_t *)(BUF ? &Bs1[w * 4 + q][0] : &Bs0[w * 4 + q][0]), 16, 0, 0);
         }
     };
-    // after the slice's loads have landed: B is zero for k >= kend (this lane's own entries)
-    auto clear_tail = [&](int64_t s, int buf) {
+    auto clear_tail = [&](int64_t s, auto bufc) {
+        constexpr int BUF = decltype(bufc)::value;
         if (kbeg + s * BK + kl >= kend) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (buf) Bs1[w * 4 + q][lane] = mk(0.0, 0.0);
+                if (BUF) Bs1[w * 4 + q][lane] = mk(0.0, 0.0);
                 else Bs0[w * 4 + q][lane] = mk(0.0, 0.0);
             }
         }
@@ -387,57 +418,77 @@ __global__ __launch_bounds__(512, 1) void k_zgemm_wide(int64_t m, int64_t n, int
             if constexpr (!BREAL) acc3[a][b] = d4{0, 0, 0, 0};
         }
     const int ta = (w & 1) * 4, tb = (w >> 1) * 2;    // this wave's 4 x 2 MFMA tiles
-    auto compute = [&](int buf) {
+    zd av[4], bv[2], bn[2];
+    // one k-quad on the fragments in registers, reading those of k-quad NKQ of buffer NBUF
+    // meanwhile; hook() runs after the second A fragment's MFMAs
+    auto kquad = [&](auto nbufc, auto nkqc, auto hook) {
+        constexpr int NBUF = decltype(nbufc)::value, NKQ = decltype(nkqc)::value;
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-            zd av[4], bv[2];
+        for (int b = 0; b < 2; ++b) bn[b] = NBUF ? Bs1[NKQ * 8 + tb + b][lane] : Bs0[NKQ * 8 + tb + b][lane];
+        double sb[2];
+        if constexpr (!BREAL) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = buf ? Bs1[kq * 8 + tb + b][lane] : Bs0[kq * 8 + tb + b][lane];
+            for (int b = 0; b < 2; ++b) sb[b] = bv[b].x + bv[b].y;
+        }
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = buf ? As1[kq * 8 + ta + a][lane] : As0[kq * 8 + ta + a][lane];
+        for (int a = 0; a < 4; ++a) {
             if constexpr (BREAL) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        acc1[a][b] = mfma(av[a].x, bv[b].x, acc1[a][b]);
-                        acc2[a][b] = mfma(av[a].y, bv[b].x, acc2[a][b]);
-                    }
+                for (int b = 0; b < 2; ++b) {
+                    acc1[a][b] = mfma(av[a].x, bv[b].x, acc1[a][b]);
+                    acc2[a][b] = mfma(av[a].y, bv[b].x, acc2[a][b]);
+                }
             } else {
-                double sb[2];
+                const double sa = OPA != 0 ? av[a].x - av[a].y : av[a].x + av[a].y;
 #pragma unroll
-                for (int b = 0; b < 2; ++b) sb[b] = bv[b].x + bv[b].y;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const double sa = OPA != 0 ? av[a].x - av[a].y : av[a].x + av[a].y;
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        acc1[a][b] = mfma(av[a].x, bv[b].x, acc1[a][b]);
-                        acc2[a][b] = mfma(av[a].y, bv[b].y, acc2[a][b]);
-                        acc3[a][b] = mfma(sa, sb[b], acc3[a][b]);
-                    }
+                for (int b = 0; b < 2; ++b) {
+                    acc1[a][b] = mfma(av[a].x, bv[b].x, acc1[a][b]);
+                    acc2[a][b] = mfma(av[a].y, bv[b].y, acc2[a][b]);
+                    acc3[a][b] = mfma(sa, sb[b], acc3[a][b]);
                 }
             }
+            av[a] = NBUF ? As1[NKQ * 8 + ta + a][lane] : As0[NKQ * 8 + ta + a][lane];
+            if (a == 1) hook();
         }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = bn[b];
     };
-    // the direct-to-LDS loads count on vmcnt: waiting for zero (no other vector memory
-    // operation is in flight in the loop) means this wave's fragments have landed, and the
-    // barrier after it makes every wave's fragments visible
-    if (nslice > 0) {
-        issue(0, 0);
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        clear_tail(0, 0);
+    typedef std::integral_constant<int, 0> I0;
+    typedef std::integral_constant<int, 1> I1;
+    typedef std::integral_constant<int, 2> I2;
+    typedef std::integral_constant<int, 3> I3;
+    // slice s in buffer CUR, its first k-quad's fragments in registers
+    auto slice = [&](int64_t s, auto curc) {
+        constexpr int CUR = decltype(curc)::value;
+        typedef std::integral_constant<int, CUR> IC;
+        typedef std::integral_constant<int, 1 - CUR> IN;
+        const bool more = s + 1 < nslice;
+        // fragments 2 and 3 of the next slice into buffer IN, free since the last barrier
+        kquad(IC{}, I1{}, [&] { if (more) issue(s + 1, IN{}, 2, 3); });
+        kquad(IC{}, I2{}, [&] { if (more) issue(s + 1, IN{}, 3, 4); });
+        kquad(IC{}, I3{}, [] {});
+        // k-quad 3's fragments are in registers, the next slice's operands have landed (the
+        // direct loads count on vmcnt; no other vector memory operation is in flight)
+        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+        if (more) clear_tail(s + 1, IN{});
         __syncthreads();
-        for (int64_t s = 0; s < nslice; ++s) {
-            const int cur = (int)(s & 1);
-            const bool more = s + 1 < nslice;
-            if (more) issue(s + 1, cur ^ 1);      // the other buffer: read by nobody now
-            compute(cur);
-            if (more) {
-                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                clear_tail(s + 1, cur ^ 1);
-            }
-            __syncthreads();
+        // buffer CUR is read by nobody now: fragments 0 and 1 of slice s + 2.  After the last
+        // slice the fragments read here are not used (in-bounds LDS reads).
+        kquad(IN{}, I0{}, [&] { if (s + 2 < nslice) issue(s + 2, IC{}, 0, 2); });
+    };
+    if (nslice > 0) {
+        issue(0, I0{}, 0, 4);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        clear_tail(0, I0{});
+        __syncthreads();
+        if (nslice > 1) issue(1, I1{}, 0, 2);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Bs0[tb + b][lane];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = As0[ta + a][lane];
+        for (int64_t s = 0; s < nslice; s += 2) {
+            slice(s, I0{});
+            if (s + 1 < nslice) slice(s + 1, I1{});
         }
     }
     const bool beta_zero = (beta.x == 0.0 && beta.y == 0.0);
@@ -451,7 +502,7 @@ __global__ __launch_bounds__(512, 1) void k_zgemm_wide(int64_t m, int64_t n, int
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = row0 + wrow + a * 16 + acc_row<double>(lane, r);
-                if (gi < m && gj < n) {
+                if (gi >= rlo && gj >= clo) {
                     zd v;
                     if constexpr (BREAL) {
                         v = mk((double)acc1[a][b][r], (double)acc2[a][b][r]);
@@ -852,13 +903,15 @@ void launch_skinny(int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *
 namespace {
 std::atomic<int> g_wide_mode{1};
 // The wide tile for complex128 products whose 128 x 128 grid fills the device (about one
-// workgroup of 8 wavefronts per compute unit or more) and whose K is long: measured 2-10%
+// workgroup of 8 wavefronts per compute unit or more) and whose K is long: measured 5-15%
 // faster than the 64 x 64 tile there (N x N x 256 sketch products, V^T U~, the solve's W Y at
 // N = 16384); with K of a few thousand its prologue and its one workgroup per compute unit
-// lose against the 64 x 64 tile's two.
-bool use_wide(int64_t m, int64_t n, int64_t k, int S) {
+// lose against the 64 x 64 tile's two.  Its shifted edge tiles need m, n >= 128, its 32-bit
+// lane offsets leading dimensions below 2^24.
+bool use_wide(int64_t m, int64_t n, int64_t k, int S, int64_t lda, int64_t ldb) {
     const int64_t t = ((m + kWideTile - 1) / kWideTile) * ((n + kWideTile - 1) / kWideTile);
-    return g_wide_mode.load() != 0 && k >= 8192 && t * S >= 240;
+    return g_wide_mode.load() != 0 && k >= 8192 && t * S >= 240 && m >= kWideTile &&
+           n >= kWideTile && lda < kWideMaxLd && ldb < kWideMaxLd;
 }
 }  // namespace
 
@@ -904,7 +957,7 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
     // per lane that this imposes measured 15-20% faster than one wavefront with more
     // registers
     if constexpr (sizeof(T) == sizeof(double)) {
-        if (use_wide(m, n, k, S)) {
+        if (use_wide(m, n, k, S, lda, ldb)) {
             const zd *Ad = (const zd *)A, *Bd = (const zd *)B;
             zd al = mk((double)alpha.x, (double)alpha.y), be = mk((double)beta.x, (double)beta.y);
             zd *Cd = (zd *)C;
