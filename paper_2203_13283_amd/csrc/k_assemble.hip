@@ -61,7 +61,7 @@ struct QuadConsts {
 // node column f; b = 1 into acc1, the node column f + 1), and for N^k the Maue term
 // K (s_a s_b w_g w_hh - k^2 n.n' h^2 w_g w_hh phi_a phi_b) with s_a = +/-1 the sign of
 // phi_a'.  Lanes with on = false add nothing (their kernel is evaluated at a harmless
-// separation).  KERNEL(R, nu, gk, Dk, St, Dt) evaluates the point-pair kernels.
+// separation).  KERNEL(R, 1/R, nu, gk, Dk, St, Dt) evaluates the point-pair kernels.
 template <int Q, typename KERNEL>
 __device__ __forceinline__ void far_block(const double *rp, int fe, bool on, double rsafe,
                                           double h, double k2, const double *__restrict__ PX,
@@ -83,11 +83,14 @@ __device__ __forceinline__ void far_block(const double *rp, int fe, bool on, dou
             double dx = rp[(0 * Q + g) * 256] - xs, dy = rp[(1 * Q + g) * 256] - ys;
             dx = on ? dx : rsafe;
             dy = on ? dy : 0.0;
-            const double R = sqrt(dx * dx + dy * dy);
-            const double nu = (dx * tys - dy * txs) / R;
+            // 1/R from one reciprocal square root; R and nu = (r - r').n' / R from it
+            const double r2 = fma(dx, dx, dy * dy);
+            const double invR = rsqrt(r2);
+            const double R = r2 * invR;
+            const double nu = (dx * tys - dy * txs) * invR;
             const double nn = rp[(3 * Q + g) * 256] * tys + rp[(2 * Q + g) * 256] * txs;
             zd gk, Dk, St, Dt;
-            kern(R, nu, gk, Dk, St, Dt);
+            kern(R, invR, nu, gk, Dk, St, Dt);
             const double xg = qc.xi[g], wg = qc.w[g];
             const double wa[2] = {h * wg * (1.0 - xg), h * wg * xg};
             const double wgh = msk * wg * wh;
@@ -180,18 +183,20 @@ __global__ __launch_bounds__(256, MODE == 2 ? 1 : 2) void k_far(int N, double h,
                                             : (!fast && !mid && min(off, N - off) > dband));
         if (__any(use)) {
             if constexpr (MODE == 1) {
-                auto K22 = [&](double R, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
-                    pair_kernels_asym<kSerMax>(c, R, nu, g0, g1, g2, g3);
+                auto K22 = [&](double R, double invR, double nu, zd &g0, zd &g1, zd &g2,
+                               zd &g3) {
+                    pair_kernels_asym<kSerMax>(c, R, invR, nu, g0, g1, g2, g3);
                 };
                 far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K22);
             } else if constexpr (MODE == 2) {
-                auto KG = [&](double R, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
+                auto KG = [&](double R, double, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
                     pair_kernels(c, R, nu, g0, g1, g2, g3);
                 };
                 far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, KG);
             } else {
-                auto K8 = [&](double R, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
-                    pair_kernels_asym<8>(c, R, nu, g0, g1, g2, g3);
+                auto K8 = [&](double R, double invR, double nu, zd &g0, zd &g1, zd &g2,
+                              zd &g3) {
+                    pair_kernels_asym<8>(c, R, invR, nu, g0, g1, g2, g3);
                 };
                 far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K8);
             }

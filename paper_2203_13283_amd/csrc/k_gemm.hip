@@ -903,14 +903,15 @@ void launch_skinny(int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *
 namespace {
 std::atomic<int> g_wide_mode{1};
 // The wide tile for complex128 products whose 128 x 128 grid fills the device (about one
-// workgroup of 8 wavefronts per compute unit or more) and whose K is long: measured 5-15%
-// faster than the 64 x 64 tile there (N x N x 256 sketch products, V^T U~, the solve's W Y at
-// N = 16384); with K of a few thousand its prologue and its one workgroup per compute unit
-// lose against the 64 x 64 tile's two.  Its shifted edge tiles need m, n >= 128, its 32-bit
-// lane offsets leading dimensions below 2^24.
+// workgroup of 8 wavefronts per compute unit or more) and whose K is not short: measured
+// 5-15% faster than the 64 x 64 tile there (at N = 16384: the sketch's N x N x 256 products
+// and their adjoints, V^T U~, the solve's W Y and U~ Z with K = 3943, the Gram-Schmidt
+// updates; 7% at K = 2048); with fewer tiles than compute units its one workgroup per
+// compute unit loses against the 64 x 64 tile's two.  Its shifted edge tiles need
+// m, n >= 128, its 32-bit lane offsets leading dimensions below 2^24.
 bool use_wide(int64_t m, int64_t n, int64_t k, int S, int64_t lda, int64_t ldb) {
     const int64_t t = ((m + kWideTile - 1) / kWideTile) * ((n + kWideTile - 1) / kWideTile);
-    return g_wide_mode.load() != 0 && k >= 8192 && t * S >= 240 && m >= kWideTile &&
+    return g_wide_mode.load() != 0 && k >= 2048 && t * S >= 240 && m >= kWideTile &&
            n >= kWideTile && lda < kWideMaxLd && ldb < kWideMaxLd;
 }
 }  // namespace
@@ -944,7 +945,8 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
     }
     // K is split when the output has too few 64 x 64 tiles to fill 256 CUs
     const int S = splitk_factor(m, n, k);
-    const int v = tuned_variant<T>(op, m, n, k, S, alpha, A, lda, B, ldb, s);
+    const bool wide = sizeof(T) == sizeof(double) && use_wide(m, n, k, S, lda, ldb);
+    const int v = wide ? 0 : tuned_variant<T>(op, m, n, k, S, alpha, A, lda, B, ldb, s);
     // work: the real flops the kernel executes -- 6 m n k for a complex product in the 3M
     // form (three real products), 4 m n k with a real B (two real products).  The classical
     // complex product counts 8 m n k; the 3M form reaches the same result with 3/4 of it.
@@ -957,7 +959,7 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
     // per lane that this imposes measured 15-20% faster than one wavefront with more
     // registers
     if constexpr (sizeof(T) == sizeof(double)) {
-        if (use_wide(m, n, k, S, lda, ldb)) {
+        if (wide) {
             const zd *Ad = (const zd *)A, *Bd = (const zd *)B;
             zd al = mk((double)alpha.x, (double)alpha.y), be = mk((double)beta.x, (double)beta.y);
             zd *Cd = (zd *)C;

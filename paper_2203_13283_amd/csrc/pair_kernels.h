@@ -94,13 +94,49 @@ struct PairConsts {
     zd ik4, ikt4;                    // i k / 4, i kt / 4
 };
 
-// Large-argument kernels (k R >= 22 for this lane) with a T-term series.
+// sin and cos of a phase x with |x| < 2^20 (the far kernels' k R: a contour of N <= 32768
+// nodes at 0.8 or more nodes per wavelength spans less than 2^17 radians): Cody and Waite's
+// reduction r = x - n pi/2 with n = rint(2 x / pi) and pi/2 split into three parts, the first
+// two with 33 significant bits so that n times them is exact, then the Taylor series of sin
+// (through r^15) and cos (through r^16) on |r| <= pi/4, whose first omitted terms are below
+// 5e-17 and 2e-18, and the quadrant n mod 4.
+__device__ __forceinline__ void sincos_phase(double x, double &s, double &c) {
+    constexpr double kP1 = 0x1.921fb544p+0, kP2 = 0x1.0b4611a6p-34,
+                     kP3 = 0x1.3198a2e037073p-69;
+    const double n = rint(x * 0.63661977236758134308);
+    double r = fma(-n, kP1, x);
+    r = fma(-n, kP2, r);
+    r = fma(-n, kP3, r);
+    const double r2 = r * r;
+    double ps = -1.0 / 1307674368000.0;
+    ps = fma(ps, r2, 1.0 / 6227020800.0);
+    ps = fma(ps, r2, -1.0 / 39916800.0);
+    ps = fma(ps, r2, 1.0 / 362880.0);
+    ps = fma(ps, r2, -1.0 / 5040.0);
+    ps = fma(ps, r2, 1.0 / 120.0);
+    ps = fma(ps, r2, -1.0 / 6.0);
+    const double sr = fma(ps * r2, r, r);
+    double pc = 1.0 / 20922789888000.0;
+    pc = fma(pc, r2, -1.0 / 87178291200.0);
+    pc = fma(pc, r2, 1.0 / 479001600.0);
+    pc = fma(pc, r2, -1.0 / 3628800.0);
+    pc = fma(pc, r2, 1.0 / 40320.0);
+    pc = fma(pc, r2, -1.0 / 720.0);
+    pc = fma(pc, r2, 1.0 / 24.0);
+    pc = fma(pc, r2, -0.5);
+    const double cr = fma(pc, r2, 1.0);
+    const int q = (int)n & 3;
+    const double a = (q & 1) ? cr : sr, b = (q & 1) ? sr : cr;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
+// Large-argument kernels (k R >= 22 for this lane) with a T-term series, given R and 1/R.
 template <int T>
-__device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R, double nu,
-                                                  zd &gk, zd &Dk, zd &St, zd &Dt) {
-    const double invR = 1.0 / R;
+__device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R, double invR,
+                                                  double nu, zd &gk, zd &Dk, zd &St, zd &Dt) {
     double sn, cs;
-    sincos(c.k * R, &sn, &cs);
+    sincos_phase(c.k * R, sn, cs);
     const double rs = rsqrt(R);
     const zd E = mk(cs * rs, sn * rs);                   // e^{ikR} R^{-1/2}
     const zd Et = E * exp(-c.beta * R);
@@ -125,6 +161,11 @@ __device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R,
     Dk = c.CD * E * mk(P1, Q1 * y) * nu;
     St = c.CS * Et * s0;
     Dt = c.CDt * Et * s1 * nu;
+}
+template <int T>
+__device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R, double nu,
+                                                  zd &gk, zd &Dk, zd &St, zd &Dt) {
+    pair_kernels_asym<T>(c, R, 1.0 / R, nu, gk, Dk, St, Dt);
 }
 
 // Any argument: ascending series / Miller recurrence below k R = 22 (kept out of line so
