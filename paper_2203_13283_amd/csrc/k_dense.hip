@@ -694,7 +694,12 @@ __global__ __launch_bounds__(64) void k_pchol_pivots(int b, const zd *W, int ldw
                 mp[q] = M[cc + (int64_t)p * b];
             }
         }
-        // the pivot's entries of the earlier rows of this panel, for every lane
+        // the pivot's entries of the earlier rows of this panel (the same for every lane),
+        // read once; the loops below over them are unrolled over the panel width, so that
+        // the lanes' LDS reads are issued ahead of the complex multiply-adds
+        zd rpv[kPcholNB];
+#pragma unroll
+        for (int i = 0; i < kPcholNB; ++i) rpv[i] = i < jp ? Rp[i * b + p] : mk(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int cc = lane + 64 * q;
@@ -705,12 +710,16 @@ __global__ __launch_bounds__(64) void k_pchol_pivots(int b, const zd *W, int ldw
                 r = mk(sd, 0.0);
             } else if (!tk[q]) {
                 r = conj(wp[q]);
-                for (int i = 0; i < jp; ++i) r = r - conj(Rp[i * b + p]) * Rp[i * b + cc];
+#pragma unroll
+                for (int i = 0; i < kPcholNB; ++i)
+                    if (i < jp) r = r - conj(rpv[i]) * Rp[i * b + cc];
                 r = r * isd;
             }
             zd z = mp[q];
             if (cc == p) z = z + mk(1.0, 0.0);
-            for (int i = 0; i < jp; ++i) z = z - Zp[i * b + cc] * Rp[i * b + p];
+#pragma unroll
+            for (int i = 0; i < kPcholNB; ++i)
+                if (i < jp) z = z - Zp[i * b + cc] * rpv[i];
             z = z * isd;
             Zp[jp * b + cc] = z;
             Z[cc + (int64_t)k * ldz] = z;
