@@ -695,11 +695,26 @@ __global__ __launch_bounds__(64) void k_pchol_pivots(int b, const zd *W, int ldw
             }
         }
         // the pivot's entries of the earlier rows of this panel (the same for every lane),
-        // read once; the loops below over them are unrolled over the panel width, so that
-        // the lanes' LDS reads are issued ahead of the complex multiply-adds
+        // read once; the sums over them below need neither W nor M, so they run while the
+        // loads of column p are in flight (unrolled over the panel width so that the lanes'
+        // LDS reads are issued ahead of the complex multiply-adds)
         zd rpv[kPcholNB];
 #pragma unroll
         for (int i = 0; i < kPcholNB; ++i) rpv[i] = i < jp ? Rp[i * b + p] : mk(0.0, 0.0);
+        zd sr[PER], sz[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int cc = lane + 64 * q;
+            sr[q] = sz[q] = mk(0.0, 0.0);
+            if (cc >= b) continue;
+#pragma unroll
+            for (int i = 0; i < kPcholNB; ++i) {
+                if (i < jp) {
+                    sr[q] = sr[q] + conj(rpv[i]) * Rp[i * b + cc];
+                    sz[q] = sz[q] + Zp[i * b + cc] * rpv[i];
+                }
+            }
+        }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int cc = lane + 64 * q;
@@ -709,17 +724,11 @@ __global__ __launch_bounds__(64) void k_pchol_pivots(int b, const zd *W, int ldw
             if (cc == p) {
                 r = mk(sd, 0.0);
             } else if (!tk[q]) {
-                r = conj(wp[q]);
-#pragma unroll
-                for (int i = 0; i < kPcholNB; ++i)
-                    if (i < jp) r = r - conj(rpv[i]) * Rp[i * b + cc];
-                r = r * isd;
+                r = (conj(wp[q]) - sr[q]) * isd;
             }
             zd z = mp[q];
             if (cc == p) z = z + mk(1.0, 0.0);
-#pragma unroll
-            for (int i = 0; i < kPcholNB; ++i)
-                if (i < jp) z = z - Zp[i * b + cc] * rpv[i];
+            z = z - sz[q];
             z = z * isd;
             Zp[jp * b + cc] = z;
             Z[cc + (int64_t)k * ldz] = z;
@@ -1032,15 +1041,20 @@ __device__ __forceinline__ zd pick16(const zd (&a)[16], int jj) {
 
 // partial pivoting over the rows held by the workgroup (one row per thread, values in a,
 // rows already chosen or absent have taken = true); the chosen row ids go to out[0..nb)
-// (-1 when no row is left).  NW wavefronts.
+// (-1 when no row is left).  NW wavefronts.  One barrier per pivot: each wavefront's best
+// row (largest |a_jj|, ties to the smaller row id) publishes its value, id and its whole row
+// in LDS slots of the pivot's parity, so that after the barrier every thread finds the
+// winner and reads its row without a second barrier (the slots of pivot jj are rewritten at
+// pivot jj + 2, after everyone has passed the barrier of pivot jj + 1).
 template <int NW>
 __device__ __forceinline__ void tournament(zd (&a)[16], bool taken, int row, int nb,
                                            int *out) {
-    const int tid = threadIdx.x;
-    __shared__ double wv[NW];
-    __shared__ int wi[NW];
-    __shared__ zd prow[16];
+    const int tid = threadIdx.x, w = tid >> 6;
+    __shared__ double wv[2][NW];
+    __shared__ int wi[2][NW];
+    __shared__ zd wrow[2][NW][16];
     for (int jj = 0; jj < nb; ++jj) {
+        const int par = jj & 1;
         double bv = taken ? -1.0 : abs2(pick16(a, jj));
         int bi = taken ? 0x7fffffff : row;
         for (int o = 32; o > 0; o >>= 1) {
@@ -1048,29 +1062,34 @@ __device__ __forceinline__ void tournament(zd (&a)[16], bool taken, int row, int
             const int oi = __shfl_xor(bi, o);
             if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
         }
-        if ((tid & 63) == 0) { wv[tid >> 6] = bv; wi[tid >> 6] = bi; }
+        if ((tid & 63) == 0) { wv[par][w] = bv; wi[par][w] = bi; }
+        if (bv >= 0.0 && !taken && row == bi) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) wrow[par][w][c] = a[c];
+        }
         __syncthreads();
-        bv = wv[0];
-        bi = wi[0];
-        for (int w = 1; w < NW; ++w)
-            if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
+        bv = wv[par][0];
+        bi = wi[par][0];
+        int bw = 0;
+        for (int v = 1; v < NW; ++v)
+            if (wv[par][v] > bv || (wv[par][v] == bv && wi[par][v] < bi)) {
+                bv = wv[par][v];
+                bi = wi[par][v];
+                bw = v;
+            }
         if (tid == 0) out[jj] = bv < 0.0 ? -1 : bi;
         if (bv >= 0.0 && !taken && row == bi) {
             taken = true;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) prow[c] = a[c];
-        }
-        __syncthreads();
-        if (bv >= 0.0 && !taken) {
-            const zd d = prow[jj];
+        } else if (bv >= 0.0 && !taken) {
+            const zd d = wrow[par][bw][jj];
             const zd dinv = (abs2(d) > 0.0) ? cinv(d) : mk(0.0, 0.0);
             const zd l = pick16(a, jj) * dinv;
 #pragma unroll
             for (int c = 1; c < 16; ++c)
-                if (c > jj && c < nb) a[c] = a[c] - l * prow[c];
+                if (c > jj && c < nb) a[c] = a[c] - l * wrow[par][bw][c];
         }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 // candidates of chunk blockIdx.x (rows k0 + 256 blockIdx.x + tid) -> cand[16 blockIdx.x ..]
@@ -1133,17 +1152,20 @@ __global__ __launch_bounds__(64 * NW) void k_tslu_final(int n, int k0, int nb, z
         }
     }
     __syncthreads();
-    // the exchanges, in order, on the panel's columns
-    for (int jj = 0; jj < nb; ++jj) {
-        const int j = k0 + jj, q = pv[jj];
-        if (q != j && tid < nb) {
-            const int64_t c = (int64_t)(k0 + tid) * lda;
-            const zd t = A[j + c];
-            A[j + c] = A[q + c];
-            A[q + c] = t;
+    // the exchanges, in order, on the panel's columns: thread tid < nb owns column k0 + tid,
+    // so the sequence needs no barrier between exchanges
+    if (tid < nb) {
+        const int64_t c = (int64_t)(k0 + tid) * lda;
+        for (int jj = 0; jj < nb; ++jj) {
+            const int j = k0 + jj, q = pv[jj];
+            if (q != j) {
+                const zd t = A[j + c];
+                A[j + c] = A[q + c];
+                A[q + c] = t;
+            }
         }
-        __syncthreads();
     }
+    __syncthreads();
     // unpivoted LU of the nb x nb top block in LDS (thread (i, c) = (tid / 16, tid % 16))
     __shared__ zd T[16][16];
     const int i = tid >> 4, c = tid & 15;
