@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -18,69 +19,103 @@ namespace cfie {
 
 namespace {
 
-zd zeval(const std::vector<zd> &zh, int M, double t, int deriv) {
-    zd acc = mk(0.0, 0.0);
-    for (int m = -M; m <= M; ++m) {
-        double s = std::sin(m * t), c = std::cos(m * t);
-        zd e = mk(c, s);
-        zd v = zh[m + M] * e;
-        if (deriv == 1) v = cmul_i(v) * (double)m;
-        if (deriv == 2) v = v * (-(double)m * (double)m);
-        acc = acc + v;
-    }
-    return acc;
+// e^{-2 pi i j / P}, j = 0..P-1
+std::vector<zd> unit_roots(int P) {
+    std::vector<zd> r(P);
+    for (int j = 0; j < P; ++j) r[j] = mk(std::cos(2.0 * kPi * j / P), -std::sin(2.0 * kPi * j / P));
+    return r;
 }
 
+// z, z' and z'' at tau_j = 2 pi j / P, with e^{i m tau_j} taken from the root table of P
+void zeval_grid(const std::vector<zd> &zh, int M, const std::vector<zd> &roots, int64_t j,
+                zd &z, zd &d1, zd &d2) {
+    const int64_t P = (int64_t)roots.size();
+    z = d1 = d2 = mk(0.0, 0.0);
+    for (int m = -M; m <= M; ++m) {
+        const int64_t r = (((int64_t)m * j) % P + P) % P;
+        const zd v = zh[m + M] * conj(roots[r]);
+        z = z + v;
+        d1 = d1 + cmul_i(v) * (double)m;
+        d2 = d2 + v * (-(double)m * (double)m);
+    }
+}
+
+// Whether segments ab and cd cross at interior points of both (parallel segments never do):
+// a + t (b - a) = c + u (d - c) with 0 < t, u < 1, compared without dividing by the
+// determinant.
 bool seg_intersect(zd a, zd b, zd c, zd d) {
     auto cross = [](zd u, zd v) { return u.x * v.y - u.y * v.x; };
-    zd r = b - a, s = d - c, ca = c - a;
-    double den = cross(r, s);
+    const zd r = b - a, s = d - c, ca = c - a;
+    const double den = cross(r, s);
     if (den == 0.0) return false;
-    double t = cross(ca, s) / den, u = cross(ca, r) / den;
-    return t > 0.0 && t < 1.0 && u > 0.0 && u < 1.0;
+    const double tn = cross(ca, s), un = cross(ca, r);
+    if (den > 0.0) return tn > 0.0 && tn < den && un > 0.0 && un < den;
+    return tn < 0.0 && tn > den && un < 0.0 && un > den;
 }
 
-// Whether two edges of the closed polygon p that do not share a vertex cross.  The edges are
-// put into the cells of a uniform grid that their bounding boxes overlap (cells about two
-// mean edge lengths wide, at most about 4 cells per edge), and only edges sharing a cell are
-// tested against each other: linear work for a smooth curve instead of all pairs.
+// Whether two edges of the closed polygon p that do not share a vertex cross.  The edges, in
+// their order along the curve, are grouped in leaves of four; a binary tree over the leaves
+// holds the bounding box of each run of consecutive edges.  Two runs are compared only when
+// their boxes overlap, and two leaves edge by edge; for a smooth curve only runs that meet
+// end to end (or pass close to each other) overlap, so the work is about linear in the
+// number of edges, with the boxes read in order.
 bool polygon_self_intersects(const std::vector<zd> &p) {
     const int64_t Q = (int64_t)p.size();
     if (Q < 4) return false;
-    double x0 = p[0].x, x1 = p[0].x, y0 = p[0].y, y1 = p[0].y, len = 0.0;
-    for (int64_t j = 0; j < Q; ++j) {
-        x0 = std::fmin(x0, p[j].x);
-        x1 = std::fmax(x1, p[j].x);
-        y0 = std::fmin(y0, p[j].y);
-        y1 = std::fmax(y1, p[j].y);
-        len += cabs(p[(j + 1) % Q] - p[j]);
+    constexpr int64_t kLeaf = 4;
+    const int64_t nl = (Q + kLeaf - 1) / kLeaf;
+    int64_t np = 1;
+    while (np < nl) np <<= 1;
+    struct Box { double x0, x1, y0, y1; };
+    const double inf = std::numeric_limits<double>::infinity();
+    std::vector<Box> bx((size_t)(2 * np), Box{inf, -inf, inf, -inf});   // empty boxes
+    for (int64_t l = 0; l < nl; ++l) {
+        Box bb{inf, -inf, inf, -inf};
+        for (int64_t e = l * kLeaf; e <= std::min(Q, (l + 1) * kLeaf); ++e) {   // vertices
+            const zd v = p[e % Q];
+            bb = Box{std::fmin(bb.x0, v.x), std::fmax(bb.x1, v.x), std::fmin(bb.y0, v.y),
+                     std::fmax(bb.y1, v.y)};
+        }
+        bx[(size_t)(np + l)] = bb;
     }
-    double cell = std::fmax(2.0 * len / (double)Q, 1e-300);
-    while (((x1 - x0) / cell + 1.0) * ((y1 - y0) / cell + 1.0) > 4.0 * (double)Q) cell *= 2.0;
-    const int64_t gx = (int64_t)((x1 - x0) / cell) + 1;
-    std::vector<std::pair<int64_t, int64_t>> ce;      // (cell, edge)
-    ce.reserve((size_t)Q * 4);
-    for (int64_t e = 0; e < Q; ++e) {
-        const zd a = p[e], b = p[(e + 1) % Q];
-        const int64_t i0 = (int64_t)((std::fmin(a.x, b.x) - x0) / cell);
-        const int64_t i1 = (int64_t)((std::fmax(a.x, b.x) - x0) / cell);
-        const int64_t j0 = (int64_t)((std::fmin(a.y, b.y) - y0) / cell);
-        const int64_t j1 = (int64_t)((std::fmax(a.y, b.y) - y0) / cell);
-        for (int64_t j = j0; j <= j1; ++j)
-            for (int64_t i = i0; i <= i1; ++i) ce.emplace_back(j * gx + i, e);
+    for (int64_t i = np - 1; i >= 1; --i) {
+        const Box &u = bx[(size_t)(2 * i)], &v = bx[(size_t)(2 * i + 1)];
+        bx[(size_t)i] = Box{std::fmin(u.x0, v.x0), std::fmax(u.x1, v.x1), std::fmin(u.y0, v.y0),
+                            std::fmax(u.y1, v.y1)};
     }
-    std::sort(ce.begin(), ce.end());
-    for (size_t lo = 0; lo < ce.size();) {
-        size_t hi = lo;
-        while (hi < ce.size() && ce[hi].first == ce[lo].first) ++hi;
-        for (size_t u = lo; u < hi; ++u)
-            for (size_t v = u + 1; v < hi; ++v) {
-                const int64_t a = ce[u].second, b = ce[v].second;
+    auto overlap = [](const Box &u, const Box &v) {
+        return u.x0 <= v.x1 && v.x0 <= u.x1 && u.y0 <= v.y1 && v.y0 <= u.y1;
+    };
+    auto leaves = [&](int64_t la, int64_t lb) {         // edges of leaf la against leaf lb
+        const int64_t ea = std::min(Q, (la + 1) * kLeaf), eb = std::min(Q, (lb + 1) * kLeaf);
+        for (int64_t a = la * kLeaf; a < ea; ++a)
+            for (int64_t b = la == lb ? a + 2 : lb * kLeaf; b < eb; ++b) {
                 const int64_t d = b > a ? b - a : a - b;
                 if (d <= 1 || d == Q - 1) continue;          // edges sharing a vertex
                 if (seg_intersect(p[a], p[(a + 1) % Q], p[b], p[(b + 1) % Q])) return true;
             }
-        lo = hi;
+        return false;
+    };
+    // pairs of nodes of one level: (i, i) = the pairs within node i, (i, j) = i against j
+    std::vector<std::pair<int64_t, int64_t>> st{{1, 1}};
+    while (!st.empty()) {
+        const auto [a, b] = st.back();
+        st.pop_back();
+        if (!overlap(bx[(size_t)a], bx[(size_t)b])) continue;   // also skips empty nodes
+        if (a >= np) {
+            if (leaves(a - np, b - np)) return true;
+            continue;
+        }
+        if (a == b) {
+            st.push_back({2 * a, 2 * a});
+            st.push_back({2 * a + 1, 2 * a + 1});
+            st.push_back({2 * a, 2 * a + 1});
+        } else {
+            st.push_back({2 * a, 2 * b});
+            st.push_back({2 * a, 2 * b + 1});
+            st.push_back({2 * a + 1, 2 * b});
+            st.push_back({2 * a + 1, 2 * b + 1});
+        }
     }
     return false;
 }
@@ -133,14 +168,13 @@ std::string build_geometry(const cfie_contour &c, HostGeometry &g) {
     }
     int P = 4096;
     while (P < 64 * (2 * g.M + 1)) P *= 2;
+    const std::vector<zd> roots = unit_roots(P);
     std::vector<double> speed(P), curv(P);
     double area = 0.0;
     double min_speed = 1e300;
     for (int j = 0; j < P; ++j) {
-        double t = 2.0 * kPi * j / P;
-        zd z = zeval(g.zhat, g.M, t, 0);
-        zd d1 = zeval(g.zhat, g.M, t, 1);
-        zd d2 = zeval(g.zhat, g.M, t, 2);
+        zd z, d1, d2;
+        zeval_grid(g.zhat, g.M, roots, j, z, d1, d2);
         double sp = cabs(d1);
         speed[j] = sp;
         min_speed = std::fmin(min_speed, sp);
@@ -153,33 +187,54 @@ std::string build_geometry(const cfie_contour &c, HostGeometry &g) {
     // self-intersection of the polygon through 16 N points of the curve (at least 1024)
     {
         const int Q = std::max(1024, 16 * c.n_nodes);
+        // w_j = e^{2 pi i j / Q} as the product of two table entries, j = 512 a + b
+        const int nb = 512, na = (Q + nb - 1) / nb;
+        std::vector<zd> wa(na), wb(nb);
+        for (int a = 0; a < na; ++a)
+            wa[a] = mk(std::cos(2.0 * kPi * ((double)a * nb) / Q), std::sin(2.0 * kPi * ((double)a * nb) / Q));
+        for (int b = 0; b < nb; ++b) wb[b] = mk(std::cos(2.0 * kPi * b / Q), std::sin(2.0 * kPi * b / Q));
         std::vector<zd> poly(Q);
-        for (int j = 0; j < Q; ++j) {
-            // z(t) = sum_m zhat_m w^m, w = e^{it}, by Horner in w and in 1/w = conj(w)
-            const double t = 2.0 * kPi * j / Q;
-            const zd w = mk(std::cos(t), std::sin(t)), wc = mk(w.x, -w.y);
-            zd hi = mk(0.0, 0.0), lo = mk(0.0, 0.0);
-            for (int m = g.M; m >= 1; --m) {
-                hi = hi * w + g.zhat[g.M + m];
-                lo = lo * wc + g.zhat[g.M - m];
+        // z(t) = sum_m zhat_m w^m, w = e^{it}, by Horner in w and in 1/w = conj(w); four
+        // points at a time, so that their recurrences overlap
+        constexpr int kU = 4;
+        for (int j0 = 0; j0 < Q; j0 += kU) {
+            zd w[kU], wc[kU], hi[kU], lo[kU];
+            for (int u = 0; u < kU; ++u) {
+                const int j = std::min(j0 + u, Q - 1);
+                w[u] = wa[j / nb] * wb[j % nb];
+                wc[u] = mk(w[u].x, -w[u].y);
+                hi[u] = lo[u] = mk(0.0, 0.0);
             }
-            poly[j] = g.zhat[g.M] + hi * w + lo * wc;
+            for (int m = g.M; m >= 1; --m)
+                for (int u = 0; u < kU; ++u) {
+                    hi[u] = hi[u] * w[u] + g.zhat[g.M + m];
+                    lo[u] = lo[u] * wc[u] + g.zhat[g.M - m];
+                }
+            for (int u = 0; u < kU && j0 + u < Q; ++u)
+                poly[j0 + u] = g.zhat[g.M] + hi[u] * w[u] + lo[u] * wc[u];
         }
         if (polygon_self_intersects(poly)) return "contour intersects itself";
     }
     // Fourier coefficients of the speed by direct summation with exact root indices
-    std::vector<zd> roots(P);
-    for (int j = 0; j < P; ++j) roots[j] = mk(std::cos(2.0 * kPi * j / P), -std::sin(2.0 * kPi * j / P));
-    double c0 = 0.0;
-    for (int j = 0; j < P; ++j) c0 += speed[j];
-    c0 /= P;
+    // the mean speed by compensated (Neumaier) summation: the perimeter 2 pi c0 sets the mesh
+    double c0 = 0.0, comp = 0.0;
+    for (int j = 0; j < P; ++j) {
+        const double t = c0 + speed[j];
+        comp += std::fabs(c0) >= std::fabs(speed[j]) ? (c0 - t) + speed[j] : (speed[j] - t) + c0;
+        c0 = t;
+    }
+    c0 = (c0 + comp) / P;
     g.c0 = c0;
     g.cm.clear();
     int mmax = P / 4;
     std::vector<zd> coef(mmax + 1);
     for (int m = 1; m <= mmax; ++m) {
         zd acc = mk(0.0, 0.0);
-        for (int j = 0; j < P; ++j) acc = acc + roots[(long)m * j % P] * speed[j];
+        for (int j = 0, r = 0; j < P; ++j) {          // r = m j mod P
+            acc = acc + roots[r] * speed[j];
+            r += m;
+            if (r >= P) r -= P;
+        }
         coef[m] = acc * (1.0 / P);
     }
     // rounding floor of the transform from its upper half, where an analytic speed has
@@ -212,9 +267,7 @@ void speed_coeffs_adjoint(const HostGeometry &g, double c0bar, const std::vector
     int P = 4096;
     while (P < 64 * (2 * g.M + 1)) P *= 2;
     const int Ms = (int)g.cm.size();
-    std::vector<zd> roots(P);
-    for (int j = 0; j < P; ++j)
-        roots[j] = mk(std::cos(2.0 * kPi * j / P), -std::sin(2.0 * kPi * j / P));
+    const std::vector<zd> roots = unit_roots(P);
     for (int j = 0; j < P; ++j) {
         double sb = c0bar;
         for (int m = 1; m <= Ms && m <= (int)cmbar.size(); ++m) {
@@ -223,7 +276,8 @@ void speed_coeffs_adjoint(const HostGeometry &g, double c0bar, const std::vector
         }
         sb /= P;
         if (sb == 0.0) continue;
-        zd d1 = zeval(g.zhat, g.M, 2.0 * kPi * j / P, 1);
+        zd z, d1, d2;
+        zeval_grid(g.zhat, g.M, roots, j, z, d1, d2);
         double sp = cabs(d1);
         zd T = d1 * (1.0 / sp);
         for (int m = -g.M; m <= g.M; ++m) {
@@ -266,17 +320,22 @@ void tanh_sinh01(double step, std::vector<double> &u, std::vector<double> &w) {
     }
 }
 
-// Lagrange basis polynomial l_g on the nodes xs, evaluated at x (barycentric form)
-double lagrange(const std::vector<double> &xs, const std::vector<double> &bw, int g, double x) {
-    double num = 0.0, den = 0.0;
-    for (size_t j = 0; j < xs.size(); ++j) {
-        double d = x - xs[j];
-        if (d == 0.0) return (int)j == g ? 1.0 : 0.0;
-        double t = bw[j] / d;
-        den += t;
-        if ((int)j == g) num = t;
+// all Lagrange basis polynomials l_0..l_{q-1} on the nodes xs, evaluated at x (barycentric
+// form), into l
+void lagrange_all(const std::vector<double> &xs, const std::vector<double> &bw, double x,
+                  double *l) {
+    const int q = (int)xs.size();
+    double den = 0.0;
+    for (int j = 0; j < q; ++j) {
+        const double d = x - xs[j];
+        if (d == 0.0) {
+            for (int i = 0; i < q; ++i) l[i] = i == j ? 1.0 : 0.0;
+            return;
+        }
+        l[j] = bw[j] / d;
+        den += l[j];
     }
-    return num / den;
+    for (int j = 0; j < q; ++j) l[j] /= den;
 }
 
 }  // namespace
@@ -298,55 +357,52 @@ void log_moments(int q, std::vector<double> &mom) {
     std::vector<double> ix, iw;
     gauss_legendre01(ni, ix, iw);
     mom.assign((size_t)3 * 5 * q * q, 0.0);
-    auto P = [&](int g, int c, double x, bool obs) {
-        double l = lagrange(xs, bw, g, x);
-        if (c == 4) return l;
-        int a = obs ? (c >> 1) : (c & 1);
-        return l * (a == 0 ? 1.0 - x : x);
-    };
-    for (int c = 0; c < 5; ++c)
-        for (int g = 0; g < q; ++g)
-            for (int hh = 0; hh < q; ++hh) {
-                // kind 0: coincident, int_0^1 log(u) F(u) du with
-                // F(u) = int_u^1 P(xi) Q(xi-u) dxi + int_0^{1-u} P(xi) Q(xi+u) dxi
-                double acc0 = 0.0;
-                for (size_t t = 0; t < tu.size(); ++t) {
-                    double u = tu[t];
-                    double F = 0.0;
-                    for (int i = 0; i < ni; ++i) {
-                        double xa = u + (1.0 - u) * ix[i];
-                        double xb = (1.0 - u) * ix[i];
-                        F += (1.0 - u) * iw[i] *
-                             (P(g, c, xa, true) * P(hh, c, xa - u, false) +
-                              P(g, c, xb, true) * P(hh, c, xb + u, false));
-                    }
-                    acc0 += tw[t] * std::log(u) * F;
-                }
-                // kind 1: source element follows, sigma = a + b, a = 1 - xi, b = xi'
-                // kind 2: source element precedes, sigma = a + b, a = xi, b = 1 - xi'
-                double acc1 = 0.0, acc2 = 0.0;
-                for (size_t t = 0; t < tu.size(); ++t) {
-                    double rho = tu[t];
-                    double s1 = 0.0, s2 = 0.0;
-                    for (int i = 0; i < nv; ++i) {
-                        double v = vx[i];
-                        double lg = std::log(rho) + std::log1p(v);
-                        // triangle a >= b: a = rho, b = rho v ; triangle a < b: b = rho, a = rho v
-                        double a1 = rho, b1 = rho * v, a2 = rho * v, b2 = rho;
-                        s1 += vw[i] * lg *
-                              (P(g, c, 1.0 - a1, true) * P(hh, c, b1, false) +
-                               P(g, c, 1.0 - a2, true) * P(hh, c, b2, false));
-                        s2 += vw[i] * lg *
-                              (P(g, c, a1, true) * P(hh, c, 1.0 - b1, false) +
-                               P(g, c, a2, true) * P(hh, c, 1.0 - b2, false));
-                    }
-                    acc1 += tw[t] * rho * s1;
-                    acc2 += tw[t] * rho * s2;
-                }
-                mom[((size_t)0 * 5 + c) * q * q + g * q + hh] = acc0;
-                mom[((size_t)1 * 5 + c) * q * q + g * q + hh] = acc1;
-                mom[((size_t)2 * 5 + c) * q * q + g * q + hh] = acc2;
+    // Every moment of one kind is a sum over the same quadrature points (xi, xi') with weight
+    // w of w P_g(xi) Q_h(xi'), where P and Q are a Lagrange polynomial times a linear hat
+    // factor (1 - x or x, none for c = 4; the observation factor is chosen by bit 1 of c,
+    // the source factor by bit 0).  The Lagrange values at a point serve all g, h and c.
+    std::vector<double> lo(q), ls(q);
+    auto point = [&](int kind, double w, double xo, double xsrc) {
+        lagrange_all(xs, bw, xo, lo.data());
+        lagrange_all(xs, bw, xsrc, ls.data());
+        for (int c = 0; c < 5; ++c) {
+            const double fo = c == 4 ? 1.0 : ((c >> 1) == 0 ? 1.0 - xo : xo);
+            const double fs = c == 4 ? 1.0 : ((c & 1) == 0 ? 1.0 - xsrc : xsrc);
+            const double f = w * fo * fs;
+            double *m = &mom[((size_t)kind * 5 + c) * q * q];
+            for (int g = 0; g < q; ++g) {
+                const double a = f * lo[g];
+                for (int h = 0; h < q; ++h) m[g * q + h] += a * ls[h];
             }
+        }
+    };
+    // kind 0: coincident, int_0^1 log(u) F(u) du with
+    // F(u) = int_u^1 P(xi) Q(xi-u) dxi + int_0^{1-u} P(xi) Q(xi+u) dxi
+    for (size_t t = 0; t < tu.size(); ++t) {
+        const double u = tu[t];
+        const double wt = tw[t] * std::log(u) * (1.0 - u);
+        for (int i = 0; i < ni; ++i) {
+            const double xa = u + (1.0 - u) * ix[i];
+            const double xb = (1.0 - u) * ix[i];
+            point(0, wt * iw[i], xa, xa - u);
+            point(0, wt * iw[i], xb, xb + u);
+        }
+    }
+    // kind 1: source element follows, sigma = a + b, a = 1 - xi, b = xi'
+    // kind 2: source element precedes, sigma = a + b, a = xi, b = 1 - xi'
+    // each over the triangles a >= b (a = rho, b = rho v) and a < b (b = rho, a = rho v)
+    for (size_t t = 0; t < tu.size(); ++t) {
+        const double rho = tu[t];
+        for (int i = 0; i < nv; ++i) {
+            const double v = vx[i];
+            const double w = tw[t] * rho * vw[i] * (std::log(rho) + std::log1p(v));
+            const double a1 = rho, b1 = rho * v, a2 = rho * v, b2 = rho;
+            point(1, w, 1.0 - a1, b1);
+            point(1, w, 1.0 - a2, b2);
+            point(2, w, a1, 1.0 - b1);
+            point(2, w, a2, 1.0 - b2);
+        }
+    }
 }
 
 }  // namespace cfie
