@@ -663,9 +663,12 @@ int orthonormalise(cfie_ctx *c, cpx<T> *Y, int b, double tau, int planned = -1) 
     gemm<T>(GEMM_N, N, k, b, cz<T>(1), Y, N, rinvT, b, cz<T>(0), Y2, N, s);
     axpby<T>(N, k, cz<T>(1), Y2, N, cz<T>(0), Y, N, s);
     // Newton-Schulz steps towards the orthonormal polar factor: Y <- Y (3 I - Y^H Y) / 2.
-    // After the pivoted step ||Y^H Y - I|| is at most ~1e-3 (FP64) or ~1e-1 (FP32 data),
-    // and each step squares it.
-    const int steps = sizeof(T) == sizeof(double) ? 3 : 4;
+    // After the pivoted step ||Y^H Y - I|| is at most ~1e-3 (FP64: the kept pivots bound the
+    // factor's condition number by rel2^(-1/2), and the error is about its square times the
+    // unit roundoff) or ~1e-1 (FP32 data), and each step squares it: two steps leave ~1e-12
+    // in FP64, far below epsilon >= 1e-7 (the skeleton Q Q^H (C - C_c) errs by about that
+    // deviation times ||C - C_c||); a third step for tighter epsilon.
+    const int steps = sizeof(T) == sizeof(double) ? (c->opt.compress_tol >= 1e-7 ? 2 : 3) : 4;
     for (int it = 0; it < steps; ++it) {
         gram64<T>(c, Y, k, c->w_gram);
         launch_polar_coef<T>(k, c->w_gram, k, rinvT, k, s);
@@ -703,8 +706,12 @@ void alloc_factor(cfie_ctx *c) {
 
 // Triangular solves with the LU factors of K (P K = L U) by blocks of kLUBlock rows (their
 // diagonal inverses Linv, Uinv) grouped into superblocks of kLUSuper rows: inside a
-// superblock each block's update reaches the superblock's other rows only, and one update of
-// inner dimension kLUSuper carries the superblock to the rest of the right-hand sides.
+// superblock each block's update reaches the superblock's other rows only.  Between
+// superblocks, lu_solve (many right-hand sides: K^-1 V^T) gathers all earlier superblocks'
+// contributions to a superblock in one product whose inner dimension is everything solved so
+// far (left-looking: kLUSuper rows by all columns of the right-hand sides, a grid that fills
+// the device once, with long K); lu_solve_adj (the few right-hand sides of a solve) carries
+// each finished superblock to all later rows in one product of inner dimension kLUSuper.
 namespace {
 struct LUSolveCtx {
     cfie_ctx *c;
@@ -720,7 +727,7 @@ struct LUSolveCtx {
     }
     // Z[r0:r0+nr] -= op(A) Z[k0:k0+kb], A given by its stored block
     void update(int op, const zd *A, int r0, int nr, int k0, int kb) const {
-        if (nr <= 0) return;
+        if (nr <= 0 || kb <= 0) return;
         gemm<double>(op, nr, m, kb, cz<double>(-1), A, c->cap, Z + k0, ldz, cz<double>(1),
                      Z + r0, ldz, c->stream);
     }
@@ -735,22 +742,22 @@ void lu_solve(cfie_ctx *c, zd *Z, int64_t ldz, int64_t m, zd *tmp) {
     launch_swaps<double>(0, n, c->piv, Z, ldz, 0, m, c->stream);
     for (int s0 = 0; s0 < n; s0 += kLUSuper) {
         const int s1 = std::min(n, s0 + kLUSuper);
+        L.update(GEMM_N, L.at(s0, 0), s0, s1 - s0, 0, s0);      // rows 0..s0 of L
         for (int k0 = s0; k0 < s1; k0 += nb) {
             const int kb = std::min(nb, s1 - k0);
             L.diag(GEMM_N, c->Linv, k0, kb);
             L.update(GEMM_N, L.at(k0 + kb, k0), k0 + kb, s1 - k0 - kb, k0, kb);
         }
-        L.update(GEMM_N, L.at(s1, s0), s1, n - s1, s0, s1 - s0);
     }
     const int nsup = (n + kLUSuper - 1) / kLUSuper;
     for (int si = nsup - 1; si >= 0; --si) {
         const int s0 = si * kLUSuper, s1 = std::min(n, s0 + kLUSuper);
+        L.update(GEMM_N, L.at(s0, s1), s0, s1 - s0, s1, n - s1);  // rows s1..n of U
         for (int k0 = s0 + ((s1 - s0 - 1) / nb) * nb; k0 >= s0; k0 -= nb) {
             const int kb = std::min(nb, s1 - k0);
             L.diag(GEMM_N, c->Uinv, k0, kb);
             L.update(GEMM_N, L.at(s0, k0), s0, k0 - s0, k0, kb);
         }
-        L.update(GEMM_N, L.at(0, s0), 0, s0, s0, s1 - s0);
     }
     c->check_launch();
 }

@@ -764,6 +764,118 @@ __global__ __launch_bounds__(64) void k_pchol_pivots(int b, const zd *W, int ldw
     }
 }
 
+// The same panel for b <= 256 by one workgroup of 256 threads, thread c owning column and row
+// c: the same arithmetic in the same order per column as k_pchol_pivots (so the same pivots
+// and values), with the sums of a column in one thread instead of four per lane.  The pivot
+// search combines the four wavefronts' candidates through LDS slots that alternate between
+// two sets (a set is rewritten two pivots later, after another barrier), so one barrier per
+// pivot orders both the search and the panel rows read by the next pivot.
+__global__ __launch_bounds__(256) void k_pchol_pivots_wg(int b, const zd *W, int ldw, zd *Z,
+                                                         int ldz, const zd *M, void *wsb) {
+    const int c = threadIdx.x, lane = c & 63, wv = c >> 6;
+    PcholWs ws = pchol_ws(wsb, b);
+    if (ws.st[2] || ws.st[0] >= b) {
+        if (c == 0) ws.st[1] = 0;
+        return;
+    }
+    __shared__ zd Rp[kPcholNB * 256];            // Rp[i * b + c]
+    __shared__ zd Zp[kPcholNB * 256];            // Zp[i * b + r]
+    __shared__ double slot_v[2][4];
+    __shared__ int slot_i[2][4];
+    const bool own = c < b;
+    double dl = own ? ws.d[c] : -1.0;
+    int tk = own ? ws.taken[c] : 1;
+    const double thr = ws.thr[0];
+    int k = ws.st[0];
+    int jp = 0;
+    bool stop = false;
+    for (; jp < kPcholNB && k < b; ++jp) {
+        // pivot: largest untaken d (ties: smallest index)
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        if (own && !tk && dl >= bv) {
+            bv = dl;
+            bi = c;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        const int par = jp & 1;
+        if (lane == 0) {
+            slot_v[par][wv] = bv;
+            slot_i[par][wv] = bi;
+        }
+        __syncthreads();
+        bv = slot_v[par][0];
+        bi = slot_i[par][0];
+#pragma unroll
+        for (int x = 1; x < 4; ++x) {
+            const double ov = slot_v[par][x];
+            const int oi = slot_i[par][x];
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (!(bv > thr)) {
+            stop = true;
+            break;
+        }
+        const int p = bi;
+        const double sd = sqrt(bv), isd = 1.0 / sd;
+        zd wp = mk(0.0, 0.0), mp = mk(0.0, 0.0);
+        if (own) {
+            wp = W[c + (int64_t)p * ldw];
+            mp = M[c + (int64_t)p * b];
+        }
+        // sums over the earlier rows of this panel (written before the barrier above)
+        zd sr = mk(0.0, 0.0), sz = mk(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < kPcholNB; ++i) {
+            if (i < jp) {
+                const zd rpv = Rp[i * b + p];
+                if (own) {
+                    sr = sr + conj(rpv) * Rp[i * b + c];
+                    sz = sz + Zp[i * b + c] * rpv;
+                }
+            }
+        }
+        if (own) {
+            // pivot row from column p of W at the panel start: W[p, c] = conj(W[c, p])
+            zd r = mk(0.0, 0.0);
+            if (c == p) {
+                r = mk(sd, 0.0);
+            } else if (!tk) {
+                r = (conj(wp) - sr) * isd;
+            }
+            zd z = mp;
+            if (c == p) z = z + mk(1.0, 0.0);
+            z = z - sz;
+            z = z * isd;
+            Zp[jp * b + c] = z;
+            Z[c + (int64_t)k * ldz] = z;
+            Rp[jp * b + c] = r;
+            if (c == p) tk = 1;
+            else if (!tk) dl -= abs2(r);
+        }
+        ++k;
+    }
+    // hand the panel to the update kernel (each thread its own column) and the state to the
+    // next panel
+    if (own) {
+        for (int i = 0; i < jp; ++i) {
+            ws.Rg[i * b + c] = Rp[i * b + c];
+            ws.Zg[i * b + c] = Zp[i * b + c];
+        }
+        ws.d[c] = dl;
+        ws.taken[c] = tk;
+    }
+    if (c == 0) {
+        ws.st[0] = k;
+        ws.st[1] = jp;
+        ws.st[2] = stop ? 1 : 0;
+    }
+}
+
 // W -= Rp^H Rp and M -= Zp Rp over the whole b x b for the panel just found (nothing after
 // the last panel: no pivots follow)
 __global__ void k_pchol_update(int b, zd *W, int ldw, zd *M, const void *wsb) {
@@ -805,8 +917,12 @@ void launch_pchol(int b, zd *W, int ldw, double thr_abs, double thr_rel, zd *Z, 
         const int npanel = (b + pchol_nb(b) - 1) / pchol_nb(b);
         const unsigned ub = (unsigned)(((int64_t)b * b + 255) / 256);
         for (int pnl = 0; pnl < npanel; ++pnl) {
-            hipLaunchKernelGGL(k_pchol_pivots, dim3(1), dim3(64), 0, s, b, (const zd *)W, ldw, Z,
-                               ldz, (const zd *)M, ws);
+            if (b <= 256)
+                hipLaunchKernelGGL(k_pchol_pivots_wg, dim3(1), dim3(256), 0, s, b, (const zd *)W,
+                                   ldw, Z, ldz, (const zd *)M, ws);
+            else
+                hipLaunchKernelGGL(k_pchol_pivots, dim3(1), dim3(64), 0, s, b, (const zd *)W,
+                                   ldw, Z, ldz, (const zd *)M, ws);
             hipLaunchKernelGGL(k_pchol_update, dim3(ub), dim3(256), 0, s, b, W, ldw, M,
                                (const void *)ws);
         }

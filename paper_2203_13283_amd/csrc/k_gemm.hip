@@ -907,12 +907,19 @@ std::atomic<int> g_wide_mode{1};
 // 5-15% faster than the 64 x 64 tile there (at N = 16384: the sketch's N x N x 256 products
 // and their adjoints, V^T U~, the solve's W Y and U~ Z with K = 3943, the Gram-Schmidt
 // updates; 7% at K = 2048); with fewer tiles than compute units its one workgroup per
-// compute unit loses against the 64 x 64 tile's two.  Its shifted edge tiles need
-// m, n >= 128, its 32-bit lane offsets leading dimensions below 2^24.
+// compute unit loses against the 64 x 64 tile's two.  From K = 256 to 2048 only for a grid of
+// one wave (240-256 tiles, one per compute unit): N x 256 x K Gram-Schmidt updates and
+// Newton-Schulz products, 256 x N x K superblock products of the triangular solves, 5-10%
+// faster; with several waves of such short-K tiles the 64 x 64 tile's two workgroups per
+// compute unit hide each other's epilogues, and it wins.  The two kernels give bitwise equal
+// results.  The shifted edge tiles need m, n >= 128, the 32-bit lane offsets leading
+// dimensions below 2^24.
 bool use_wide(int64_t m, int64_t n, int64_t k, int S, int64_t lda, int64_t ldb) {
     const int64_t t = ((m + kWideTile - 1) / kWideTile) * ((n + kWideTile - 1) / kWideTile);
-    return g_wide_mode.load() != 0 && k >= 2048 && t * S >= 240 && m >= kWideTile &&
-           n >= kWideTile && lda < kWideMaxLd && ldb < kWideMaxLd;
+    const int64_t g = t * S;
+    const bool fit = k >= 2048 ? g >= 240 : (k >= 256 && g >= 240 && g <= 256);
+    return g_wide_mode.load() != 0 && fit && m >= kWideTile && n >= kWideTile &&
+           lda < kWideMaxLd && ldb < kWideMaxLd;
 }
 }  // namespace
 
