@@ -54,15 +54,19 @@ constexpr int kFarCols = 64;          // node columns per wavefront
 template <int Q>
 struct QuadConsts {
     double xi[Q], w[Q];
+    double ha0[Q], ha1[Q];           // h w_g phi_0(xi_g), h w_g phi_1(xi_g) (far kernel)
 };
 
-// 2x2 block of element pair (e, f) for the four matrices, accumulated point pair by point
-// pair: A_b[m][a] += K_m(g, hh) h^2 w_g w_hh phi_a(xi_g) phi_b(xi_hh) (b = 0 into acc0, the
-// node column f; b = 1 into acc1, the node column f + 1), and for N^k the Maue term
-// K (s_a s_b w_g w_hh - k^2 n.n' h^2 w_g w_hh phi_a phi_b) with s_a = +/-1 the sign of
-// phi_a'.  Lanes with on = false add nothing (their kernel is evaluated at a harmless
-// separation).  KERNEL(R, 1/R, nu, gk, Dk, St, Dt) evaluates the point-pair kernels.
-template <int Q, typename KERNEL>
+// 2x2 block of element pair (e, f) for the four matrices: A_b[m][a] += sum_hh h w_hh
+// phi_b(xi_hh) sum_g K_m(g, hh) h w_g phi_a(xi_g) (b = 0 into acc0, the node column f; b = 1
+// into acc1, the node column f + 1), and for N^k the Maue term K (s_a s_b w_g w_hh -
+// k^2 n.n' h^2 w_g w_hh phi_a phi_b) with s_a = +/-1 the sign of phi_a'.  SPLIT: the sums
+// over the row element's points g come first, weighted by phi_a only, and the column
+// weights phi_b once per column point hh (half the multiply-adds per point pair, for 36 more
+// registers); otherwise every point pair adds into the accumulators with its full weight.
+// Lanes with on = false add nothing (their kernel is evaluated at a harmless separation).
+// KERNEL(R, 1/R, nu, gk, Dk, St, Dt) evaluates the point-pair kernels.
+template <int Q, bool SPLIT, typename KERNEL>
 __device__ __forceinline__ void far_block(const double *rp, int fe, bool on, double rsafe,
                                           double h, double k2, const double *__restrict__ PX,
                                           const double *__restrict__ PY,
@@ -72,17 +76,22 @@ __device__ __forceinline__ void far_block(const double *rp, int fe, bool on, dou
                                           zd (&acc1)[4][2], KERNEL kern) {
     // rp: this lane's row-element points in LDS, [4][Q] with stride 256 (x, y, tx, ty)
     const double msk = on ? 1.0 : 0.0;
+    // lanes that add nothing get dx = rsafe, dy = 0 (multiplies instead of selects)
+    const double dx_off = on ? 0.0 : rsafe;
 #pragma unroll 1
     for (int hh = 0; hh < Q; ++hh) {
         const double xs = PX[fe * Q + hh], ys = PY[fe * Q + hh];
         const double txs = PTX[fe * Q + hh], tys = PTY[fe * Q + hh];
         const double xh = qc.xi[hh], wh = qc.w[hh];
         const double wb0 = msk * h * wh * (1.0 - xh), wb1 = msk * h * wh * xh;
+        const double whm = msk * wh;
+        zd sD[2], sDt[2], sS[2], sNn[2], sNw = mk(0.0, 0.0);
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) sD[aa] = sDt[aa] = sS[aa] = sNn[aa] = mk(0.0, 0.0);
 #pragma unroll 1
         for (int g = 0; g < Q; ++g) {
-            double dx = rp[(0 * Q + g) * 256] - xs, dy = rp[(1 * Q + g) * 256] - ys;
-            dx = on ? dx : rsafe;
-            dy = on ? dy : 0.0;
+            const double dx = fma(rp[(0 * Q + g) * 256] - xs, msk, dx_off);
+            const double dy = (rp[(1 * Q + g) * 256] - ys) * msk;
             // 1/R from one reciprocal square root; R and nu = (r - r').n' / R from it
             const double r2 = fma(dx, dx, dy * dy);
             const double invR = rsqrt(r2);
@@ -91,21 +100,47 @@ __device__ __forceinline__ void far_block(const double *rp, int fe, bool on, dou
             const double nn = rp[(3 * Q + g) * 256] * tys + rp[(2 * Q + g) * 256] * txs;
             zd gk, Dk, St, Dt;
             kern(R, invR, nu, gk, Dk, St, Dt);
-            const double xg = qc.xi[g], wg = qc.w[g];
-            const double wa[2] = {h * wg * (1.0 - xg), h * wg * xg};
-            const double wgh = msk * wg * wh;
+            const double wa[2] = {qc.ha0[g], qc.ha1[g]};
+            if constexpr (SPLIT) {
+                const zd gn = gk * nn;
+                sNw = sNw + gk * qc.w[g];
+#pragma unroll
+                for (int aa = 0; aa < 2; ++aa) {
+                    sD[aa] = sD[aa] + Dk * wa[aa];
+                    sDt[aa] = sDt[aa] + Dt * wa[aa];
+                    sS[aa] = sS[aa] + St * wa[aa];
+                    sNn[aa] = sNn[aa] + gn * wa[aa];
+                }
+            } else {
+                const double wgh = whm * qc.w[g];
+#pragma unroll
+                for (int aa = 0; aa < 2; ++aa) {
+                    const double w0 = wa[aa] * wb0, w1 = wa[aa] * wb1;
+                    acc0[0][aa] = acc0[0][aa] + Dk * w0;
+                    acc1[0][aa] = acc1[0][aa] + Dk * w1;
+                    acc0[2][aa] = acc0[2][aa] + Dt * w0;
+                    acc1[2][aa] = acc1[2][aa] + Dt * w1;
+                    acc0[3][aa] = acc0[3][aa] + St * w0;
+                    acc1[3][aa] = acc1[3][aa] + St * w1;
+                    // s_a s_b: + for a == b
+                    acc0[1][aa] = acc0[1][aa] + gk * ((aa == 0 ? wgh : -wgh) - k2 * nn * w0);
+                    acc1[1][aa] = acc1[1][aa] + gk * ((aa == 1 ? wgh : -wgh) - k2 * nn * w1);
+                }
+            }
+        }
+        if constexpr (SPLIT) {
+            const zd nw = sNw * whm;
 #pragma unroll
             for (int aa = 0; aa < 2; ++aa) {
-                const double w0 = wa[aa] * wb0, w1 = wa[aa] * wb1;
-                acc0[0][aa] = acc0[0][aa] + Dk * w0;
-                acc1[0][aa] = acc1[0][aa] + Dk * w1;
-                acc0[2][aa] = acc0[2][aa] + Dt * w0;
-                acc1[2][aa] = acc1[2][aa] + Dt * w1;
-                acc0[3][aa] = acc0[3][aa] + St * w0;
-                acc1[3][aa] = acc1[3][aa] + St * w1;
+                acc0[0][aa] = acc0[0][aa] + sD[aa] * wb0;
+                acc1[0][aa] = acc1[0][aa] + sD[aa] * wb1;
+                acc0[2][aa] = acc0[2][aa] + sDt[aa] * wb0;
+                acc1[2][aa] = acc1[2][aa] + sDt[aa] * wb1;
+                acc0[3][aa] = acc0[3][aa] + sS[aa] * wb0;
+                acc1[3][aa] = acc1[3][aa] + sS[aa] * wb1;
                 // s_a s_b: + for a == b
-                acc0[1][aa] = acc0[1][aa] + gk * ((aa == 0 ? wgh : -wgh) - k2 * nn * w0);
-                acc1[1][aa] = acc1[1][aa] + gk * ((aa == 1 ? wgh : -wgh) - k2 * nn * w1);
+                acc0[1][aa] = acc0[1][aa] + (aa == 0 ? nw : -nw) - sNn[aa] * (k2 * wb0);
+                acc1[1][aa] = acc1[1][aa] + (aa == 1 ? nw : -nw) - sNn[aa] * (k2 * wb1);
             }
         }
     }
@@ -187,18 +222,18 @@ __global__ __launch_bounds__(256, MODE == 2 ? 1 : 2) void k_far(int N, double h,
                                zd &g3) {
                     pair_kernels_asym<kSerMax>(c, R, invR, nu, g0, g1, g2, g3);
                 };
-                far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K22);
+                far_block<Q, false>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K22);
             } else if constexpr (MODE == 2) {
                 auto KG = [&](double R, double, double nu, zd &g0, zd &g1, zd &g2, zd &g3) {
                     pair_kernels(c, R, nu, g0, g1, g2, g3);
                 };
-                far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, KG);
+                far_block<Q, true>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, KG);
             } else {
                 auto K8 = [&](double R, double invR, double nu, zd &g0, zd &g1, zd &g2,
                               zd &g3) {
                     pair_kernels_asym<8>(c, R, invR, nu, g0, g1, g2, g3);
                 };
-                far_block<Q>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K8);
+                far_block<Q, true>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K8);
             }
         }
         if (f >= j0) {
@@ -379,7 +414,12 @@ void launch_assemble_far(const AsmParams &p, const PointTable &far, const double
 #define CFIE_FAR_CASE(QQ)                                                                   \
     case QQ: {                                                                             \
         QuadConsts<QQ> qc;                                                                 \
-        for (int i = 0; i < QQ; ++i) { qc.xi[i] = xi[i]; qc.w[i] = w[i]; }                 \
+        for (int i = 0; i < QQ; ++i) {                                                     \
+            qc.xi[i] = xi[i];                                                              \
+            qc.w[i] = w[i];                                                                \
+            qc.ha0[i] = p.h * w[i] * (1.0 - xi[i]);                                        \
+            qc.ha1[i] = p.h * w[i] * xi[i];                                                \
+        }                                                                                  \
         hipLaunchKernelGGL((k_far<QQ, 0>), dim3(blocks), dim3(256), 0, s, p.N, p.h, c,     \
                            p.nb, dband, p.r0, p.r1, p.ld, p.out[0], p.out[1], p.out[2],     \
                            p.out[3], far.x, far.y, far.tx, far.ty, qc, n_row_tiles);       \

@@ -100,6 +100,14 @@ struct PairConsts {
 // two with 33 significant bits so that n times them is exact, then the Taylor series of sin
 // (through r^15) and cos (through r^16) on |r| <= pi/4, whose first omitted terms are below
 // 5e-17 and 2e-18, and the quadrant n mod 4.
+// p x + c for a Horner step whose coefficient c is a loop-invariant value: one three-address
+// FMA (the coefficient stays in its register; the two-address form would first copy it into
+// the destination)
+__device__ __forceinline__ double horner(double p, double x, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(x), "v"(c));
+    return r;
+}
 __device__ __forceinline__ void sincos_phase(double x, double &s, double &c) {
     constexpr double kP1 = 0x1.921fb544p+0, kP2 = 0x1.0b4611a6p-34,
                      kP3 = 0x1.3198a2e037073p-69;
@@ -109,26 +117,54 @@ __device__ __forceinline__ void sincos_phase(double x, double &s, double &c) {
     r = fma(-n, kP3, r);
     const double r2 = r * r;
     double ps = -1.0 / 1307674368000.0;
-    ps = fma(ps, r2, 1.0 / 6227020800.0);
-    ps = fma(ps, r2, -1.0 / 39916800.0);
-    ps = fma(ps, r2, 1.0 / 362880.0);
-    ps = fma(ps, r2, -1.0 / 5040.0);
-    ps = fma(ps, r2, 1.0 / 120.0);
-    ps = fma(ps, r2, -1.0 / 6.0);
+    ps = horner(ps, r2, 1.0 / 6227020800.0);
+    ps = horner(ps, r2, -1.0 / 39916800.0);
+    ps = horner(ps, r2, 1.0 / 362880.0);
+    ps = horner(ps, r2, -1.0 / 5040.0);
+    ps = horner(ps, r2, 1.0 / 120.0);
+    ps = horner(ps, r2, -1.0 / 6.0);
     const double sr = fma(ps * r2, r, r);
     double pc = 1.0 / 20922789888000.0;
-    pc = fma(pc, r2, -1.0 / 87178291200.0);
-    pc = fma(pc, r2, 1.0 / 479001600.0);
-    pc = fma(pc, r2, -1.0 / 3628800.0);
-    pc = fma(pc, r2, 1.0 / 40320.0);
-    pc = fma(pc, r2, -1.0 / 720.0);
-    pc = fma(pc, r2, 1.0 / 24.0);
+    pc = horner(pc, r2, -1.0 / 87178291200.0);
+    pc = horner(pc, r2, 1.0 / 479001600.0);
+    pc = horner(pc, r2, -1.0 / 3628800.0);
+    pc = horner(pc, r2, 1.0 / 40320.0);
+    pc = horner(pc, r2, -1.0 / 720.0);
+    pc = horner(pc, r2, 1.0 / 24.0);
     pc = fma(pc, r2, -0.5);
     const double cr = fma(pc, r2, 1.0);
     const int q = (int)n & 3;
     const double a = (q & 1) ? cr : sr, b = (q & 1) ? sr : cr;
     s = (q & 2) ? -a : a;
     c = ((q + 1) & 2) ? -b : b;
+}
+
+// e^x for x <= 0 (the decay e^{-beta R} of the complex wavenumber's kernels): Cody and
+// Waite's reduction x = n ln 2 + r, |r| <= ln 2 / 2, with ln 2 split so that n times its
+// leading part (28 significant bits) is exact, then e^r by its Taylor series to r^13 (the
+// remainder is below 1e-17 relative) and the scaling by 2^n.  x <= 0 needs no overflow
+// handling, and the scaling flushes x below about -745 to zero.
+__device__ __forceinline__ double exp_decay(double x) {
+    constexpr double kL2E = 0x1.71547652b82fep+0, kLn2Hi = 0x1.62e42ff000000p-1,
+                     kLn2Lo = -0x1.718432a1b0e26p-35;
+    const double n = rint(x * kL2E);
+    double r = fma(-n, kLn2Hi, x);
+    r = fma(-n, kLn2Lo, r);
+    double p = 1.0 / 6227020800.0;
+    p = horner(p, r, 1.0 / 479001600.0);
+    p = horner(p, r, 1.0 / 39916800.0);
+    p = horner(p, r, 1.0 / 3628800.0);
+    p = horner(p, r, 1.0 / 362880.0);
+    p = horner(p, r, 1.0 / 40320.0);
+    p = horner(p, r, 1.0 / 5040.0);
+    p = horner(p, r, 1.0 / 720.0);
+    p = horner(p, r, 1.0 / 120.0);
+    p = horner(p, r, 1.0 / 24.0);
+    p = horner(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
 }
 
 // Large-argument kernels (k R >= 22 for this lane) with a T-term series, given R and 1/R.
@@ -139,7 +175,7 @@ __device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R,
     sincos_phase(c.k * R, sn, cs);
     const double rs = rsqrt(R);
     const zd E = mk(cs * rs, sn * rs);                   // e^{ikR} R^{-1/2}
-    const zd Et = E * exp(-c.beta * R);
+    const zd Et = E * exp_decay(-c.beta * R);
     const double y = invR * c.invk, y2 = y * y;
     double P0 = kSer.p[0][T / 2 - 1], Q0 = kSer.q[0][T / 2 - 1];
     double P1 = kSer.p[1][T / 2 - 1], Q1 = kSer.q[1][T / 2 - 1];
@@ -151,12 +187,28 @@ __device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R,
         Q1 = fma(Q1, y2, kSer.q[1][j]);
     }
     const zd w = c.iwk * invR;                           // i / (kt R)
-    zd s0 = mk(kSer.a[0][T - 1], 0.0), s1 = mk(kSer.a[1][T - 1], 0.0);
+    // s0, s1 = sum_n a_n w^n with real a_n, by the second-order recurrence for a real
+    // polynomial at a complex point (Knuth, TAOCP vol. 2, sec. 4.6.4): w is a root of
+    // t^2 - r t + q with r = 2 Re w, q = |w|^2; b_k = a_k + r b_{k+1} - q b_{k+2} gives the
+    // remainder b_1 t + a_0 - q b_2 of the division by that quadratic, so
+    // p(w) = (Re w) b_1 + a_0 - q b_2 + i (Im w) b_1: two real operations per term instead
+    // of the four of a complex Horner step.
+    static_assert(T >= 3, "series too short for the recurrence");
+    const double rr = 2.0 * w.x, mq = -fma(w.x, w.x, w.y * w.y);
+    double u1 = kSer.a[0][T - 1], v1 = kSer.a[1][T - 1];    // b_{k+1}
+    double u2 = fma(rr, u1, kSer.a[0][T - 2]), v2 = fma(rr, v1, kSer.a[1][T - 2]);
 #pragma unroll
-    for (int n = T - 2; n >= 0; --n) {
-        s0 = mk(fma(s0.x, w.x, fma(-s0.y, w.y, kSer.a[0][n])), fma(s0.x, w.y, s0.y * w.x));
-        s1 = mk(fma(s1.x, w.x, fma(-s1.y, w.y, kSer.a[1][n])), fma(s1.x, w.y, s1.y * w.x));
+    for (int n = T - 3; n >= 1; --n) {                       // (u2, u1) <- (b_{n+1}, b_n)
+        const double u = fma(rr, u2, fma(mq, u1, kSer.a[0][n]));
+        const double v = fma(rr, v2, fma(mq, v1, kSer.a[1][n]));
+        u1 = u2;
+        u2 = u;
+        v1 = v2;
+        v2 = v;
     }
+    // u2 = b_1, u1 = b_2
+    const zd s0 = mk(fma(w.x, u2, fma(mq, u1, kSer.a[0][0])), w.y * u2);
+    const zd s1 = mk(fma(w.x, v2, fma(mq, v1, kSer.a[1][0])), w.y * v2);
     gk = c.Cg * E * mk(P0, Q0 * y);
     Dk = c.CD * E * mk(P1, Q1 * y) * nu;
     St = c.CS * Et * s0;
