@@ -139,6 +139,15 @@ __device__ __forceinline__ void sincos_phase(double x, double &s, double &c) {
     c = ((q + 1) & 2) ? -b : b;
 }
 
+// 1/sqrt(x) for positive, finite, normal x: the hardware estimate y refined by one step of
+// the second-order iteration y (1 + e/2 + 3 e^2/8), e = 1 - x y^2, whose error is about the
+// cube of the estimate's; the checks for zero, infinity and denormals are left out.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // e^x for x <= 0 (the decay e^{-beta R} of the complex wavenumber's kernels): Cody and
 // Waite's reduction x = n ln 2 + r, |r| <= ln 2 / 2, with ln 2 split so that n times its
 // leading part (28 significant bits) is exact, then e^r by its Taylor series to r^13 (the
@@ -173,7 +182,7 @@ __device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R,
                                                   double nu, zd &gk, zd &Dk, zd &St, zd &Dt) {
     double sn, cs;
     sincos_phase(c.k * R, sn, cs);
-    const double rs = rsqrt(R);
+    const double rs = rsqrt_pos(R);
     const zd E = mk(cs * rs, sn * rs);                   // e^{ikR} R^{-1/2}
     const zd Et = E * exp_decay(-c.beta * R);
     const double y = invR * c.invk, y2 = y * y;
