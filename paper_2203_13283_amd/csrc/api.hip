@@ -1341,12 +1341,16 @@ void assemble_kernels(cfie_ctx *c) {
     // rows of symmetric circulants equal their first columns: their DFTs are the
     // eigenvalues of the four circulants
     launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, c->aux);
+    // the contour's near band (entries |i - j| <= nb + 1) follows on the second stream: the
+    // far passes write only the other entries, so the two run side by side (the near
+    // kernels' latency-bound waves fill compute units that the far passes leave idle)
+    AsmParams pn = p;
+    pn.ws = near_ws;
+    launch_assemble_near(pn, c->pn, c->xn.data(), c->wn.data(), c->d_mom, c->aux);
     HIPCHK(hipEventRecord(c->ev_join, c->aux));
-    // the contour's matrices
+    // the contour's far entries
     p.ws = band_ws;
     launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
-    p.ws = near_ws;
-    launch_assemble_near(p, c->pn, c->xn.data(), c->wn.data(), c->d_mom, s);
     c->check_launch();
     HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
     aux_join.joined = true;
