@@ -61,8 +61,11 @@ void launch_swaps_reverse(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda
                           int64_t c1, hipStream_t s);
 void launch_tri_inv_blocks(int n, int blk, const zd *A, int64_t lda, zd *Linv, zd *Uinv,
                            hipStream_t s);
-void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
-                    hipStream_t s);
+template <typename T>
+void launch_swaps2(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t a0,
+                   int64_t a1, int64_t b0, int64_t b1, hipStream_t s);
+void launch_panel_u12(int kb, const zd *L11, int64_t lda, zd *A12, int64_t ncols,
+                      const zd *Lin, zd *Lout, int ldl, hipStream_t s);
 void launch_add_identity(int n, zd *A, int64_t lda, hipStream_t s);
 // A = a I (set) or A += a I on the diagonal (n x n)
 template <typename T>
@@ -998,7 +1001,6 @@ cfie_status factor_impl(cfie_ctx *c) {
         c->Linv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
         c->Uinv = c->alloc_n<zd>((size_t)nblk * kLUBlock * kLUBlock);
     }
-    zd *tmp = c->tmp_buf<zd>(SLOT_LU_TMP, (size_t)kLUPanel * std::max(ell, 1));
     constexpr int kPanels = kLUSuper / kLUPanel;
     zd *Lp = c->tmp_buf<zd>(SLOT_LU_LP, (size_t)kPanels * kLUPanel * kLUPanel);
     int *panel_ws = c->tmp_buf<int>(SLOT_LU_PANEL, lu_panel_ws_ints());
@@ -1011,33 +1013,28 @@ cfie_status factor_impl(cfie_ctx *c) {
             const int kb = std::min(pw, S1 - k0);
             zd *Lpi = Lp + (size_t)((k0 - S0) / pw) * kLUPanel * kLUPanel;
             launch_lu_panel(ell, k0, kb, K, cap, c->piv, c->info, panel_ws, s);
-            launch_swaps<double>(k0, k0 + kb, c->piv, K, cap, S0, k0, s);
-            launch_swaps<double>(k0, k0 + kb, c->piv, K, cap, k0 + kb, S1, s);
-            launch_tri_inv(kb, at(k0, k0), cap, true, Lpi, kLUPanel, s);
+            // the panel's row swaps on the superpanel's columns left and right of it
+            launch_swaps2<double>(k0, k0 + kb, c->piv, K, cap, S0, k0, k0 + kb, S1, s);
+            // L11^-1 (kept in Lpi for the superpanel's block row of U) and U12 inside the
+            // superpanel, then its trailing update over all rows below
             const int restS = S1 - k0 - kb;
-            if (restS > 0) {
-                // U12 inside the superpanel, then its trailing update over all rows below
-                gemm<double>(GEMM_N, kb, restS, kb, cz<double>(1), Lpi, kLUPanel, at(k0, k0 + kb),
-                             cap, cz<double>(0), tmp, kb, s);
-                axpby<double>(kb, restS, cz<double>(1), tmp, kb, cz<double>(0), at(k0, k0 + kb),
-                              cap, s);
+            launch_panel_u12(kb, at(k0, k0), cap, at(k0, k0 + kb), restS, nullptr, Lpi,
+                             kLUPanel, s);
+            if (restS > 0)
                 gemm<double>(GEMM_N, ell - k0 - kb, restS, kb, cz<double>(-1), at(k0 + kb, k0),
                              cap, at(k0, k0 + kb), cap, cz<double>(1), at(k0 + kb, k0 + kb), cap,
                              s);
-            }
             c->check_launch();
         }
         const int rest = ell - S1;
-        launch_swaps<double>(S0, S1, c->piv, K, cap, 0, S0, s);
+        // the superpanel's row swaps on the columns left and right of it
+        launch_swaps2<double>(S0, S1, c->piv, K, cap, 0, S0, S1, ell, s);
         if (rest > 0) {
-            launch_swaps<double>(S0, S1, c->piv, K, cap, S1, ell, s);
             // U12 = L11^-1 K[S0:S1, S1:ell] by the panels' diagonal inverses
             for (int k0 = S0; k0 < S1; k0 += pw) {
                 const int kb = std::min(pw, S1 - k0);
                 const zd *Lpi = Lp + (size_t)((k0 - S0) / pw) * kLUPanel * kLUPanel;
-                gemm<double>(GEMM_N, kb, rest, kb, cz<double>(1), Lpi, kLUPanel, at(k0, S1), cap,
-                             cz<double>(0), tmp, kb, s);
-                axpby<double>(kb, rest, cz<double>(1), tmp, kb, cz<double>(0), at(k0, S1), cap, s);
+                launch_panel_u12(kb, nullptr, cap, at(k0, S1), rest, Lpi, nullptr, kLUPanel, s);
                 const int below = S1 - k0 - kb;
                 if (below > 0)
                     gemm<double>(GEMM_N, below, rest, kb, cz<double>(-1), at(k0 + kb, k0), cap,
@@ -1056,7 +1053,6 @@ cfie_status factor_impl(cfie_ctx *c) {
         int info = 0;
         HIPCHK(hipMemcpyAsync(&info, c->info, sizeof(int), hipMemcpyDeviceToHost, s));
         c->sync();
-        c->tmp_free(tmp);
         c->tmp_free(Lp);
         c->tmp_free(panel_ws);
         if (info) return fail(c, CFIE_ESINGULAR, "zero pivot in the capacitance matrix");

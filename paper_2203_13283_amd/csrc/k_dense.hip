@@ -1386,6 +1386,31 @@ void launch_swaps(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_
     hipLaunchKernelGGL(k_swaps<T>, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, k0, k1, piv, A,
                        lda, c0, c1, false);
 }
+// the swaps of piv[k0 .. k1) on two column ranges [a0, a1) and [b0, b1) in one launch (the
+// columns left and right of an LU panel)
+template <typename T>
+__global__ void k_swaps2(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t a0,
+                         int64_t na, int64_t b0, int64_t nb) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= na + nb) return;
+    const int64_t c = t < na ? a0 + t : b0 + (t - na);
+    cpx<T> *col = A + c * lda;
+    for (int j = k0; j < k1; ++j) {
+        const int p = piv[j];
+        if (p != j) { cpx<T> v = col[j]; col[j] = col[p]; col[p] = v; }
+    }
+}
+template <typename T>
+void launch_swaps2(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t a0,
+                   int64_t a1, int64_t b0, int64_t b1, hipStream_t s) {
+    const int64_t na = a1 > a0 ? a1 - a0 : 0, nb = b1 > b0 ? b1 - b0 : 0;
+    if (na + nb == 0 || k1 <= k0) return;
+    hipLaunchKernelGGL(k_swaps2<T>, dim3((unsigned)((na + nb + 127) / 128)), dim3(128), 0, s, k0,
+                       k1, piv, A, lda, a0, na, b0, nb);
+}
+template void launch_swaps2<double>(int, int, const int *, zd *, int64_t, int64_t, int64_t,
+                                    int64_t, int64_t, hipStream_t);
+
 // the inverse permutation: the swaps of piv[k0 .. k1) in reverse order
 template <typename T>
 void launch_swaps_reverse(int k0, int k1, const int *piv, cpx<T> *A, int64_t lda, int64_t c0,
@@ -1431,12 +1456,6 @@ __device__ __forceinline__ void tri_inv_body(int nb, const zd *A, int64_t lda, b
     for (int q = 0; q < nb; ++q)
         if (c < nb) Inv[c + q * ldi] = X[q + c * 65];
 }
-__global__ __launch_bounds__(64) void k_tri_inv(int nb, const zd *A, int64_t lda, bool lower,
-                                                zd *Inv, int ldi) {
-    __shared__ zd Ab[64 * 65];
-    __shared__ zd X[64 * 65];
-    tri_inv_body(nb, A, lda, lower, Inv, ldi, Ab, X);
-}
 // all diagonal blocks of an n x n LU at once: workgroup (bi, 0) inverts the unit lower
 // triangle of block bi into Linv + bi blk^2, (bi, 1) the upper one into Uinv + bi blk^2
 __global__ __launch_bounds__(64) void k_tri_inv_blocks(int n, int blk, const zd *A,
@@ -1450,15 +1469,77 @@ __global__ __launch_bounds__(64) void k_tri_inv_blocks(int n, int blk, const zd 
     zd *Inv = (lower ? Linv : Uinv) + (size_t)bi * blk * blk;
     tri_inv_body(kb, Ad, lda, lower, Inv, blk, Ab, X);
 }
-void launch_tri_inv(int nb, const zd *A, int64_t lda, bool lower, zd *Inv, int ldi,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_inv, dim3(1), dim3(64), 0, s, nb, A, lda, lower, Inv, ldi);
-}
 void launch_tri_inv_blocks(int n, int blk, const zd *A, int64_t lda, zd *Linv, zd *Uinv,
                            hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_tri_inv_blocks, dim3((n + blk - 1) / blk, 2), dim3(64), 0, s, n, blk, A,
                        lda, Linv, Uinv);
+}
+
+// U12 <- L11^-1 A12 in place for the kb x ncols block A12 of an LU panel (kb <= 16), L11 the
+// unit lower triangle of the panel's diagonal block.  With Lin == nullptr the inverse is
+// formed from L11 (forward substitution, one column per thread, as tri_inv_body) and workgroup
+// 0 stores it to Lout (ld ldl) for later blocks; otherwise Lin (ld ldl) is used.  One thread
+// per column of A12: y_r = x_r + sum_{q < r} Linv[r, q] x_q.  This replaces a tiny GEMM into a
+// temporary, the copy back and the separate inverse.
+__global__ __launch_bounds__(256) void k_panel_u12(int kb, const zd *L11, int64_t lda,
+                                                   zd *A12, int64_t ncols, const zd *Lin,
+                                                   zd *Lout, int ldl) {
+    __shared__ zd Li[16 * 17];                    // Li[r + 17 q] = Linv[r, q]
+    const int tid = threadIdx.x;
+    if (Lin == nullptr) {
+        __shared__ zd Ab[16 * 17];
+        if (tid < kb * kb) {
+            const int r = tid % kb, q = tid / kb;
+            Ab[r + 17 * q] = L11[r + (int64_t)q * lda];
+        }
+        __syncthreads();
+        if (tid < kb) {
+            const int c = tid;                    // column c of the inverse
+            for (int r = 0; r < kb; ++r) {
+                zd sum = mk(r == c ? 1.0 : 0.0, 0.0);
+                if (r > c)
+                    for (int q = c; q < r; ++q) sum = sum - Ab[r + 17 * q] * Li[q + 17 * c];
+                Li[r + 17 * c] = r < c ? mk(0.0, 0.0) : sum;
+            }
+        }
+        __syncthreads();
+        if (blockIdx.x == 0 && tid < kb * kb) {
+            const int r = tid % kb, q = tid / kb;
+            Lout[r + (int64_t)q * ldl] = Li[r + 17 * q];
+        }
+    } else {
+        if (tid < kb * kb) {
+            const int r = tid % kb, q = tid / kb;
+            Li[r + 17 * q] = Lin[r + (int64_t)q * ldl];
+        }
+        __syncthreads();
+    }
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + tid;
+    if (c >= ncols) return;
+    zd *col = A12 + c * lda;
+    zd x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = r < kb ? col[r] : mk(0.0, 0.0);
+#pragma unroll
+    for (int r = 15; r >= 1; --r) {               // rows from the bottom: x_q, q < r, unchanged
+        if (r >= kb) continue;
+        zd y = x[r];
+#pragma unroll
+        for (int q = 0; q < 15; ++q)
+            if (q < r) y = y + Li[r + 17 * q] * x[q];
+        x[r] = y;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (r < kb) col[r] = x[r];
+}
+void launch_panel_u12(int kb, const zd *L11, int64_t lda, zd *A12, int64_t ncols,
+                      const zd *Lin, zd *Lout, int ldl, hipStream_t s) {
+    if (kb <= 0 || kb > 16 || (Lin != nullptr && ncols <= 0)) return;
+    const unsigned nblk = (unsigned)std::max<int64_t>(1, (ncols + 255) / 256);
+    hipLaunchKernelGGL(k_panel_u12, dim3(nblk), dim3(256), 0, s, kb, L11, lda, A12,
+                       ncols < 0 ? 0 : ncols, Lin, Lout, ldl);
 }
 
 // identity added to the diagonal: A += I
