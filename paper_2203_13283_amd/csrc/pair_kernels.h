@@ -94,12 +94,6 @@ struct PairConsts {
     zd ik4, ikt4;                    // i k / 4, i kt / 4
 };
 
-// sin and cos of a phase x with |x| < 2^20 (the far kernels' k R: a contour of N <= 32768
-// nodes at 0.8 or more nodes per wavelength spans less than 2^17 radians): Cody and Waite's
-// reduction r = x - n pi/2 with n = rint(2 x / pi) and pi/2 split into three parts, the first
-// two with 33 significant bits so that n times them is exact, then the Taylor series of sin
-// (through r^15) and cos (through r^16) on |r| <= pi/4, whose first omitted terms are below
-// 5e-17 and 2e-18, and the quadrant n mod 4.
 // p x + c for a Horner step whose coefficient c is a loop-invariant value: one three-address
 // FMA (the coefficient stays in its register; the two-address form would first copy it into
 // the destination)
@@ -108,6 +102,13 @@ __device__ __forceinline__ double horner(double p, double x, double c) {
     asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(x), "v"(c));
     return r;
 }
+
+// sin and cos of a phase x with |x| < 2^20 (the far kernels' k R: a contour of N <= 32768
+// nodes at 0.8 or more nodes per wavelength spans less than 2^17 radians): Cody and Waite's
+// reduction r = x - n pi/2 with n = rint(2 x / pi) and pi/2 split into three parts, the first
+// two with 33 significant bits so that n times them is exact, then the Taylor series of sin
+// (through r^15) and cos (through r^16) on |r| <= pi/4, whose first omitted terms are below
+// 5e-17 and 2e-18, and the quadrant n mod 4.
 __device__ __forceinline__ void sincos_phase(double x, double &s, double &c) {
     constexpr double kP1 = 0x1.921fb544p+0, kP2 = 0x1.0b4611a6p-34,
                      kP3 = 0x1.3198a2e037073p-69;
@@ -204,10 +205,11 @@ __device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R,
     // of the four of a complex Horner step.
     static_assert(T >= 3, "series too short for the recurrence");
     const double rr = 2.0 * w.x, mq = -fma(w.x, w.x, w.y * w.y);
-    double u1 = kSer.a[0][T - 1], v1 = kSer.a[1][T - 1];    // b_{k+1}
+    // (u2, u1) = (b_k, b_{k+1}), from k = T - 2 down to k = 1 (b_{T-1} = a_{T-1}, b_T = 0)
+    double u1 = kSer.a[0][T - 1], v1 = kSer.a[1][T - 1];
     double u2 = fma(rr, u1, kSer.a[0][T - 2]), v2 = fma(rr, v1, kSer.a[1][T - 2]);
 #pragma unroll
-    for (int n = T - 3; n >= 1; --n) {                       // (u2, u1) <- (b_{n+1}, b_n)
+    for (int n = T - 3; n >= 1; --n) {
         const double u = fma(rr, u2, fma(mq, u1, kSer.a[0][n]));
         const double v = fma(rr, v2, fma(mq, v1, kSer.a[1][n]));
         u1 = u2;
