@@ -183,32 +183,14 @@ __global__ __launch_bounds__(256, MODE == 2 ? 1 : 2) void k_far(int N, double h,
     int e = i0 - 1 + lane;
     e = (e % N + N) % N;
     if constexpr (MODE != 0) {
-        // Most tiles hold no element pair for these passes: bounding circles of the row and
-        // column elements' reference points (centroid, largest distance to it) bound every
-        // reference-point distance of the tile from below by D, and k (D - 2h) >= kFarFast
-        // (with a margin far above the rounding of D) means far_kRmin >= kFarFast for every
-        // pair, all of them taken by the 8-term pass.  The test is per wavefront (uniform).
-        auto wsum = [](double v) {
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            return v;
-        };
-        auto wmax = [](double v) {
-            for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-            return v;
-        };
-        const double xr = PX[e * Q + Q / 2], yr = PY[e * Q + Q / 2];
-        const double rcx = wsum(xr) * (1.0 / 64), rcy = wsum(yr) * (1.0 / 64);
-        const double rr = wmax(sqrt((xr - rcx) * (xr - rcx) + (yr - rcy) * (yr - rcy)));
-        // the column elements j0 - 1 .. jend - 1 (up to 65: two per lane, clamped)
+        // most tiles hold no element pair for these passes (the column elements j0 - 1 ..
+        // jend - 1, up to 65: two per lane, clamped)
         const int fa = min(j0 - 1 + lane, jend - 1), fb = min(j0 + lane, jend - 1);
         const int fea = (fa % N + N) % N, feb = (fb % N + N) % N;
-        const double xa = PX[fea * Q + Q / 2], ya = PY[fea * Q + Q / 2];
-        const double xb = PX[feb * Q + Q / 2], yb = PY[feb * Q + Q / 2];
-        const double ccx = wsum(xa + xb) * (1.0 / 128), ccy = wsum(ya + yb) * (1.0 / 128);
-        const double rc = wmax(fmax(sqrt((xa - ccx) * (xa - ccx) + (ya - ccy) * (ya - ccy)),
-                                    sqrt((xb - ccx) * (xb - ccx) + (yb - ccy) * (yb - ccy))));
-        const double D = sqrt((rcx - ccx) * (rcx - ccx) + (rcy - ccy) * (rcy - ccy)) - rr - rc;
-        if (c.k * (D - 2.0 * h) >= kFarFast + 1e-6) return;
+        if (far_tile_all_fast(c.k, h, PX[e * Q + Q / 2], PY[e * Q + Q / 2],
+                              PX[fea * Q + Q / 2], PY[fea * Q + Q / 2], PX[feb * Q + Q / 2],
+                              PY[feb * Q + Q / 2]))
+            return;
     }
     // the row element's Gauss points live in LDS (one column of 4 Q doubles per thread)
     __shared__ double rows_lds[4 * Q * 256];

@@ -79,6 +79,19 @@ __global__ __launch_bounds__(256) void k_grad_far(int N, double h, PairConsts c,
     const int e = valid ? e_raw : N - 1;
     const int e1 = (e + 1) % N;
     const int f0 = strip * SL, f1 = min(N, f0 + SL);
+    if constexpr (MODE != 0) {
+        // most tiles hold no element pair for these passes (SL = 128 columns: two per lane,
+        // clamped); such a wavefront adds nothing and reports zero scalar derivatives
+        const int fa = min(f0 + lane, f1 - 1), fb = min(f0 + 64 + lane, f1 - 1);
+        if (far_tile_all_fast(c.k, h, PX[e * Q + Q / 2], PY[e * Q + Q / 2], PX[fa * Q + Q / 2],
+                              PY[fa * Q + Q / 2], PX[fb * Q + Q / 2], PY[fb * Q + Q / 2])) {
+            if (lane == 0) {
+                spart[2 * (size_t)wave] = 0.0;
+                spart[2 * (size_t)wave + 1] = 0.0;
+            }
+            return;
+        }
+    }
     // own points and their adjoints in LDS (stride 256: one column per thread)
     __shared__ double lds[8 * Q * 256];
     double *own = lds + threadIdx.x;                    // [4][Q]: x, y, tx, ty

@@ -287,4 +287,29 @@ __device__ __forceinline__ double far_kRmin(double k, double h, double dxr, doub
 }
 constexpr double kFarFast = 200.0;    // k R above which the 8-term series is used
 
+// Whether no element pair of a wavefront's tile can need the 22-term or small-argument
+// passes: every lane holds one row element's reference point (xr, yr) and two column
+// elements' (xa, ya), (xb, yb).  Bounding circles of the two sets (centroid, largest
+// distance to it) bound every reference-point distance of the tile from below by D, and
+// k (D - 2h) >= kFarFast (with a margin far above the rounding of D) means far_kRmin >=
+// kFarFast for every pair of the tile.  The result is the same on all lanes.
+__device__ __forceinline__ bool far_tile_all_fast(double k, double h, double xr, double yr,
+                                                  double xa, double ya, double xb, double yb) {
+    auto wsum = [](double v) {
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        return v;
+    };
+    auto wmax = [](double v) {
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        return v;
+    };
+    const double rcx = wsum(xr) * (1.0 / 64), rcy = wsum(yr) * (1.0 / 64);
+    const double rr = wmax(sqrt((xr - rcx) * (xr - rcx) + (yr - rcy) * (yr - rcy)));
+    const double ccx = wsum(xa + xb) * (1.0 / 128), ccy = wsum(ya + yb) * (1.0 / 128);
+    const double rc = wmax(fmax(sqrt((xa - ccx) * (xa - ccx) + (ya - ccy) * (ya - ccy)),
+                                sqrt((xb - ccx) * (xb - ccx) + (yb - ccy) * (yb - ccy))));
+    const double D = sqrt((rcx - ccx) * (rcx - ccx) + (rcy - ccy) * (rcy - ccy)) - rr - rc;
+    return k * (D - 2.0 * h) >= kFarFast + 1e-6;
+}
+
 }  // namespace cfie
