@@ -65,7 +65,8 @@ struct QuadConsts {
 // weights phi_b once per column point hh (half the multiply-adds per point pair, for 36 more
 // registers); otherwise every point pair adds into the accumulators with its full weight.
 // Lanes with on = false add nothing (their kernel is evaluated at a harmless separation).
-// KERNEL(R, 1/R, nu, gk, Dk, St, Dt) evaluates the point-pair kernels.
+// KERNEL(R, 1/R, nu, gk, Dk, St, Dt) evaluates the point-pair kernels (in the large-argument
+// passes without their constant prefactors, which the write-out applies).
 template <int Q, bool SPLIT, typename KERNEL>
 __device__ __forceinline__ void far_block(const double *rp, int fe, bool on, double rsafe,
                                           double h, double k2, const double *__restrict__ PX,
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(256, MODE == 2 ? 1 : 2) void k_far(int N, double h,
             if constexpr (MODE == 1) {
                 auto K22 = [&](double R, double invR, double nu, zd &g0, zd &g1, zd &g2,
                                zd &g3) {
-                    pair_kernels_asym<kSerMax>(c, R, invR, nu, g0, g1, g2, g3);
+                    pair_kernels_asym_unscaled<kSerMax>(c, R, invR, nu, g0, g1, g2, g3);
                 };
                 far_block<Q, false>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K22);
             } else if constexpr (MODE == 2) {
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(256, MODE == 2 ? 1 : 2) void k_far(int N, double h,
             } else {
                 auto K8 = [&](double R, double invR, double nu, zd &g0, zd &g1, zd &g2,
                               zd &g3) {
-                    pair_kernels_asym<8>(c, R, invR, nu, g0, g1, g2, g3);
+                    pair_kernels_asym_unscaled<8>(c, R, invR, nu, g0, g1, g2, g3);
                 };
                 far_block<Q, true>(rp, fe, use, rsafe, h, k2, PX, PY, PTX, PTY, qc, acc0, acc1, K8);
             }
@@ -256,12 +257,15 @@ __global__ __launch_bounds__(256, MODE == 2 ? 1 : 2) void k_far(int N, double h,
             const int mine = (use || used_prev) ? 1 : 0;
             const bool touched = MODE != 0 ? (mine | __shfl_down(mine, 1)) != 0 : true;
             zd *outs[4] = {o0, o1, o2, o3};
+            // the large-argument passes sum kernels without their constant prefactors
+            const zd scale[4] = {c.CD, c.Cg, c.CDt, c.CS};
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 // row out_row = e + 1: own a = 1 part + a = 0 part of lane + 1
                 double nx = __shfl_down(acc0[m][0].x, 1);
                 double ny = __shfl_down(acc0[m][0].y, 1);
                 zd v = acc0[m][1] + mk(nx, ny);
+                if constexpr (MODE != 2) v = scale[m] * v;
                 if (row_ok && dd >= nb + 2 && touched) {
                     zd *dst = outs[m] + (int64_t)out_row + (int64_t)j * ld;
                     if (MODE != 0) v = v + *dst;

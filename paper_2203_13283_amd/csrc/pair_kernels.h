@@ -177,10 +177,13 @@ __device__ __forceinline__ double exp_decay(double x) {
     return ldexp(p, (int)n);
 }
 
-// Large-argument kernels (k R >= 22 for this lane) with a T-term series, given R and 1/R.
+// Large-argument kernels (k R >= 22 for this lane) with a T-term series, given R and 1/R,
+// without their constant prefactors: gk / Cg, Dk / CD, St / CS, Dt / CDt (a sum of such
+// values over point pairs is multiplied by the prefactor once).
 template <int T>
-__device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R, double invR,
-                                                  double nu, zd &gk, zd &Dk, zd &St, zd &Dt) {
+__device__ __forceinline__ void pair_kernels_asym_unscaled(const PairConsts &c, double R,
+                                                           double invR, double nu, zd &gk,
+                                                           zd &Dk, zd &St, zd &Dt) {
     double sn, cs;
     sincos_phase(c.k * R, sn, cs);
     const double rs = rsqrt_pos(R);
@@ -220,10 +223,20 @@ __device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R,
     // u2 = b_1, u1 = b_2
     const zd s0 = mk(fma(w.x, u2, fma(mq, u1, kSer.a[0][0])), w.y * u2);
     const zd s1 = mk(fma(w.x, v2, fma(mq, v1, kSer.a[1][0])), w.y * v2);
-    gk = c.Cg * E * mk(P0, Q0 * y);
-    Dk = c.CD * E * mk(P1, Q1 * y) * nu;
-    St = c.CS * Et * s0;
-    Dt = c.CDt * Et * s1 * nu;
+    gk = E * mk(P0, Q0 * y);
+    Dk = E * mk(P1 * nu, Q1 * y * nu);
+    St = Et * s0;
+    Dt = Et * (s1 * nu);
+}
+// the same with the prefactors
+template <int T>
+__device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R, double invR,
+                                                  double nu, zd &gk, zd &Dk, zd &St, zd &Dt) {
+    pair_kernels_asym_unscaled<T>(c, R, invR, nu, gk, Dk, St, Dt);
+    gk = c.Cg * gk;
+    Dk = c.CD * Dk;
+    St = c.CS * St;
+    Dt = c.CDt * Dt;
 }
 template <int T>
 __device__ __forceinline__ void pair_kernels_asym(const PairConsts &c, double R, double nu,
