@@ -30,9 +30,9 @@ FP64_PEAK = 78.6e12
 HBM_PEAK = 8.0e12
 # FP64 flops per Gauss point pair of the far-pair assembly kernels, counted on the metric
 # workload with rocprofv3 (64 x (ADD_F64 + MUL_F64 + 2 FMA_F64) wave instructions of the four
-# far kernels on the contour, 2.290e12, over its N^2 q^2 = 6.711e9 point pairs;
+# far kernels on the contour, 2.129e12, over its N^2 q^2 = 6.711e9 point pairs;
 # profiles/valu_hbm_kernels_perturbed16384.md)
-FAR_FLOPS_PER_PAIR = 341.2
+FAR_FLOPS_PER_PAIR = 317.2
 
 
 def parse():
