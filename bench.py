@@ -47,6 +47,8 @@ def parse():
                     help="perturbed16384 (the metric), ellipse4096, ellipse256, batch64, "
                          "shapegrad8192 or serve16384")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--sketch", choices=("srft", "gaussian"), default="srft",
+                    help="test matrix of the range finder's blocks after the first")
     ap.add_argument("--refine", choices=("factored", "dense"), default="dense",
                     help="mixed precision: residuals factor by factor or with C formed densely "
                          "in FP64 at factor time")
@@ -77,13 +79,14 @@ def parse():
     return ap.parse_args()
 
 
-def step(P, w, prec, eps, profile, form=0, refine=0, solve_reps=1):
+def step(P, w, prec, eps, profile, form=0, refine=0, solve_reps=1, sketch=None):
     """One pass of the hot path: assemble, factor, right-hand sides, solve.  The solve runs
     solve_reps times on the same right-hand sides (each a full solve); its time is their
     median."""
     import torch
     s = P.Solver(precision=prec, compress_tol=eps, block=256, refine_tol=1e-8,
-                 profile=profile, remainder_form=form, refine_form=refine)
+                 profile=profile, remainder_form=form, refine_form=refine,
+                 test_matrix=P.SKETCH_SRFT if sketch is None else sketch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.assemble(w.zhat, w.n_nodes, w.k)
@@ -455,8 +458,9 @@ def main():
         del src, dst
     cold = None
     refine = P.REFINE_DENSE if a.refine == "dense" else P.REFINE_FACTORED
+    sk = P.SKETCH_SRFT if a.sketch == "srft" else P.SKETCH_GAUSSIAN
     for _ in range(a.warmup):
-        s, B, X, _t = step(P, w, prec, eps, False, form, refine)
+        s, B, X, _t = step(P, w, prec, eps, False, form, refine, sketch=sk)
         cold = _t["setup_s"] if cold is None else cold
         del s, B, X
     torch.cuda.synchronize()
@@ -467,7 +471,7 @@ def main():
     for _ in range(a.steps):
         if last is not None:
             del last
-        s, B, X, t = step(P, w, prec, eps, a.profile, form, refine, a.solve_reps)
+        s, B, X, t = step(P, w, prec, eps, a.profile, form, refine, a.solve_reps, sketch=sk)
         cold = t["setup_s"] if cold is None else cold
         times.append(t)
         for name, (n, work, ms) in s.profile().items():
@@ -500,7 +504,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.description}", "N": w.n_nodes, "nrhs": nrhs,
                    "k": w.k, "compress_tol": eps, "solve_reps": a.solve_reps,
-                   "precision": "fp64" if prec == P.CFIE_FP64 else "mixed"},
+                   "precision": "fp64" if prec == P.CFIE_FP64 else "mixed",
+                   "sketch": a.sketch},
         "setup_s": setup_s,
         "setup_cold_s": cold,
         "phase_s": {"assemble+factor": setup_s, "rhs": med["rhs_s"], "solve": solve_s,
@@ -553,7 +558,7 @@ def main():
         legs = []
         for rf in forms:
             torch.cuda.empty_cache()
-            so, Bo, Xo, to = step(P, w, other, eps_o, False, form, rf)
+            so, Bo, Xo, to = step(P, w, other, eps_o, False, form, rf, sketch=sk)
             io = so.info()
             res_o, err_o = accuracy(P, so, w, Bo, Xo)
             legs.append({"precision": "mixed" if other == P.CFIE_MIXED else "fp64",
@@ -569,7 +574,7 @@ def main():
     if a.tight and prec == P.CFIE_FP64 and a.eps is None:
         # the FP64 path at the parity level of 1e-10 (nearly full rank at this size)
         torch.cuda.empty_cache()
-        st, Bt, Xt, tt = step(P, w, P.CFIE_FP64, 1e-10, False, form)
+        st, Bt, Xt, tt = step(P, w, P.CFIE_FP64, 1e-10, False, form, sketch=sk)
         it = st.info()
         res_t, err_t = accuracy(P, st, w, Bt, Xt)
         out["fp64_tight"] = {"compress_tol": 1e-10, "value": nrhs / tt["solve_s"],

@@ -103,7 +103,22 @@ typedef struct {
                              one has no column above tau                                 */
     int32_t refine_form;  /* mixed precision: how the FP64 residual b - C x of each refinement
                              sweep applies C (CFIE_REFINE_*)                                 */
+    int32_t test_matrix;  /* random test matrix of the sketch blocks (CFIE_SKETCH_*)         */
 } cfie_options;
+
+/* cfie_options.test_matrix.  The first sketch block is always real Gaussian.  With
+ * CFIE_SKETCH_SRFT and N a power of two, C - C_c applied factor by factor, the later blocks
+ * take columns of a subsampled randomized Fourier transform Omega = D F S (Halko, Martinsson
+ * and Tropp, SIAM Review 53 (2011), Sec. 4.6: D diagonal of unit-modulus entries of uniform
+ * random phase, F the N-point DFT, S distinct columns in a seeded random order): D^k D F and
+ * N^k D F are formed once by FFTs along their rows (32 N^2 bytes more during the
+ * factorisation in FP64, 16 N^2 in mixed precision), and each block's products with D^k and
+ * N^k become column gathers.  The Gaussian form is used where this does not apply (N not a
+ * power of two, C - C_c formed densely, all N Fourier columns drawn). */
+enum {
+    CFIE_SKETCH_GAUSSIAN = 0,    /* real Gaussian blocks (Philox4x32-10 stream of seed)        */
+    CFIE_SKETCH_SRFT = 1         /* Gaussian first block, then SRFT columns                    */
+};
 
 /* cfie_options.refine_form.  Factor by factor, a residual costs four N x N complex products
  * per right-hand side (24 N^2 real flops executed in the 3M form); with C formed once in FP64
@@ -179,7 +194,7 @@ cfie_status cfie_profile_reset(cfie_ctx *ctx);
 /* Fill *opt with defaults: FP64, compress_tol 1e-10, block 128, max_rank 0, seed 1,
  * refine_tol 1e-8, max_refine 20, quad_far 5, quad_near 10, near_band 6, no injection,
  * no profiling, remainder_form CFIE_REMAINDER_AUTO, solve_graphs 0, oversample 16,
- * refine_form CFIE_REFINE_FACTORED. */
+ * refine_form CFIE_REFINE_FACTORED, test_matrix CFIE_SKETCH_SRFT. */
 void cfie_default_options(cfie_options *opt);
 
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for
@@ -292,6 +307,18 @@ enum {
  * for an unknown op.  Used for residuals, diagnostics and the tests. */
 cfie_status cfie_apply(cfie_ctx *ctx, int op, const void *X_dev, int64_t ldx, void *Y_dev,
                        int64_t ldy, int64_t nrhs);
+
+/* The row transform behind CFIE_SKETCH_SRFT, for checking it: out = A diag(d) F with
+ * F_ij = e^{-2 pi i i j / N}, N = the context's node count (a power of two; EINVAL otherwise,
+ * ESTATE before cfie_assemble).  A_dev: device, m x N complex128, column-major, lda >= m;
+ * d_dev: device, N complex128; out_dev: device, m x N, ldo >= m, must not overlap A_dev.
+ * Column j of A diag(d) F is written to column p of out with j = cfie_srft_frequency(N, p),
+ * the digit reversal of the radix passes.  Runs on the context's stream. */
+cfie_status cfie_srft_rows(cfie_ctx *ctx, const void *A_dev, int64_t lda, int64_t m,
+                           const void *d_dev, void *out_dev, int64_t ldo);
+/* The frequency j held at output position p (0 <= p < N) of cfie_srft_rows; -1 if N is not
+ * a power of two or p is out of range. */
+int64_t cfie_srft_frequency(int64_t n, int64_t p);
 
 /* Copy one internal matrix (CFIE_MAT_*) to dst_dev (device, complex128, column-major,
  * leading dimension ld >= N).  ESTATE if it does not exist yet. */

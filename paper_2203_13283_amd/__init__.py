@@ -24,12 +24,12 @@ from . import _lib
 from ._lib import (CFIE_FP64, CFIE_MIXED, CfieError, MAT_CC_EIG, MAT_CIRCLE_ROW, MAT_DK,
                    MAT_DKT, MAT_G, MAT_NK, MAT_SKT, OP_C, OP_C_ADJ, OP_CC, OP_CC_INV,
                    OP_REMAINDER, OP_SKELETON, REFINE_DENSE, REFINE_FACTORED, REMAINDER_AUTO,
-                   REMAINDER_DENSE, REMAINDER_FACTORED)
+                   REMAINDER_DENSE, REMAINDER_FACTORED, SKETCH_GAUSSIAN, SKETCH_SRFT)
 
 __all__ = ["Solver", "solve_batch", "solve_group", "RecordedBatch", "far_field_of_shape", "CfieError", "CFIE_FP64", "CFIE_MIXED", "MAT_G", "MAT_DK",
            "MAT_NK", "MAT_DKT", "MAT_SKT", "MAT_CC_EIG", "MAT_CIRCLE_ROW", "OP_C", "OP_CC",
            "OP_CC_INV", "OP_REMAINDER", "OP_SKELETON", "OP_C_ADJ", "load_library", "REMAINDER_AUTO", "REMAINDER_FACTORED", "REFINE_FACTORED", "REFINE_DENSE",
-           "REMAINDER_DENSE",
+           "REMAINDER_DENSE", "SKETCH_GAUSSIAN", "SKETCH_SRFT", "srft_frequency",
            "set_gemm_autotune", "gemm_tuned_classes"]
 
 
@@ -53,6 +53,11 @@ def gemm_tuned_classes() -> int:
     return int(_lib.load().cfie_gemm_tuned_classes())
 
 
+def srft_frequency(n: int, p: int) -> int:
+    """Frequency held at output position p of the row transform (cfie_srft_frequency)."""
+    return int(_lib.load().cfie_srft_frequency(n, p))
+
+
 def _torch():
     import torch
     return torch
@@ -70,7 +75,8 @@ class Solver:
                  refine_tol: float = 1e-8, max_refine: int = 20, quad_far: int = 5,
                  quad_near: int = 10, near_band: int = 6, fail_alloc_after: int = -1,
                  profile: bool = False, remainder_form: int = 0, solve_graphs: bool = False,
-                 oversample: int = 16, refine_form: int = 0, device: int = 0, stream=None):
+                 oversample: int = 16, refine_form: int = 0, test_matrix: int = 1,
+                 device: int = 0, stream=None):
         lib = _lib.load()
         torch = _torch()
         o = _lib.default_options()
@@ -90,6 +96,7 @@ class Solver:
         o.solve_graphs = 1 if solve_graphs else 0
         o.oversample = oversample
         o.refine_form = refine_form
+        o.test_matrix = test_matrix
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -249,6 +256,23 @@ class Solver:
         self._check(self._lib.cfie_export_matrix(self._h, which, _ptr(buf), self.N),
                     "cfie_export_matrix")
         return buf.t() if cols == self.N else buf
+
+    def srft_rows(self, A, d):
+        """A diag(d) F (F_ij = e^{-2 pi i i j / N}) with its columns at the digit-reversed
+        positions of cfie_srft_rows (column p holds frequency srft_frequency(N, p)).
+        A: (m, N) complex128 CUDA tensor in natural (row, column) indexing, d: N complex128.
+        Returns an (m, N) tensor in natural indexing."""
+        torch = _torch()
+        self._check_batch(A, self.N, "A")
+        if d.dtype != torch.complex128 or d.numel() != self.N or not d.is_contiguous():
+            raise ValueError("d must be a contiguous complex128 tensor of N entries")
+        m = A.shape[0]
+        out = torch.empty((self.N, m), dtype=torch.complex128, device=self.device)
+        # column-major m x N: A's transpose view is that matrix with leading dimension m
+        At = A.t().contiguous()
+        self._check(self._lib.cfie_srft_rows(self._h, _ptr(At), max(m, 1), m, _ptr(d),
+                                             _ptr(out), max(m, 1)), "cfie_srft_rows")
+        return out.t()
 
     def info(self) -> dict:
         i = _lib.Info()

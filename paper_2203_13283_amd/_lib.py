@@ -25,6 +25,7 @@ MAT_G, MAT_DK, MAT_NK, MAT_DKT, MAT_SKT, MAT_CC_EIG, MAT_CIRCLE_ROW = range(7)
 OP_C, OP_CC, OP_CC_INV, OP_REMAINDER, OP_SKELETON, OP_C_ADJ = range(6)
 REFINE_FACTORED, REFINE_DENSE = 0, 1
 REMAINDER_AUTO, REMAINDER_FACTORED, REMAINDER_DENSE = 0, 1, 2
+SKETCH_GAUSSIAN, SKETCH_SRFT = 0, 1
 
 EXPORTED = [
     "cfie_default_options", "cfie_create", "cfie_assemble", "cfie_factor", "cfie_solve",
@@ -34,6 +35,7 @@ EXPORTED = [
     "cfie_set_gemm_autotune", "cfie_gemm_tuned_classes", "cfie_solve_group",
     "cfie_solve_batch_grouped", "cfie_solve_noalloc", "cfie_set_gemm_wide",
     "cfie_batch_record", "cfie_batch_launch", "cfie_batch_nodes", "cfie_batch_destroy",
+    "cfie_srft_rows", "cfie_srft_frequency",
 ]
 
 
@@ -50,7 +52,8 @@ class Options(ctypes.Structure):
                 ("quad_near", ctypes.c_int32), ("near_band", ctypes.c_int32),
                 ("fail_alloc_after", ctypes.c_int64), ("profile", ctypes.c_int32),
                 ("remainder_form", ctypes.c_int32), ("solve_graphs", ctypes.c_int32),
-                ("oversample", ctypes.c_int32), ("refine_form", ctypes.c_int32)]
+                ("oversample", ctypes.c_int32), ("refine_form", ctypes.c_int32),
+                ("test_matrix", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -156,6 +159,10 @@ def load(path: str = LIB_PATH):
     lib.cfie_set_gemm_wide.restype = ctypes.c_int
     lib.cfie_gemm_tuned_classes.argtypes = []
     lib.cfie_gemm_tuned_classes.restype = ctypes.c_int
+    lib.cfie_srft_rows.argtypes = [vp, vp, i64, i64, vp, vp, i64]
+    lib.cfie_srft_rows.restype = i32
+    lib.cfie_srft_frequency.argtypes = [i64, i64]
+    lib.cfie_srft_frequency.restype = i64
     _lib = lib
     return lib
 

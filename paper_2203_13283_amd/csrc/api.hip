@@ -552,20 +552,38 @@ template <> struct Ops<float> {
     static const zf *dCinvH(cfie_ctx *c) { return c->fCinvH; }
 };
 
+// A sketch block X drawn from the SRFT test matrix: the columns of D^k D F and N^k D F (AF,
+// formed once by launch_srft_rows) at the block's positions perm(off + t) are its products
+// with D^k and N^k
+template <typename T>
+struct SrftFirst {
+    const cpx<T> *AF[2];
+    SrftPerm q;
+    int64_t off;
+};
+
 // Y = C X, C = (G/2 + Dkt) G^{-1} (G/2 - Dk) + Skt G^{-1} Nk   (eq. (6))
 // temps: T, W1, W2 (N x m each)
-// (x_real: X has zero imaginary parts, so its products with D^k and N^k are two real ones)
+// (x_real: X has zero imaginary parts, so its products with D^k and N^k are two real ones;
+// fs: X is an SRFT block whose products with D^k and N^k are gathered)
 template <typename T>
 void apply_C(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
-             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, bool x_real = false) {
+             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, bool x_real = false,
+             const SrftFirst<T> *fs = nullptr) {
     const int N = c->N;
     const double h = c->hg.L / N;
     hipStream_t s = c->stream;
     const int nt = (int)c->gcoef.size();
     const int opx = x_real ? GEMM_NREAL : GEMM_N;
-    gemm<T>(opx, N, m, N, cz<T>(1), Ops<T>::mat(c, 0), N, X, ldx, cz<T>(0), Tt, N, s);
+    auto first = [&](int i) {
+        if (fs)
+            launch_srft_gather<T>(N, fs->q, fs->off, (int)m, fs->AF[i], N, Tt, N, s);
+        else
+            gemm<T>(opx, N, m, N, cz<T>(1), Ops<T>::mat(c, i), N, X, ldx, cz<T>(0), Tt, N, s);
+    };
+    first(0);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0.5), X, ldx, cz<T>(-1), Tt, N, W1, N, m, s);
-    gemm<T>(opx, N, m, N, cz<T>(1), Ops<T>::mat(c, 1), N, X, ldx, cz<T>(0), Tt, N, s);
+    first(1);
     launch_ginv_ex<T>(N, nt, c->g_t0, c->d_gcoef, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(1),
                       Tt, N, W2, N, m, s);
     launch_gmul<T>(N, h, cz<T>(0), (const cpx<T> *)nullptr, 0, cz<T>(0.5), W1, N, Y, ldy, m, s);
@@ -593,9 +611,10 @@ void residual64(cfie_ctx *c, const zd *B, int64_t ldb, const zd *X, zd *R, int64
 // Y = (C - C_c) X ; temps T, W1, W2, Z
 template <typename T>
 void apply_R(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, int64_t m,
-             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z, bool x_real = false) {
+             cpx<T> *Tt, cpx<T> *W1, cpx<T> *W2, cpx<T> *Z, bool x_real = false,
+             const SrftFirst<T> *fs = nullptr) {
     const int N = c->N;
-    apply_C<T>(c, X, ldx, Y, ldy, m, Tt, W1, W2, x_real);
+    apply_C<T>(c, X, ldx, Y, ldy, m, Tt, W1, W2, x_real, fs);
     axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, c->stream);
     circ_apply<T>(c, Ops<T>::dC(c), Z, N, m);
     axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, c->stream);
@@ -800,8 +819,15 @@ enum {
     SLOT_W64, SLOT_TMPN, SLOT_CD,
     SLOT_BAND_WS, SLOT_NEAR_WS, SLOT_BAND_WS_C, SLOT_NEAR_WS_C, SLOT_EIG_NAT, SLOT_EIG_NATF,
     SLOT_EIG_WORK,
-    SLOT_RHS_ANG, SLOT_RHS_E, SLOT_RHS_H, SLOT_RHS_GE, SLOT_RHS_GH, SLOT_RHS_B
+    SLOT_RHS_ANG, SLOT_RHS_E, SLOT_RHS_H, SLOT_RHS_GE, SLOT_RHS_GH, SLOT_RHS_B,
+    SLOT_SRFT_D, SLOT_SRFT0, SLOT_SRFT1
 };
+
+// Philox stream of the SRFT diagonal (the Gaussian blocks use the streams 0, 1, 2, ...)
+constexpr uint64_t kSrftStream = 0x5352465444494147ull;
+template <typename T> const cpx<T> *twN_of(cfie_ctx *c);
+template <> const zd *twN_of<double>(cfie_ctx *c) { return (const zd *)c->fft.twN; }
+template <> const zf *twN_of<float>(cfie_ctx *c) { return (const zf *)c->fft.twMf; }
 
 // C of eq. (6) as a dense N x N matrix, C = (G/2 + D^kt) M + S^kt G^-1 N^k with
 // M = G^-1 (G/2 - D^k) (two N x N x N products), minus C_c (applied to the identity by FFT)
@@ -861,11 +887,28 @@ cfie_status factor_impl(cfie_ctx *c) {
     launch_fill_int(1, 0, c->info, s);                 // pivot flag (also for rank 0)
     size_t bi = 0;                                     // block index (schedule of a replay)
     bool pending_dense = false;     // C - C_c was just formed densely (automatic switch)
+    // SRFT test matrix (N a power of two): blocks after the first take the columns of D F at
+    // positions perm(srft_off + t); D^k D F and N^k D F are formed when the second block is
+    // drawn, so a sketch that one block completes does not pay for them.  The order of the
+    // decisions depends on the schedule only, so a replay repeats them.
+    int lgN = 0;
+    while ((1 << lgN) < N) ++lgN;
+    const bool srft = c->opt.test_matrix == CFIE_SKETCH_SRFT && (1 << lgN) == N;
+    const SrftPerm sq = srft_perm(c->opt.seed, lgN);
+    int64_t srft_off = 0;
+    cpx<T> *AF0 = nullptr, *AF1 = nullptr, *dv = nullptr;
+    auto srft_release = [&]() {
+        c->tmp_free(AF0);
+        c->tmp_free(AF1);
+        c->tmp_free(dv);
+        AF0 = AF1 = dv = nullptr;
+    };
     while (replay ? bi < c->sched.size() : ell < cap) {
         cfie_ctx::BlockPlan bp;
         if (replay) {
             bp = c->sched[bi];
             if (bp.dense_before && !Rd) {
+                srft_release();
                 Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
                 form_dense<T>(c, Rd, true);
             }
@@ -875,11 +918,26 @@ cfie_status factor_impl(cfie_ctx *c) {
             pending_dense = false;
         }
         const int bb = bp.bb;
-        randn<T>(N, bb, c->opt.seed, blk++, Om, N, s);    // real Gaussian block
-        if (Rd)
-            gemm<T>(GEMM_NREAL, N, bb, N, cz<T>(1), Rd, N, Om, N, cz<T>(0), Y, N, s);
-        else
-            apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z, true);
+        if (srft && !Rd && bi > 0 && srft_off + bb <= N) {
+            if (!AF0) {
+                dv = c->tmp_buf<cpx<T>>(SLOT_SRFT_D, (size_t)N);
+                AF0 = c->tmp_buf<cpx<T>>(SLOT_SRFT0, (size_t)N * N);
+                AF1 = c->tmp_buf<cpx<T>>(SLOT_SRFT1, (size_t)N * N);
+                launch_steinhaus<T>(N, c->opt.seed, kSrftStream, dv, s);
+                launch_srft_rows<T>(N, N, Ops<T>::mat(c, 0), N, dv, twN_of<T>(c), AF0, N, s);
+                launch_srft_rows<T>(N, N, Ops<T>::mat(c, 1), N, dv, twN_of<T>(c), AF1, N, s);
+            }
+            launch_srft_omega<T>(N, sq, srft_off, bb, dv, twN_of<T>(c), Om, N, s);
+            const SrftFirst<T> fs{{AF0, AF1}, sq, srft_off};
+            apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z, false, &fs);
+            srft_off += bb;
+        } else {
+            randn<T>(N, bb, c->opt.seed, blk++, Om, N, s);    // real Gaussian block
+            if (Rd)
+                gemm<T>(GEMM_NREAL, N, bb, N, cz<T>(1), Rd, N, Om, N, cz<T>(0), Y, N, s);
+            else
+                apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z, true);
+        }
         if (ell > 0) {
             // block Gram-Schmidt against Q.  After one pass the kept directions deviate from
             // orthogonality to Q by about the unit roundoff times ||Y|| / tau (they are kept
@@ -933,10 +991,12 @@ cfie_status factor_impl(cfie_ctx *c) {
         // remaining range with at least p columns of oversampling: the remainder left after
         // it exceeds tau only with a probability that falls geometrically with p (Halko,
         // Martinsson and Tropp's bound for a Gaussian test matrix), so no further block is
-        // drawn
+        // drawn.  SRFT blocks carry a weaker bound in theory (their Sec. 11) and behave like
+        // Gaussian ones in practice (their Sec. 7.4); the rule is kept for both.
         const int p = c->opt.oversample;
         if (p > 0 && bb >= 2 * p && kept <= bb - p) break;
         if (!Rd && c->opt.remainder_form == CFIE_REMAINDER_AUTO && 2 * ell >= N && ell < cap) {
+            srft_release();
             Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
             form_dense<T>(c, Rd, true);
             pending_dense = true;           // a replay forms it before the next block
@@ -948,6 +1008,7 @@ cfie_status factor_impl(cfie_ctx *c) {
         Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
         form_dense<T>(c, Rd, true);
     }
+    srft_release();
     c->rank = ell;
     c->fac_mark();                                     // end of the range finder
     if (ell == 0) {
@@ -1841,6 +1902,7 @@ void cfie_default_options(cfie_options *o) {
     o->solve_graphs = 0;
     o->oversample = 16;
     o->refine_form = CFIE_REFINE_FACTORED;
+    o->test_matrix = CFIE_SKETCH_SRFT;
 }
 
 const char *cfie_status_string(cfie_status s) {
@@ -1877,6 +1939,8 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, c
         return bad("remainder_form must be CFIE_REMAINDER_AUTO, _FACTORED or _DENSE");
     if (o.solve_graphs != 0 && o.solve_graphs != 1) return bad("solve_graphs must be 0 or 1");
     if (o.oversample < 0 || o.oversample > 256) return bad("oversample must be in [0, 256]");
+    if (o.test_matrix != CFIE_SKETCH_GAUSSIAN && o.test_matrix != CFIE_SKETCH_SRFT)
+        return bad("test_matrix must be CFIE_SKETCH_GAUSSIAN or CFIE_SKETCH_SRFT");
     if (o.refine_form != CFIE_REFINE_FACTORED && o.refine_form != CFIE_REFINE_DENSE)
         return bad("refine_form must be CFIE_REFINE_FACTORED or CFIE_REFINE_DENSE");
     int ndev = 0;
@@ -2893,6 +2957,32 @@ cfie_status cfie_apply(cfie_ctx *c, int op, const void *X, int64_t ldx, void *Y,
         c->dfree(Tt); c->dfree(W1); c->dfree(W2); c->dfree(Z);
         return CFIE_OK;
     });
+}
+
+cfie_status cfie_srft_rows(cfie_ctx *c, const void *A, int64_t lda, int64_t m, const void *d,
+                           void *out, int64_t ldo) {
+    if (!c) return CFIE_EINVAL;
+    if (c->state < 1) return fail(c, CFIE_ESTATE, "nothing assembled yet");
+    const int N = c->N;
+    if ((N & (N - 1)) != 0) return fail(c, CFIE_EINVAL, "N is not a power of two");
+    if (!A || !d || !out) return fail(c, CFIE_EINVAL, "NULL pointer");
+    if (m < 0 || lda < std::max<int64_t>(m, 1) || ldo < std::max<int64_t>(m, 1))
+        return fail(c, CFIE_EINVAL, "m < 0 or a leading dimension below m");
+    return guarded(c, [&]() -> cfie_status {
+        HIPCHK(hipSetDevice(c->device));
+        launch_srft_rows<double>(m, N, (const zd *)A, lda, (const zd *)d,
+                                 (const zd *)c->fft.twN, (zd *)out, ldo, c->stream);
+        c->check_launch();
+        c->sync();
+        return CFIE_OK;
+    });
+}
+
+int64_t cfie_srft_frequency(int64_t n, int64_t p) {
+    if (n < 1 || n > (int64_t)1 << 30 || (n & (n - 1)) != 0 || p < 0 || p >= n) return -1;
+    int lgN = 0;
+    while (((int64_t)1 << lgN) < n) ++lgN;
+    return srft_freq(srft_plan(lgN), (int)p);
 }
 
 cfie_status cfie_export_matrix(cfie_ctx *c, int which, void *dst, int64_t ld) {

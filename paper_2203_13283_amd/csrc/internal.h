@@ -195,6 +195,70 @@ void launch_circ_apply_padded(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int6
 void launch_padded_diagonal(const FFTPlan &p, const zd *eig_over_N, zd *work, zd *dT, zf *fT,
                             hipStream_t s);
 
+// ------------------------------------------------------------------ SRFT test matrix -----
+// Subsampled randomized Fourier transform (Halko, Martinsson and Tropp, SIAM Review 2011,
+// Sec. 4.6): Omega = D F S with D = diag(d), |d_i| = 1 of uniform random phase, F the N-point
+// DFT matrix F_ij = e^{-2 pi i i j / N} (N a power of two) and S a random choice of columns.
+// A D F is formed once by radix-2^b decimation-in-frequency passes along the rows of A, which
+// leave column j of A D F at a digit-reversed position p; the sketch then takes the columns
+// at the positions p = perm(t), t = 0, 1, 2, ... of a seeded bijection of [0, N).
+struct SrftPlan {
+    int lgN = 0, npass = 0;
+    int bits[8] = {};                // log2 of each pass's radix, first pass first
+};
+__host__ __device__ inline SrftPlan srft_plan(int lgN) {
+    SrftPlan p;
+    p.lgN = lgN;
+    p.npass = lgN <= 0 ? 0 : (lgN + 4) / 5;           // radices of at most 32
+    for (int l = 0; l < p.npass; ++l) p.bits[l] = lgN / p.npass + (l < lgN % p.npass ? 1 : 0);
+    return p;
+}
+// frequency j of the column at position p: pass l contributes its digit e_l at weight
+// 2^(bits of the later passes) to the position and at 2^(bits of the earlier passes) to j
+__host__ __device__ inline int srft_freq(const SrftPlan &p, int pos) {
+    int j = 0, lo = 0, hi = p.lgN;
+    for (int l = 0; l < p.npass; ++l) {
+        hi -= p.bits[l];
+        const int e = (pos >> hi) & ((1 << p.bits[l]) - 1);
+        j |= e << lo;
+        lo += p.bits[l];
+    }
+    return j;
+}
+// seeded bijection of [0, 2^lgN): three rounds of an odd multiply-add and an xor-shift, each
+// invertible modulo 2^lgN
+struct SrftPerm {
+    int lgN = 0;
+    uint32_t mul[3] = {}, add[3] = {};
+};
+SrftPerm srft_perm(uint64_t seed, int lgN);
+__host__ __device__ inline uint32_t srft_perm_apply(const SrftPerm &q, uint32_t x) {
+    const uint32_t mask = q.lgN >= 32 ? 0xffffffffu : ((1u << q.lgN) - 1u);
+    const int sh = q.lgN / 2 > 0 ? q.lgN / 2 : 1;
+    for (int r = 0; r < 3; ++r) {
+        x = (x * q.mul[r] + q.add[r]) & mask;
+        x ^= x >> sh;
+    }
+    return x;
+}
+// out = A D F (m x N, columns at the digit-reversed positions): the first pass reads A and d
+// and writes out, the others work in place on out.  tw: e^{-2 pi i j / N}, j < N.
+template <typename T>
+void launch_srft_rows(int64_t m, int N, const cpx<T> *A, int64_t lda, const cpx<T> *d,
+                      const cpx<T> *tw, cpx<T> *out, int64_t ldo, hipStream_t s);
+// Om[:, t] = D F[:, j(perm(off + t))] for t < nb (N x nb): the test-matrix columns whose
+// products are the columns of A D F gathered by launch_srft_gather
+template <typename T>
+void launch_srft_omega(int N, const SrftPerm &q, int64_t off, int nb, const cpx<T> *d,
+                       const cpx<T> *tw, cpx<T> *Om, int64_t ldo, hipStream_t s);
+// out[:, t] = AF[:, perm(off + t)] for t < nb (AF: m x N from launch_srft_rows)
+template <typename T>
+void launch_srft_gather(int64_t m, const SrftPerm &q, int64_t off, int nb, const cpx<T> *AF,
+                        int64_t ldaf, cpx<T> *out, int64_t ldo, hipStream_t s);
+// d_i = e^{2 pi i u_i}, u_i uniform from the Philox stream (seed, stream), i < n
+template <typename T>
+void launch_steinhaus(int64_t n, uint64_t seed, uint64_t stream, cpx<T> *d, hipStream_t s);
+
 // complex GEMM: C = alpha * op(A) * B + beta * C, op(A) = A (GEMM_N), A^H (GEMM_C) or the
 // elementwise conjugate of A (GEMM_R); GEMM_NREAL: op(A) = A and B real-valued (stored
 // complex, its imaginary parts taken as zero and not read), two real products instead of

@@ -330,6 +330,30 @@ void randn(int64_t m, int64_t n, uint64_t seed, uint64_t stream, cpx<T> *X, int6
 template void randn<double>(int64_t, int64_t, uint64_t, uint64_t, zd *, int64_t, hipStream_t);
 template void randn<float>(int64_t, int64_t, uint64_t, uint64_t, zf *, int64_t, hipStream_t);
 
+// Unit-modulus entries of uniform random phase (the diagonal D of the SRFT test matrix):
+// one 53-bit uniform u per entry from the same Philox stream layout, d = e^{2 pi i u}.
+template <typename T>
+__global__ void k_steinhaus(int64_t n, uint64_t seed, uint64_t stream, cpx<T> *d) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= n) return;
+    uint32_t ctr[4] = {(uint32_t)tid, (uint32_t)(tid >> 32), (uint32_t)stream,
+                       (uint32_t)(stream >> 32)};
+    philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u = (double)(((uint64_t)ctr[0] << 21) ^ (ctr[1] >> 11)) *
+                     (1.0 / 9007199254740992.0);
+    double sn, cs;
+    sincospi(2.0 * u, &sn, &cs);
+    d[tid] = mk((T)cs, (T)sn);
+}
+template <typename T>
+void launch_steinhaus(int64_t n, uint64_t seed, uint64_t stream, cpx<T> *d, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_steinhaus<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       seed, stream, d);
+}
+template void launch_steinhaus<double>(int64_t, uint64_t, uint64_t, zd *, hipStream_t);
+template void launch_steinhaus<float>(int64_t, uint64_t, uint64_t, zf *, hipStream_t);
+
 // ------------------------------------------------------------------ column norms ---------
 // out[c] = sum_i |X_ic|^2 (double), one block per column
 template <typename T>

@@ -47,11 +47,40 @@ def test_create_rejects_bad_options_before_touching_a_device():
     o = _lib.default_options()
     o.quad_far = 7
     assert lib.cfie_create(ctypes.byref(o), 0, None, ctypes.byref(h)) == _lib.CFIE_EINVAL
+    o = _lib.default_options()
+    assert o.test_matrix == _lib.SKETCH_SRFT
+    o.test_matrix = 2
+    assert lib.cfie_create(ctypes.byref(o), 0, None, ctypes.byref(h)) == _lib.CFIE_EINVAL
+    assert b"test_matrix" in lib.cfie_last_error(None)
     assert lib.cfie_create(None, 0, None, None) == _lib.CFIE_EINVAL
     # NULL context handling of every entry point
     assert lib.cfie_factor(None) == _lib.CFIE_EINVAL
     assert lib.cfie_solve(None, None, 0, None, 0, 0) == _lib.CFIE_EINVAL
+    assert lib.cfie_srft_rows(None, None, 0, 0, None, None, 0) == _lib.CFIE_EINVAL
     lib.cfie_destroy(None)
+
+
+def test_srft_frequency_map():
+    """Position -> frequency of the row transform's radix passes (host function).  One pass
+    (N <= 32) leaves the natural order; two passes of 2^b1 and 2^b2 points leave frequency
+    j = e1 + 2^b1 e2 at position p = 2^b2 e1 + e2 (the digits swapped); in general the map is
+    a permutation of [0, N) that is its own inverse when all passes have the same radix."""
+    from paper_2203_13283_amd import _lib
+    lib = _lib.load()
+    f = lib.cfie_srft_frequency
+    for n in (8, 16, 32):
+        assert [f(n, p) for p in range(n)] == list(range(n))
+    # N = 64: passes of 8 and 8; N = 128: passes of 16 and 8
+    for n, b1, b2 in ((64, 3, 3), (128, 4, 3), (1024, 5, 5)):
+        for p in range(n):
+            e1, e2 = p >> b2, p & ((1 << b2) - 1)
+            assert f(n, p) == e1 + (e2 << b1), (n, p)
+    for n in (2048, 16384, 32768):
+        js = [f(n, p) for p in range(n)]
+        assert sorted(js) == list(range(n))
+    assert [f(16384, f(16384, p)) for p in range(0, 16384, 37)] != list(range(0, 16384, 37))
+    assert all(f(1024, f(1024, p)) == p for p in range(1024))
+    assert f(1000, 3) == -1 and f(64, 64) == -1 and f(64, -1) == -1
 
 
 def test_group_solve_argument_checks_before_touching_a_device():

@@ -1,0 +1,136 @@
+"""The SRFT test matrix of the sketch (GPU, through the C ABI).
+
+The range finder's blocks after the first may take their test columns from a subsampled
+randomized Fourier transform Omega = D F S (cfie_options.test_matrix, Halko, Martinsson and
+Tropp 2011, Sec. 4.6); the products of D^k and N^k with those columns are then columns of
+D^k D F and N^k D F, formed once by radix passes along the rows (cfie_srft_rows).
+
+* cfie_srft_rows against numpy's FFT of A diag(d) (a library transform, not the oracle: the
+  oracle has no sketch) at N = 8, 1024 and 2048 -- one, two and three radix passes -- with
+  300 rows (a ragged last workgroup of rows); columns mapped by srft_frequency;
+* the factorisation with SRFT blocks against the one with Gaussian blocks and against the
+  oracle's dense-LU solution at N = 1024 (several blocks of 64): FP64 at epsilon = 1e-10
+  within the 1e-10 bar, at epsilon = 1e-5 within 3 x the error the Gaussian sketch reaches
+  and within epsilon (both about 1.1e-6 here), mixed precision after refinement within
+  1e-6; ranks within 10 %;
+* all N Fourier columns drawn (N = 256, blocks of 64, the oversampling stop off): the sketch
+  falls back to Gaussian blocks and still meets the 1e-10 bar;
+* N not a power of two: the option changes nothing (bitwise the same solution), and
+  cfie_srft_rows rejects the context.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import system as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2203_13283_amd")
+
+
+def _solver_at(N, **kw):
+    zh = W.ellipse_coeffs(1.0, 0.6)
+    L = S.Contour(zh).L
+    k = 2 * math.pi * N / (10 * L)
+    s = P.Solver(**kw)
+    s.assemble(zh, N, k)
+    return s, zh, k
+
+
+@pytest.mark.parametrize("N", [8, 1024, 2048])
+def test_srft_rows_against_numpy_fft(N):
+    s, _, _ = _solver_at(N)
+    rng = np.random.default_rng(N)
+    m = 300
+    A = rng.standard_normal((m, N)) + 1j * rng.standard_normal((m, N))
+    d = np.exp(2j * np.pi * rng.random(N))
+    got = s.srft_rows(torch.as_tensor(A, device="cuda"),
+                      torch.as_tensor(d, device="cuda")).cpu().numpy()
+    ref = np.fft.fft(A * d[None, :], axis=1)
+    js = np.array([P.srft_frequency(N, p) for p in range(N)])
+    assert sorted(js.tolist()) == list(range(N))
+    err = np.abs(got - ref[:, js]).max() / np.abs(ref).max()
+    print(f"N={N}: max error {err:.2e}")
+    assert err <= 5e-15 * max(1.0, math.log2(N))
+
+
+def _factor_solve(N, zh, k, ang, **kw):
+    s = P.Solver(**kw)
+    s.assemble(zh, N, k)
+    s.factor()
+    X = s.solve(s.plane_wave_rhs(ang)).cpu().numpy().T
+    r = s.info()["rank"]
+    s.close()
+    torch.cuda.empty_cache()
+    return X, r
+
+
+@pytest.fixture(scope="module")
+def ref1024():
+    N = 1024
+    zh = W.ellipse_coeffs(1.0, 0.6)
+    L = S.Contour(zh).L
+    k = 2 * math.pi * N / (10 * L)
+    ang = W.plane_wave_angles(8)
+    prob = S.Problem(zh, N, k, workers=8)
+    return N, zh, k, ang, prob.solve(prob.rhs(ang))
+
+
+@pytest.mark.parametrize("eps", [1e-10, 1e-5])
+def test_factor_srft_against_gaussian_and_oracle(ref1024, eps):
+    N, zh, k, ang, xr = ref1024
+    Xs, rs = _factor_solve(N, zh, k, ang, compress_tol=eps, block=64,
+                           test_matrix=P.SKETCH_SRFT)
+    Xg, rg = _factor_solve(N, zh, k, ang, compress_tol=eps, block=64,
+                           test_matrix=P.SKETCH_GAUSSIAN)
+    es, eg = S.rel_err(Xs, xr), S.rel_err(Xg, xr)
+    print(f"eps={eps:g}: rank SRFT {rs} Gaussian {rg}; rel.err SRFT {es:.2e} Gaussian {eg:.2e}")
+    assert abs(rs - rg) <= 0.1 * rg + 8
+    if eps <= 1e-10:
+        assert es <= 1e-10 and eg <= 1e-10
+    else:
+        assert es <= max(3 * eg, 1e-9) and es <= eps
+
+
+def test_factor_srft_mixed_precision(ref1024):
+    N, zh, k, ang, xr = ref1024
+    X, r = _factor_solve(N, zh, k, ang, precision=P.CFIE_MIXED, compress_tol=1e-3, block=64,
+                         refine_tol=1e-8, test_matrix=P.SKETCH_SRFT)
+    err = S.rel_err(X, xr)
+    print(f"mixed, SRFT: rank {r}, rel.err {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_srft_columns_exhausted_falls_back_to_gaussian():
+    w = W.get("ellipse256")
+    prob = S.Problem(w.zhat, w.n_nodes, w.k)
+    ang = W.plane_wave_angles(8)
+    xr = prob.solve(prob.rhs(ang))
+    X, r = _factor_solve(w.n_nodes, w.zhat, w.k, ang, compress_tol=1e-10, block=64,
+                         oversample=0, test_matrix=P.SKETCH_SRFT)
+    err = S.rel_err(X, xr)
+    print(f"N=256, blocks of 64, no oversampling stop: rank {r}, rel.err {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_non_power_of_two_is_unchanged():
+    N = 1000
+    zh = W.ellipse_coeffs(1.0, 0.6)
+    L = S.Contour(zh).L
+    k = 2 * math.pi * N / (10 * L)
+    ang = W.plane_wave_angles(4)
+    Xs, rs = _factor_solve(N, zh, k, ang, compress_tol=1e-8, block=64,
+                           test_matrix=P.SKETCH_SRFT)
+    Xg, rg = _factor_solve(N, zh, k, ang, compress_tol=1e-8, block=64,
+                           test_matrix=P.SKETCH_GAUSSIAN)
+    assert rs == rg and np.array_equal(Xs, Xg)
+    s, _, _ = _solver_at(N)
+    A = torch.zeros((4, N), dtype=torch.complex128, device="cuda")
+    d = torch.ones(N, dtype=torch.complex128, device="cuda")
+    with pytest.raises(P.CfieError) as ei:
+        s.srft_rows(A, d)
+    assert ei.value.status == 1
