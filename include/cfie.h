@@ -107,14 +107,15 @@ typedef struct {
 } cfie_options;
 
 /* cfie_options.test_matrix.  The first sketch block is always real Gaussian.  With
- * CFIE_SKETCH_SRFT and N a power of two, C - C_c applied factor by factor, the later blocks
- * take columns of a subsampled randomized Fourier transform Omega = D F S (Halko, Martinsson
- * and Tropp, SIAM Review 53 (2011), Sec. 4.6: D diagonal of unit-modulus entries of uniform
- * random phase, F the N-point DFT, S distinct columns in a seeded random order): D^k D F and
- * N^k D F are formed once by FFTs along their rows (32 N^2 bytes more during the
- * factorisation in FP64, 16 N^2 in mixed precision), and each block's products with D^k and
- * N^k become column gathers.  The Gaussian form is used where this does not apply (N not a
- * power of two, C - C_c formed densely, all N Fourier columns drawn). */
+ * CFIE_SKETCH_SRFT the later blocks take columns of a subsampled randomized Fourier
+ * transform Omega = (D F)[0:N, S] (Halko, Martinsson and Tropp, SIAM Review 53 (2011),
+ * Sec. 4.6: D diagonal of unit-modulus entries of uniform random phase, F the DFT of length
+ * M = the smallest power of two >= N, S distinct columns in a seeded random order).  With
+ * C - C_c applied factor by factor, D^k D F and N^k D F are formed once by FFTs along their
+ * rows (32 N M bytes more during the factorisation in FP64, 16 N M in mixed precision) and
+ * each block's products with D^k and N^k become column gathers; with C - C_c formed densely,
+ * (C - C_c) D F is formed once (16 N M bytes, 8 N M) and a block is a column gather.  Once
+ * all M Fourier columns have been drawn the blocks are Gaussian again. */
 enum {
     CFIE_SKETCH_GAUSSIAN = 0,    /* real Gaussian blocks (Philox4x32-10 stream of seed)        */
     CFIE_SKETCH_SRFT = 1         /* Gaussian first block, then SRFT columns                    */
@@ -308,12 +309,13 @@ enum {
 cfie_status cfie_apply(cfie_ctx *ctx, int op, const void *X_dev, int64_t ldx, void *Y_dev,
                        int64_t ldy, int64_t nrhs);
 
-/* The row transform behind CFIE_SKETCH_SRFT, for checking it: out = A diag(d) F with
- * F_ij = e^{-2 pi i i j / N}, N = the context's node count (a power of two; EINVAL otherwise,
- * ESTATE before cfie_assemble).  A_dev: device, m x N complex128, column-major, lda >= m;
- * d_dev: device, N complex128; out_dev: device, m x N, ldo >= m, must not overlap A_dev.
- * Column j of A diag(d) F is written to column p of out with j = cfie_srft_frequency(N, p),
- * the digit reversal of the radix passes.  Runs on the context's stream. */
+/* The row transform behind CFIE_SKETCH_SRFT, for checking it: out = A_0 diag(d) F with
+ * F_ij = e^{-2 pi i i j / M}, M = the smallest power of two >= N, N = the context's node
+ * count, A_0 = A with M - N zero columns appended (ESTATE before cfie_assemble).  A_dev:
+ * device, m x N complex128, column-major, lda >= m; d_dev: device, N complex128; out_dev:
+ * device, m x M, ldo >= m, must not overlap A_dev.  Column j of A_0 diag(d) F is written to
+ * column p of out with j = cfie_srft_frequency(M, p), the digit reversal of the radix
+ * passes.  Runs on the context's stream. */
 cfie_status cfie_srft_rows(cfie_ctx *ctx, const void *A_dev, int64_t lda, int64_t m,
                            const void *d_dev, void *out_dev, int64_t ldo);
 /* The frequency j held at output position p (0 <= p < N) of cfie_srft_rows; -1 if N is not

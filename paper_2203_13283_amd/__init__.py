@@ -258,16 +258,20 @@ class Solver:
         return buf.t() if cols == self.N else buf
 
     def srft_rows(self, A, d):
-        """A diag(d) F (F_ij = e^{-2 pi i i j / N}) with its columns at the digit-reversed
-        positions of cfie_srft_rows (column p holds frequency srft_frequency(N, p)).
-        A: (m, N) complex128 CUDA tensor in natural (row, column) indexing, d: N complex128.
-        Returns an (m, N) tensor in natural indexing."""
+        """A_0 diag(d) F (F_ij = e^{-2 pi i i j / M}, M the smallest power of two >= N, A_0 =
+        A with M - N zero columns appended), its columns at the digit-reversed positions of
+        cfie_srft_rows (column p holds frequency srft_frequency(M, p)).  A: (m, N) complex128
+        CUDA tensor in natural (row, column) indexing, d: N complex128.  Returns an (m, M)
+        tensor in natural indexing."""
         torch = _torch()
         self._check_batch(A, self.N, "A")
         if d.dtype != torch.complex128 or d.numel() != self.N or not d.is_contiguous():
             raise ValueError("d must be a contiguous complex128 tensor of N entries")
         m = A.shape[0]
-        out = torch.empty((self.N, m), dtype=torch.complex128, device=self.device)
+        M = 1
+        while M < self.N:
+            M *= 2
+        out = torch.empty((M, m), dtype=torch.complex128, device=self.device)
         # column-major m x N: A's transpose view is that matrix with leading dimension m
         At = A.t().contiguous()
         self._check(self._lib.cfie_srft_rows(self._h, _ptr(At), max(m, 1), m, _ptr(d),

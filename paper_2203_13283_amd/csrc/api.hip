@@ -820,14 +820,15 @@ enum {
     SLOT_BAND_WS, SLOT_NEAR_WS, SLOT_BAND_WS_C, SLOT_NEAR_WS_C, SLOT_EIG_NAT, SLOT_EIG_NATF,
     SLOT_EIG_WORK,
     SLOT_RHS_ANG, SLOT_RHS_E, SLOT_RHS_H, SLOT_RHS_GE, SLOT_RHS_GH, SLOT_RHS_B,
-    SLOT_SRFT_D, SLOT_SRFT0, SLOT_SRFT1
+    SLOT_SRFT_D, SLOT_SRFT0, SLOT_SRFT1, SLOT_SRFT_RD
 };
 
 // Philox stream of the SRFT diagonal (the Gaussian blocks use the streams 0, 1, 2, ...)
 constexpr uint64_t kSrftStream = 0x5352465444494147ull;
-template <typename T> const cpx<T> *twN_of(cfie_ctx *c);
-template <> const zd *twN_of<double>(cfie_ctx *c) { return (const zd *)c->fft.twN; }
-template <> const zf *twN_of<float>(cfie_ctx *c) { return (const zf *)c->fft.twMf; }
+// e^{-2 pi i j / M}, j < M, M = fft.M (a power of two)
+template <typename T> const cpx<T> *twM_of(cfie_ctx *c);
+template <> const zd *twM_of<double>(cfie_ctx *c) { return (const zd *)c->fft.twM; }
+template <> const zf *twM_of<float>(cfie_ctx *c) { return (const zf *)c->fft.twMf; }
 
 // C of eq. (6) as a dense N x N matrix, C = (G/2 + D^kt) M + S^kt G^-1 N^k with
 // M = G^-1 (G/2 - D^k) (two N x N x N products), minus C_c (applied to the identity by FFT)
@@ -887,28 +888,38 @@ cfie_status factor_impl(cfie_ctx *c) {
     launch_fill_int(1, 0, c->info, s);                 // pivot flag (also for rank 0)
     size_t bi = 0;                                     // block index (schedule of a replay)
     bool pending_dense = false;     // C - C_c was just formed densely (automatic switch)
-    // SRFT test matrix (N a power of two): blocks after the first take the columns of D F at
-    // positions perm(srft_off + t); D^k D F and N^k D F are formed when the second block is
-    // drawn, so a sketch that one block completes does not pay for them.  The order of the
+    // SRFT test matrix: blocks after the first take the columns of D F (F of the length
+    // Mf = the smallest power of two >= N, its first N rows) at positions
+    // perm(srft_off + t).  Factor by factor, D^k D F and N^k D F are formed when the second
+    // block is drawn, so a sketch that one block completes does not pay for them; with
+    // C - C_c formed densely, (C - C_c) D F, and a block is a column gather.  The order of the
     // decisions depends on the schedule only, so a replay repeats them.
-    int lgN = 0;
-    while ((1 << lgN) < N) ++lgN;
-    const bool srft = c->opt.test_matrix == CFIE_SKETCH_SRFT && (1 << lgN) == N;
-    const SrftPerm sq = srft_perm(c->opt.seed, lgN);
+    int lgM = 0;
+    while ((1 << lgM) < N) ++lgM;
+    const int Mf = 1 << lgM;
+    const bool srft = c->opt.test_matrix == CFIE_SKETCH_SRFT;
+    const SrftPerm sq = srft_perm(c->opt.seed, lgM);
+    const cpx<T> *twf = twM_of<T>(c);
+    const int tws = c->fft.M / Mf;
     int64_t srft_off = 0;
-    cpx<T> *AF0 = nullptr, *AF1 = nullptr, *dv = nullptr;
-    auto srft_release = [&]() {
+    cpx<T> *AF0 = nullptr, *AF1 = nullptr, *AFd = nullptr, *dv = nullptr;
+    auto srft_release_factored = [&]() {
         c->tmp_free(AF0);
         c->tmp_free(AF1);
+        AF0 = AF1 = nullptr;
+    };
+    auto srft_release = [&]() {
+        srft_release_factored();
+        c->tmp_free(AFd);
         c->tmp_free(dv);
-        AF0 = AF1 = dv = nullptr;
+        AFd = dv = nullptr;
     };
     while (replay ? bi < c->sched.size() : ell < cap) {
         cfie_ctx::BlockPlan bp;
         if (replay) {
             bp = c->sched[bi];
             if (bp.dense_before && !Rd) {
-                srft_release();
+                srft_release_factored();
                 Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
                 form_dense<T>(c, Rd, true);
             }
@@ -918,18 +929,35 @@ cfie_status factor_impl(cfie_ctx *c) {
             pending_dense = false;
         }
         const int bb = bp.bb;
-        if (srft && !Rd && bi > 0 && srft_off + bb <= N) {
-            if (!AF0) {
+        // A remainder whose images of the n_d Fourier columns drawn so far have been taken
+        // into Q holds its energy in the other Mf - n_d columns of D F, so an undrawn column's
+        // squared norm estimates Mf / (Mf - n_d) times the squared Frobenius norm that a
+        // fresh Gaussian column estimates: an SRFT block's norms are scaled by
+        // ((Mf - n_d) / Mf)^(1/2) for the stop test and the kept directions (tau_b)
+        double est_scale = 1.0;
+        if (srft && bi > 0 && srft_off + bb <= Mf) {
+            est_scale = std::sqrt((double)(Mf - srft_off) / (double)Mf);
+            if (!dv) {
                 dv = c->tmp_buf<cpx<T>>(SLOT_SRFT_D, (size_t)N);
-                AF0 = c->tmp_buf<cpx<T>>(SLOT_SRFT0, (size_t)N * N);
-                AF1 = c->tmp_buf<cpx<T>>(SLOT_SRFT1, (size_t)N * N);
                 launch_steinhaus<T>(N, c->opt.seed, kSrftStream, dv, s);
-                launch_srft_rows<T>(N, N, Ops<T>::mat(c, 0), N, dv, twN_of<T>(c), AF0, N, s);
-                launch_srft_rows<T>(N, N, Ops<T>::mat(c, 1), N, dv, twN_of<T>(c), AF1, N, s);
             }
-            launch_srft_omega<T>(N, sq, srft_off, bb, dv, twN_of<T>(c), Om, N, s);
-            const SrftFirst<T> fs{{AF0, AF1}, sq, srft_off};
-            apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z, false, &fs);
+            if (Rd) {
+                if (!AFd) {
+                    AFd = c->tmp_buf<cpx<T>>(SLOT_SRFT_RD, (size_t)N * Mf);
+                    launch_srft_rows<T>(N, N, Mf, Rd, N, dv, twf, tws, AFd, N, s);
+                }
+                launch_srft_gather<T>(N, sq, srft_off, bb, AFd, N, Y, N, s);
+            } else {
+                if (!AF0) {
+                    AF0 = c->tmp_buf<cpx<T>>(SLOT_SRFT0, (size_t)N * Mf);
+                    AF1 = c->tmp_buf<cpx<T>>(SLOT_SRFT1, (size_t)N * Mf);
+                    launch_srft_rows<T>(N, N, Mf, Ops<T>::mat(c, 0), N, dv, twf, tws, AF0, N, s);
+                    launch_srft_rows<T>(N, N, Mf, Ops<T>::mat(c, 1), N, dv, twf, tws, AF1, N, s);
+                }
+                launch_srft_omega<T>(N, sq, srft_off, bb, dv, twf, tws, Om, N, s);
+                const SrftFirst<T> fs{{AF0, AF1}, sq, srft_off};
+                apply_R<T>(c, Om, N, Y, N, bb, Tt, W1, W2, Z, false, &fs);
+            }
             srft_off += bb;
         } else {
             randn<T>(N, bb, c->opt.seed, blk++, Om, N, s);    // real Gaussian block
@@ -959,10 +987,12 @@ cfie_status factor_impl(cfie_ctx *c) {
             }
         }
         colnorm2<T>(N, bb, Y, N, c->w_norm, s);
+        const double tau_b = tau / est_scale;
         if (replay) {
             if (bp.probe) {
                 // the planned sketch stopped here: the remainder must still be below tau
-                launch_replay_check(bb, c->w_norm, tau * tau, 1, nullptr, 0, 1, c->rec_flags, s);
+                launch_replay_check(bb, c->w_norm, tau_b * tau_b, 1, nullptr, 0, 1,
+                                    c->rec_flags, s);
                 break;
             }
         } else {
@@ -971,7 +1001,7 @@ cfie_status factor_impl(cfie_ctx *c) {
             c->sync();
             double mx = 0.0;
             for (int i = 0; i < bb; ++i) mx = std::max(mx, nrm[i]);
-            c->remainder_est = std::sqrt(mx);
+            c->remainder_est = std::sqrt(mx) * est_scale;
             if (ell == 0) y_first = c->remainder_est;
             if (c->remainder_est <= tau) {
                 bp.probe = true;
@@ -979,7 +1009,7 @@ cfie_status factor_impl(cfie_ctx *c) {
                 break;
             }
         }
-        int kept = orthonormalise<T>(c, Y, bb, tau, replay ? bp.kept : -1);
+        int kept = orthonormalise<T>(c, Y, bb, tau_b, replay ? bp.kept : -1);
         bp.kept = kept;
         if (c->rec_mode == 1) c->sched.push_back(bp);
         ++bi;
@@ -996,7 +1026,7 @@ cfie_status factor_impl(cfie_ctx *c) {
         const int p = c->opt.oversample;
         if (p > 0 && bb >= 2 * p && kept <= bb - p) break;
         if (!Rd && c->opt.remainder_form == CFIE_REMAINDER_AUTO && 2 * ell >= N && ell < cap) {
-            srft_release();
+            srft_release_factored();
             Rd = c->tmp_buf<cpx<T>>(SLOT_RD, (size_t)N * N);
             form_dense<T>(c, Rd, true);
             pending_dense = true;           // a replay forms it before the next block
@@ -2964,14 +2994,16 @@ cfie_status cfie_srft_rows(cfie_ctx *c, const void *A, int64_t lda, int64_t m, c
     if (!c) return CFIE_EINVAL;
     if (c->state < 1) return fail(c, CFIE_ESTATE, "nothing assembled yet");
     const int N = c->N;
-    if ((N & (N - 1)) != 0) return fail(c, CFIE_EINVAL, "N is not a power of two");
     if (!A || !d || !out) return fail(c, CFIE_EINVAL, "NULL pointer");
     if (m < 0 || lda < std::max<int64_t>(m, 1) || ldo < std::max<int64_t>(m, 1))
         return fail(c, CFIE_EINVAL, "m < 0 or a leading dimension below m");
     return guarded(c, [&]() -> cfie_status {
         HIPCHK(hipSetDevice(c->device));
-        launch_srft_rows<double>(m, N, (const zd *)A, lda, (const zd *)d,
-                                 (const zd *)c->fft.twN, (zd *)out, ldo, c->stream);
+        int Mf = 1;
+        while (Mf < N) Mf <<= 1;
+        launch_srft_rows<double>(m, N, Mf, (const zd *)A, lda, (const zd *)d,
+                                 (const zd *)c->fft.twM, c->fft.M / Mf, (zd *)out, ldo,
+                                 c->stream);
         c->check_launch();
         c->sync();
         return CFIE_OK;

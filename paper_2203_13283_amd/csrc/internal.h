@@ -197,11 +197,12 @@ void launch_padded_diagonal(const FFTPlan &p, const zd *eig_over_N, zd *work, zd
 
 // ------------------------------------------------------------------ SRFT test matrix -----
 // Subsampled randomized Fourier transform (Halko, Martinsson and Tropp, SIAM Review 2011,
-// Sec. 4.6): Omega = D F S with D = diag(d), |d_i| = 1 of uniform random phase, F the N-point
-// DFT matrix F_ij = e^{-2 pi i i j / N} (N a power of two) and S a random choice of columns.
-// A D F is formed once by radix-2^b decimation-in-frequency passes along the rows of A, which
-// leave column j of A D F at a digit-reversed position p; the sketch then takes the columns
-// at the positions p = perm(t), t = 0, 1, 2, ... of a seeded bijection of [0, N).
+// Sec. 4.6): Omega = (D F)[0:N, S] with D = diag(d), |d_i| = 1 of uniform random phase, F
+// the M-point DFT matrix F_ij = e^{-2 pi i i j / M} (M the smallest power of two >= N; its
+// first N rows when M > N) and S a random choice of columns.  A D F is formed once by
+// radix-2^b decimation-in-frequency passes along the rows of A (zero-padded to M columns),
+// which leave column j of A D F at a digit-reversed position p; the sketch then takes the
+// columns at the positions p = perm(t), t = 0, 1, 2, ... of a seeded bijection of [0, M).
 struct SrftPlan {
     int lgN = 0, npass = 0;
     int bits[8] = {};                // log2 of each pass's radix, first pass first
@@ -241,16 +242,17 @@ __host__ __device__ inline uint32_t srft_perm_apply(const SrftPerm &q, uint32_t 
     }
     return x;
 }
-// out = A D F (m x N, columns at the digit-reversed positions): the first pass reads A and d
-// and writes out, the others work in place on out.  tw: e^{-2 pi i j / N}, j < N.
+// out = A D F (m x M, columns at the digit-reversed positions; M a power of two >= N, the
+// columns N..M-1 of A taken as zero): the first pass reads A and d and writes out, the others
+// work in place on out.  tw: e^{-2 pi i j / (M tws)}, so that w_M^j = tw[j tws].
 template <typename T>
-void launch_srft_rows(int64_t m, int N, const cpx<T> *A, int64_t lda, const cpx<T> *d,
-                      const cpx<T> *tw, cpx<T> *out, int64_t ldo, hipStream_t s);
-// Om[:, t] = D F[:, j(perm(off + t))] for t < nb (N x nb): the test-matrix columns whose
-// products are the columns of A D F gathered by launch_srft_gather
+void launch_srft_rows(int64_t m, int N, int M, const cpx<T> *A, int64_t lda, const cpx<T> *d,
+                      const cpx<T> *tw, int tws, cpx<T> *out, int64_t ldo, hipStream_t s);
+// Om[:, t] = (D F)[0:N, j(perm(off + t))] for t < nb (N x nb, F of length M = 2^q.lgN): the
+// test-matrix columns whose products are the columns of A D F gathered by launch_srft_gather
 template <typename T>
 void launch_srft_omega(int N, const SrftPerm &q, int64_t off, int nb, const cpx<T> *d,
-                       const cpx<T> *tw, cpx<T> *Om, int64_t ldo, hipStream_t s);
+                       const cpx<T> *tw, int tws, cpx<T> *Om, int64_t ldo, hipStream_t s);
 // out[:, t] = AF[:, perm(off + t)] for t < nb (AF: m x N from launch_srft_rows)
 template <typename T>
 void launch_srft_gather(int64_t m, const SrftPerm &q, int64_t off, int nb, const cpx<T> *AF,

@@ -467,15 +467,17 @@ void launch_padded_diagonal(const FFTPlan &p, const zd *eig_over_N, zd *work, zd
 
 
 // ------------------------------------------------------------------ SRFT row transform ---
-// A D F for the sketch's structured test matrix (the SrftPlan passes): pass l of radix
-// R = 2^bits[l] splits sub-arrays of L columns (L = N for the first pass, then L / R for the
-// next) with stride S = L / R.  Butterfly group g (blockIdx.y, so uniform over the
-// workgroup) takes the columns c_b = B + a + S b, b < R (B = (g / S) L, a = g mod S), forms
-// the R-point DFT y_e = sum_b x_b w_R^{b e}, scales y_e by w_L^{a e} and writes it to column
-// B + a + S e: the same columns, so every pass after the first runs in place.  After all
-// passes column j of A D F sits at the position whose pass digits are those of j in reverse
-// order (srft_freq).  Lanes run along the rows: every load and store is a row segment of 64
-// consecutive entries (1 KiB in FP64), and the table reads are uniform over the workgroup.
+// A D F for the sketch's structured test matrix (the SrftPlan passes over the transform
+// length M, a power of two >= the N columns of A; columns N..M-1 of A count as zero): pass l
+// of radix R = 2^bits[l] splits sub-arrays of L columns (L = M for the first pass, then
+// L / R for the next) with stride S = L / R.  Butterfly group g (blockIdx.y, so uniform
+// over the workgroup) takes the columns c_b = B + a + S b, b < R (B = (g / S) L,
+// a = g mod S), forms the R-point DFT y_e = sum_b x_b w_R^{b e}, scales y_e by w_L^{a e} and
+// writes it to column B + a + S e: the same columns, so every pass after the first runs in
+// place.  After all passes column j of A D F sits at the position whose pass digits are
+// those of j in reverse order (srft_freq).  Lanes run along the rows: every load and store
+// is a row segment of 64 consecutive entries (1 KiB in FP64), and the table reads are
+// uniform over the workgroup.  tw holds e^{-2 pi i j / (M tws)}: w_M^j = tw[j tws].
 constexpr int bitrev_const(int q, int bits) {
     int r = 0;
     for (int i = 0; i < bits; ++i) r |= ((q >> i) & 1) << (bits - 1 - i);
@@ -484,11 +486,11 @@ constexpr int bitrev_const(int q, int bits) {
 constexpr int log2_const(int r) { return r <= 1 ? 0 : 1 + log2_const(r / 2); }
 
 template <typename T, int R, bool FIRST>
-__global__ __launch_bounds__(256) void k_srft_pass(int64_t m, int N, int L,
+__global__ __launch_bounds__(256) void k_srft_pass(int64_t m, int N, int M, int L,
                                                    const cpx<T> *__restrict__ A, int64_t lda,
                                                    const cpx<T> *__restrict__ d,
-                                                   const cpx<T> *__restrict__ tw, cpx<T> *out,
-                                                   int64_t ldo) {
+                                                   const cpx<T> *__restrict__ tw, int tws,
+                                                   cpx<T> *out, int64_t ldo) {
     constexpr int RB = log2_const(R);
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= m) return;
@@ -500,10 +502,13 @@ __global__ __launch_bounds__(256) void k_srft_pass(int64_t m, int N, int L,
 #pragma unroll
     for (int b = 0; b < R; ++b) {
         const int col = B + a + S * b;
-        if constexpr (FIRST) x[b] = A[r + (int64_t)col * lda] * d[col];
-        else x[b] = out[r + (int64_t)col * ldo];
+        if constexpr (FIRST)
+            x[b] = col < N ? A[r + (int64_t)col * lda] * d[col] : mk((T)0, (T)0);
+        else
+            x[b] = out[r + (int64_t)col * ldo];
     }
     // R-point DFT by radix-2 decimation in frequency in registers: x[q] ends as y_{rev(q)}
+    const int wst = (M / 2) * tws;                   // table step of w_2
 #pragma unroll
     for (int h = R / 2; h >= 1; h >>= 1) {
 #pragma unroll
@@ -515,13 +520,13 @@ __global__ __launch_bounds__(256) void k_srft_pass(int64_t m, int N, int L,
                 cpx<T> t = u - v;
                 if (k != 0) {
                     if (2 * k == h) t = mk(t.y, -t.x);               // w_{2h}^{h/2} = -i
-                    else t = t * tw[k * (N / (2 * h))];            // w_{2h}^k
+                    else t = t * tw[k * (wst / h)];                // w_{2h}^k
                 }
                 x[b0 + k + h] = t;
             }
         }
     }
-    const int tsc = N / L;
+    const int tsc = (M / L) * tws;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int e = bitrev_const(q, RB);
@@ -532,25 +537,26 @@ __global__ __launch_bounds__(256) void k_srft_pass(int64_t m, int N, int L,
 }
 
 template <typename T>
-void launch_srft_rows(int64_t m, int N, const cpx<T> *A, int64_t lda, const cpx<T> *d,
-                      const cpx<T> *tw, cpx<T> *out, int64_t ldo, hipStream_t s) {
+void launch_srft_rows(int64_t m, int N, int M, const cpx<T> *A, int64_t lda, const cpx<T> *d,
+                      const cpx<T> *tw, int tws, cpx<T> *out, int64_t ldo, hipStream_t s) {
     if (m <= 0) return;
-    int lgN = 0;
-    while ((1 << lgN) < N) ++lgN;
-    if ((1 << lgN) != N) throw std::invalid_argument("SRFT length must be a power of two");
-    const SrftPlan p = srft_plan(lgN);
-    int L = N;
+    int lgM = 0;
+    while ((1 << lgM) < M) ++lgM;
+    if ((1 << lgM) != M || N > M || N < 1 || tws < 1)
+        throw std::invalid_argument("SRFT length must be a power of two >= N");
+    const SrftPlan p = srft_plan(lgM);
+    int L = M;
     for (int l = 0; l < p.npass; ++l) {
         const int R = 1 << p.bits[l];
-        const dim3 grid((unsigned)((m + 255) / 256), (unsigned)(N / R));
-#define CFIE_SRFT_CASE(RR)                                                                   \
-    case RR:                                                                                 \
-        if (l == 0)                                                                          \
-            hipLaunchKernelGGL((k_srft_pass<T, RR, true>), grid, dim3(256), 0, s, m, N, L, A, \
-                               lda, d, tw, out, ldo);                                        \
-        else                                                                                 \
-            hipLaunchKernelGGL((k_srft_pass<T, RR, false>), grid, dim3(256), 0, s, m, N, L,  \
-                               (const cpx<T> *)nullptr, (int64_t)0, d, tw, out, ldo);        \
+        const dim3 grid((unsigned)((m + 255) / 256), (unsigned)(M / R));
+#define CFIE_SRFT_CASE(RR)                                                                    \
+    case RR:                                                                                  \
+        if (l == 0)                                                                           \
+            hipLaunchKernelGGL((k_srft_pass<T, RR, true>), grid, dim3(256), 0, s, m, N, M, L,  \
+                               A, lda, d, tw, tws, out, ldo);                                 \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_srft_pass<T, RR, false>), grid, dim3(256), 0, s, m, N, M, L, \
+                               (const cpx<T> *)nullptr, (int64_t)0, d, tw, tws, out, ldo);    \
         break;
         switch (R) {
             CFIE_SRFT_CASE(2)
@@ -564,38 +570,39 @@ void launch_srft_rows(int64_t m, int N, const cpx<T> *A, int64_t lda, const cpx<
         L /= R;
     }
 }
-template void launch_srft_rows<double>(int64_t, int, const zd *, int64_t, const zd *,
-                                       const zd *, zd *, int64_t, hipStream_t);
-template void launch_srft_rows<float>(int64_t, int, const zf *, int64_t, const zf *,
-                                      const zf *, zf *, int64_t, hipStream_t);
+template void launch_srft_rows<double>(int64_t, int, int, const zd *, int64_t, const zd *,
+                                       const zd *, int, zd *, int64_t, hipStream_t);
+template void launch_srft_rows<float>(int64_t, int, int, const zf *, int64_t, const zf *,
+                                      const zf *, int, zf *, int64_t, hipStream_t);
 
-// Om[i, t] = d_i w_N^{i j}, j the frequency at position perm(off + t)
+// Om[i, t] = d_i w_M^{i j} (i < N), j the frequency at position perm(off + t)
 template <typename T>
-__global__ void k_srft_omega(int N, SrftPlan p, SrftPerm q, int64_t off, int nb,
+__global__ void k_srft_omega(int N, int M, SrftPlan p, SrftPerm q, int64_t off, int nb,
                              const cpx<T> *__restrict__ d, const cpx<T> *__restrict__ tw,
-                             cpx<T> *Om, int64_t ldo) {
+                             int tws, cpx<T> *Om, int64_t ldo) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= (int64_t)N * nb) return;
     const int i = (int)(tid % N), t = (int)(tid / N);
     const int j = srft_freq(p, (int)srft_perm_apply(q, (uint32_t)(off + t)));
-    const int idx = (int)(((int64_t)i * j) & (N - 1));
+    const int64_t idx = (((int64_t)i * j) & (M - 1)) * tws;
     Om[i + (int64_t)t * ldo] = d[i] * tw[idx];
 }
 
 template <typename T>
 void launch_srft_omega(int N, const SrftPerm &q, int64_t off, int nb, const cpx<T> *d,
-                       const cpx<T> *tw, cpx<T> *Om, int64_t ldo, hipStream_t s) {
+                       const cpx<T> *tw, int tws, cpx<T> *Om, int64_t ldo, hipStream_t s) {
     const int64_t t = (int64_t)N * nb;
     if (t <= 0) return;
-    if (off < 0 || off + nb > N) throw std::invalid_argument("SRFT columns exhausted");
+    const int M = 1 << q.lgN;
+    if (N > M || off < 0 || off + nb > M) throw std::invalid_argument("SRFT columns exhausted");
     const SrftPlan p = srft_plan(q.lgN);
     hipLaunchKernelGGL(k_srft_omega<T>, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, N,
-                       p, q, off, nb, d, tw, Om, ldo);
+                       M, p, q, off, nb, d, tw, tws, Om, ldo);
 }
 template void launch_srft_omega<double>(int, const SrftPerm &, int64_t, int, const zd *,
-                                        const zd *, zd *, int64_t, hipStream_t);
+                                        const zd *, int, zd *, int64_t, hipStream_t);
 template void launch_srft_omega<float>(int, const SrftPerm &, int64_t, int, const zf *,
-                                       const zf *, zf *, int64_t, hipStream_t);
+                                       const zf *, int, zf *, int64_t, hipStream_t);
 
 template <typename T>
 __global__ void k_srft_gather(int64_t m, SrftPerm q, int64_t off, int nb,

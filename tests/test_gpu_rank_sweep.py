@@ -10,12 +10,12 @@ and that the inner rank grows no faster than k^(1/3).  Asserted here:
   LU is below epsilon and falls monotonically with k;
 * rank: the randomized range finder keeps a direction while a test column of the
   remaining remainder has norm above tau = epsilon ||C_c||_2 -- a Gaussian column, or (the
-  default) a column of the SRFT D F, whose entries are independent of unit modulus -- and
-  such a column's squared norm has the squared Frobenius norm of the remaining singular
-  values as its mean.  So its rank lies between the exact rank r*(epsilon) =
+  default) a column of the SRFT D F, whose entries are independent of unit modulus, scaled
+  for the columns already drawn -- and such a column's squared norm has the squared
+  Frobenius norm of the remaining singular values as its mean.  So its rank lies between the exact rank r*(epsilon) =
   #{sigma_i > tau} and the Frobenius rank r_F(epsilon) = min{r : (sum_{i>r} sigma_i^2)^(1/2)
   <= tau}, plus what a randomized range finder needs beyond r_F to capture those
-  directions: r* <= r <= 1.15 r_F + 16 (measured r / r_F = 1.16, 1.13, 1.12, 1.11 with the
+  directions: r* <= r <= 1.15 r_F + 16 (measured r / r_F = 1.16, 1.12, 1.11, 1.10 with the
   SRFT blocks; 1.14, 1.14, 1.12, 1.10 with Gaussian ones);
 * the rank fraction r*/N of the oracle does not grow with k.
 The k^(1/3) bound on the rank is not reproduced with the readings of the paper used here

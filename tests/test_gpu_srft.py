@@ -1,22 +1,25 @@
 """The SRFT test matrix of the sketch (GPU, through the C ABI).
 
 The range finder's blocks after the first may take their test columns from a subsampled
-randomized Fourier transform Omega = D F S (cfie_options.test_matrix, Halko, Martinsson and
-Tropp 2011, Sec. 4.6); the products of D^k and N^k with those columns are then columns of
-D^k D F and N^k D F, formed once by radix passes along the rows (cfie_srft_rows).
+randomized Fourier transform Omega = (D F)[0:N, S] (cfie_options.test_matrix, Halko,
+Martinsson and Tropp 2011, Sec. 4.6; F of length M, the smallest power of two >= N); the
+products of D^k and N^k (or of the dense C - C_c) with those columns are then columns of
+D^k D F and N^k D F (or (C - C_c) D F), formed once by radix passes along the rows
+(cfie_srft_rows).
 
-* cfie_srft_rows against numpy's FFT of A diag(d) (a library transform, not the oracle: the
-  oracle has no sketch) at N = 8, 1024 and 2048 -- one, two and three radix passes -- with
-  300 rows (a ragged last workgroup of rows); columns mapped by srft_frequency;
+* cfie_srft_rows against numpy's FFT of A diag(d), zero-padded to M columns (a library
+  transform, not the oracle: the oracle has no sketch) at N = 8, 1000, 1024 and 2048 -- one,
+  two and three radix passes, and a padded length -- with 300 rows (a ragged last workgroup
+  of rows); columns mapped by srft_frequency;
 * the factorisation with SRFT blocks against the one with Gaussian blocks and against the
   oracle's dense-LU solution at N = 1024 (several blocks of 64): FP64 at epsilon = 1e-10
   within the 1e-10 bar, at epsilon = 1e-5 within 3 x the error the Gaussian sketch reaches
   and within epsilon (both about 1.1e-6 here), mixed precision after refinement within
-  1e-6; ranks within 10 %;
-* all N Fourier columns drawn (N = 256, blocks of 64, the oversampling stop off): the sketch
+  1e-6; ranks within 10 %; the same with C - C_c formed densely, and at N = 1000 (the
+  padded transform);
+* all M Fourier columns drawn (N = 256, blocks of 64, the oversampling stop off): the sketch
   falls back to Gaussian blocks and still meets the 1e-10 bar;
-* N not a power of two: the option changes nothing (bitwise the same solution), and
-  cfie_srft_rows rejects the context.
+* cfie_srft_rows before cfie_assemble is ESTATE.
 """
 import math
 
@@ -41,21 +44,23 @@ def _solver_at(N, **kw):
     return s, zh, k
 
 
-@pytest.mark.parametrize("N", [8, 1024, 2048])
+@pytest.mark.parametrize("N", [8, 1000, 1024, 2048])
 def test_srft_rows_against_numpy_fft(N):
     s, _, _ = _solver_at(N)
     rng = np.random.default_rng(N)
     m = 300
+    M = 1 << (N - 1).bit_length()
     A = rng.standard_normal((m, N)) + 1j * rng.standard_normal((m, N))
     d = np.exp(2j * np.pi * rng.random(N))
     got = s.srft_rows(torch.as_tensor(A, device="cuda"),
                       torch.as_tensor(d, device="cuda")).cpu().numpy()
-    ref = np.fft.fft(A * d[None, :], axis=1)
-    js = np.array([P.srft_frequency(N, p) for p in range(N)])
-    assert sorted(js.tolist()) == list(range(N))
+    assert got.shape == (m, M)
+    ref = np.fft.fft(A * d[None, :], n=M, axis=1)
+    js = np.array([P.srft_frequency(M, p) for p in range(M)])
+    assert sorted(js.tolist()) == list(range(M))
     err = np.abs(got - ref[:, js]).max() / np.abs(ref).max()
-    print(f"N={N}: max error {err:.2e}")
-    assert err <= 5e-15 * max(1.0, math.log2(N))
+    print(f"N={N} (M={M}): max error {err:.2e}")
+    assert err <= 5e-15 * max(1.0, math.log2(M))
 
 
 def _factor_solve(N, zh, k, ang, **kw):
@@ -71,7 +76,10 @@ def _factor_solve(N, zh, k, ang, **kw):
 
 @pytest.fixture(scope="module")
 def ref1024():
-    N = 1024
+    return _reference(1024)
+
+
+def _reference(N):
     zh = W.ellipse_coeffs(1.0, 0.6)
     L = S.Contour(zh).L
     k = 2 * math.pi * N / (10 * L)
@@ -80,15 +88,26 @@ def ref1024():
     return N, zh, k, ang, prob.solve(prob.rhs(ang))
 
 
+@pytest.fixture(scope="module")
+def ref1000():
+    return _reference(1000)
+
+
+def _srft_vs_gaussian(ref, eps, **kw):
+    N, zh, k, ang, xr = ref
+    Xs, rs = _factor_solve(N, zh, k, ang, compress_tol=eps, block=64,
+                           test_matrix=P.SKETCH_SRFT, **kw)
+    Xg, rg = _factor_solve(N, zh, k, ang, compress_tol=eps, block=64,
+                           test_matrix=P.SKETCH_GAUSSIAN, **kw)
+    es, eg = S.rel_err(Xs, xr), S.rel_err(Xg, xr)
+    print(f"N={N} eps={eps:g} {kw}: rank SRFT {rs} Gaussian {rg}; "
+          f"rel.err SRFT {es:.2e} Gaussian {eg:.2e}")
+    return rs, rg, es, eg
+
+
 @pytest.mark.parametrize("eps", [1e-10, 1e-5])
 def test_factor_srft_against_gaussian_and_oracle(ref1024, eps):
-    N, zh, k, ang, xr = ref1024
-    Xs, rs = _factor_solve(N, zh, k, ang, compress_tol=eps, block=64,
-                           test_matrix=P.SKETCH_SRFT)
-    Xg, rg = _factor_solve(N, zh, k, ang, compress_tol=eps, block=64,
-                           test_matrix=P.SKETCH_GAUSSIAN)
-    es, eg = S.rel_err(Xs, xr), S.rel_err(Xg, xr)
-    print(f"eps={eps:g}: rank SRFT {rs} Gaussian {rg}; rel.err SRFT {es:.2e} Gaussian {eg:.2e}")
+    rs, rg, es, eg = _srft_vs_gaussian(ref1024, eps)
     assert abs(rs - rg) <= 0.1 * rg + 8
     if eps <= 1e-10:
         assert es <= 1e-10 and eg <= 1e-10
@@ -117,20 +136,26 @@ def test_srft_columns_exhausted_falls_back_to_gaussian():
     assert err <= 1e-10
 
 
-def test_non_power_of_two_is_unchanged():
-    N = 1000
-    zh = W.ellipse_coeffs(1.0, 0.6)
-    L = S.Contour(zh).L
-    k = 2 * math.pi * N / (10 * L)
-    ang = W.plane_wave_angles(4)
-    Xs, rs = _factor_solve(N, zh, k, ang, compress_tol=1e-8, block=64,
-                           test_matrix=P.SKETCH_SRFT)
-    Xg, rg = _factor_solve(N, zh, k, ang, compress_tol=1e-8, block=64,
-                           test_matrix=P.SKETCH_GAUSSIAN)
-    assert rs == rg and np.array_equal(Xs, Xg)
-    s, _, _ = _solver_at(N)
-    A = torch.zeros((4, N), dtype=torch.complex128, device="cuda")
-    d = torch.ones(N, dtype=torch.complex128, device="cuda")
-    with pytest.raises(P.CfieError) as ei:
-        s.srft_rows(A, d)
-    assert ei.value.status == 1
+def test_factor_srft_dense_remainder(ref1024):
+    rs, rg, es, eg = _srft_vs_gaussian(ref1024, 1e-10, remainder_form=P.REMAINDER_DENSE)
+    assert abs(rs - rg) <= 0.1 * rg + 8
+    assert es <= 1e-10 and eg <= 1e-10
+
+
+@pytest.mark.parametrize("eps", [1e-10, 1e-5])
+def test_factor_srft_padded_length(ref1000, eps):
+    rs, rg, es, eg = _srft_vs_gaussian(ref1000, eps)
+    assert abs(rs - rg) <= 0.1 * rg + 8
+    if eps <= 1e-10:
+        assert es <= 1e-10 and eg <= 1e-10
+    else:
+        assert es <= max(3 * eg, 1e-9) and es <= eps
+
+
+def test_srft_rows_before_assemble():
+    import ctypes
+    from paper_2203_13283_amd import _lib
+    s = P.Solver()
+    st = _lib.load().cfie_srft_rows(s._h, ctypes.c_void_p(8), 1, 1, ctypes.c_void_p(8),
+                                    ctypes.c_void_p(8), 1)
+    assert st == 4
