@@ -266,15 +266,16 @@ def batch_main(a):
     prec = P.CFIE_FP64 if a.precision == "fp64" else P.CFIE_MIXED
     eps = a.eps if a.eps is not None else (1e-6 if prec == P.CFIE_FP64 else 1e-3)
     nrhs = sum(p["angles"].size for p in probs)
+    sk = P.SKETCH_SRFT if a.sketch == "srft" else P.SKETCH_GAUSSIAN
     for _ in range(a.warmup):
-        P.solve_batch(probs[:4], precision=prec, compress_tol=eps, block=128)
+        P.solve_batch(probs[:4], precision=prec, compress_tol=eps, block=128, test_matrix=sk)
     torch.cuda.synchronize()
     times = []
     for _ in range(a.steps):
         t0 = time.perf_counter()
         sols, res = P.solve_batch(probs, precision=prec, compress_tol=eps, block=128,
                                   refine_tol=1e-8, n_streams=4, grouped=a.grouped,
-                                  sweeps=2)
+                                  sweeps=2, test_matrix=sk)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     med = sorted(times)[len(times) // 2]
@@ -304,7 +305,7 @@ def batch_main(a):
                    "problems": len(probs), "N_min": min(Ns), "N_max": max(Ns),
                    "nrhs_total": nrhs, "compress_tol": eps, "streams": 4,
                    "precision": a.precision, "gemm_autotune": bool(a.autotune),
-                   "grouped_solve": bool(a.grouped)},
+                   "grouped_solve": bool(a.grouped), "sketch": a.sketch},
         "problems_per_s": len(probs) / med,
         "rel_residual_sampled": worst,
         "max_rank": max(r["rank"] for r in res),

@@ -138,8 +138,13 @@ struct cfie_ctx {
     cfie_options opt;
     int device = 0;
     hipStream_t stream = nullptr;
-    // second stream for the equivalent circle's first row (assembled beside the contour's)
+    // second stream for the equivalent circle's first row (assembled beside the contour's);
+    // not used by the contexts of a batch (single_stream), whose problems already run side
+    // by side on the batch's streams: with four hardware queues per process, a context's own
+    // second stream shares a queue with another problem's stream, and its wait for the
+    // fork event then holds that problem's work back
     hipStream_t aux = nullptr;
+    bool single_stream = false;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Profiler prof;
     int64_t prof_n[PROF_KINDS] = {0, 0, 0, 0, 0};
@@ -312,11 +317,12 @@ struct cfie_ctx {
         keep_bytes[slot] = need;
         return (T *)p;
     }
-    // release a temporary from tmp_buf: freed (after the stream drains) in a plain context,
-    // kept otherwise
+    // release a temporary from tmp_buf: a stream-ordered free in a plain context (every
+    // temporary is used on the context's stream, or on the second stream joined back to it
+    // before the free), kept otherwise.  No host wait: on a device whose hardware queues are
+    // shared by several streams, it would also wait for the other streams' queued work.
     void tmp_free(void *p) {
         if (rec_mode != 0 || !p) return;
-        sync();
         dfree(p);
     }
     // kept temporaries released (a new problem on a planned context)
@@ -1412,34 +1418,38 @@ void assemble_kernels(cfie_ctx *c) {
     zd *near_ws = c->tmp_buf<zd>(SLOT_NEAR_WS, near_ws_elems(p));
     // if anything below throws, the circle's kernels finish before its buffers can be
     // freed and reused in the context stream's order
+    const bool two = !c->single_stream;
+    hipStream_t as = two ? c->aux : s;
     struct AuxJoin {
         hipStream_t aux;
         bool joined = false;
         ~AuxJoin() {
-            if (!joined) (void)hipStreamSynchronize(aux);
+            if (!joined && aux) (void)hipStreamSynchronize(aux);
         }
-    } aux_join{c->aux};
-    HIPCHK(hipEventRecord(c->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+    } aux_join{two ? c->aux : nullptr};
+    if (two) {
+        HIPCHK(hipEventRecord(c->ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+    }
     pc.ws = band_ws_c;
-    launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), c->aux);
+    launch_assemble_far(pc, c->cf, c->xf.data(), c->wf.data(), as);
     pc.ws = near_ws_c;
-    launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, c->aux);
+    launch_assemble_near(pc, c->cn, c->xn.data(), c->wn.data(), c->d_mom, as);
     // rows of symmetric circulants equal their first columns: their DFTs are the
     // eigenvalues of the four circulants
-    launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, c->aux);
+    launch_dft_direct_tw(N, c->crow, N, c->mu, N, 4, (const zd *)c->fft.twN, as);
     // the contour's near band (entries |i - j| <= nb + 1) follows on the second stream: the
     // far passes write only the other entries, so the two run side by side (the near
     // kernels' latency-bound waves fill compute units that the far passes leave idle)
     AsmParams pn = p;
     pn.ws = near_ws;
-    launch_assemble_near(pn, c->pn, c->xn.data(), c->wn.data(), c->d_mom, c->aux);
-    HIPCHK(hipEventRecord(c->ev_join, c->aux));
+    launch_assemble_near(pn, c->pn, c->xn.data(), c->wn.data(), c->d_mom, as);
+    if (two) HIPCHK(hipEventRecord(c->ev_join, c->aux));
     // the contour's far entries
     p.ws = band_ws;
     launch_assemble_far(p, c->pf, c->xf.data(), c->wf.data(), s);
     c->check_launch();
-    HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
+    if (two) HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
     aux_join.joined = true;
     c->tmp_free(band_ws);
     c->tmp_free(near_ws);
@@ -1508,6 +1518,49 @@ void *noalloc_scratch_address(int device) {
     g_noalloc_ptr[device] = p;
     return p;
 }
+
+// Contexts hold their device memory in HIP's default stream-ordered pool.  By default the
+// pool returns memory it holds unused to the system at every synchronisation, so that each
+// factorisation maps its temporaries (the SRFT transforms, the dense remainder) anew, and
+// contexts on concurrent streams then wait for one another's mappings.  While a context lives
+// on a device, the pool keeps freed memory for reuse (release threshold raised); when the
+// last one is destroyed the threshold goes back to 0 and the pool is trimmed.
+std::mutex g_pool_mu;
+std::map<int, int> g_pool_users;
+void pool_retain(int device) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (g_pool_users[device]++ > 0) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    uint64_t thr = UINT64_MAX;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr) != hipSuccess)
+        (void)hipGetLastError();
+}
+void pool_release(int device) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    auto it = g_pool_users.find(device);
+    if (it == g_pool_users.end() || --it->second > 0) return;
+    g_pool_users.erase(it);
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    uint64_t thr = 0;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr) != hipSuccess ||
+        hipMemPoolTrimTo(pool, 0) != hipSuccess)
+        (void)hipGetLastError();
+}
+
+// keeps the pool's memory for the duration of a call that creates and destroys contexts
+struct PoolHold {
+    int device;
+    explicit PoolHold(int d) : device(d) { pool_retain(d); }
+    ~PoolHold() { pool_release(device); }
+};
 
 // Layout of the allocation-free FP64 solve's scratch for blocks of m columns and a last
 // block of `tail` columns (0: none): Z (rank x m), the packed copy of the block when X is
@@ -1989,6 +2042,7 @@ cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream, c
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->noalloc_ws = noalloc_scratch_address(device);
+    pool_retain(device);
     *out = c;
     return CFIE_OK;
 }
@@ -1999,6 +2053,7 @@ cfie_status cfie_solve_batch(const cfie_options *opt, int device, int n_streams,
         return CFIE_EINVAL;
     if (n_items == 0) return CFIE_OK;
     if (hipSetDevice(device) != hipSuccess) return CFIE_EHIP;
+    const PoolHold pool_hold(device);
     // largest problems first (work ~ N^2 (assembly, sketch) + N nrhs)
     std::vector<int64_t> order((size_t)n_items);
     for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
@@ -2034,6 +2089,7 @@ cfie_status cfie_solve_batch(const cfie_options *opt, int device, int n_streams,
             cfie_ctx *c = nullptr;
             cfie_status st = cfie_create(opt, device, streams[(size_t)t], &c);
             if (st == CFIE_OK) {
+                c->single_stream = true;
                 st = cfie_assemble(c, &it.contour, it.k);
                 if (st == CFIE_OK || st >= 100) {
                     cfie_status sf = cfie_factor(c);
@@ -2129,6 +2185,7 @@ cfie_status cfie_solve_batch_grouped(const cfie_options *opt, int device, int n_
     for (int64_t i = 0; i < n_items; ++i)
         if (items[i].nrhs > kGroupMaxRhs) return CFIE_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return CFIE_EHIP;
+    const PoolHold pool_hold(device);
     std::vector<int64_t> order((size_t)n_items);
     for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
     auto work = [&](int64_t i) {
@@ -2166,6 +2223,7 @@ cfie_status cfie_solve_batch_grouped(const cfie_options *opt, int device, int n_
             cfie_ctx *c = nullptr;
             cfie_status st = cfie_create(opt, device, streams[(size_t)t], &c);
             if (st == CFIE_OK) {
+                c->single_stream = true;
                 st = cfie_assemble(c, &it.contour, it.k);
                 if (st == CFIE_OK || st >= 100) {
                     cfie_status sf = cfie_factor(c);
@@ -2461,8 +2519,11 @@ void cfie_destroy(cfie_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->stream) splitk_release(c->device, c->stream);
+    // a batch's contexts share its streams, whose workspaces the batch releases at its end
+    if (c->stream && !c->single_stream) splitk_release(c->device, c->stream);
+    const int dev = c->device;
     delete c;
+    pool_release(dev);
 }
 
 const char *cfie_last_error(const cfie_ctx *c) {
@@ -2556,7 +2617,7 @@ cfie_status cfie_assemble(cfie_ctx *c, const cfie_contour *contour, double k) {
         c->scal = c->alloc_n<double>(4);
         if (c->opt.precision == CFIE_MIXED)
             for (int i = 0; i < 4; ++i) c->mat32[i] = c->alloc_n<zf>(nn);
-        if (!c->aux) {
+        if (!c->aux && !c->single_stream) {
             HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));

@@ -619,7 +619,10 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_skinny(int64_t m, int n, int64
 }
 
 // grow-only device workspaces for split-K partial products, one per (device, stream) so that
-// contexts on different streams can run from different host threads
+// contexts on different streams can run from different host threads.  Stream-ordered
+// allocation and release: hipMalloc / hipFree may wait for the whole device, which on a
+// device shared by several streams (batched problems) stalls one stream behind the others'
+// queued work.
 namespace {
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_ws;
@@ -636,12 +639,11 @@ void *splitk_ws(size_t need, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_ws_mu);
     auto &e = g_ws[{dev, s}];
     if (e.second < need) {
-        (void)hipStreamSynchronize(s);
-        if (e.first) (void)hipFree(e.first);
+        if (e.first) (void)hipFreeAsync(e.first, s);
         e.first = nullptr;
         e.second = 0;
         size_t nb = need + need / 2;
-        if (hipMalloc(&e.first, nb) != hipSuccess) {
+        if (hipMallocAsync(&e.first, nb, s) != hipSuccess) {
             (void)hipGetLastError();
             e.first = nullptr;
             return nullptr;
@@ -656,10 +658,7 @@ void splitk_release(int device, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_ws_mu);
     auto it = g_ws.find({device, s});
     if (it == g_ws.end()) return;
-    if (it->second.first) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(it->second.first);
-    }
+    if (it->second.first) (void)hipFreeAsync(it->second.first, s);
     g_ws.erase(it);
 }
 
