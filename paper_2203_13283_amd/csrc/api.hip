@@ -532,12 +532,12 @@ template <typename T> cpx<T> cz(double a, double b = 0.0) { return mk((T)a, (T)b
 // of length M through a grow-only workspace
 template <typename T>
 void circ_apply(cfie_ctx *c, const cpx<T> *d, cpx<T> *X, int64_t ldx, int64_t m,
-                cpx<T> *ws = nullptr) {
+                cpx<T> *ws = nullptr, const cpx<T> *src = nullptr, int64_t lds = 0) {
     if (c->fft.M == c->N) {
-        launch_circ_apply<T>(c->fft, d, X, ldx, m, c->stream);
+        launch_circ_apply<T>(c->fft, d, X, ldx, m, c->stream, src, lds);
     } else {
         cpx<T> *P = ws ? ws : c->scratch<cpx<T>>(3, (size_t)c->fft.M * (size_t)m);
-        launch_circ_apply_padded<T>(c->fft, d, X, ldx, m, P, c->stream);
+        launch_circ_apply_padded<T>(c->fft, d, X, ldx, m, P, c->stream, src, lds);
     }
 }
 
@@ -621,8 +621,7 @@ void apply_R(cfie_ctx *c, const cpx<T> *X, int64_t ldx, cpx<T> *Y, int64_t ldy, 
              const SrftFirst<T> *fs = nullptr) {
     const int N = c->N;
     apply_C<T>(c, X, ldx, Y, ldy, m, Tt, W1, W2, x_real, fs);
-    axpby<T>(N, m, cz<T>(1), X, ldx, cz<T>(0), Z, N, c->stream);
-    circ_apply<T>(c, Ops<T>::dC(c), Z, N, m);
+    circ_apply<T>(c, Ops<T>::dC(c), Z, N, m, nullptr, X, ldx);
     axpby<T>(N, m, cz<T>(-1), Z, N, cz<T>(1), Y, ldy, c->stream);
     c->check_launch();
 }
@@ -1183,10 +1182,11 @@ cfie_status factor_impl(cfie_ctx *c) {
 // X <- C^{-1} X in precision T (X is N x m in T, ld N) by eq. (9):
 // X = C_c^{-1} X - U~ (K^{-1} V^T) C_c^{-1} X, with U~ = C_c^{-1} U; Z: rank x m scratch
 template <typename T>
-void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, cpx<T> *Z, cpx<T> *ws = nullptr) {
+void woodbury(cfie_ctx *c, cpx<T> *X, int64_t m, cpx<T> *Z, cpx<T> *ws = nullptr,
+              const cpx<T> *src = nullptr, int64_t lds = 0) {
     const int N = c->N;
     hipStream_t s = c->stream;
-    circ_apply<T>(c, Ops<T>::dCinv(c), X, N, m, ws);
+    circ_apply<T>(c, Ops<T>::dCinv(c), X, N, m, ws, src, lds);
     const int r = c->rank;
     if (r == 0) return;
     const cpx<T> *Wf = (const cpx<T> *)c->Wf, *Ut = (const cpx<T> *)c->Ut;
@@ -1371,9 +1371,11 @@ cfie_status solve_fp64(cfie_ctx *c, const zd *B, int64_t ldb, zd *X, int64_t ldx
     for (int64_t j = 0; j < nrhs; j += chunk) {
         int64_t m = std::min(chunk, nrhs - j);
         zd *Xj = direct ? X + j * ldx : work;
-        if (!(direct && B == X))
-            axpby<double>(N, m, cz<double>(1), B + j * ldb, ldb, cz<double>(0), Xj, N, s);
-        woodbury<double>(c, Xj, m, Zd);
+        // X = C_c^-1 B reads B directly (in place when B is X)
+        if (direct && B == X)
+            woodbury<double>(c, Xj, m, Zd);
+        else
+            woodbury<double>(c, Xj, m, Zd, nullptr, B + j * ldb, ldb);
         if (!direct) axpby<double>(N, m, cz<double>(1), work, N, cz<double>(0), X + j * ldx, ldx, s);
     }
     c->sync();

@@ -180,15 +180,18 @@ struct FFTPlan {
     double *twN = nullptr;           // e^{-2 pi i j / N},  j < N    (aliases twM when M == N)
 };
 // y = IFFT(d .* FFT(x)) column by column at the transform length M (d in the transposed
-// layout of length M, 1/M folded in).
+// layout of length M, 1/M folded in), written to x; the input is src (ld lds) when src is
+// given, else x itself.
 template <typename T>
 void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx,
-                       int64_t nb, hipStream_t s);
-// the same for M > N: x (N x nb, ld ldx) zero-padded into P (M x nb), transformed, and the
-// first N rows copied back
+                       int64_t nb, hipStream_t s, const cpx<T> *src = nullptr,
+                       int64_t lds = 0);
+// the same for M > N: the input (N x nb) zero-padded into P (M x nb), transformed, and the
+// first N rows copied to x (ld ldx)
 template <typename T>
 void launch_circ_apply_padded(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx,
-                              int64_t nb, cpx<T> *P, hipStream_t s);
+                              int64_t nb, cpx<T> *P, hipStream_t s, const cpx<T> *src = nullptr,
+                              int64_t lds = 0);
 // diagonal of length M in the transposed layout from the natural-order eigenvalues d_m / N
 // (m < N) of a circulant of length N: its first column by an inverse DFT, wrapped to length
 // M, transformed and scaled by 1/M (direct DFTs; once per assembly)

@@ -260,10 +260,11 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 3 : 4) void k_fft_mid4096(
 
 // step A (forward or inverse) for one (n1, column) per thread; N1, N2 powers of two.
 // N2 is a template parameter so the per-thread vectors stay in registers.
+// The input is read from src (leading dimension lds), which may be x itself.
 template <typename T, int N2>
 __global__ __launch_bounds__(256) void k_fft_stepA(int N1, const cpx<T> *__restrict__ twN,
-                                                   cpx<T> *x, int64_t ldx, int64_t ncol,
-                                                   bool inverse) {
+                                                   const cpx<T> *src, int64_t lds, cpx<T> *x,
+                                                   int64_t ldx, int64_t ncol, bool inverse) {
     int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= (int64_t)N1 * ncol) return;
     const int lg1 = ilog2(N1);
@@ -271,9 +272,10 @@ __global__ __launch_bounds__(256) void k_fft_stepA(int N1, const cpx<T> *__restr
     const int n1 = (int)(tid & (N1 - 1));
     const int64_t c = tid >> lg1;
     cpx<T> *col = x + c * ldx;
+    const cpx<T> *scol = src + c * lds;
     cpx<T> v[N2], o[N2];
 #pragma unroll
-    for (int a = 0; a < N2; ++a) v[a] = col[n1 + (int64_t)N1 * a];
+    for (int a = 0; a < N2; ++a) v[a] = scol[n1 + (int64_t)N1 * a];
     if (!inverse) {
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
@@ -299,17 +301,28 @@ __global__ __launch_bounds__(256) void k_fft_stepA(int N1, const cpx<T> *__restr
 }
 
 template <typename T>
-void launch_stepA(const FFTPlan &p, const cpx<T> *twN, cpx<T> *x, int64_t ldx, int64_t nb,
-                  bool inverse, hipStream_t s) {
+void launch_stepA(const FFTPlan &p, const cpx<T> *twN, const cpx<T> *src, int64_t lds,
+                  cpx<T> *x, int64_t ldx, int64_t nb, bool inverse, hipStream_t s) {
     const int bs = 256;
     int64_t n = (int64_t)p.N1 * nb;
     dim3 g((unsigned)((n + bs - 1) / bs));
     switch (p.N2) {
-    case 2: hipLaunchKernelGGL((k_fft_stepA<T, 2>), g, dim3(bs), 0, s, p.N1, twN, x, ldx, nb, inverse); break;
-    case 4: hipLaunchKernelGGL((k_fft_stepA<T, 4>), g, dim3(bs), 0, s, p.N1, twN, x, ldx, nb, inverse); break;
-    case 8: hipLaunchKernelGGL((k_fft_stepA<T, 8>), g, dim3(bs), 0, s, p.N1, twN, x, ldx, nb, inverse); break;
-    default: hipLaunchKernelGGL((k_fft_stepA<T, 16>), g, dim3(bs), 0, s, p.N1, twN, x, ldx, nb, inverse); break;
+    case 2: hipLaunchKernelGGL((k_fft_stepA<T, 2>), g, dim3(bs), 0, s, p.N1, twN, src, lds, x, ldx, nb, inverse); break;
+    case 4: hipLaunchKernelGGL((k_fft_stepA<T, 4>), g, dim3(bs), 0, s, p.N1, twN, src, lds, x, ldx, nb, inverse); break;
+    case 8: hipLaunchKernelGGL((k_fft_stepA<T, 8>), g, dim3(bs), 0, s, p.N1, twN, src, lds, x, ldx, nb, inverse); break;
+    default: hipLaunchKernelGGL((k_fft_stepA<T, 16>), g, dim3(bs), 0, s, p.N1, twN, src, lds, x, ldx, nb, inverse); break;
     }
+}
+
+// x[:, j] = src[:, j] for the n x nb block (the input copy of a circulant product whose
+// first pass works in place)
+template <typename T>
+__global__ void k_copy_cols(int64_t n, int64_t nb, const cpx<T> *__restrict__ src, int64_t lds,
+                            cpx<T> *x, int64_t ldx) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int64_t i = t % n, j = t / n;
+    x[i + j * ldx] = src[i + j * lds];
 }
 
 template <typename T> const cpx<T> *tw1_of(const FFTPlan &p);
@@ -321,12 +334,22 @@ template <> const zf *twN_of<float>(const FFTPlan &p) { return (const zf *)p.twM
 
 template <typename T>
 void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx, int64_t nb,
-                       hipStream_t s) {
+                       hipStream_t s, const cpx<T> *src, int64_t lds) {
     if (nb <= 0) return;
     const int bs = 256;
+    if (!src) {
+        src = x;
+        lds = ldx;
+    }
+    if (src != x && p.N2 == 1) {
+        // one pass, in place: copy the input first
+        const int64_t n = (int64_t)p.M * nb;
+        hipLaunchKernelGGL(k_copy_cols<T>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s,
+                           (int64_t)p.M, nb, src, lds, x, ldx);
+    }
     // algorithmic work: bytes of one read and one write of the batch
     ProfScope prof(PROF_FFT, 2.0 * sizeof(cpx<T>) * (double)p.M * (double)nb, s);
-    if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), x, ldx, nb, false, s);
+    if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), src, lds, x, ldx, nb, false, s);
     if (p.N1 == 4096) {
         hipLaunchKernelGGL(k_fft_mid4096<T>, dim3((unsigned)(p.N2 * nb)), dim3(256), 0, s,
                            p.N2, tw1_of<T>(p), d, x, ldx);
@@ -335,13 +358,13 @@ void launch_circ_apply(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx
         hipLaunchKernelGGL(k_fft_mid<T>, dim3((unsigned)(p.N2 * nb)), dim3(bs), sh, s, p.N1,
                            p.N2, tw1_of<T>(p), d, x, ldx);
     }
-    if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), x, ldx, nb, true, s);
+    if (p.N2 > 1) launch_stepA<T>(p, twN_of<T>(p), x, ldx, x, ldx, nb, true, s);
 }
 
 template void launch_circ_apply<double>(const FFTPlan &, const zd *, zd *, int64_t, int64_t,
-                                        hipStream_t);
+                                        hipStream_t, const zd *, int64_t);
 template void launch_circ_apply<float>(const FFTPlan &, const zf *, zf *, int64_t, int64_t,
-                                       hipStream_t);
+                                       hipStream_t, const zf *, int64_t);
 
 template <typename T>
 __global__ void k_pad(int N, int M, int64_t nb, const cpx<T> *__restrict__ x, int64_t ldx,
@@ -362,20 +385,25 @@ __global__ void k_unpad(int N, int M, int64_t nb, const cpx<T> *__restrict__ P, 
 
 template <typename T>
 void launch_circ_apply_padded(const FFTPlan &p, const cpx<T> *d, cpx<T> *x, int64_t ldx,
-                              int64_t nb, cpx<T> *P, hipStream_t s) {
+                              int64_t nb, cpx<T> *P, hipStream_t s, const cpx<T> *src,
+                              int64_t lds) {
     if (nb <= 0) return;
     const int bs = 256;
+    if (!src) {
+        src = x;
+        lds = ldx;
+    }
     int64_t nM = (int64_t)p.M * nb, nN = (int64_t)p.N * nb;
     hipLaunchKernelGGL(k_pad<T>, dim3((unsigned)((nM + bs - 1) / bs)), dim3(bs), 0, s, p.N, p.M,
-                       nb, (const cpx<T> *)x, ldx, P);
-    launch_circ_apply<T>(p, d, P, p.M, nb, s);
+                       nb, src, lds, P);
+    launch_circ_apply<T>(p, d, P, p.M, nb, s, (const cpx<T> *)nullptr, 0);
     hipLaunchKernelGGL(k_unpad<T>, dim3((unsigned)((nN + bs - 1) / bs)), dim3(bs), 0, s, p.N,
                        p.M, nb, (const cpx<T> *)P, x, ldx);
 }
 template void launch_circ_apply_padded<double>(const FFTPlan &, const zd *, zd *, int64_t,
-                                               int64_t, zd *, hipStream_t);
+                                               int64_t, zd *, hipStream_t, const zd *, int64_t);
 template void launch_circ_apply_padded<float>(const FFTPlan &, const zf *, zf *, int64_t,
-                                              int64_t, zf *, hipStream_t);
+                                              int64_t, zf *, hipStream_t, const zf *, int64_t);
 
 // DFT by direct summation: y_m = scale sum_q x_q w^{m q} with w = tw[1] (tw: the n-th roots
 // of unity, e^{-2 pi i j / n}), conjugated for inverse.  One wavefront per output m (so that
