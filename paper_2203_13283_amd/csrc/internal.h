@@ -214,7 +214,9 @@ __host__ __device__ inline SrftPlan srft_plan(int lgN) {
     SrftPlan p;
     p.lgN = lgN;
     p.npass = lgN <= 0 ? 0 : (lgN + 4) / 5;           // radices of at most 32
-    for (int l = 0; l < p.npass; ++l) p.bits[l] = lgN / p.npass + (l < lgN % p.npass ? 1 : 0);
+    // the larger radices last, where the columns of a butterfly group lie closer together
+    for (int l = 0; l < p.npass; ++l)
+        p.bits[l] = lgN / p.npass + (l >= p.npass - lgN % p.npass ? 1 : 0);
     return p;
 }
 // frequency j of the column at position p: pass l contributes its digit e_l at weight

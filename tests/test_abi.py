@@ -70,8 +70,8 @@ def test_srft_frequency_map():
     f = lib.cfie_srft_frequency
     for n in (8, 16, 32):
         assert [f(n, p) for p in range(n)] == list(range(n))
-    # N = 64: passes of 8 and 8; N = 128: passes of 16 and 8
-    for n, b1, b2 in ((64, 3, 3), (128, 4, 3), (1024, 5, 5)):
+    # N = 64: passes of 8 and 8; N = 128: passes of 8 and 16
+    for n, b1, b2 in ((64, 3, 3), (128, 3, 4), (1024, 5, 5)):
         for p in range(n):
             e1, e2 = p >> b2, p & ((1 << b2) - 1)
             assert f(n, p) == e1 + (e2 << b1), (n, p)
