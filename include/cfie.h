@@ -115,7 +115,7 @@ typedef struct {
  * rows (32 N M bytes more during the factorisation in FP64, 16 N M in mixed precision) and
  * each block's products with D^k and N^k become column gathers; with C - C_c formed densely,
  * (C - C_c) D F is formed once (16 N M bytes, 8 N M) and a block is a column gather.  Once
- * all M Fourier columns have been drawn the blocks are Gaussian again. */
+ * N Fourier columns have been drawn the blocks are Gaussian. */
 enum {
     CFIE_SKETCH_GAUSSIAN = 0,    /* real Gaussian blocks (Philox4x32-10 stream of seed)        */
     CFIE_SKETCH_SRFT = 1         /* Gaussian first block, then SRFT columns                    */

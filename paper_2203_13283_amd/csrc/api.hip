@@ -893,11 +893,13 @@ cfie_status factor_impl(cfie_ctx *c) {
     launch_fill_int(1, 0, c->info, s);                 // pivot flag (also for rank 0)
     size_t bi = 0;                                     // block index (schedule of a replay)
     bool pending_dense = false;     // C - C_c was just formed densely (automatic switch)
-    // SRFT test matrix: blocks after the first take the columns of D F (F of the length
-    // Mf = the smallest power of two >= N, its first N rows) at positions
-    // perm(srft_off + t).  Factor by factor, D^k D F and N^k D F are formed when the second
-    // block is drawn, so a sketch that one block completes does not pay for them; with
-    // C - C_c formed densely, (C - C_c) D F, and a block is a column gather.  The order of the
+    // SRFT test matrix: the blocks after the first take the columns of D F (F of the length
+    // Mf = the smallest power of two >= N, its first N rows) at positions perm(srft_off + t),
+    // up to N columns in all.  Factor by factor, D^k D F and N^k D F are formed when the
+    // second block is drawn, so a sketch that one block completes does not pay for them; with
+    // C - C_c formed densely, (C - C_c) D F, and a block is a column gather.  (The first block
+    // stays Gaussian: on a small mesh a few SRFT blocks would cover the whole Fourier basis,
+    // and a sketch that has seen every column keeps every direction.)  The order of the
     // decisions depends on the schedule only, so a replay repeats them.
     int lgM = 0;
     while ((1 << lgM) < N) ++lgM;
@@ -940,7 +942,11 @@ cfie_status factor_impl(cfie_ctx *c) {
         // fresh Gaussian column estimates: an SRFT block's norms are scaled by
         // ((Mf - n_d) / Mf)^(1/2) for the stop test and the kept directions (tau_b)
         double est_scale = 1.0;
-        if (srft && bi > 0 && srft_off + bb <= Mf) {
+        // at most N Fourier columns: more columns of the padded transform (Mf > N) than the
+        // dimension N are no longer independent samples of what remains (their images lie in
+        // the span the earlier columns have already given Q), so the sketch goes on with
+        // Gaussian blocks from there
+        if (srft && bi > 0 && srft_off + bb <= std::min(Mf, N)) {
             est_scale = std::sqrt((double)(Mf - srft_off) / (double)Mf);
             if (!dv) {
                 dv = c->tmp_buf<cpx<T>>(SLOT_SRFT_D, (size_t)N);

@@ -17,7 +17,7 @@ D^k D F and N^k D F (or (C - C_c) D F), formed once by radix passes along the ro
   and within epsilon (both about 1.1e-6 here), mixed precision after refinement within
   1e-6; ranks within 10 %; the same with C - C_c formed densely, and at N = 1000 (the
   padded transform);
-* all M Fourier columns drawn (N = 256, blocks of 64, the oversampling stop off): the sketch
+* all N Fourier columns drawn (N = 256, blocks of 64, the oversampling stop off): the sketch
   falls back to Gaussian blocks and still meets the 1e-10 bar;
 * cfie_srft_rows before cfie_assemble is ESTATE.
 """
