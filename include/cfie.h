@@ -200,7 +200,10 @@ void cfie_default_options(cfie_options *opt);
 
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for
  * the null stream).  *out is set only on success.  EINVAL on bad options, EHIP if the
- * device cannot be selected. */
+ * device cannot be selected.  Device memory comes from the device's default stream-ordered
+ * pool (hipMallocAsync); while any context lives on the device the pool keeps memory that
+ * contexts free (its release threshold raised) so that later factorisations reuse it, and
+ * when the last one is destroyed the threshold returns to 0 and the pool is trimmed. */
 cfie_status cfie_create(const cfie_options *opt, int device, void *hip_stream,
                         cfie_ctx **out);
 
