@@ -842,11 +842,20 @@ void set_splitk_override(void *p, size_t bytes) {
 }
 
 namespace {
-int splitk_factor(int64_t m, int64_t n, int64_t k) {
+int splitk_factor(int op, int64_t m, int64_t n, int64_t k) {
     const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
     int S = 1;
     if (tiles < 192 && k >= 4096) {
         S = (int)std::min<int64_t>((512 + tiles - 1) / tiles, k / 512);
+        // A^H products whose 128 x 128 grid is short of one wave (the sketch's projections
+        // Q^H Y against the directions found so far): enough K slices for one wave of wide
+        // tiles.  The split depends on the shape only, not on the tile that runs it, so the
+        // tile choice stays bitwise-neutral.
+        if (op == GEMM_C && m >= kWideTile && n >= kWideTile) {
+            const int64_t tw =
+                ((m + kWideTile - 1) / kWideTile) * ((n + kWideTile - 1) / kWideTile);
+            S = (int)std::max<int64_t>(S, std::min<int64_t>((256 + tw - 1) / tw, k / 512));
+        }
         S = std::max(1, std::min(S, 64));
     }
     return S;
@@ -932,7 +941,7 @@ size_t gemm_splitk_bytes(int op, int64_t m, int64_t n, int64_t k, size_t elem) {
         skinny_split(m, n, k, S, kchunk);
         return S > 1 ? (size_t)S * (size_t)m * (size_t)n * elem : 0;
     }
-    int S = splitk_factor(m, n, k);
+    int S = splitk_factor(op, m, n, k);
     if (S <= 1) return 0;
     const int64_t kchunk = ((k + S - 1) / S + 15) / 16 * 16;
     S = (int)((k + kchunk - 1) / kchunk);
@@ -950,7 +959,7 @@ void gemm(int op, int64_t m, int64_t n, int64_t k, cpx<T> alpha, const cpx<T> *A
         return;
     }
     // K is split when the output has too few 64 x 64 tiles to fill 256 CUs
-    const int S = splitk_factor(m, n, k);
+    const int S = splitk_factor(op, m, n, k);
     const bool wide = sizeof(T) == sizeof(double) && use_wide(m, n, k, S, lda, ldb);
     const int v = wide ? 0 : tuned_variant<T>(op, m, n, k, S, alpha, A, lda, B, ldb, s);
     // work: the real flops the kernel executes -- 6 m n k for a complex product in the 3M
