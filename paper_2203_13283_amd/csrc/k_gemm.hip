@@ -430,6 +430,7 @@ __global__ __launch_bounds__(512, 1) void k_zgemm_wide(int64_t m, int64_t n, int
 #pragma unroll
             for (int b = 0; b < 2; ++b) sb[b] = bv[b].x + bv[b].y;
         }
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             if constexpr (BREAL) {
@@ -450,6 +451,7 @@ __global__ __launch_bounds__(512, 1) void k_zgemm_wide(int64_t m, int64_t n, int
             av[a] = NBUF ? As1[NKQ * 8 + ta + a][lane] : As0[NKQ * 8 + ta + a][lane];
             if (a == 1) hook();
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int b = 0; b < 2; ++b) bv[b] = bn[b];
     };
