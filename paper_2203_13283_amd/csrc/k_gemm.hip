@@ -175,6 +175,7 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
         }
     };
     auto mma_slice = [&]() {
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int k4 = 0; k4 < BKT; k4 += 4) {
             const int kk = k4 + (lane >> 4);
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(256, MINB) void k_zgemm(int64_t m, int64_t n, int64
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
     };
 
     typedef std::integral_constant<bool, false> no_t;
